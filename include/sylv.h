@@ -1,0 +1,198 @@
+/*
+ * sylv.h - C ABI of the MI355X factorized Krylov solver for the Sylvester equation
+ *
+ *      A X + X B = C1 C2^T                                     (problem statement, eq. (1.1))
+ *
+ * with sparse A (n x n), B (m x m) and a low-rank right-hand side C1 (n x s), C2 (m x s).
+ * The solution is returned in factored form X = V Xc W^T (Corollary 3.3): V (n x r_v) and
+ * W (m x r_w) have orthonormal columns spanning block Krylov spaces of A and B^T, Xc is a small
+ * r_v x r_w core.
+ *
+ * Conventions for every call below
+ *   - Sizes are int64_t. Dense arrays are row-major with an explicit leading dimension
+ *     (elements between consecutive rows).
+ *   - Array pointers are DEVICE pointers (memory of the GPU the context was created on),
+ *     allocated and owned by the caller, unless the parameter is marked "host".
+ *   - The library allocates no device memory: every device buffer it needs lives in the
+ *     workspace the caller passes to sylv_create (size from sylv_workspace_bytes). The library
+ *     allocates only the host-side context and small host arrays for histories.
+ *   - All device work is issued on the stream given to sylv_create (a hipStream_t passed as
+ *     void*; NULL is the default stream). Calls that return a status wait for their work.
+ *   - Return codes: 0 success, > 0 a solver outcome with a valid iterate, < 0 an error that
+ *     leaves the context unchanged. sylv_status_string() names each code.
+ *   - A context is not thread-safe; use one context per stream.
+ */
+#ifndef SYLV_H
+#define SYLV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  SYLV_OK = 0,              /* converged: ||R_{k+1}|| <= tol * ||R_0|| (Alg. 4.1/4.2)       */
+  SYLV_NOT_CONVERGED = 1,   /* max_iter reached; the last iterate is kept                   */
+  SYLV_BREAKDOWN = 2,       /* a denominator of the recurrences vanished (or <P,Q> <= 0 in
+                               CG); the last completed iterate is kept                       */
+  SYLV_ERR_INVALID = -1,    /* bad argument (sizes, NULL pointers, malformed CSR)           */
+  SYLV_ERR_HIP = -2,        /* a HIP runtime call failed                                     */
+  SYLV_ERR_WORKSPACE = -3,  /* workspace missing, misaligned or smaller than required        */
+  SYLV_ERR_RHS_RANK = -4,   /* C1 or C2 is not of full column rank (its QR fails)           */
+  SYLV_ERR_STATE = -5       /* call out of order (e.g. factors requested before a solve)     */
+};
+
+enum { SYLV_METHOD_CG = 0, SYLV_METHOD_BICGSTAB = 1 };
+
+/* Compressed sparse row matrix: rows x rows, int32 row_ptr (rows + 1 entries, row_ptr[0] = 0)
+ * and col_idx (nnz entries, sorted and unique within each row, 0 <= col < rows), float64
+ * values (nnz). Device pointers, borrowed until sylv_destroy. */
+typedef struct {
+  int64_t rows;
+  int64_t nnz;
+  const int32_t *row_ptr;
+  const int32_t *col_idx;
+  const double *values;
+} sylv_csr;
+
+/* One problem A X + X B = C1 C2^T (eq. (1.1)).
+ * lyapunov != 0 selects the Lyapunov equation A X + X A^T = C1 C1^T (Section 4.3): B and C2
+ * are ignored, n must equal m, and the solution is X = V Xc V^T.
+ * C1 is n x s with leading dimension ldc1 >= s; C2 is m x s with ldc2 >= s. Both are read
+ * during sylv_create only. 1 <= s <= 8 and s <= min(n, m). */
+typedef struct {
+  int64_t n, m, s;
+  sylv_csr A;
+  sylv_csr B;
+  int lyapunov;
+  const double *C1;
+  int64_t ldc1;
+  const double *C2;
+  int64_t ldc2;
+} sylv_problem;
+
+/* Options. method and max_iter size the workspace (the basis grows by s columns per CG
+ * iteration and by 2s per BiCGSTAB iteration). check_every: the host waits for the device's
+ * convergence flag every this many iterations (iterations enqueued after convergence do no
+ * work). closure_tol: a new basis block whose norm after orthogonalization is at most
+ * closure_tol times ||M V_j||_F is replaced by a zero block (Krylov space exhausted).
+ * sylv_default_options() fills sensible values. */
+typedef struct {
+  int method;
+  int max_iter;
+  int check_every;
+  int record_history;
+  double closure_tol;
+} sylv_options;
+
+/* Outcome of one solve. rank_v / rank_w: number of columns of the returned V and W;
+ * rel_res_recursive: ||R_k|| / ||R_0|| from the recurrence (the algorithm's stopping test). */
+typedef struct {
+  int status;
+  int iters;
+  int64_t rank_v;
+  int64_t rank_w;
+  double rel_res_recursive;
+  double seconds;
+} sylv_result;
+
+void sylv_default_options(sylv_options *opt);
+
+/* Bytes of device workspace sylv_create needs for this problem and these options. Returns 0
+ * if the problem or options are invalid. */
+size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt);
+
+/* Validates the problem, forms B^T in CSR on the device (unless Lyapunov), and computes the
+ * QR factorizations C1 = V_1 R_L, C2 = W_1 R_R (Alg. 4.1 step 1, Alg. 4.2 step 2).
+ * workspace: device buffer of ws_bytes >= sylv_workspace_bytes(), 256-byte aligned, owned by
+ * the caller and used exclusively by this context until sylv_destroy.
+ * Errors: SYLV_ERR_INVALID, SYLV_ERR_WORKSPACE, SYLV_ERR_RHS_RANK, SYLV_ERR_HIP. */
+int sylv_create(void **ctx, const sylv_problem *prob, const sylv_options *opt,
+                void *workspace, size_t ws_bytes, void *stream);
+
+/* Factorized CG, Algorithm 4.1 (A and B symmetric positive definite), zero initial guess,
+ * stopping test ||R_{k+1}|| <= tol ||R_0||. max_iter <= the value the workspace was sized
+ * for. On return the iterate X_{k+1} = V_{k+1} Xc W_{k+1}^T is available through
+ * sylv_get_factors. Returns the status also stored in res (res may be NULL). */
+int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res);
+
+/* Factorized BiCGSTAB, Algorithm 4.2 with R~0 = R0; on return X_{k+1} = V_{2k+2} Xc
+ * W_{2k+2}^T. Same conventions as sylv_factored_cg. */
+int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res);
+
+/* True residual of the current iterate in FP64: abs_res = ||A X + X B - C1 C2^T||_F and
+ * rel_res = abs_res / ||C1 C2^T||_F (host pointers). Evaluated from the factors without
+ * forming X, as traces of small Gram products of the tall factors (inner product of
+ * Section 2 / eq. (3.10), operator eq. (3.11) plus the basis defect A V - V H). */
+int sylv_residual_norm(void *ctx, double *abs_res, double *rel_res);
+
+/* Copies the factors of the current iterate: V (n x rank_v, ldv), Xc (rank_v x rank_w, ldx),
+ * W (m x rank_w, ldw), device pointers. Any of V, Xc, W may be NULL to skip it; rank_v and
+ * rank_w (host) receive the ranks, so a first call with all arrays NULL queries the sizes.
+ * For a Lyapunov problem W is V. SYLV_ERR_STATE before a solve. */
+int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx,
+                     double *W, int64_t ldw, int64_t *rank_v, int64_t *rank_w);
+
+/* Per-iteration history of the last solve, host arrays of capacity cap (any may be NULL):
+ * relres[k] = ||R_{k+1}|| / ||R_0||, alpha[k], beta[k], omega[k] (omega only for BiCGSTAB;
+ * beta[k] is undefined for the final iteration). *count receives the number of iterations. */
+int sylv_get_history(void *ctx, double *relres, double *alpha, double *beta, double *omega,
+                     int cap, int *count);
+
+void sylv_destroy(void *ctx);
+
+const char *sylv_status_string(int status);
+
+/* ---- measurement hooks ---- */
+
+/* Time per kernel family, summed over the iterations the solves actually ran. */
+typedef struct {
+  int family;        /* index; sylv_kernel_family_name() names it                        */
+  int64_t launches;  /* timed launches                                                   */
+  double ms;         /* summed launch durations (HIP events on the context's stream)     */
+  double bytes;      /* summed algorithmic bytes (the data the method must move)         */
+  double flops;      /* summed algorithmic floating-point operations                     */
+} sylv_kernel_stat;
+
+/* on != 0: later solves record HIP events around every launch of the timed kernel families
+ * (this serializes nothing but adds event overhead; use it for measurement runs) and the
+ * statistics restart from zero; on == 0 stops recording. */
+int sylv_set_profiling(void *ctx, int on);
+
+/* Copies up to cap family records into out (host); *count receives the number of families.
+ * SYLV_ERR_STATE if profiling is off. */
+int sylv_get_kernel_stats(void *ctx, sylv_kernel_stat *out, int cap, int *count);
+
+const char *sylv_kernel_family_name(int family);
+
+/* ---- building blocks, exposed for testing and reuse (same stream/ownership rules) ---- */
+
+/* Y = A X for CSR A (rows x rows) and a row-major panel X (rows x s, leading dimension ldx),
+ * Y rows x s with leading dimension ldy; 1 <= s <= 8. The CSR SpMM of the block Lanczos /
+ * Arnoldi step (eq. (3.8)). */
+int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double *Y,
+              int64_t ldy, void *stream);
+
+/* Transpose of a square CSR matrix (rows x rows, nnz entries) into caller buffers:
+ * out_row_ptr (rows + 1), out_col_idx (nnz), out_values (nnz). The result is canonical
+ * (sorted column indices), so it is bit-identical to any other exact transpose. scratch:
+ * device buffer of at least sylv_csr_transpose_scratch_bytes(rows) bytes. */
+size_t sylv_csr_transpose_scratch_bytes(int64_t rows);
+int sylv_csr_transpose(const sylv_csr *A, int32_t *out_row_ptr, int32_t *out_col_idx,
+                       double *out_values, void *scratch, void *stream);
+
+/* C (M x N, ldc) = alpha * op(A) op(B) + beta * C in FP64 on FP64 MFMA, with element strides:
+ * A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs] (a transpose is a swap of the two
+ * strides). The dense contraction behind the Gram products of the residual evaluation and the
+ * core operator eq. (3.11). beta == 0 ignores C's old contents. */
+int sylv_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t a_rs,
+               int64_t a_cs, const double *B, int64_t b_rs, int64_t b_cs, double beta, double *C,
+               int64_t ldc, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SYLV_H */

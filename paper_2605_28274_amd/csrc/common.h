@@ -1,0 +1,330 @@
+// Internal definitions shared by the HIP translation units of libsylv (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+#include "sylv.h"
+
+#define SYLV_MAX_S 8
+#define WAVE 64
+
+// Per-solve scalar state, resident in device memory. All recurrence scalars are FP64 and are
+// produced and consumed on the device; the host only polls `done`.
+struct DevState {
+  double rho;        // rho_k
+  double rho_next;   // rho_{k+1}
+  double alpha, omega, beta;
+  double normR0;     // ||R_0||_F = ||C1 C2^T||_F
+  double tol;
+  double relres;     // ||R_{k+1}|| / ||R_0||
+  double pq;         // CG: <P_k, Q_k(1:(k+1)s, 1:(k+1)s)>
+  double ts, tt;     // BiCGSTAB: <T(1:(2k+2)s,.), S>, <T, T>
+  int done;          // set once the solve stopped (converged or breakdown)
+  int status;        // SYLV_OK / SYLV_BREAKDOWN once done
+  int iters;         // completed iterations when done
+  int rho_zero;      // BiCGSTAB: rho_{k+1} == 0 (breakdown after the update)
+};
+
+// State of one basis (V with H, or W with G) for the block orthonormalization of a new block.
+struct SideState {
+  double ref2;                          // ||M V_j||_F^2 before orthogonalization
+  double g[SYLV_MAX_S * SYLV_MAX_S];    // Gram matrix of the current pass
+  double T1[SYLV_MAX_S * SYLV_MAX_S];   // first-pass normalizer (U1 = U T1)
+  double Hs1[SYLV_MAX_S * SYLV_MAX_S];  // first-pass subdiagonal factor (U = U1 Hs1)
+  double T[SYLV_MAX_S * SYLV_MAX_S];    // combined normalizer (V_{j+1} = U T)
+  int mode;                             // 0 regular, 1 closed (zero block), 2 deflated
+  int pad_[3];
+};
+
+// Counter slots for the "last workgroup reduces" pattern; each kernel family owns a range.
+enum {
+  CNT_SPMM = 0,
+  CNT_LZ1 = 8,
+  CNT_UPD = 16,
+  CNT_NRM = 24,
+  CNT_CORE = 32,
+  CNT_ELEM = 40,
+  CNT_GRAM = 64,  // one counter per 256-column tile of the basis (up to CNT_MAX)
+  CNT_MAX = 4096
+};
+
+#define HIPOK(x)                                      \
+  do {                                                \
+    hipError_t e_ = (x);                              \
+    if (e_ != hipSuccess) return SYLV_ERR_HIP;        \
+  } while (0)
+
+// ---- wave / block reductions (deterministic: fixed shuffle tree, fixed LDS order) ----
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Sum over a group of g lanes (g a power of two <= 64, groups aligned to g).
+__device__ __forceinline__ double group_sum(double v, int g) {
+  for (int off = g >> 1; off > 0; off >>= 1) v += __shfl_xor(v, off, WAVE);
+  return v;
+}
+
+// Block-wide sum of NV values per thread; result valid in thread 0. blockDim.x <= 1024.
+template <int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds /* >= 16*NV */) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int w = threadIdx.x / WAVE;
+  const int nw = (blockDim.x + WAVE - 1) / WAVE;
+#pragma unroll
+  for (int i = 0; i < NV; ++i) v[i] = wave_sum(v[i]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) lds[w * NV + i] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+      double a = 0.0;
+      for (int q = 0; q < nw; ++q) a += lds[q * NV + i];
+      v[i] = a;
+    }
+  }
+  __syncthreads();
+}
+
+// Returns true in every thread of the workgroup that arrives last at `counter` (grid of
+// `nblocks` workgroups). Partial results written before the call are visible to it. The last
+// workgroup must reset the counter (reset_counter) when done.
+__device__ __forceinline__ bool last_block(int *counter, int nblocks) {
+  __shared__ int s_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int prev = atomicAdd(counter, 1);
+    s_last = (prev == nblocks - 1);
+  }
+  __syncthreads();
+  const bool last = s_last != 0;
+  if (last) __threadfence();
+  return last;
+}
+
+__device__ __forceinline__ void reset_counter(int *counter) {
+  if (threadIdx.x == 0) atomicExch(counter, 0);
+}
+
+// Block-reduces NV values per thread, stores one partial per workgroup, and lets the last
+// workgroup of the grid sum the partials into out[0..NV) (shared memory of the caller). The
+// final sum is spread over the workgroup in a fixed order, so results are deterministic.
+// Returns true in every thread of the last workgroup (out is valid there).
+template <int NV>
+__device__ bool reduce_grid(double (&v)[NV], double *partials, int *counter, double *out) {
+  __shared__ double lds[16 * NV];
+  block_sum<NV>(v, lds);
+  const int nb = gridDim.x * gridDim.y;
+  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) partials[(size_t)bid * NV + i] = v[i];
+  }
+  if (!last_block(counter, nb)) return false;
+  double a[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) a[i] = 0.0;
+  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) a[i] += partials[(size_t)b * NV + i];
+  block_sum<NV>(a, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] = a[i];
+  __syncthreads();
+  reset_counter(counter);
+  return true;
+}
+
+// ---- small dense helpers executed by one thread (s <= 8) ----
+
+// Cholesky G = R^T R (upper R) of an s x s SPD matrix. Returns the smallest pivot ratio
+// d_i / G_ii (<= 0 on failure); rows of exactly-zero diagonal are passed through as identity.
+__device__ inline double chol_upper(const double *G, double *R, int s) {
+  double minratio = 1.0;
+  for (int i = 0; i < s * s; ++i) R[i] = 0.0;
+  for (int j = 0; j < s; ++j) {
+    double d = G[j * s + j];
+    if (d == 0.0) {  // an exactly zero column (deflated direction)
+      R[j * s + j] = 1.0;
+      continue;
+    }
+    for (int k = 0; k < j; ++k) d -= R[k * s + j] * R[k * s + j];
+    const double ratio = d / G[j * s + j];
+    if (ratio < minratio) minratio = ratio;
+    if (!(d > 0.0)) return ratio;
+    const double rjj = sqrt(d);
+    R[j * s + j] = rjj;
+    for (int i = j + 1; i < s; ++i) {
+      double v = G[j * s + i];
+      for (int k = 0; k < j; ++k) v -= R[k * s + j] * R[k * s + i];
+      R[j * s + i] = v / rjj;
+    }
+  }
+  return minratio;
+}
+
+// Inverse of an upper-triangular s x s matrix.
+__device__ inline void inv_upper(const double *R, double *Ri, int s) {
+  for (int i = 0; i < s * s; ++i) Ri[i] = 0.0;
+  for (int j = 0; j < s; ++j) {
+    Ri[j * s + j] = 1.0 / R[j * s + j];
+    for (int i = j - 1; i >= 0; --i) {
+      double v = 0.0;
+      for (int k = i + 1; k <= j; ++k) v += R[i * s + k] * Ri[k * s + j];
+      Ri[i * s + j] = -v / R[i * s + i];
+    }
+  }
+}
+
+// C = A B for s x s row-major matrices (C must not alias A or B).
+__device__ inline void matmul_small(const double *A, const double *B, double *C, int s) {
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) {
+      double v = 0.0;
+      for (int k = 0; k < s; ++k) v += A[i * s + k] * B[k * s + j];
+      C[i * s + j] = v;
+    }
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric s x s matrix: G = Z diag(lam) Z^T.
+__device__ inline void jacobi_eig(const double *G, double *lam, double *Z, int s) {
+  double a[SYLV_MAX_S * SYLV_MAX_S];
+  for (int i = 0; i < s * s; ++i) a[i] = G[i];
+  for (int i = 0; i < s; ++i)
+    for (int j = 0; j < s; ++j) Z[i * s + j] = (i == j) ? 1.0 : 0.0;
+  for (int sweep = 0; sweep < 60; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < s; ++i)
+      for (int j = 0; j < s; ++j) {
+        tot += a[i * s + j] * a[i * s + j];
+        if (i != j) off += a[i * s + j] * a[i * s + j];
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < s; ++p)
+      for (int q = p + 1; q < s; ++q) {
+        const double apq = a[p * s + q];
+        if (apq == 0.0) continue;
+        const double theta = (a[q * s + q] - a[p * s + p]) / (2.0 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+        const double c = 1.0 / sqrt(t * t + 1.0), sn = t * c;
+        for (int k = 0; k < s; ++k) {  // columns p, q
+          const double akp = a[k * s + p], akq = a[k * s + q];
+          a[k * s + p] = c * akp - sn * akq;
+          a[k * s + q] = sn * akp + c * akq;
+        }
+        for (int k = 0; k < s; ++k) {  // rows p, q
+          const double apk = a[p * s + k], aqk = a[q * s + k];
+          a[p * s + k] = c * apk - sn * aqk;
+          a[q * s + k] = sn * apk + c * aqk;
+        }
+        for (int k = 0; k < s; ++k) {
+          const double zkp = Z[k * s + p], zkq = Z[k * s + q];
+          Z[k * s + p] = c * zkp - sn * zkq;
+          Z[k * s + q] = sn * zkp + c * zkq;
+        }
+      }
+  }
+  for (int i = 0; i < s; ++i) lam[i] = a[i * s + i];
+}
+
+// ---- launchers implemented in the .hip files (all return 0 or SYLV_ERR_HIP) ----
+
+struct SideDesc {
+  int64_t rows;            // n (V side) or m (W side)
+  int64_t nnz;
+  const int32_t *rp;       // CSR of the operator applied to the basis (A, or B^T)
+  const int32_t *ci;
+  const double *val;
+  double *basis;           // rows x ldb row-major; block j occupies columns [j s, (j+1) s)
+  int64_t ldb;
+  double *H;               // block Hessenberg, ldc x ldc row-major
+  double *U;               // rows x s work panel
+  double *coef;            // compact coefficient block (ldb x s)
+  SideState *ss;           // device
+};
+
+struct Scratch {
+  double *partials;        // reduction partials
+  size_t partial_cap;      // in doubles
+  int *counters;           // CNT_MAX ints, zero at rest
+  void *prof;              // kernel timing recorder (null: off)
+};
+
+// Kernel families timed by the optional profiler (HIP events around each launch).
+enum {
+  FAM_SPMM = 0,     // M V_j (+ Lanczos local update / norms)
+  FAM_GRAM,         // Arnoldi V^T U
+  FAM_UPDATE,       // Arnoldi U -= V C
+  FAM_QR,           // block Cholesky-QR passes and normalization
+  FAM_CORE_OP,      // eq. (3.11) on dense Hessenberg cores (FP64 MFMA)
+  FAM_CORE_BAND,    // eq. (3.11) on block-tridiagonal cores
+  FAM_CORE_ELEM,    // core axpys, inner products and scalar updates
+  FAM_COUNT
+};
+void prof_begin(const Scratch &sc, hipStream_t st);
+void prof_end(const Scratch &sc, int fam, double bytes, double flops, hipStream_t st);
+
+int launch_spmm(int s, int64_t rows, const int32_t *rp, const int32_t *ci, const double *val,
+                const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t st);
+int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
+                     const double *val, const double *X, int64_t ldx, int ncols, double *Y,
+                     int64_t ldy, hipStream_t st);
+int launch_csr_transpose(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                         const double *val, int32_t *orp, int32_t *oci, double *oval,
+                         void *scratch, hipStream_t st);
+size_t csr_transpose_scratch(int64_t rows);
+
+// Block orthonormalization steps (krylov.hip).
+int launch_first_block(int s, const SideDesc &sd, const double *C, int64_t ldc_in,
+                       double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
+int launch_lanczos_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
+                        const Scratch &sc, DevState *ds, hipStream_t st);
+int launch_arnoldi_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
+                        const Scratch &sc, DevState *ds, hipStream_t st);
+
+// Core recurrences (core.hip).
+int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, double *P,
+                         double *Rt, int64_t ldc, double tol, DevState *ds, hipStream_t st);
+int launch_cg_core(int s, int p, const double *H, const double *G, const double *P, double *Q,
+                   int64_t ldc, const Scratch &sc, DevState *ds, double *hist, int k,
+                   int max_iter, hipStream_t st);
+int launch_cg_update(int s, int p, double *X, double *R, double *P, const double *Q, int64_t ldc,
+                     const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
+                     hipStream_t st);
+int launch_bicg_s(int s, int p, const double *Q, const double *R, double *S, const double *Rt,
+                  int64_t ldc, DevState *ds, double *hist, int k, int max_iter, hipStream_t st);
+int launch_bicg_omega(int s, int p, const double *T, const double *S, const double *Rt,
+                      int64_t ldc, const Scratch &sc, DevState *ds, double *hist, int k,
+                      int max_iter, hipStream_t st);
+int launch_bicg_update(int s, int p, double *X, double *R, double *P, const double *Q,
+                       const double *S, const double *T, int64_t ldc, const Scratch &sc,
+                       DevState *ds, double *hist, int k, int max_iter, hipStream_t st);
+
+// Dense FP64 GEMM C (M x N) = alpha * op(A) op(B) + beta * C with element strides:
+// A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs], C(i,j) = C[i*ldc + j].
+int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t a_rs,
+                int64_t a_cs, const double *B, int64_t b_rs, int64_t b_cs, double beta, double *C,
+                int64_t ldc, hipStream_t st);
+// Core Sylvester operator eq. (3.11) on dense padded cores: Q = [H P, 0] + [P G^T; 0] where
+// P is p x p and H, G are (p+s) x p (Hessenberg), all ldc-strided; the result is written over
+// the full (p+s) region rounded up to the tile size (entries outside are exact zeros).
+int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,
+                   int64_t ldc, const int *done, hipStream_t st);
+int launch_csr_validate(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, int *flag,
+                        hipStream_t st);
+int launch_dot(int64_t M, int64_t N, const double *A, int64_t lda, const double *B, int64_t ldb,
+               double *out, const Scratch &sc, hipStream_t st);
+int launch_rhat(int s, int q, const double *Lx, const double *R0, double *Rh, int64_t ldc,
+                hipStream_t st);

@@ -1,0 +1,212 @@
+// CSR kernels: SpMM with tall-skinny panels (the sparse products of the block Lanczos /
+// Arnoldi step, eq. (3.8)), the wide SpMM of the residual evaluation, CSR validation and an
+// exact CSR transpose (B^T for the W basis).
+#include "common.h"
+
+namespace {
+
+// Y[r, 0:S] = sum_q A[r, c_q] X[c_q, 0:S]; one thread per row. Stencil rows hold 3-7
+// entries, so a row's column indices and values are a few contiguous words and the gathered
+// panel rows are S contiguous doubles that mostly hit L2 (neighbouring grid points).
+template <int S>
+__global__ __launch_bounds__(256) void spmm_kernel(int64_t rows, const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ ci,
+                                                   const double *__restrict__ val,
+                                                   const double *__restrict__ X, int64_t ldx,
+                                                   double *__restrict__ Y, int64_t ldy) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  double acc[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) acc[t] = 0.0;
+  const int b = rp[r], e = rp[r + 1];
+  for (int q = b; q < e; ++q) {
+    const double a = val[q];
+    const double *x = X + (int64_t)ci[q] * ldx;
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+  }
+  double *y = Y + r * ldy;
+#pragma unroll
+  for (int t = 0; t < S; ++t) y[t] = acc[t];
+}
+
+// Wide SpMM for rows [r0, r1): Y[r - r0, 0:ncols] = A[r, :] X[:, 0:ncols]; one wave per row,
+// lanes across columns (coalesced reads of X rows and writes of Y rows).
+__global__ __launch_bounds__(256) void spmm_wide_kernel(int64_t r0, int64_t r1,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const double *__restrict__ val,
+                                                        const double *__restrict__ X, int64_t ldx,
+                                                        int ncols, double *__restrict__ Y,
+                                                        int64_t ldy) {
+  const int64_t r = r0 + (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (r >= r1) return;
+  const int b = rp[r], e = rp[r + 1];
+  double *y = Y + (r - r0) * ldy;
+  for (int j0 = 0; j0 < ncols; j0 += 4 * WAVE) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int q = b; q < e; ++q) {
+      const double a = val[q];
+      const double *x = X + (int64_t)ci[q] * ldx;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u * WAVE + lane;
+        if (j < ncols) acc[u] = fma(a, x[j], acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * WAVE + lane;
+      if (j < ncols) y[j] = acc[u];
+    }
+  }
+}
+
+__global__ void csr_count_kernel(int64_t nnz, const int32_t *__restrict__ ci, int *cnt) {
+  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q < nnz) atomicAdd(&cnt[ci[q] + 1], 1);
+}
+
+// Exclusive scan of cnt[0..rows] (cnt[0] = 0) into out[0..rows]; one workgroup of 1024 threads.
+__global__ __launch_bounds__(1024) void scan_kernel(int64_t len, const int *__restrict__ cnt,
+                                                    int32_t *__restrict__ out) {
+  __shared__ int buf[1024];
+  __shared__ int carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (int64_t base = 0; base < len; base += 1024) {
+    const int64_t i = base + threadIdx.x;
+    int v = (i < len) ? cnt[i] : 0;
+    buf[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
+      int t = (threadIdx.x >= off) ? buf[threadIdx.x - off] : 0;
+      __syncthreads();
+      buf[threadIdx.x] += t;
+      __syncthreads();
+    }
+    if (i < len) out[i] = carry + buf[threadIdx.x];
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += buf[1023];
+    __syncthreads();
+  }
+}
+
+__global__ void csr_scatter_kernel(int64_t rows, const int32_t *__restrict__ rp,
+                                   const int32_t *__restrict__ ci, const double *__restrict__ val,
+                                   int *cursor, int32_t *__restrict__ oci,
+                                   double *__restrict__ oval) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  for (int q = rp[r]; q < rp[r + 1]; ++q) {
+    const int c = ci[q];
+    const int pos = atomicAdd(&cursor[c], 1);
+    oci[pos] = (int32_t)r;
+    oval[pos] = val[q];
+  }
+}
+
+// Sorts each row of the transposed matrix by column (insertion sort; rows are short).
+__global__ void csr_sort_rows_kernel(int64_t rows, const int32_t *__restrict__ rp,
+                                     int32_t *__restrict__ ci, double *__restrict__ val) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int b = rp[r], e = rp[r + 1];
+  for (int i = b + 1; i < e; ++i) {
+    const int32_t c = ci[i];
+    const double v = val[i];
+    int j = i - 1;
+    while (j >= b && ci[j] > c) {
+      ci[j + 1] = ci[j];
+      val[j + 1] = val[j];
+      --j;
+    }
+    ci[j + 1] = c;
+    val[j + 1] = v;
+  }
+}
+
+}  // namespace
+
+int launch_spmm(int s, int64_t rows, const int32_t *rp, const int32_t *ci, const double *val,
+                const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t st) {
+  if (rows <= 0) return 0;
+  const dim3 grid((unsigned)((rows + 255) / 256)), block(256);
+  switch (s) {
+#define CASE(SS) \
+  case SS: spmm_kernel<SS><<<grid, block, 0, st>>>(rows, rp, ci, val, X, ldx, Y, ldy); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
+                     const double *val, const double *X, int64_t ldx, int ncols, double *Y,
+                     int64_t ldy, hipStream_t st) {
+  (void)s;
+  if (r1 <= r0 || ncols <= 0) return 0;
+  const int64_t nr = r1 - r0;
+  spmm_wide_kernel<<<(unsigned)((nr + 3) / 4), 256, 0, st>>>(r0, r1, rp, ci, val, X, ldx, ncols,
+                                                              Y, ldy);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+size_t csr_transpose_scratch(int64_t rows) { return (size_t)(rows + 2) * 2 * sizeof(int) + 256; }
+
+int launch_csr_transpose(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci,
+                         const double *val, int32_t *orp, int32_t *oci, double *oval,
+                         void *scratch, hipStream_t st) {
+  int *cnt = reinterpret_cast<int *>(scratch);
+  int *cursor = cnt + (rows + 2);
+  HIPOK(hipMemsetAsync(cnt, 0, sizeof(int) * (rows + 1), st));
+  if (nnz > 0)
+    csr_count_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(nnz, ci, cnt);
+  HIPOK(hipGetLastError());
+  scan_kernel<<<1, 1024, 0, st>>>(rows + 1, cnt, orp);
+  HIPOK(hipGetLastError());
+  // cursor[c] = orp[c]; the +1 shift of cnt makes the inclusive scan of cnt the row starts
+  HIPOK(hipMemcpyAsync(cursor, orp, sizeof(int) * rows, hipMemcpyDeviceToDevice, st));
+  const unsigned g = (unsigned)((rows + 255) / 256);
+  csr_scatter_kernel<<<g, 256, 0, st>>>(rows, rp, ci, val, cursor, oci, oval);
+  HIPOK(hipGetLastError());
+  csr_sort_rows_kernel<<<g, 256, 0, st>>>(rows, orp, oci, oval);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+namespace {
+// Flags malformed CSR: bit 1 row_ptr[0] != 0, bit 2 row_ptr[rows] != nnz, bit 4 a row range
+// outside [0, nnz] or decreasing, bit 8 a column index out of range or not strictly increasing.
+__global__ void csr_validate_kernel(int64_t rows, int64_t nnz, const int32_t *__restrict__ rp,
+                                    const int32_t *__restrict__ ci, int *flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  if (r == 0 && rp[0] != 0) atomicOr(flag, 1);
+  if (r == rows - 1 && (int64_t)rp[rows] != nnz) atomicOr(flag, 2);
+  const int64_t b = rp[r], e = rp[r + 1];
+  if (b < 0 || e < b || e > nnz) {
+    atomicOr(flag, 4);
+    return;
+  }
+  int prev = -1;
+  for (int64_t q = b; q < e; ++q) {
+    const int c = ci[q];
+    if (c < 0 || c >= rows || c <= prev) atomicOr(flag, 8);
+    prev = c;
+  }
+}
+}  // namespace
+
+int launch_csr_validate(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, int *flag,
+                        hipStream_t st) {
+  if (rows <= 0) return 0;
+  csr_validate_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(rows, nnz, rp, ci, flag);
+  HIPOK(hipGetLastError());
+  return 0;
+}

@@ -74,8 +74,9 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.rc_rows = std::min<int64_t>(maxrows, 16384);
   const int64_t tiles = (L.ldb + 255) / 256;
   const int64_t t16 = L.ldc / 16;
-  L.partial_cap = (size_t)std::max<int64_t>(
-      {256 * tiles * 256 * L.s, t16 * t16 * 2 + 64, (int64_t)1024 * 66, 4096});
+  L.partial_cap = std::max<size_t>(
+      {(size_t)(256 * tiles * 256 * L.s), (size_t)(t16 * t16 * 2 + 64), (size_t)1024 * 66,
+       arnoldi_partials_needed((int)L.s, L.n, L.lyap ? 0 : L.m, L.ldb)});
   size_t cur = 0;
   const size_t c2 = (size_t)L.ldc * L.ldc * sizeof(double);
   L.off_V = bump(cur, (size_t)L.n * L.ldb * 8);
@@ -491,8 +492,7 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
     // Q_k (step 6) and alpha_k (step 7)
     const double q2 = (double)(p + s) * (p + s);
     prof_begin(c->sc, c->st);
-    if ((e = launch_cg_core(s, p, c->H, c->G, c->P, c->Q, L.ldc, c->sc, c->ds, c->hist, k,
-                            max_iter, c->st)))
+    if ((e = launch_cg_core(s, p, c->H, c->G, c->P, c->Q, L.ldc, c->sc, c->ds, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_BAND, 8.0 * ((double)p * p + q2) + 2 * 8.0 * 3 * s * (p + s),
              2.0 * 2.0 * 3.0 * s * (double)p * (p + s), c->st);
@@ -534,11 +534,9 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
   for (int k = 0; k < max_iter; ++k) {
     const int p = (2 * k + 1) * s;
     set_iter(c, k);
+    const SideDesc *sw = L.lyap ? nullptr : &c->sw;
     // (2k+1)-th block Arnoldi step on both sides (Alg. 4.2 steps 5-6)
-    if ((e = launch_arnoldi_step(s, c->sv, 2 * k, L.ldc, c->closure_tol, c->sc, c->ds, c->st)))
-      return e;
-    if (!L.lyap &&
-        (e = launch_arnoldi_step(s, c->sw, 2 * k, L.ldc, c->closure_tol, c->sc, c->ds, c->st)))
+    if ((e = launch_arnoldi_pair(s, c->sv, sw, 2 * k, L.ldc, c->closure_tol, c->sc, c->ds, c->st)))
       return e;
     // Q_k (step 7), alpha_k (step 8), S_k (step 9)
     prof_begin(c->sc, c->st);
@@ -551,24 +549,21 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 3.0 * q1, 2.0 * q1, c->st);
     // (2k+2)-th Arnoldi step (steps 10-11)
-    if ((e = launch_arnoldi_step(s, c->sv, 2 * k + 1, L.ldc, c->closure_tol, c->sc, c->ds, c->st)))
-      return e;
-    if (!L.lyap && (e = launch_arnoldi_step(s, c->sw, 2 * k + 1, L.ldc, c->closure_tol, c->sc,
-                                            c->ds, c->st)))
+    if ((e = launch_arnoldi_pair(s, c->sv, sw, 2 * k + 1, L.ldc, c->closure_tol, c->sc, c->ds,
+                                 c->st)))
       return e;
     // T_k (step 12), omega_k (step 13), rho_{k+1}, beta_k (steps 18-19)
     prof_begin(c->sc, c->st);
     if ((e = launch_core_op(s, p + s, c->H, c->G, c->S, c->T, L.ldc, done, c->st))) return e;
     prof_end(c->sc, FAM_CORE_OP, coreop_bytes(p + s), coreop_flops(p + s), c->st);
     prof_begin(c->sc, c->st);
-    if ((e = launch_bicg_omega(s, p, c->T, c->S, c->Rt, L.ldc, c->sc, c->ds, c->hist, k,
-                               max_iter, c->st)))
+    if ((e = launch_bicg_omega(s, p, c->T, c->S, L.ldc, c->sc, c->ds, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 2.0 * q2, 4.0 * q2, c->st);
     // X, R, P updates and the stopping test (steps 14-15, 20)
     prof_begin(c->sc, c->st);
-    if ((e = launch_bicg_update(s, p, c->X, c->R, c->P, c->Q, c->S, c->T, L.ldc, c->sc, c->ds,
-                                c->hist, k, max_iter, c->st)))
+    if ((e = launch_bicg_update(s, p, c->X, c->R, c->P, c->Q, c->S, c->T, c->Rt, L.ldc, c->sc,
+                                c->ds, c->hist, k, max_iter, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 8.0 * q2, 12.0 * q2, c->st);
     if ((k + 1) % c->check_every == 0 && k + 1 < max_iter) {

@@ -1,0 +1,519 @@
+// Block Arnoldi step j for both bases at once (Algorithm 4.2, steps 5-6 and 10-11): the V basis
+// of K(A, C1) and the W basis of K(B^T, C2) advance in lockstep, so every launch below covers
+// both: workgroups [0, nb_0) work on basis 0 and [nb_0, nb_0 + nb_1) on basis 1. This halves
+// the launches of the step and fills the GPU with the smaller basis' work as well.
+//
+// Step (per basis, M the operator, V the row-major rows x ldb basis, U a rows x s panel):
+//   U = M V_j, partials of ||U||^2                                 spmm_pair
+//   two classical Gram-Schmidt sweeps:
+//     C = V[:, 0:ncols]^T U  (split-K over row chunks)            gram_part_pair
+//     sum of the chunk partials -> H column block j, coef         gram_reduce_pair
+//     U -= V[:, 0:ncols] C   (coef staged in LDS)                  update_pair
+//   (the second sweep's update also leaves partials of U^T U)
+//   first Cholesky-QR pass + closure test, partials of G2          qr2_pair
+//   second pass, V_{j+1} = U T, H_{j+1,j}                          final_pair
+// No kernel ends in a grid-wide fence: each reduction leaves one partial per workgroup and the
+// next kernel sums them in a fixed order (deterministic) after the kernel boundary; the small
+// s x s factorizations are then formed redundantly in every workgroup, and workgroup 0 records
+// them.
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int NG = 8;          // thread groups splitting the chunk sum in gram_reduce_pair
+constexpr int OPB = TPB / NG;  // outputs per gram_reduce_pair workgroup
+constexpr int UCH = 128;       // rows of U staged in LDS at a time by gram_part_pair
+constexpr int NQ = 4;          // 256-column groups processed together by gram_part_pair
+
+struct ArSide {
+  int64_t rows, nnz;
+  const int32_t *rp, *ci;
+  const double *val;
+  double *basis;
+  int64_t ldb;
+  double *H;
+  double *U;
+  double *coef;
+  SideState *ss;
+  double *part;    // Gram chunk partials of this basis
+  double *aux;     // partials of ||M V_j||^2, U^T U and of the second-pass Gram
+  int *cnt;        // counters of this basis (unused: no grid-wide reductions)
+  int nb_spmm, nb_upd, nb_qr;  // workgroups whose partials sit in aux
+  int b0, nb;      // workgroup range of this basis in the current launch
+  int64_t rpc;     // rows per chunk (gram) or rows per workgroup (update)
+};
+
+struct ArPair {
+  ArSide s[2];
+  int nsides;
+};
+
+// The basis this workgroup works on (selected without dynamic indexing of the kernel argument)
+// and the workgroup's index within that basis' range.
+__device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd) {
+  sd = (P.nsides > 1 && (int)blockIdx.x >= P.s[1].b0) ? 1 : 0;
+  const ArSide A = sd ? P.s[1] : P.s[0];
+  lb = (int)blockIdx.x - A.b0;
+  return A;
+}
+
+template <int S>
+__global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, int jb, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double red[1] = {0.0};
+  const int64_t r = (int64_t)lb * TPB + threadIdx.x;
+  if (r < A.rows) {
+    double acc[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = 0.0;
+    const int b = A.rp[r], e = A.rp[r + 1];
+    for (int q = b; q < e; ++q) {
+      const double a = A.val[q];
+      const double *x = A.basis + (int64_t)A.ci[q] * A.ldb + jb * S;
+#pragma unroll
+      for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      A.U[r * S + t] = acc[t];
+      red[0] = fma(acc[t], acc[t], red[0]);
+    }
+  }
+  __shared__ double lds[16];
+  block_sum<1>(red, lds);
+  if (threadIdx.x == 0) A.aux[lb] = red[0];
+}
+
+// Chunk partials of C = V^T U: workgroup lb owns rows [lb*rpc, (lb+1)*rpc) and all ncols
+// columns; thread t accumulates columns t + 256 q. part[lb][c][t] (rows of V are read once,
+// coalesced; U rows come from LDS).
+template <int S>
+__global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ double Us[UCH * S];
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  double *part = A.part + (size_t)lb * ncols * S;
+  for (int c0 = 0; c0 < ncols; c0 += TPB * NQ) {
+    double acc[NQ][S];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int t = 0; t < S; ++t) acc[q][t] = 0.0;
+    for (int64_t rb = r0; rb < r1; rb += UCH) {
+      const int nr = (int)((r1 - rb < UCH) ? r1 - rb : UCH);
+      __syncthreads();
+      for (int e = threadIdx.x; e < nr * S; e += TPB) Us[e] = A.U[rb * S + e];
+      __syncthreads();
+      const double *vrow = A.basis + rb * A.ldb + c0 + threadIdx.x;
+      int r = 0;
+      for (; r + 2 <= nr; r += 2) {
+        double v0[NQ], v1[NQ];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const bool ok = c0 + q * TPB + (int)threadIdx.x < ncols;
+          v0[q] = ok ? vrow[(int64_t)r * A.ldb + q * TPB] : 0.0;
+          v1[q] = ok ? vrow[(int64_t)(r + 1) * A.ldb + q * TPB] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+#pragma unroll
+          for (int t = 0; t < S; ++t) {
+            acc[q][t] = fma(v0[q], Us[r * S + t], acc[q][t]);
+            acc[q][t] = fma(v1[q], Us[(r + 1) * S + t], acc[q][t]);
+          }
+      }
+      for (; r < nr; ++r) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          const bool ok = c0 + q * TPB + (int)threadIdx.x < ncols;
+          const double v = ok ? vrow[(int64_t)r * A.ldb + q * TPB] : 0.0;
+#pragma unroll
+          for (int t = 0; t < S; ++t) acc[q][t] = fma(v, Us[r * S + t], acc[q][t]);
+        }
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int c = c0 + q * TPB + threadIdx.x;
+      if (c < ncols)
+#pragma unroll
+        for (int t = 0; t < S; ++t) part[c * S + t] = acc[q][t];
+    }
+  }
+}
+
+// Sums the nchunk partials of OPB consecutive outputs per workgroup: thread group g (of NG)
+// adds chunks [g nchunk / NG, (g+1) nchunk / NG) for its output, then group 0 adds the NG
+// group sums in order and writes column block j of H (store in sweep 1, add in sweep 2) and the
+// compact coefficients.
+__global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int ncols, int nchunk0,
+                                                        int nchunk1, int64_t ldh, int hcol,
+                                                        int pass, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ double gs[NG][OPB];
+  const int nchunk = sd ? nchunk1 : nchunk0;
+  const int nout = ncols * S;
+  const int ol = threadIdx.x % OPB, g = threadIdx.x / OPB;
+  const int o = lb * OPB + ol;
+  const int q0 = (int)((int64_t)nchunk * g / NG), q1 = (int)((int64_t)nchunk * (g + 1) / NG);
+  double a0 = 0.0, a1 = 0.0;
+  if (o < nout) {
+    int q = q0;
+    for (; q + 2 <= q1; q += 2) {
+      a0 += A.part[(size_t)q * nout + o];
+      a1 += A.part[(size_t)(q + 1) * nout + o];
+    }
+    if (q < q1) a0 += A.part[(size_t)q * nout + o];
+  }
+  gs[g][ol] = a0 + a1;
+  __syncthreads();
+  if (g == 0 && o < nout) {
+    double a = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) a += gs[q][ol];
+    const int c = o / S, t = o % S;
+    double *h = A.H + (int64_t)c * ldh + hcol + t;
+    *h = (pass == 1) ? a : *h + a;
+    A.coef[o] = a;
+  }
+}
+
+// U[r] -= V[r, 0:ncols] C with C (ncols x S) in LDS; one wave per row, lanes across columns.
+// With gram != 0 (second sweep) also reduces U^T U and runs the first QR pass per basis.
+template <int S>
+__global__ __launch_bounds__(TPB) void update_pair(ArPair P, int ncols, int gram,
+                                                   double closure_tol, const DevState *ds) {
+  if (ds->done) return;
+  extern __shared__ double Cs[];
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  for (int e = threadIdx.x; e < ncols * S; e += TPB) Cs[e] = A.coef[e];
+  __syncthreads();
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  for (int64_t r = r0 + w; r < r1; r += TPB / WAVE) {
+    const double *vr = A.basis + r * A.ldb;
+    double acc[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = 0.0;
+    int c = lane;
+    for (; c + 3 * WAVE < ncols; c += 4 * WAVE) {
+      const double v0 = vr[c], v1 = vr[c + WAVE], v2 = vr[c + 2 * WAVE], v3 = vr[c + 3 * WAVE];
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        acc[t] = fma(v0, Cs[c * S + t], acc[t]);
+        acc[t] = fma(v1, Cs[(c + WAVE) * S + t], acc[t]);
+        acc[t] = fma(v2, Cs[(c + 2 * WAVE) * S + t], acc[t]);
+        acc[t] = fma(v3, Cs[(c + 3 * WAVE) * S + t], acc[t]);
+      }
+    }
+    for (; c < ncols; c += WAVE) {
+      const double v = vr[c];
+#pragma unroll
+      for (int t = 0; t < S; ++t) acc[t] = fma(v, Cs[c * S + t], acc[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = wave_sum(acc[t]);
+    if (lane == 0) {
+      double u[S];
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        u[t] = A.U[r * S + t] - acc[t];
+        A.U[r * S + t] = u[t];
+      }
+      if (gram) {
+#pragma unroll
+        for (int a = 0; a < S; ++a)
+#pragma unroll
+          for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
+      }
+    }
+  }
+  if (!gram) return;
+  __shared__ double lds[16 * S * S];
+  block_sum<S * S>(g, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
+}
+
+// Sums n partial records of NV values (stride NV) in a fixed order; every thread gets the sum.
+template <int NV>
+__device__ __forceinline__ void sum_records(const double *p, int n, double (&out)[NV]) {
+  __shared__ double lds[16 * NV];
+  __shared__ double res[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = 0.0;
+  for (int b = threadIdx.x; b < n; b += TPB)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] += p[(size_t)b * NV + i];
+  block_sum<NV>(out, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) res[i] = out[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = res[i];
+}
+
+// First Cholesky-QR pass and closure test from the partials of ||M V_j||^2 and U^T U (every
+// workgroup forms the same factors; workgroup 0 records them), then partials of
+// G2 = (U T1)^T (U T1).
+template <int S>
+__global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ SideState st;
+  double ref[1], G1[S * S];
+  sum_records<1>(A.aux, A.nb_spmm, ref);
+  sum_records<S * S>(A.aux + A.nb_spmm, A.nb_upd, G1);
+  if (threadIdx.x == 0) {
+    st.ref2 = ref[0];
+    finish_pass1(&st, S, closure_tol, G1);
+    if (lb == 0) {
+      A.ss->ref2 = st.ref2;
+      A.ss->mode = st.mode;
+      for (int i = 0; i < S * S; ++i) {
+        A.ss->T1[i] = st.T1[i];
+        A.ss->Hs1[i] = st.Hs1[i];
+      }
+    }
+  }
+  __syncthreads();
+  double T1[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) T1[i] = st.T1[i];
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    double u[S], u1[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < S; ++a) v = fma(u[a], T1[a * S + b], v);
+      u1[b] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u1[a], u1[b], g[a * S + b]);
+  }
+  __shared__ double lds[16 * S * S];
+  block_sum<S * S>(g, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + A.nb_upd * S * S + lb * S * S + i] = g[i];
+}
+
+// Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
+// V[:, (j+1)s : (j+2)s] = U T; workgroup 0 records T and writes H_{j+1,j}.
+template <int S>
+__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
+                                                  const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ SideState st;
+  double G2[S * S];
+  sum_records<S * S>(A.aux + A.nb_spmm + A.nb_upd * S * S, A.nb_qr, G2);
+  if (threadIdx.x == 0) {
+    st.mode = A.ss->mode;
+    for (int i = 0; i < S * S; ++i) {
+      st.T1[i] = A.ss->T1[i];
+      st.Hs1[i] = A.ss->Hs1[i];
+    }
+    finish_pass2(&st, S, G2);
+    if (lb == 0) {
+      for (int i = 0; i < S * S; ++i) {
+        A.ss->T[i] = st.T[i];
+        A.ss->Hs1[i] = st.Hs1[i];
+      }
+      for (int a = 0; a < S; ++a)
+        for (int b = 0; b < S; ++b)
+          A.H[(int64_t)((jb + 1) * S + a) * ldh + jb * S + b] = st.Hs1[a * S + b];
+    }
+  }
+  __syncthreads();
+  double T[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) T[i] = st.T[i];
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    double u[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < S; ++a) v = fma(u[a], T[a * S + b], v);
+      A.basis[r * A.ldb + (jb + 1) * S + b] = v;
+    }
+  }
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Rows per gram chunk: large enough that the chunk partials stay a small fraction of the basis
+// read (2 s / rpc), small enough for a few hundred workgroups, at most 512 chunks per basis.
+int64_t gram_rpc(int s, int64_t rows, int64_t total_rows) {
+  int64_t rpc = std::max<int64_t>(32 * s, cdiv(total_rows, 1024));
+  rpc = std::min<int64_t>(rpc, std::max<int64_t>(16, cdiv(total_rows, 256)));
+  rpc = std::max<int64_t>(rpc, cdiv(rows, 512));
+  return std::max<int64_t>(rpc, 1);
+}
+
+struct Plan {
+  ArPair P;
+  int nchunk[2];
+};
+
+ArSide make_side(const SideDesc &d, const Scratch &sc, int idx, size_t half, size_t aux_len) {
+  ArSide a{};
+  a.rows = d.rows;
+  a.nnz = d.nnz;
+  a.rp = d.rp;
+  a.ci = d.ci;
+  a.val = d.val;
+  a.basis = d.basis;
+  a.ldb = d.ldb;
+  a.H = d.H;
+  a.U = d.U;
+  a.coef = d.coef;
+  a.ss = d.ss;
+  a.part = sc.partials + (size_t)idx * half;
+  a.aux = a.part + half - aux_len;
+  a.cnt = sc.counters + CNT_PAIR + idx * 1536;
+  return a;
+}
+
+// Sets the workgroup ranges of a launch with per-basis workgroup counts nb0, nb1.
+void set_ranges(ArPair &P, int64_t nb0, int64_t nb1) {
+  P.s[0].b0 = 0;
+  P.s[0].nb = (int)nb0;
+  P.s[1].b0 = (int)nb0;
+  P.s[1].nb = (int)nb1;
+}
+
+unsigned total_blocks(const ArPair &P) {
+  return (unsigned)(P.s[0].nb + (P.nsides > 1 ? P.s[1].nb : 0));
+}
+
+constexpr int64_t UROWS = 64;    // rows per update_pair workgroup
+constexpr int64_t QR_MAXWG = 512;
+
+int64_t nb_rows(int64_t rows) { return cdiv(rows, TPB); }
+int64_t nb_qr(int64_t rows) { return std::min<int64_t>(nb_rows(rows), QR_MAXWG); }
+size_t aux_len(int s, int64_t rows) {
+  return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows)) * s * s + 16);
+}
+
+template <int S>
+int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                   double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  ArPair P{};
+  const size_t half = sc.partial_cap / 2;
+  P.nsides = sw ? 2 : 1;
+  const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
+  const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
+  P.s[0] = make_side(sv, sc, 0, half, aux0);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  for (int i = 0; i < P.nsides; ++i) {
+    const int64_t rows = i ? rows1 : rows0;
+    P.s[i].nb_spmm = (int)nb_rows(rows);
+    P.s[i].nb_upd = (int)cdiv(rows, UROWS);
+    P.s[i].nb_qr = (int)nb_qr(rows);
+  }
+  const int64_t total = rows0 + rows1;
+  const int ncols = (jb + 1) * S;
+  const int nout = ncols * S;
+  const double bytes_v = 8.0 * (double)total * ncols, flops_v = 2.0 * (double)total * ncols * S;
+
+  // U = M V_j
+  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+  prof_begin(sc, st);
+  spmm_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_SPMM,
+           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,
+           2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S, st);
+
+  // chunking of the Gram sweeps
+  const int64_t rpc0 = gram_rpc(S, rows0, total), rpc1 = sw ? gram_rpc(S, rows1, total) : 1;
+  const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
+  if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
+    return SYLV_ERR_WORKSPACE;
+  const size_t lds = (size_t)nout * sizeof(double);
+  if (lds > 64 * 1024) return SYLV_ERR_WORKSPACE;
+  const int64_t rtiles = cdiv(nout, OPB);
+
+  for (int pass = 1; pass <= 2; ++pass) {
+    P.s[0].rpc = rpc0;
+    P.s[1].rpc = rpc1;
+    set_ranges(P, nch0, nch1);
+    prof_begin(sc, st);
+    gram_part_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ncols, ds);
+    HIPOK(hipGetLastError());
+    set_ranges(P, rtiles, sw ? rtiles : 0);
+    gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S, ncols, nch0, nch1, ldh, jb * S, pass,
+                                                      ds);
+    HIPOK(hipGetLastError());
+    prof_end(sc, FAM_GRAM, bytes_v + 8.0 * total * S + 8.0 * nout * P.nsides, flops_v, st);
+    P.s[0].rpc = UROWS;
+    P.s[1].rpc = UROWS;
+    set_ranges(P, cdiv(rows0, UROWS), sw ? cdiv(rows1, UROWS) : 0);
+    prof_begin(sc, st);
+    update_pair<S><<<total_blocks(P), TPB, lds, st>>>(P, ncols, pass == 2, closure_tol, ds);
+    HIPOK(hipGetLastError());
+    prof_end(sc, FAM_UPDATE, bytes_v + 16.0 * total * S + 8.0 * nout * P.nsides, flops_v, st);
+  }
+  // QR passes and the new block
+  set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
+  prof_begin(sc, st);
+  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+  HIPOK(hipGetLastError());
+  final_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  return 0;
+}
+
+}  // namespace
+
+size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols) {
+  const int64_t total = rows_v + rows_w;
+  const int64_t n0 = cdiv(rows_v, gram_rpc(s, rows_v, total));
+  const int64_t n1 = rows_w ? cdiv(rows_w, gram_rpc(s, rows_w, total)) : 0;
+  const size_t per0 = (size_t)n0 * max_cols * s + aux_len(s, rows_v);
+  const size_t per1 = rows_w ? (size_t)n1 * max_cols * s + aux_len(s, rows_w) : 0;
+  return 2 * std::max(per0, per1);
+}
+
+int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  switch (s) {
+#define CASE(SS) \
+  case SS: return arnoldi_pair_t<SS>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
+}

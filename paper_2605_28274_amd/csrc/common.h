@@ -47,7 +47,7 @@ enum {
   CNT_NRM = 24,
   CNT_CORE = 32,
   CNT_ELEM = 40,
-  CNT_GRAM = 64,  // one counter per 256-column tile of the basis (up to CNT_MAX)
+  CNT_PAIR = 512,  // paired Arnoldi: 1536 counters per basis
   CNT_MAX = 4096
 };
 
@@ -117,16 +117,15 @@ __device__ __forceinline__ void reset_counter(int *counter) {
   if (threadIdx.x == 0) atomicExch(counter, 0);
 }
 
-// Block-reduces NV values per thread, stores one partial per workgroup, and lets the last
-// workgroup of the grid sum the partials into out[0..NV) (shared memory of the caller). The
-// final sum is spread over the workgroup in a fixed order, so results are deterministic.
-// Returns true in every thread of the last workgroup (out is valid there).
+// Block-reduces NV values per thread, stores one partial per workgroup (index bid of nb), and
+// lets the last of the nb workgroups sum the partials into out[0..NV) (shared memory of the
+// caller). The final sum is spread over the workgroup in a fixed order, so results are
+// deterministic. Returns true in every thread of that last workgroup (out is valid there).
 template <int NV>
-__device__ bool reduce_grid(double (&v)[NV], double *partials, int *counter, double *out) {
+__device__ bool reduce_sub(double (&v)[NV], int bid, int nb, double *partials, int *counter,
+                           double *out) {
   __shared__ double lds[16 * NV];
   block_sum<NV>(v, lds);
-  const int nb = gridDim.x * gridDim.y;
-  const int bid = blockIdx.y * gridDim.x + blockIdx.x;
   if (threadIdx.x == 0) {
 #pragma unroll
     for (int i = 0; i < NV; ++i) partials[(size_t)bid * NV + i] = v[i];
@@ -145,6 +144,13 @@ __device__ bool reduce_grid(double (&v)[NV], double *partials, int *counter, dou
   __syncthreads();
   reset_counter(counter);
   return true;
+}
+
+// reduce_sub over the whole (x, y) grid.
+template <int NV>
+__device__ bool reduce_grid(double (&v)[NV], double *partials, int *counter, double *out) {
+  return reduce_sub<NV>(v, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, partials,
+                        counter, out);
 }
 
 // ---- small dense helpers executed by one thread (s <= 8) ----
@@ -239,6 +245,66 @@ __device__ inline void jacobi_eig(const double *G, double *lam, double *Z, int s
   for (int i = 0; i < s; ++i) lam[i] = a[i * s + i];
 }
 
+// Closure / rank decision after the first Cholesky-QR pass (thread 0 of the last workgroup).
+// G = U^T U, ss->ref2 = ||M V_j||_F^2. Sets ss->mode, ss->T1 (U1 = U T1) and ss->Hs1 (U = U1 Hs1).
+__device__ inline void finish_pass1(SideState *ss, int s, double closure_tol, const double *G) {
+  double tr = 0.0;
+  for (int i = 0; i < s; ++i) tr += G[i * s + i];
+  for (int i = 0; i < s * s; ++i) {
+    ss->T1[i] = 0.0;
+    ss->Hs1[i] = 0.0;
+  }
+  if (!(tr > closure_tol * closure_tol * ss->ref2)) {  // Krylov space closed: zero block
+    ss->mode = 1;
+    return;
+  }
+  double R[SYLV_MAX_S * SYLV_MAX_S];
+  const double minratio = chol_upper(G, R, s);
+  if (minratio > 1e-14) {
+    ss->mode = 0;
+    inv_upper(R, ss->T1, s);
+    for (int i = 0; i < s * s; ++i) ss->Hs1[i] = R[i];
+    return;
+  }
+  // Some directions of U (nearly) vanish: orthonormalize through the eigen-decomposition of
+  // G = Z diag(lam) Z^T, keeping eigenvalues above the closure threshold.
+  double lam[SYLV_MAX_S], Z[SYLV_MAX_S * SYLV_MAX_S];
+  jacobi_eig(G, lam, Z, s);
+  double lmax = 0.0;
+  for (int i = 0; i < s; ++i) lmax = fmax(lmax, lam[i]);
+  const double thr = fmax(closure_tol * closure_tol * ss->ref2, 1e-14 * lmax);
+  int kept = 0;
+  for (int i = 0; i < s; ++i) {
+    if (lam[i] > thr) {
+      const double sq = sqrt(lam[i]);
+      for (int a = 0; a < s; ++a) {
+        ss->T1[a * s + i] = Z[a * s + i] / sq;
+        ss->Hs1[i * s + a] = sq * Z[a * s + i];
+      }
+      ++kept;
+    }
+  }
+  ss->mode = kept ? 2 : 1;
+}
+
+// Second Cholesky-QR pass: G2 = (U T1)^T (U T1) = R2^T R2; V_{j+1} = U T1 R2^{-1}, H_{j+1,j} = R2 Hs1.
+__device__ inline void finish_pass2(SideState *ss, int s, const double *G2) {
+  if (ss->mode == 1) {
+    for (int i = 0; i < s * s; ++i) {
+      ss->T[i] = 0.0;
+      ss->Hs1[i] = 0.0;
+    }
+    return;
+  }
+  double R2[SYLV_MAX_S * SYLV_MAX_S], R2i[SYLV_MAX_S * SYLV_MAX_S], tmp[SYLV_MAX_S * SYLV_MAX_S];
+  chol_upper(G2, R2, s);
+  inv_upper(R2, R2i, s);
+  matmul_small(ss->T1, R2i, ss->T, s);
+  matmul_small(R2, ss->Hs1, tmp, s);
+  for (int i = 0; i < s * s; ++i) ss->Hs1[i] = tmp[i];
+}
+
+
 // ---- launchers implemented in the .hip files (all return 0 or SYLV_ERR_HIP) ----
 
 struct SideDesc {
@@ -291,26 +357,30 @@ int launch_first_block(int s, const SideDesc &sd, const double *C, int64_t ldc_i
                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
 int launch_lanczos_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
                         const Scratch &sc, DevState *ds, hipStream_t st);
-int launch_arnoldi_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
-                        const Scratch &sc, DevState *ds, hipStream_t st);
+
+// Both bases' block Arnoldi steps j (same j) in shared launches (arnoldi.hip); sw may be null
+// (Lyapunov: one basis).
+int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
+// Workspace doubles the paired Arnoldi step needs in Scratch::partials.
+size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols);
 
 // Core recurrences (core.hip).
 int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, double *P,
                          double *Rt, int64_t ldc, double tol, DevState *ds, hipStream_t st);
 int launch_cg_core(int s, int p, const double *H, const double *G, const double *P, double *Q,
-                   int64_t ldc, const Scratch &sc, DevState *ds, double *hist, int k,
-                   int max_iter, hipStream_t st);
+                   int64_t ldc, const Scratch &sc, DevState *ds, hipStream_t st);
 int launch_cg_update(int s, int p, double *X, double *R, double *P, const double *Q, int64_t ldc,
                      const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
                      hipStream_t st);
 int launch_bicg_s(int s, int p, const double *Q, const double *R, double *S, const double *Rt,
                   int64_t ldc, DevState *ds, double *hist, int k, int max_iter, hipStream_t st);
-int launch_bicg_omega(int s, int p, const double *T, const double *S, const double *Rt,
-                      int64_t ldc, const Scratch &sc, DevState *ds, double *hist, int k,
-                      int max_iter, hipStream_t st);
+int launch_bicg_omega(int s, int p, const double *T, const double *S, int64_t ldc,
+                      const Scratch &sc, DevState *ds, hipStream_t st);
 int launch_bicg_update(int s, int p, double *X, double *R, double *P, const double *Q,
-                       const double *S, const double *T, int64_t ldc, const Scratch &sc,
-                       DevState *ds, double *hist, int k, int max_iter, hipStream_t st);
+                       const double *S, const double *T, const double *Rt, int64_t ldc,
+                       const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
+                       hipStream_t st);
 
 // Dense FP64 GEMM C (M x N) = alpha * op(A) op(B) + beta * C with element strides:
 // A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs], C(i,j) = C[i*ldc + j].

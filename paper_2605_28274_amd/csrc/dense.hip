@@ -1,4 +1,4 @@
-// Dense FP64 products on small cores and tall factors.
+// Dense FP64 products on small cores and tall factors, on FP64 MFMA (v_mfma_f64_16x16x4f64).
 //
 // * core_op: the Sylvester operator on cores, eq. (3.11): Q = [H P, 0] + [P G^T; 0], with H, G
 //   block upper Hessenberg (block Arnoldi). The K range of each output tile skips the
@@ -6,40 +6,45 @@
 // * gemm: C = alpha op(A) op(B) + beta C with arbitrary element strides, used by the residual
 //   evaluation (tall-skinny Grams V^T E with K = n, and small core products).
 //
-// Both use 64 x 64 output tiles per 256-thread workgroup with FP64 MFMA 16x16x4 (each wave owns
-// a 32 x 32 quarter = 2 x 2 MFMA tiles), K staged through LDS in slabs of 16.
+// Tiling: 64 x 64 output tile per 256-thread workgroup, each wave a 32 x 32 quarter (2 x 2 MFMA
+// tiles); K in slabs of 32 staged through double-buffered LDS. The next slab's global loads are
+// issued into registers before the MFMAs of the current slab, so one barrier per slab remains
+// and the load latency overlaps the matrix-core work.
 #include "common.h"
 
 namespace {
 
-constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int LD = BM + 1;  // +1 pad: fewer bank conflicts on the transposed fills
+static_assert(BM == BN, "one LDS slab shape serves both operands");
 
 typedef double v4d __attribute__((ext_vector_type(4)));
 
-// Register tile of one wave: 2 x 2 MFMA accumulators of 16 x 16.
 struct WaveAcc {
   v4d c[2][2];
 };
 
-// LDS layout: As[k][i] (A slab transposed, i fastest) and Bs[k][j]; +1 pad on the fast dim
-// breaks bank conflicts of the column-wise fills.
-struct Slabs {
-  double As[BK][BM + 1];
-  double Bs[BK][BN + 1];
+typedef double Slab[BK][LD];
+
+struct Smem {
+  Slab As[2];
+  Slab Bs[2];
 };
 
 // MFMA f64 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator element v of lane l holds D[4 * v + l / 16][l % 16].
-__device__ __forceinline__ void mma_slab(const Slabs &sl, WaveAcc &acc, int wm, int wn) {
+__device__ __forceinline__ void mma_slab(const Slab &As, const Slab &Bs,
+                                         WaveAcc &acc, int wm, int wn, int kmax) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll
   for (int kk = 0; kk < BK; kk += 4) {
+    if (kk >= kmax) break;
     double a[2], b[2];
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      a[t] = sl.As[kk + lk][wm * 32 + t * 16 + li];
-      b[t] = sl.Bs[kk + lk][wn * 32 + t * 16 + li];
+      a[t] = As[kk + lk][wm * 32 + t * 16 + li];
+      b[t] = Bs[kk + lk][wn * 32 + t * 16 + li];
     }
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
@@ -56,7 +61,6 @@ __device__ __forceinline__ void zero_acc(WaveAcc &acc) {
     for (int tj = 0; tj < 2; ++tj) acc.c[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
 }
 
-// Calls f(i_local, j_local, value) for each accumulator element of this thread.
 template <typename F>
 __device__ __forceinline__ void for_each_acc(const WaveAcc &acc, int wm, int wn, F f) {
   const int lane = threadIdx.x & 63;
@@ -70,94 +74,146 @@ __device__ __forceinline__ void for_each_acc(const WaveAcc &acc, int wm, int wn,
         f(wm * 32 + ti * 16 + v * 4 + rq, wn * 32 + tj * 16 + col, acc.c[ti][tj][v]);
 }
 
-// ---- core operator: unmasked loads (all indices < ldc; entries outside active cores are 0) ----
+// ---- slab loaders for row-major operands inside ldc-strided buffers (no bounds masks) ----
+// "rows" slab: 64 rows x 32 consecutive columns of a row-major matrix, stored transposed
+//   (dst[k][i]); thread t loads row t/4, columns 8*(t%4) .. +7 as four 16-byte loads.
+// "cols" slab: 32 rows x 64 consecutive columns, stored as is (dst[k][j]); thread t loads row
+//   t/8, columns 8*(t%8) .. +7.
+struct RegSlab {
+  double2 v[4];
+};
 
+__device__ __forceinline__ void load_rows(const double *base, int64_t ld, RegSlab &r) {
+  const int i = threadIdx.x >> 2, k = (threadIdx.x & 3) * 8;
+  const double2 *p = reinterpret_cast<const double2 *>(base + (int64_t)i * ld + k);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) r.v[u] = p[u];
+}
+
+__device__ __forceinline__ void store_rows(Slab &dst, const RegSlab &r) {
+  const int i = threadIdx.x >> 2, k = (threadIdx.x & 3) * 8;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    dst[k + 2 * u][i] = r.v[u].x;
+    dst[k + 2 * u + 1][i] = r.v[u].y;
+  }
+}
+
+__device__ __forceinline__ void load_cols(const double *base, int64_t ld, RegSlab &r) {
+  const int k = threadIdx.x >> 3, j = (threadIdx.x & 7) * 8;
+  const double2 *p = reinterpret_cast<const double2 *>(base + (int64_t)k * ld + j);
+#pragma unroll
+  for (int u = 0; u < 4; ++u) r.v[u] = p[u];
+}
+
+__device__ __forceinline__ void store_cols(Slab &dst, const RegSlab &r) {
+  const int k = threadIdx.x >> 3, j = (threadIdx.x & 7) * 8;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    dst[k][j + 2 * u] = r.v[u].x;
+    dst[k][j + 2 * u + 1] = r.v[u].y;
+  }
+}
+
+// One pipelined product over K slabs [l_begin, l_end) (multiples of BK):
+//   B_FROM_ROWS == false: acc += A(i0.., l) * B(l, j0..)  with B row-major (cols slab)
+//   B_FROM_ROWS == true : acc += A(i0.., l) * B(j0.., l)^T (B given by its rows: rows slab)
+template <bool B_FROM_ROWS>
+__device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn,
+                                          const double *A, const double *B, int64_t ld,
+                                          int l_begin, int l_end) {
+  if (l_begin >= l_end) return;
+  RegSlab ra, rb;
+  load_rows(A + l_begin, ld, ra);
+  if (B_FROM_ROWS) load_rows(B + l_begin, ld, rb);
+  else load_cols(B + (int64_t)l_begin * ld, ld, rb);
+  int buf = 0;
+  __syncthreads();  // previous users of the LDS buffers are done
+  store_rows(sm.As[0], ra);
+  if (B_FROM_ROWS) store_rows(sm.Bs[0], rb);
+  else store_cols(sm.Bs[0], rb);
+  __syncthreads();
+  for (int l0 = l_begin; l0 < l_end; l0 += BK) {
+    const bool more = l0 + BK < l_end;
+    if (more) {
+      load_rows(A + l0 + BK, ld, ra);
+      if (B_FROM_ROWS) load_rows(B + l0 + BK, ld, rb);
+      else load_cols(B + (int64_t)(l0 + BK) * ld, ld, rb);
+    }
+    mma_slab(sm.As[buf], sm.Bs[buf], acc, wm, wn, BK);
+    if (more) {
+      store_rows(sm.As[buf ^ 1], ra);
+      if (B_FROM_ROWS) store_rows(sm.Bs[buf ^ 1], rb);
+      else store_cols(sm.Bs[buf ^ 1], rb);
+    }
+    __syncthreads();
+    buf ^= 1;
+  }
+}
+
+// ---- core operator (all indices < ldc; entries outside the active cores are exact zeros) ----
 __global__ __launch_bounds__(256) void core_op_kernel(int s, int p, const double *__restrict__ H,
                                                       const double *__restrict__ G,
                                                       const double *__restrict__ P,
                                                       double *__restrict__ Q, int64_t ldc,
                                                       const int *done) {
   if (done && *done) return;
-  __shared__ Slabs sl;
+  __shared__ Smem sm;
   const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
   const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
   WaveAcc acc;
   zero_acc(acc);
   const int pk = (p + BK - 1) / BK * BK;
-  // phase 1: H[i0:i0+64, l] P[l, j0:j0+64] for l in [lstart, p); skipped when j0 >= p
+  // [H P, 0]: rows of H in this tile start at column block (i0/s - 1)
   if (j0 < p) {
     int ls = (i0 / s - 1) * s;
     ls = ls < 0 ? 0 : ls / BK * BK;
-    for (int l0 = ls; l0 < pk; l0 += BK) {
-      // A slab: H rows i0..i0+63, cols l0..l0+15 -> As[k][i]
-      for (int e = threadIdx.x; e < BM * BK; e += 256) {
-        const int ii = e / BK, kk = e % BK;
-        sl.As[kk][ii] = H[(int64_t)(i0 + ii) * ldc + l0 + kk];
-      }
-      // B slab: P rows l0..l0+15, cols j0..j0+63 -> Bs[k][j]
-      for (int e = threadIdx.x; e < BK * BN; e += 256) {
-        const int kk = e / BN, jj = e % BN;
-        sl.Bs[kk][jj] = P[(int64_t)(l0 + kk) * ldc + j0 + jj];
-      }
-      __syncthreads();
-      mma_slab(sl, acc, wm, wn);
-      __syncthreads();
-    }
+    pipelined<false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, P + j0, ldc, ls, pk);
   }
-  // phase 2: P[i0:i0+64, l] G[j0:j0+64, l]^T; skipped when i0 >= p
+  // [P G^T; 0]: rows of G in this tile start at column block (j0/s - 1)
   if (i0 < p) {
     int ls = (j0 / s - 1) * s;
     ls = ls < 0 ? 0 : ls / BK * BK;
-    for (int l0 = ls; l0 < pk; l0 += BK) {
-      for (int e = threadIdx.x; e < BM * BK; e += 256) {
-        const int ii = e / BK, kk = e % BK;
-        sl.As[kk][ii] = P[(int64_t)(i0 + ii) * ldc + l0 + kk];
-      }
-      for (int e = threadIdx.x; e < BN * BK; e += 256) {
-        const int jj = e / BK, kk = e % BK;
-        sl.Bs[kk][jj] = G[(int64_t)(j0 + jj) * ldc + l0 + kk];
-      }
-      __syncthreads();
-      mma_slab(sl, acc, wm, wn);
-      __syncthreads();
-    }
+    pipelined<true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, G + (int64_t)j0 * ldc, ldc, ls, pk);
   }
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
     Q[(int64_t)(i0 + ii) * ldc + j0 + jj] = v;
   });
 }
 
-// ---- generic strided GEMM with bounds masks ----
-
+// ---- generic strided GEMM with bounds masks (residual Grams and core products) ----
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const double *__restrict__ A, int64_t a_rs,
                                                    int64_t a_cs, const double *__restrict__ B,
                                                    int64_t b_rs, int64_t b_cs, double beta,
                                                    double *__restrict__ C, int64_t ldc) {
-  __shared__ Slabs sl;
+  __shared__ Smem sm;
   const int64_t i0 = (int64_t)blockIdx.y * BM, j0 = (int64_t)blockIdx.x * BN;
   const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
   WaveAcc acc;
   zero_acc(acc);
-  // A slab fill: choose the thread mapping along A's unit-stride dimension for coalescing.
+  // thread mapping along each operand's unit-stride dimension (coalesced fills)
   const bool a_k_fast = (a_cs == 1);
   const bool b_j_fast = (b_cs == 1) || (b_rs != 1);
-  for (int64_t l0 = 0; l0 < K; l0 += BK) {
+  const int64_t nslab = (K + BK - 1) / BK;
+  int buf = 0;
+  for (int64_t sl = 0; sl < nslab; ++sl) {
+    const int64_t l0 = sl * BK;
     for (int e = threadIdx.x; e < BM * BK; e += 256) {
       int ii, kk;
       if (a_k_fast) { ii = e / BK; kk = e % BK; } else { kk = e / BM; ii = e % BM; }
       const int64_t gi = i0 + ii, gk = l0 + kk;
-      sl.As[kk][ii] = (gi < M && gk < K) ? A[gi * a_rs + gk * a_cs] : 0.0;
+      sm.As[buf][kk][ii] = (gi < M && gk < K) ? A[gi * a_rs + gk * a_cs] : 0.0;
     }
     for (int e = threadIdx.x; e < BK * BN; e += 256) {
       int kk, jj;
       if (b_j_fast) { kk = e / BN; jj = e % BN; } else { jj = e / BK; kk = e % BK; }
       const int64_t gk = l0 + kk, gj = j0 + jj;
-      sl.Bs[kk][jj] = (gk < K && gj < N) ? B[gk * b_rs + gj * b_cs] : 0.0;
+      sm.Bs[buf][kk][jj] = (gk < K && gj < N) ? B[gk * b_rs + gj * b_cs] : 0.0;
     }
     __syncthreads();
-    mma_slab(sl, acc, wm, wn);
-    __syncthreads();
+    mma_slab(sm.As[buf], sm.Bs[buf], acc, wm, wn, BK);
+    buf ^= 1;  // the other buffer is free: its last readers passed the barrier above
   }
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
     const int64_t gi = i0 + ii, gj = j0 + jj;
@@ -174,7 +230,7 @@ int launch_core_op(int s, int p, const double *H, const double *G, const double 
                    int64_t ldc, const int *done, hipStream_t st) {
   const int q = p + s;
   const unsigned t = (unsigned)((q + BM - 1) / BM);
-  if ((int64_t)t * BM > ldc) return SYLV_ERR_WORKSPACE;
+  if ((int64_t)t * BM > ldc || ((p + BK - 1) / BK * BK) > ldc) return SYLV_ERR_WORKSPACE;
   core_op_kernel<<<dim3(t, t), 256, 0, st>>>(s, p, H, G, P, Q, ldc, done);
   HIPOK(hipGetLastError());
   return 0;

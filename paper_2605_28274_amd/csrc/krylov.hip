@@ -1,13 +1,12 @@
-// One step of the block Lanczos process (Algorithm 4.1) or block Arnoldi process (Algorithm 4.2):
-// given the newest basis block V_j, compute U = M V_j, orthogonalize it against the basis
-// (the local three-term recurrence for Lanczos, two classical Gram-Schmidt sweeps over all
-// blocks for Arnoldi), then orthonormalize U = V_{j+1} H_{j+1,j} by two Cholesky-QR passes.
+// One step of the block Lanczos process (Algorithm 4.1): given the newest basis block V_j,
+// compute U = M V_j, orthogonalize it locally (three-term recurrence), then orthonormalize
+// U = V_{j+1} H_{j+1,j} by two Cholesky-QR passes; plus the QR of the first block (C1 = V_1 R_L).
+// The block Arnoldi step of Algorithm 4.2 is in arnoldi.hip.
 // The new block is appended to the basis and its coefficients to column block j of H, so that
 // M V_j = V_{j+1} H_{j+1,j} holds column block by column block (eq. (3.8)).
 //
 // Data layout: the basis is row-major rows x ldb (row r holds all basis entries of grid point
-// r), so SpMM gathers s contiguous doubles per neighbour, the Gram V^T U streams whole rows
-// (thread per basis column, coalesced), and the update U -= V C streams each row once.
+// r), so SpMM gathers s contiguous doubles per neighbour.
 //
 // Every kernel returns at entry once the solve is done (device flag), so iterations enqueued
 // beyond convergence cost only their launch.
@@ -16,66 +15,6 @@
 namespace {
 
 constexpr int TPB = 256;
-
-// Closure / rank decision after the first Cholesky-QR pass (thread 0 of the last workgroup).
-// G = U^T U, ss->ref2 = ||M V_j||_F^2. Sets ss->mode, ss->T1 (U1 = U T1) and ss->Hs1 (U = U1 Hs1).
-__device__ void finish_pass1(SideState *ss, int s, double closure_tol, const double *G) {
-  double tr = 0.0;
-  for (int i = 0; i < s; ++i) tr += G[i * s + i];
-  for (int i = 0; i < s * s; ++i) {
-    ss->T1[i] = 0.0;
-    ss->Hs1[i] = 0.0;
-  }
-  if (!(tr > closure_tol * closure_tol * ss->ref2)) {  // Krylov space closed: zero block
-    ss->mode = 1;
-    return;
-  }
-  double R[SYLV_MAX_S * SYLV_MAX_S];
-  const double minratio = chol_upper(G, R, s);
-  if (minratio > 1e-14) {
-    ss->mode = 0;
-    inv_upper(R, ss->T1, s);
-    for (int i = 0; i < s * s; ++i) ss->Hs1[i] = R[i];
-    return;
-  }
-  // Some directions of U (nearly) vanish: orthonormalize through the eigen-decomposition of
-  // G = Z diag(lam) Z^T, keeping eigenvalues above the closure threshold.
-  double lam[SYLV_MAX_S], Z[SYLV_MAX_S * SYLV_MAX_S];
-  jacobi_eig(G, lam, Z, s);
-  double lmax = 0.0;
-  for (int i = 0; i < s; ++i) lmax = fmax(lmax, lam[i]);
-  const double thr = fmax(closure_tol * closure_tol * ss->ref2, 1e-14 * lmax);
-  int kept = 0;
-  for (int i = 0; i < s; ++i) {
-    if (lam[i] > thr) {
-      const double sq = sqrt(lam[i]);
-      for (int a = 0; a < s; ++a) {
-        ss->T1[a * s + i] = Z[a * s + i] / sq;
-        ss->Hs1[i * s + a] = sq * Z[a * s + i];
-      }
-      ++kept;
-    }
-  }
-  ss->mode = kept ? 2 : 1;
-}
-
-// Second Cholesky-QR pass: G2 = (U T1)^T (U T1) = R2^T R2; V_{j+1} = U T1 R2^{-1}, H_{j+1,j} = R2 Hs1.
-__device__ void finish_pass2(SideState *ss, int s, const double *G2) {
-  if (ss->mode == 1) {
-    for (int i = 0; i < s * s; ++i) {
-      ss->T[i] = 0.0;
-      ss->Hs1[i] = 0.0;
-    }
-    return;
-  }
-  double R2[SYLV_MAX_S * SYLV_MAX_S], R2i[SYLV_MAX_S * SYLV_MAX_S], tmp[SYLV_MAX_S * SYLV_MAX_S];
-  chol_upper(G2, R2, s);
-  inv_upper(R2, R2i, s);
-  matmul_small(ss->T1, R2i, ss->T, s);
-  matmul_small(R2, ss->Hs1, tmp, s);
-  for (int i = 0; i < s * s; ++i) ss->Hs1[i] = tmp[i];
-}
-
 
 // First block: G = C^T C for C1 (or C2); the last workgroup runs pass 1 with ref2 = ||C||^2.
 template <int S>
@@ -274,160 +213,6 @@ __global__ __launch_bounds__(TPB) void lz_update_kernel(int64_t rows, const doub
     finish_pass1(ss, S, closure_tol, out);
 }
 
-// ---- block Arnoldi (classical Gram-Schmidt, two sweeps) ----
-
-// U = M V_j and ||U||^2.
-template <int S>
-__global__ __launch_bounds__(TPB) void ar_spmm_kernel(int64_t rows, const int32_t *__restrict__ rp,
-                                                      const int32_t *__restrict__ ci,
-                                                      const double *__restrict__ val,
-                                                      const double *__restrict__ V, int64_t ldb,
-                                                      int jb, double *__restrict__ U, SideState *ss,
-                                                      double *partials, int *counter,
-                                                      const DevState *ds) {
-  if (ds->done) return;
-  double red[1] = {0.0};
-  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (r < rows) {
-    double acc[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = 0.0;
-    const int b = rp[r], e = rp[r + 1];
-    for (int q = b; q < e; ++q) {
-      const double a = val[q];
-      const double *x = V + (int64_t)ci[q] * ldb + jb * S;
-#pragma unroll
-      for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < S; ++t) {
-      U[r * S + t] = acc[t];
-      red[0] = fma(acc[t], acc[t], red[0]);
-    }
-  }
-  __shared__ double out[1];
-  if (reduce_grid<1>(red, partials, counter, out) && threadIdx.x == 0) ss->ref2 = out[0];
-}
-
-// C = V[:, 0:ncols]^T U (ncols x S): one thread per basis column, rows split in chunks.
-// The last workgroup of each 256-column tile sums the chunks in order, stores (pass 1) or adds
-// (pass 2) C into column block j of H, and keeps a compact copy in coef for the update.
-template <int S>
-__global__ __launch_bounds__(TPB) void gram_kernel(const double *__restrict__ V, int64_t ldb,
-                                                   int ncols, const double *__restrict__ U,
-                                                   int64_t rows, int64_t rows_per_chunk,
-                                                   double *partials, int ncols_pad, double *H,
-                                                   int64_t ldh, int hcol, int pass,
-                                                   double *__restrict__ coef, int *counters,
-                                                   const DevState *ds) {
-  if (ds->done) return;
-  const int tile = blockIdx.x, chunk = blockIdx.y;
-  const int c = tile * TPB + threadIdx.x;
-  const int64_t r0 = (int64_t)chunk * rows_per_chunk;
-  const int64_t r1 = (r0 + rows_per_chunk < rows) ? r0 + rows_per_chunk : rows;
-  double acc[S];
-#pragma unroll
-  for (int t = 0; t < S; ++t) acc[t] = 0.0;
-  if (c < ncols) {
-    const double *vp = V + c;
-    int64_t r = r0;
-    for (; r + 4 <= r1; r += 4) {
-      const double v0 = vp[r * ldb], v1 = vp[(r + 1) * ldb], v2 = vp[(r + 2) * ldb],
-                   v3 = vp[(r + 3) * ldb];
-#pragma unroll
-      for (int t = 0; t < S; ++t) {
-        acc[t] = fma(v0, U[r * S + t], acc[t]);
-        acc[t] = fma(v1, U[(r + 1) * S + t], acc[t]);
-        acc[t] = fma(v2, U[(r + 2) * S + t], acc[t]);
-        acc[t] = fma(v3, U[(r + 3) * S + t], acc[t]);
-      }
-    }
-    for (; r < r1; ++r) {
-      const double v = vp[r * ldb];
-#pragma unroll
-      for (int t = 0; t < S; ++t) acc[t] = fma(v, U[r * S + t], acc[t]);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < S; ++t) partials[((size_t)chunk * ncols_pad + c) * S + t] = acc[t];
-  if (!last_block(&counters[CNT_GRAM + tile], gridDim.y)) return;
-  if (c < ncols) {
-    double sum[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) sum[t] = 0.0;
-    for (int q = 0; q < (int)gridDim.y; ++q)
-#pragma unroll
-      for (int t = 0; t < S; ++t) sum[t] += partials[((size_t)q * ncols_pad + c) * S + t];
-#pragma unroll
-    for (int t = 0; t < S; ++t) {
-      double *h = H + (int64_t)c * ldh + hcol + t;
-      *h = (pass == 1) ? sum[t] : *h + sum[t];
-      coef[c * S + t] = sum[t];
-    }
-  }
-  __syncthreads();
-  reset_counter(&counters[CNT_GRAM + tile]);
-}
-
-// U[r] -= V[r, 0:ncols] coef; G lanes per row. With gram != 0 also reduces U^T U and runs the
-// first QR pass in the last workgroup.
-template <int S>
-__global__ __launch_bounds__(TPB) void update_kernel(const double *__restrict__ V, int64_t ldb,
-                                                     int ncols, const double *__restrict__ coef,
-                                                     double *__restrict__ U, int64_t rows, int G,
-                                                     int gram, double closure_tol, SideState *ss,
-                                                     double *partials, int *counter,
-                                                     const DevState *ds) {
-  if (ds->done) return;
-  const int lane = threadIdx.x % G;
-  const int64_t r = (int64_t)blockIdx.x * (TPB / G) + threadIdx.x / G;
-  double acc[S];
-#pragma unroll
-  for (int t = 0; t < S; ++t) acc[t] = 0.0;
-  if (r < rows) {
-    const double *vr = V + r * ldb;
-    int c = lane;
-    for (; c + 3 * G < ncols; c += 4 * G) {
-      const double v0 = vr[c], v1 = vr[c + G], v2 = vr[c + 2 * G], v3 = vr[c + 3 * G];
-#pragma unroll
-      for (int t = 0; t < S; ++t) {
-        acc[t] = fma(v0, coef[c * S + t], acc[t]);
-        acc[t] = fma(v1, coef[(c + G) * S + t], acc[t]);
-        acc[t] = fma(v2, coef[(c + 2 * G) * S + t], acc[t]);
-        acc[t] = fma(v3, coef[(c + 3 * G) * S + t], acc[t]);
-      }
-    }
-    for (; c < ncols; c += G) {
-      const double v = vr[c];
-#pragma unroll
-      for (int t = 0; t < S; ++t) acc[t] = fma(v, coef[c * S + t], acc[t]);
-    }
-  }
-#pragma unroll
-  for (int t = 0; t < S; ++t) acc[t] = group_sum(acc[t], G);
-  double g[S * S];
-#pragma unroll
-  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  if (r < rows && lane == 0) {
-    double u[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) {
-      u[t] = U[r * S + t] - acc[t];
-      U[r * S + t] = u[t];
-    }
-    if (gram) {
-#pragma unroll
-      for (int a = 0; a < S; ++a)
-#pragma unroll
-        for (int b = 0; b < S; ++b) g[a * S + b] = u[a] * u[b];
-    }
-  }
-  if (!gram) return;
-  __shared__ double out[S * S];
-  if (reduce_grid<S * S>(g, partials, counter, out) && threadIdx.x == 0)
-    finish_pass1(ss, S, closure_tol, out);
-}
-
 unsigned grid_rows(int64_t rows) { return (unsigned)((rows + TPB - 1) / TPB); }
 
 // Workgroups for the pass-2 Gram and first-block kernels: enough to cover the rows, capped so
@@ -485,49 +270,6 @@ int lanczos_step_t(const SideDesc &sd, int jb, int64_t ldh, double closure_tol, 
   return finish_step<S>(sd, jb, ldh, sc, ds, st);
 }
 
-template <int S>
-int arnoldi_step_t(const SideDesc &sd, int jb, int64_t ldh, double closure_tol, const Scratch &sc,
-                   DevState *ds, hipStream_t st) {
-  prof_begin(sc, st);
-  ar_spmm_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.rows, sd.rp, sd.ci, sd.val, sd.basis,
-                                                        sd.ldb, jb, sd.U, sd.ss, sc.partials,
-                                                        sc.counters + CNT_SPMM, ds);
-  HIPOK(hipGetLastError());
-  prof_end(sc, FAM_SPMM, 12.0 * sd.nnz + 4.0 * (sd.rows + 1) + 16.0 * sd.rows * S,
-           2.0 * sd.nnz * S, st);
-  const int ncols = (jb + 1) * S;
-  const int tiles = (ncols + TPB - 1) / TPB;
-  const int ncols_pad = tiles * TPB;
-  int64_t nchunks = (2048 + tiles - 1) / tiles;
-  const int64_t maxchunks = (sd.rows + 31) / 32;
-  if (nchunks > maxchunks) nchunks = maxchunks;
-  if (nchunks > 256) nchunks = 256;
-  if (nchunks < 1) nchunks = 1;
-  const int64_t rpc = (sd.rows + nchunks - 1) / nchunks;
-  nchunks = (sd.rows + rpc - 1) / rpc;
-  if ((size_t)nchunks * ncols_pad * S > sc.partial_cap) return SYLV_ERR_WORKSPACE;
-  if (CNT_GRAM + tiles > CNT_MAX) return SYLV_ERR_WORKSPACE;
-  int G = 1;
-  while (G < 64 && G * 8 < ncols) G <<= 1;
-  const unsigned ugrid = (unsigned)((sd.rows + (TPB / G) - 1) / (TPB / G));
-  const double vbytes = 8.0 * sd.rows * ncols, flops = 2.0 * sd.rows * ncols * S;
-  for (int pass = 1; pass <= 2; ++pass) {
-    prof_begin(sc, st);
-    gram_kernel<S><<<dim3(tiles, (unsigned)nchunks), TPB, 0, st>>>(
-        sd.basis, sd.ldb, ncols, sd.U, sd.rows, rpc, sc.partials, ncols_pad, sd.H, ldh, jb * S,
-        pass, sd.coef, sc.counters, ds);
-    HIPOK(hipGetLastError());
-    prof_end(sc, FAM_GRAM, vbytes + 8.0 * sd.rows * S + 8.0 * ncols * S, flops, st);
-    prof_begin(sc, st);
-    update_kernel<S><<<ugrid, TPB, 0, st>>>(sd.basis, sd.ldb, ncols, sd.coef, sd.U, sd.rows, G,
-                                            pass == 2, closure_tol, sd.ss, sc.partials,
-                                            sc.counters + CNT_UPD, ds);
-    HIPOK(hipGetLastError());
-    prof_end(sc, FAM_UPDATE, vbytes + 16.0 * sd.rows * S + 8.0 * ncols * S, flops, st);
-  }
-  return finish_step<S>(sd, jb, ldh, sc, ds, st);
-}
-
 }  // namespace
 
 #define DISPATCH_S(s, call)            \
@@ -554,7 +296,3 @@ int launch_lanczos_step(int s, const SideDesc &sd, int jb, int64_t ldh, double c
   DISPATCH_S(s, lanczos_step_t<S>(sd, jb, ldh, closure_tol, sc, ds, st));
 }
 
-int launch_arnoldi_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
-                        const Scratch &sc, DevState *ds, hipStream_t st) {
-  DISPATCH_S(s, arnoldi_step_t<S>(sd, jb, ldh, closure_tol, sc, ds, st));
-}

@@ -12,12 +12,8 @@ __global__ __launch_bounds__(TPB) void dot_kernel(int64_t M, int64_t N, const do
                                                   int64_t ldb, double *partials, int *counter,
                                                   double *out) {
   double v = 0.0;
-  const int64_t total = M * N;
-  for (int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * TPB) {
-    const int64_t i = e / N, j = e % N;
-    v = fma(A[i * lda + j], B[i * ldb + j], v);
-  }
+  for (int64_t i = blockIdx.x; i < M; i += gridDim.x)
+    for (int64_t j = threadIdx.x; j < N; j += TPB) v = fma(A[i * lda + j], B[i * ldb + j], v);
   double vv[1] = {v};
   __shared__ double res[1];
   if (reduce_grid<1>(vv, partials, counter, res) && threadIdx.x == 0) *out = res[0];
@@ -39,8 +35,7 @@ __global__ __launch_bounds__(TPB) void rhat_kernel(int s, int q, const double *_
 
 int launch_dot(int64_t M, int64_t N, const double *A, int64_t lda, const double *B, int64_t ldb,
                double *out, const Scratch &sc, hipStream_t st) {
-  int64_t g = (M * N + TPB - 1) / TPB;
-  if (g > 1024) g = 1024;
+  int64_t g = M < 1024 ? M : 1024;
   if (g < 1) g = 1;
   dot_kernel<<<(unsigned)g, TPB, 0, st>>>(M, N, A, lda, B, ldb, sc.partials,
                                           sc.counters + CNT_ELEM + 4, out);

@@ -145,6 +145,10 @@ void sylv_destroy(void *ctx);
 
 const char *sylv_status_string(int status);
 
+/* Text of the last HIP runtime error the library saw in this thread (empty if none); useful
+ * after a SYLV_ERR_HIP return. The string stays valid until the next library call. */
+const char *sylv_last_error(void);
+
 /* ---- measurement hooks ---- */
 
 /* Time per kernel family, summed over the iterations the solves actually ran. */

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <new>
 #include <vector>
@@ -27,7 +28,7 @@ struct Layout {
   size_t off_U, off_Uw, off_coefV, off_coefW, off_btrp, off_btci, off_btval, off_tscr;
   size_t off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
   size_t off_E, off_GVV, off_GWW, off_GVE, off_GWE, off_GEEa, off_GEEb, off_Lx, off_M1, off_M2;
-  size_t off_dots, off_flag;
+  size_t off_dots, off_flag, off_panV, off_panW;
   size_t total = 0;
 };
 
@@ -122,6 +123,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.off_Lx = bump(cur, c2);
   L.off_M1 = bump(cur, c2);
   L.off_M2 = bump(cur, c2);
+  L.off_panV = bump(cur, (size_t)2 * L.n * L.s * 8);
+  L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * 8);
   L.off_dots = bump(cur, 16 * 8);
   L.off_flag = bump(cur, 16 * sizeof(int));
   L.total = cur + ALIGN;
@@ -244,6 +247,12 @@ int begin_solve(Ctx *c, double tol, int max_iter, int method) {
   double *zero[] = {c->H, c->G, c->X, c->R, c->P, c->Q, c->S, c->T};
   for (double *z : zero)
     if (z) HIPOK(hipMemsetAsync(z, 0, c2, c->st));
+  // the compact copy of block 1 (V_1, W_1) is the first SpMM input; earlier solves reused it
+  HIPOK(hipMemcpy2DAsync(c->sv.panel[0], L.s * 8, c->sv.basis, L.ldb * 8, L.s * 8, L.n,
+                         hipMemcpyDeviceToDevice, c->st));
+  if (!L.lyap)
+    HIPOK(hipMemcpy2DAsync(c->sw.panel[0], L.s * 8, c->sw.basis, L.ldb * 8, L.s * 8, L.m,
+                           hipMemcpyDeviceToDevice, c->st));
   // R0 = R_L R_R^T from the first-block factors kept since sylv_create
   int e = launch_setup_scalars((int)L.s, c->RL, c->RR, c->R, c->P, c->Rt, L.ldc, tol, c->ds,
                                c->st);
@@ -285,7 +294,15 @@ int end_solve(Ctx *c, int max_iter, double seconds, sylv_result *res) {
 
 }  // namespace
 
+thread_local char g_last_error[512] = "";
+
+void note_hip_error(hipError_t e, const char *what) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
 extern "C" {
+
+const char *sylv_last_error(void) { return g_last_error; }
 
 void sylv_default_options(sylv_options *opt) {
   if (!opt) return;
@@ -391,12 +408,14 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
   }
   c->sv = SideDesc{L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
                    at<double>(c, L.off_V), L.ldb, c->H, at<double>(c, L.off_U),
-                   at<double>(c, L.off_coefV), c->ssv};
+                   at<double>(c, L.off_coefV), c->ssv,
+                   {at<double>(c, L.off_panV), at<double>(c, L.off_panV) + L.n * L.s}};
   if (L.lyap) {
     c->sw = c->sv;
   } else {
     c->sw = SideDesc{L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<double>(c, L.off_W), L.ldb,
-                     c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw};
+                     c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw,
+                     {at<double>(c, L.off_panW), at<double>(c, L.off_panW) + L.m * L.s}};
   }
   // QR factorizations C1 = V_1 R_L, C2 = W_1 R_R (Alg. 4.1 step 1, Alg. 4.2 step 2)
   const int s = (int)L.s;

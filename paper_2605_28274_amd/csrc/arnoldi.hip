@@ -38,6 +38,8 @@ struct ArSide {
   double *U;
   double *coef;
   SideState *ss;
+  const double *pin;  // compact copy of block j (SpMM input)
+  double *pout;       // compact copy of block j+1 (written with the new block)
   double *part;    // Gram chunk partials of this basis
   double *aux;     // partials of ||M V_j||^2, U^T U and of the second-pass Gram
   int *cnt;        // counters of this basis (unused: no grid-wide reductions)
@@ -61,23 +63,17 @@ __device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd) {
 }
 
 template <int S>
-__global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, int jb, const DevState *ds) {
+__global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
+  const int64_t r0 = (int64_t)lb * TPB;
+  const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+  double acc[S];
+  spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, A.pin, S, acc);
   double red[1] = {0.0};
-  const int64_t r = (int64_t)lb * TPB + threadIdx.x;
-  if (r < A.rows) {
-    double acc[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = 0.0;
-    const int b = A.rp[r], e = A.rp[r + 1];
-    for (int q = b; q < e; ++q) {
-      const double a = A.val[q];
-      const double *x = A.basis + (int64_t)A.ci[q] * A.ldb + jb * S;
-#pragma unroll
-      for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
-    }
+  const int64_t r = r0 + threadIdx.x;
+  if (r < r1) {
 #pragma unroll
     for (int t = 0; t < S; ++t) {
       A.U[r * S + t] = acc[t];
@@ -205,41 +201,54 @@ __global__ __launch_bounds__(TPB) void update_pair(ArPair P, int ncols, int gram
   double g[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  for (int64_t r = r0 + w; r < r1; r += TPB / WAVE) {
-    const double *vr = A.basis + r * A.ldb;
-    double acc[S];
+  // each wave updates two rows at a time (twice the loads in flight)
+  for (int64_t ra = r0 + 2 * w; ra < r1; ra += 2 * (TPB / WAVE)) {
+    const bool two = ra + 1 < r1;
+    const double *v0 = A.basis + ra * A.ldb;
+    const double *v1 = two ? v0 + A.ldb : v0;
+    double acc0[S], acc1[S];
 #pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = 0.0;
+    for (int t = 0; t < S; ++t) acc0[t] = acc1[t] = 0.0;
     int c = lane;
-    for (; c + 3 * WAVE < ncols; c += 4 * WAVE) {
-      const double v0 = vr[c], v1 = vr[c + WAVE], v2 = vr[c + 2 * WAVE], v3 = vr[c + 3 * WAVE];
+    for (; c + WAVE < ncols; c += 2 * WAVE) {
+      const double x0 = v0[c], x1 = v0[c + WAVE], y0 = v1[c], y1 = v1[c + WAVE];
 #pragma unroll
       for (int t = 0; t < S; ++t) {
-        acc[t] = fma(v0, Cs[c * S + t], acc[t]);
-        acc[t] = fma(v1, Cs[(c + WAVE) * S + t], acc[t]);
-        acc[t] = fma(v2, Cs[(c + 2 * WAVE) * S + t], acc[t]);
-        acc[t] = fma(v3, Cs[(c + 3 * WAVE) * S + t], acc[t]);
+        const double c0 = Cs[c * S + t], c1 = Cs[(c + WAVE) * S + t];
+        acc0[t] = fma(x0, c0, acc0[t]);
+        acc0[t] = fma(x1, c1, acc0[t]);
+        acc1[t] = fma(y0, c0, acc1[t]);
+        acc1[t] = fma(y1, c1, acc1[t]);
       }
     }
-    for (; c < ncols; c += WAVE) {
-      const double v = vr[c];
+    if (c < ncols) {
+      const double x0 = v0[c], y0 = v1[c];
 #pragma unroll
-      for (int t = 0; t < S; ++t) acc[t] = fma(v, Cs[c * S + t], acc[t]);
+      for (int t = 0; t < S; ++t) {
+        acc0[t] = fma(x0, Cs[c * S + t], acc0[t]);
+        acc1[t] = fma(y0, Cs[c * S + t], acc1[t]);
+      }
     }
 #pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = wave_sum(acc[t]);
+    for (int t = 0; t < S; ++t) {
+      acc0[t] = wave_sum(acc0[t]);
+      acc1[t] = wave_sum(acc1[t]);
+    }
     if (lane == 0) {
-      double u[S];
+      for (int h = 0; h < (two ? 2 : 1); ++h) {
+        const int64_t r = ra + h;
+        double u[S];
 #pragma unroll
-      for (int t = 0; t < S; ++t) {
-        u[t] = A.U[r * S + t] - acc[t];
-        A.U[r * S + t] = u[t];
-      }
-      if (gram) {
+        for (int t = 0; t < S; ++t) {
+          u[t] = A.U[r * S + t] - (h ? acc1[t] : acc0[t]);
+          A.U[r * S + t] = u[t];
+        }
+        if (gram) {
 #pragma unroll
-        for (int a = 0; a < S; ++a)
+          for (int a = 0; a < S; ++a)
 #pragma unroll
-          for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
+            for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
+        }
       }
     }
   }
@@ -366,6 +375,7 @@ __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
 #pragma unroll
       for (int a = 0; a < S; ++a) v = fma(u[a], T[a * S + b], v);
       A.basis[r * A.ldb + (jb + 1) * S + b] = v;
+      A.pout[r * S + b] = v;
     }
   }
 }
@@ -417,7 +427,7 @@ unsigned total_blocks(const ArPair &P) {
   return (unsigned)(P.s[0].nb + (P.nsides > 1 ? P.s[1].nb : 0));
 }
 
-constexpr int64_t UROWS = 64;    // rows per update_pair workgroup
+constexpr int64_t UROWS = 32;    // rows per update_pair workgroup
 constexpr int64_t QR_MAXWG = 512;
 
 int64_t nb_rows(int64_t rows) { return cdiv(rows, TPB); }
@@ -450,7 +460,12 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   // U = M V_j
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
   prof_begin(sc, st);
-  spmm_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ds);
+  for (int i = 0; i < P.nsides; ++i) {
+    const SideDesc &d = i ? *sw : sv;
+    P.s[i].pin = d.panel[jb % 2];
+    P.s[i].pout = d.panel[(jb + 1) % 2];
+  }
+  spmm_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_SPMM,
            12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,

@@ -51,10 +51,16 @@ enum {
   CNT_MAX = 4096
 };
 
+// Records the last HIP runtime error seen by the library (reported by sylv_last_error).
+void note_hip_error(hipError_t e, const char *what);
+
 #define HIPOK(x)                                      \
   do {                                                \
     hipError_t e_ = (x);                              \
-    if (e_ != hipSuccess) return SYLV_ERR_HIP;        \
+    if (e_ != hipSuccess) {                           \
+      note_hip_error(e_, #x);                         \
+      return SYLV_ERR_HIP;                            \
+    }                                                 \
   } while (0)
 
 // ---- wave / block reductions (deterministic: fixed shuffle tree, fixed LDS order) ----
@@ -151,6 +157,58 @@ template <int NV>
 __device__ bool reduce_grid(double (&v)[NV], double *partials, int *counter, double *out) {
   return reduce_sub<NV>(v, blockIdx.y * gridDim.x + blockIdx.x, gridDim.x * gridDim.y, partials,
                         counter, out);
+}
+
+// ---- CSR SpMM building block ----
+
+constexpr int SPMM_TPB = 256;   // rows per workgroup (one per thread)
+constexpr int SPMM_CAP = 2048;  // CSR entries staged in LDS per workgroup
+
+// acc = A[r, :] X[:, 0:S] for row r = r0 + threadIdx.x (< r1), X with leading dimension ldx.
+// The workgroup's CSR range rp[r0] .. rp[r1] is contiguous; when it fits SPMM_CAP it is staged
+// in LDS with coalesced loads and every thread walks its row from LDS (stencil rows are short,
+// so direct per-thread reads of col_idx / values would be strided across the wave). Larger
+// ranges are read directly. All threads of the workgroup must call (it synchronizes).
+template <int S>
+__device__ __forceinline__ void spmm_rows(int64_t r0, int64_t r1, const int32_t *__restrict__ rp,
+                                          const int32_t *__restrict__ ci,
+                                          const double *__restrict__ val,
+                                          const double *__restrict__ X, int64_t ldx,
+                                          double (&acc)[S]) {
+  __shared__ int s_ci[SPMM_CAP];
+  __shared__ double s_val[SPMM_CAP];
+#pragma unroll
+  for (int t = 0; t < S; ++t) acc[t] = 0.0;
+  const int64_t r = r0 + threadIdx.x;
+  const int base = rp[r0];
+  const int len = rp[r1] - base;
+  const bool staged = len <= SPMM_CAP;
+  if (staged) {
+    for (int e = threadIdx.x; e < len; e += blockDim.x) {
+      s_ci[e] = ci[base + e];
+      s_val[e] = val[base + e];
+    }
+  }
+  __syncthreads();
+  if (r < r1) {
+    const int b = rp[r], e = rp[r + 1];
+    if (staged) {
+      for (int q = b - base; q < e - base; ++q) {
+        const double a = s_val[q];
+        const double *x = X + (int64_t)s_ci[q] * ldx;
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+      }
+    } else {
+      for (int q = b; q < e; ++q) {
+        const double a = val[q];
+        const double *x = X + (int64_t)ci[q] * ldx;
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+      }
+    }
+  }
+  __syncthreads();
 }
 
 // ---- small dense helpers executed by one thread (s <= 8) ----
@@ -319,6 +377,8 @@ struct SideDesc {
   double *U;               // rows x s work panel
   double *coef;            // compact coefficient block (ldb x s)
   SideState *ss;           // device
+  double *panel[2];        // compact rows x s copies of the two newest blocks: block j in
+                           // panel[j % 2] (SpMM input and Lanczos local terms)
 };
 
 struct Scratch {

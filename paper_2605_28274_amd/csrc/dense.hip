@@ -33,25 +33,28 @@ struct Smem {
 
 // MFMA f64 16x16x4 operand layout (wave64): lane l supplies A[l % 16][l / 16] and
 // B[l / 16][l % 16]; accumulator element v of lane l holds D[4 * v + l / 16][l % 16].
-__device__ __forceinline__ void mma_slab(const Slab &As, const Slab &Bs,
-                                         WaveAcc &acc, int wm, int wn, int kmax) {
+// All operands of the slab are read from LDS first (one wait), then the slab's 32 MFMAs issue
+// back to back on four independent accumulators.
+__device__ __forceinline__ void mma_slab(const Slab &As, const Slab &Bs, WaveAcc &acc, int wm,
+                                         int wn) {
   const int lane = threadIdx.x & 63;
   const int li = lane & 15, lk = lane >> 4;
+  double a[BK / 4][2], b[BK / 4][2];
 #pragma unroll
-  for (int kk = 0; kk < BK; kk += 4) {
-    if (kk >= kmax) break;
-    double a[2], b[2];
+  for (int q = 0; q < BK / 4; ++q)
 #pragma unroll
     for (int t = 0; t < 2; ++t) {
-      a[t] = As[kk + lk][wm * 32 + t * 16 + li];
-      b[t] = Bs[kk + lk][wn * 32 + t * 16 + li];
+      a[q][t] = As[4 * q + lk][wm * 32 + t * 16 + li];
+      b[q][t] = Bs[4 * q + lk][wn * 32 + t * 16 + li];
     }
+#pragma unroll
+  for (int q = 0; q < BK / 4; ++q)
 #pragma unroll
     for (int ti = 0; ti < 2; ++ti)
 #pragma unroll
       for (int tj = 0; tj < 2; ++tj)
-        acc.c[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.c[ti][tj], 0, 0, 0);
-  }
+        acc.c[ti][tj] =
+            __builtin_amdgcn_mfma_f64_16x16x4f64(a[q][ti], b[q][tj], acc.c[ti][tj], 0, 0, 0);
 }
 
 __device__ __forceinline__ void zero_acc(WaveAcc &acc) {
@@ -115,52 +118,65 @@ __device__ __forceinline__ void store_cols(Slab &dst, const RegSlab &r) {
   }
 }
 
+template <bool B_FROM_ROWS>
+__device__ __forceinline__ void load_slab(const double *A, const double *B, int64_t ld, int l,
+                                          RegSlab &ra, RegSlab &rb) {
+  load_rows(A + l, ld, ra);
+  if (B_FROM_ROWS) load_rows(B + l, ld, rb);
+  else load_cols(B + (int64_t)l * ld, ld, rb);
+}
+
+template <bool B_FROM_ROWS>
+__device__ __forceinline__ void store_slab(Smem &sm, int buf, const RegSlab &ra,
+                                           const RegSlab &rb) {
+  store_rows(sm.As[buf], ra);
+  if (B_FROM_ROWS) store_rows(sm.Bs[buf], rb);
+  else store_cols(sm.Bs[buf], rb);
+}
+
 // One pipelined product over K slabs [l_begin, l_end) (multiples of BK):
 //   B_FROM_ROWS == false: acc += A(i0.., l) * B(l, j0..)  with B row-major (cols slab)
 //   B_FROM_ROWS == true : acc += A(i0.., l) * B(j0.., l)^T (B given by its rows: rows slab)
+// Global loads run two slabs ahead of the MFMAs (two register sets, the loop unrolled by two so
+// they stay static); LDS is double-buffered with one barrier per slab.
 template <bool B_FROM_ROWS>
 __device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn,
                                           const double *A, const double *B, int64_t ld,
                                           int l_begin, int l_end) {
   if (l_begin >= l_end) return;
-  RegSlab ra, rb;
-  load_rows(A + l_begin, ld, ra);
-  if (B_FROM_ROWS) load_rows(B + l_begin, ld, rb);
-  else load_cols(B + (int64_t)l_begin * ld, ld, rb);
-  int buf = 0;
+  const int nsl = (l_end - l_begin) / BK;
+  // Prefetches are unconditional (a slab index past the end re-reads the last slab, always in
+  // bounds), so the number of loads in flight is the same on every path and the wait before an
+  // LDS fill only covers the older register set.
+  auto lslab = [&](int t) { return l_begin + (t < nsl ? t : nsl - 1) * BK; };
+  RegSlab ra0, rb0, ra1, rb1;
+  load_slab<B_FROM_ROWS>(A, B, ld, lslab(0), ra0, rb0);
+  load_slab<B_FROM_ROWS>(A, B, ld, lslab(1), ra1, rb1);
   __syncthreads();  // previous users of the LDS buffers are done
-  store_rows(sm.As[0], ra);
-  if (B_FROM_ROWS) store_rows(sm.Bs[0], rb);
-  else store_cols(sm.Bs[0], rb);
+  store_slab<B_FROM_ROWS>(sm, 0, ra0, rb0);
   __syncthreads();
-  for (int l0 = l_begin; l0 < l_end; l0 += BK) {
-    const bool more = l0 + BK < l_end;
-    if (more) {
-      load_rows(A + l0 + BK, ld, ra);
-      if (B_FROM_ROWS) load_rows(B + l0 + BK, ld, rb);
-      else load_cols(B + (int64_t)(l0 + BK) * ld, ld, rb);
-    }
-    mma_slab(sm.As[buf], sm.Bs[buf], acc, wm, wn, BK);
-    if (more) {
-      store_rows(sm.As[buf ^ 1], ra);
-      if (B_FROM_ROWS) store_rows(sm.Bs[buf ^ 1], rb);
-      else store_cols(sm.Bs[buf ^ 1], rb);
-    }
+  // invariant at slab t: LDS[t % 2] holds slab t; register set (t+1) % 2 holds slab t+1
+  int t = 0;
+  for (; t + 1 < nsl; t += 2) {
+    load_slab<B_FROM_ROWS>(A, B, ld, lslab(t + 2), ra0, rb0);
+    mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+    store_slab<B_FROM_ROWS>(sm, 1, ra1, rb1);
     __syncthreads();
-    buf ^= 1;
+    load_slab<B_FROM_ROWS>(A, B, ld, lslab(t + 3), ra1, rb1);
+    mma_slab(sm.As[1], sm.Bs[1], acc, wm, wn);
+    store_slab<B_FROM_ROWS>(sm, 0, ra0, rb0);
+    __syncthreads();
   }
+  if (t < nsl) mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);  // odd slab count: the last slab
 }
 
 // ---- core operator (all indices < ldc; entries outside the active cores are exact zeros) ----
-__global__ __launch_bounds__(256) void core_op_kernel(int s, int p, const double *__restrict__ H,
-                                                      const double *__restrict__ G,
-                                                      const double *__restrict__ P,
-                                                      double *__restrict__ Q, int64_t ldc,
-                                                      const int *done) {
-  if (done && *done) return;
-  __shared__ Smem sm;
-  const int i0 = blockIdx.y * BM, j0 = blockIdx.x * BN;
-  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+// The K range of output tile (I, J) has (T - I) + (T - J) slab-rows of work (T tiles per side),
+// so workgroup b computes the complementary pair of tiles b and T*T - 1 - b, i.e. (I, J) and
+// (T-1-I, T-1-J): every workgroup then does the same amount of matrix-core work.
+__device__ __forceinline__ void core_op_tile(Smem &sm, int s, int p, const double *H,
+                                             const double *G, const double *P, double *Q,
+                                             int64_t ldc, int i0, int j0, int wm, int wn) {
   WaveAcc acc;
   zero_acc(acc);
   const int pk = (p + BK - 1) / BK * BK;
@@ -179,6 +195,20 @@ __global__ __launch_bounds__(256) void core_op_kernel(int s, int p, const double
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
     Q[(int64_t)(i0 + ii) * ldc + j0 + jj] = v;
   });
+}
+
+__global__ __launch_bounds__(256) void core_op_kernel(int s, int p, int T,
+                                                      const double *__restrict__ H,
+                                                      const double *__restrict__ G,
+                                                      const double *__restrict__ P,
+                                                      double *__restrict__ Q, int64_t ldc,
+                                                      const int *done) {
+  if (done && *done) return;
+  __shared__ Smem sm;
+  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  const int t1 = blockIdx.x, t2 = T * T - 1 - t1;
+  core_op_tile(sm, s, p, H, G, P, Q, ldc, (t1 / T) * BM, (t1 % T) * BN, wm, wn);
+  if (t2 != t1) core_op_tile(sm, s, p, H, G, P, Q, ldc, (t2 / T) * BM, (t2 % T) * BN, wm, wn);
 }
 
 // ---- generic strided GEMM with bounds masks (residual Grams and core products) ----
@@ -212,7 +242,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
       sm.Bs[buf][kk][jj] = (gk < K && gj < N) ? B[gk * b_rs + gj * b_cs] : 0.0;
     }
     __syncthreads();
-    mma_slab(sm.As[buf], sm.Bs[buf], acc, wm, wn, BK);
+    mma_slab(sm.As[buf], sm.Bs[buf], acc, wm, wn);
     buf ^= 1;  // the other buffer is free: its last readers passed the barrier above
   }
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
@@ -229,9 +259,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,
                    int64_t ldc, const int *done, hipStream_t st) {
   const int q = p + s;
-  const unsigned t = (unsigned)((q + BM - 1) / BM);
-  if ((int64_t)t * BM > ldc || ((p + BK - 1) / BK * BK) > ldc) return SYLV_ERR_WORKSPACE;
-  core_op_kernel<<<dim3(t, t), 256, 0, st>>>(s, p, H, G, P, Q, ldc, done);
+  const int T = (q + BM - 1) / BM;
+  if ((int64_t)T * BM > ldc || ((p + BK - 1) / BK * BK) > ldc) return SYLV_ERR_WORKSPACE;
+  core_op_kernel<<<(unsigned)((T * T + 1) / 2), 256, 0, st>>>(s, p, T, H, G, P, Q, ldc, done);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -84,8 +84,9 @@ __global__ __launch_bounds__(TPB) void pass2_gram_kernel(const double *__restric
 template <int S>
 __global__ __launch_bounds__(TPB) void final_kernel(const double *__restrict__ U, int64_t rows,
                                                     double *__restrict__ V, int64_t ldb, int ocol,
-                                                    const SideState *ss, double *H, int64_t ldh,
-                                                    int hrow, int hcol, const DevState *ds) {
+                                                    double *__restrict__ pout, const SideState *ss,
+                                                    double *H, int64_t ldh, int hrow, int hcol,
+                                                    const DevState *ds) {
   if (ds && ds->done) return;
   double T[S * S];
 #pragma unroll
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(TPB) void final_kernel(const double *__restrict__ U
 #pragma unroll
       for (int a = 0; a < S; ++a) v = fma(u[a], T[a * S + b], v);
       V[r * ldb + ocol + b] = v;
+      pout[r * S + b] = v;
     }
   }
   if (H && blockIdx.x == 0 && threadIdx.x < S * S) {
@@ -116,9 +118,9 @@ __global__ __launch_bounds__(TPB) void final_kernel(const double *__restrict__ U
 template <int S>
 __global__ __launch_bounds__(TPB) void lz_spmm_kernel(
     int64_t rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const double *__restrict__ val, const double *__restrict__ V, int64_t ldb, int jb,
-    double *__restrict__ U, double *H, int64_t ldh, SideState *ss, double *partials, int *counter,
-    const DevState *ds) {
+    const double *__restrict__ val, const double *__restrict__ Vj, const double *__restrict__ Vjm1,
+    int jb, double *__restrict__ U, double *H, int64_t ldh, SideState *ss, double *partials,
+    int *counter, const DevState *ds) {
   if (ds->done) return;
   double hup[S * S];  // hup[u][t] = H_{j-1,j}[u][t] = H[j s + t][(j-1) s + u]
   if (jb > 0) {
@@ -127,25 +129,19 @@ __global__ __launch_bounds__(TPB) void lz_spmm_kernel(
 #pragma unroll
       for (int t = 0; t < S; ++t) hup[u * S + t] = H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + u];
   }
+  const int64_t r0 = (int64_t)blockIdx.x * TPB;
+  const int64_t r1 = (r0 + TPB < rows) ? r0 + TPB : rows;
+  double acc[S];
+  spmm_rows<S>(r0, r1, rp, ci, val, Vj, S, acc);
   double red[S * S + 1];
 #pragma unroll
   for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
-  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (r < rows) {
-    double acc[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = 0.0;
-    const int b = rp[r], e = rp[r + 1];
-    for (int q = b; q < e; ++q) {
-      const double a = val[q];
-      const double *x = V + (int64_t)ci[q] * ldb + jb * S;
-#pragma unroll
-      for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
-    }
+  const int64_t r = r0 + threadIdx.x;
+  if (r < r1) {
 #pragma unroll
     for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
     if (jb > 0) {
-      const double *vp = V + r * ldb + (jb - 1) * S;
+      const double *vp = Vjm1 + r * S;
 #pragma unroll
       for (int u = 0; u < S; ++u) {
         const double vu = vp[u];
@@ -153,7 +149,7 @@ __global__ __launch_bounds__(TPB) void lz_spmm_kernel(
         for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
       }
     }
-    const double *vj = V + r * ldb + jb * S;
+    const double *vj = Vj + r * S;
 #pragma unroll
     for (int a = 0; a < S; ++a) {
       const double va = vj[a];
@@ -177,8 +173,8 @@ __global__ __launch_bounds__(TPB) void lz_spmm_kernel(
 
 // U -= V_j H_jj; partial U^T U; last workgroup runs the first QR pass.
 template <int S>
-__global__ __launch_bounds__(TPB) void lz_update_kernel(int64_t rows, const double *__restrict__ V,
-                                                        int64_t ldb, int jb, double *__restrict__ U,
+__global__ __launch_bounds__(TPB) void lz_update_kernel(int64_t rows, const double *__restrict__ Vj,
+                                                        double *__restrict__ U,
                                                         double closure_tol, SideState *ss,
                                                         double *partials, int *counter,
                                                         const DevState *ds) {
@@ -194,7 +190,7 @@ __global__ __launch_bounds__(TPB) void lz_update_kernel(int64_t rows, const doub
     double u[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) u[t] = U[r * S + t];
-    const double *vj = V + r * ldb + jb * S;
+    const double *vj = Vj + r * S;
 #pragma unroll
     for (int a = 0; a < S; ++a) {
       const double va = vj[a];
@@ -231,8 +227,9 @@ int first_block_t(const SideDesc &sd, const double *C, int64_t ldc_in, double cl
   pass2_gram_kernel<S><<<grid_capped(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.ss, sc.partials,
                                                              sc.counters + CNT_NRM + 1, nullptr);
   HIPOK(hipGetLastError());
-  final_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.basis, sd.ldb, 0, sd.ss,
-                                                      nullptr, 0, 0, 0, nullptr);
+  final_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.basis, sd.ldb, 0,
+                                                      sd.panel[0], sd.ss, nullptr, 0, 0, 0,
+                                                      nullptr);
   HIPOK(hipGetLastError());
   return 0;
 }
@@ -245,8 +242,8 @@ int finish_step(const SideDesc &sd, int jb, int64_t ldh, const Scratch &sc, DevS
                                                              sc.counters + CNT_NRM + 1, ds);
   HIPOK(hipGetLastError());
   final_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.basis, sd.ldb,
-                                                      (jb + 1) * S, sd.ss, sd.H, ldh, (jb + 1) * S,
-                                                      jb * S, ds);
+                                                      (jb + 1) * S, sd.panel[(jb + 1) % 2], sd.ss,
+                                                      sd.H, ldh, (jb + 1) * S, jb * S, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * sd.rows * S * 2 + 8.0 * sd.rows * S, 6.0 * sd.rows * S * S, st);
   return 0;
@@ -256,11 +253,11 @@ template <int S>
 int lanczos_step_t(const SideDesc &sd, int jb, int64_t ldh, double closure_tol, const Scratch &sc,
                    DevState *ds, hipStream_t st) {
   prof_begin(sc, st);
-  lz_spmm_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.rows, sd.rp, sd.ci, sd.val, sd.basis,
-                                                        sd.ldb, jb, sd.U, sd.H, ldh, sd.ss,
-                                                        sc.partials, sc.counters + CNT_LZ1, ds);
+  lz_spmm_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(
+      sd.rows, sd.rp, sd.ci, sd.val, sd.panel[jb % 2], sd.panel[(jb + 1) % 2], jb, sd.U, sd.H, ldh,
+      sd.ss, sc.partials, sc.counters + CNT_LZ1, ds);
   HIPOK(hipGetLastError());
-  lz_update_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.rows, sd.basis, sd.ldb, jb, sd.U,
+  lz_update_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.rows, sd.panel[jb % 2], sd.U,
                                                           closure_tol, sd.ss, sc.partials,
                                                           sc.counters + CNT_UPD, ds);
   HIPOK(hipGetLastError());

@@ -5,30 +5,24 @@
 
 namespace {
 
-// Y[r, 0:S] = sum_q A[r, c_q] X[c_q, 0:S]; one thread per row. Stencil rows hold 3-7
-// entries, so a row's column indices and values are a few contiguous words and the gathered
-// panel rows are S contiguous doubles that mostly hit L2 (neighbouring grid points).
+// Y[r, 0:S] = sum_q A[r, c_q] X[c_q, 0:S]; one thread per row, CSR range staged in LDS.
 template <int S>
-__global__ __launch_bounds__(256) void spmm_kernel(int64_t rows, const int32_t *__restrict__ rp,
-                                                   const int32_t *__restrict__ ci,
-                                                   const double *__restrict__ val,
-                                                   const double *__restrict__ X, int64_t ldx,
-                                                   double *__restrict__ Y, int64_t ldy) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= rows) return;
+__global__ __launch_bounds__(SPMM_TPB) void spmm_kernel(int64_t rows,
+                                                        const int32_t *__restrict__ rp,
+                                                        const int32_t *__restrict__ ci,
+                                                        const double *__restrict__ val,
+                                                        const double *__restrict__ X, int64_t ldx,
+                                                        double *__restrict__ Y, int64_t ldy) {
+  const int64_t r0 = (int64_t)blockIdx.x * SPMM_TPB;
+  const int64_t r1 = (r0 + SPMM_TPB < rows) ? r0 + SPMM_TPB : rows;
   double acc[S];
+  spmm_rows<S>(r0, r1, rp, ci, val, X, ldx, acc);
+  const int64_t r = r0 + threadIdx.x;
+  if (r < r1) {
+    double *y = Y + r * ldy;
 #pragma unroll
-  for (int t = 0; t < S; ++t) acc[t] = 0.0;
-  const int b = rp[r], e = rp[r + 1];
-  for (int q = b; q < e; ++q) {
-    const double a = val[q];
-    const double *x = X + (int64_t)ci[q] * ldx;
-#pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+    for (int t = 0; t < S; ++t) y[t] = acc[t];
   }
-  double *y = Y + r * ldy;
-#pragma unroll
-  for (int t = 0; t < S; ++t) y[t] = acc[t];
 }
 
 // Wide SpMM for rows [r0, r1): Y[r - r0, 0:ncols] = A[r, :] X[:, 0:ncols]; one wave per row,
@@ -133,7 +127,7 @@ __global__ void csr_sort_rows_kernel(int64_t rows, const int32_t *__restrict__ r
 int launch_spmm(int s, int64_t rows, const int32_t *rp, const int32_t *ci, const double *val,
                 const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t st) {
   if (rows <= 0) return 0;
-  const dim3 grid((unsigned)((rows + 255) / 256)), block(256);
+  const dim3 grid((unsigned)((rows + SPMM_TPB - 1) / SPMM_TPB)), block(SPMM_TPB);
   switch (s) {
 #define CASE(SS) \
   case SS: spmm_kernel<SS><<<grid, block, 0, st>>>(rows, rp, ci, val, X, ldx, Y, ldy); break;

@@ -28,11 +28,17 @@ SYLV_METHOD_CG, SYLV_METHOD_BICGSTAB = 0, 1
 
 class SylvError(RuntimeError):
     def __init__(self, code: int, what: str):
-        super().__init__(f"{what}: {status_string(code)} ({code})")
+        msg = f"{what}: {status_string(code)} ({code})"
+        if code == SYLV_ERR_HIP:
+            msg += f" [{_lib.sylv_last_error().decode()}]"
+        super().__init__(msg)
         self.code = code
 
 
 def _load():
+    # torch ships its own HIP runtime; loading it first makes libsylv bind to that same runtime
+    # (one HIP runtime per process, shared device memory and streams)
+    import torch  # noqa: F401
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(
             f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
@@ -85,6 +91,8 @@ _lib.sylv_destroy.argtypes = [c_void_p]
 _lib.sylv_destroy.restype = None
 _lib.sylv_status_string.argtypes = [c_int]
 _lib.sylv_status_string.restype = ctypes.c_char_p
+_lib.sylv_last_error.argtypes = []
+_lib.sylv_last_error.restype = ctypes.c_char_p
 _lib.sylv_spmm.argtypes = [POINTER(sylv_csr), c_int64, c_void_p, c_int64, c_void_p, c_int64,
                            c_void_p]
 _lib.sylv_spmm.restype = c_int

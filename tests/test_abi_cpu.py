@@ -1,0 +1,78 @@
+"""CPU checks of the C ABI: the library loads without a GPU, exports every function the header
+declares, and its host-only calls (options, workspace sizing, status strings) behave as stated.
+No device compute runs here."""
+import ctypes
+
+import numpy as np
+import pytest
+
+from workloads import configs
+
+sylv = pytest.importorskip("paper_2605_28274_amd.sylv")
+
+
+def test_exports_every_declared_symbol():
+    names = sylv.declared_functions()
+    assert len(names) >= 14
+    lib = ctypes.CDLL(sylv.LIB_PATH)
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_status_strings_and_defaults():
+    assert sylv.status_string(0) == "converged"
+    assert "rank" in sylv.status_string(sylv.SYLV_ERR_RHS_RANK)
+    assert sylv.status_string(12345) == "unknown status"
+    o = sylv.default_options()
+    assert o.max_iter > 0 and o.check_every > 0 and 0 < o.closure_tol < 1e-6
+
+
+def _problem(n=256, m=192, s=1, lyap=0, nnzA=766, nnzB=574):
+    # pointers are never dereferenced by the sizing call; any non-null value works
+    fake = 0x1000
+    A = sylv.sylv_csr(n, nnzA, fake, fake, fake)
+    B = sylv.sylv_csr(m, nnzB, fake, fake, fake)
+    return sylv.sylv_problem(n, m, s, A, B, lyap, fake, s, fake, s)
+
+
+def test_workspace_bytes_grows_with_max_iter_and_method():
+    p = _problem()
+    cg = sylv.sylv_workspace_bytes(p, sylv.default_options(sylv.SYLV_METHOD_CG, 100))
+    cg2 = sylv.sylv_workspace_bytes(p, sylv.default_options(sylv.SYLV_METHOD_CG, 200))
+    bi = sylv.sylv_workspace_bytes(p, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 100))
+    assert 0 < cg < cg2 and cg < bi
+
+
+@pytest.mark.parametrize("bad", [
+    dict(n=0), dict(s=0), dict(s=9), dict(s=300), dict(lyap=1),
+])
+def test_workspace_bytes_rejects_invalid(bad):
+    kw = dict(n=256, m=192, s=1, lyap=0)
+    kw.update(bad)
+    p = _problem(**kw)
+    assert sylv.sylv_workspace_bytes(p, sylv.default_options(sylv.SYLV_METHOD_CG, 10)) == 0
+
+
+def test_workspace_bytes_rejects_bad_options():
+    p = _problem()
+    o = sylv.default_options(sylv.SYLV_METHOD_CG, 0)
+    assert sylv.sylv_workspace_bytes(p, o) == 0
+    o = sylv.default_options(7, 10)
+    assert sylv.sylv_workspace_bytes(p, o) == 0
+
+
+def test_create_rejects_missing_workspace_without_device_work():
+    p = _problem()
+    o = sylv.default_options(sylv.SYLV_METHOD_CG, 10)
+    h = ctypes.c_void_p()
+    rc = sylv._lib.sylv_create(ctypes.byref(h), ctypes.byref(p), ctypes.byref(o), None, 0, None)
+    assert rc == sylv.SYLV_ERR_WORKSPACE
+    rc = sylv._lib.sylv_create(None, ctypes.byref(p), ctypes.byref(o), None, 0, None)
+    assert rc == sylv.SYLV_ERR_INVALID
+
+
+def test_c2_workspace_is_modest():
+    p = configs.c2_bicgstab()
+    prob = _problem(p.n, p.m, p.s, 0, p.A.nnz, p.B.nnz)
+    nb = sylv.sylv_workspace_bytes(prob, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 800))
+    assert 0 < nb < 4 * 2**30

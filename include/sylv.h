@@ -179,6 +179,17 @@ const char *sylv_kernel_family_name(int family);
 int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double *Y,
               int64_t ldy, void *stream);
 
+/* Sliced-ELLPACK copy of a CSR matrix, the layout the solver's SpMM streams (slices of 64 rows,
+ * each stored column-major with the slice's maximum row length; short rows padded with zero
+ * values). sylv_sell_bytes: device bytes of the copy (0 for an invalid matrix).
+ * sylv_sell_build: builds it into the caller's buffer; SYLV_ERR_WORKSPACE when the padding
+ * exceeds the reserved 25% (matrices with very uneven rows stay in CSR).
+ * sylv_sell_spmm: Y = A X as sylv_spmm, reading the copy built from the same A. */
+size_t sylv_sell_bytes(const sylv_csr *A);
+int sylv_sell_build(const sylv_csr *A, void *sell, size_t bytes, void *stream);
+int sylv_sell_spmm(const sylv_csr *A, const void *sell, int64_t s, const double *X, int64_t ldx,
+                   double *Y, int64_t ldy, void *stream);
+
 /* Transpose of a square CSR matrix (rows x rows, nnz entries) into caller buffers:
  * out_row_ptr (rows + 1), out_col_idx (nnz), out_values (nnz). The result is canonical
  * (sorted column indices), so it is bit-identical to any other exact transpose. scratch:

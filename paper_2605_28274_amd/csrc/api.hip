@@ -28,7 +28,7 @@ struct Layout {
   size_t off_U, off_Uw, off_coefV, off_coefW, off_btrp, off_btci, off_btval, off_tscr;
   size_t off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
   size_t off_E, off_GVV, off_GWW, off_GVE, off_GWE, off_GEEa, off_GEEb, off_Lx, off_M1, off_M2;
-  size_t off_dots, off_flag, off_panV, off_panW;
+  size_t off_dots, off_flag, off_panV, off_panW, off_sellA, off_sellB;
   size_t total = 0;
 };
 
@@ -125,6 +125,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.off_M2 = bump(cur, c2);
   L.off_panV = bump(cur, (size_t)2 * L.n * L.s * 8);
   L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * 8);
+  L.off_sellA = bump(cur, sell_bytes(L.n, pb->A.nnz));
+  L.off_sellB = L.lyap ? L.off_sellA : bump(cur, sell_bytes(L.m, pb->B.nnz));
   L.off_dots = bump(cur, 16 * 8);
   L.off_flag = bump(cur, 16 * sizeof(int));
   L.total = cur + ALIGN;
@@ -417,6 +419,20 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
                      c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw,
                      {at<double>(c, L.off_panW), at<double>(c, L.off_panW) + L.m * L.s}};
   }
+  // SELL copies of A and B^T for the Krylov SpMM (CSR stays in use if the padding is large)
+  c->sv.sell = SellMat{};
+  e = build_sell(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
+                 at<void>(c, L.off_sellA), st);
+  if (e == 0) c->sv.sell = sell_view(L.n, pb->A.nnz, at<void>(c, L.off_sellA));
+  else if (e != SYLV_ERR_WORKSPACE) return fail(e);
+  if (L.lyap) {
+    c->sw.sell = c->sv.sell;
+  } else {
+    c->sw.sell = SellMat{};
+    e = build_sell(L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<void>(c, L.off_sellB), st);
+    if (e == 0) c->sw.sell = sell_view(L.m, pb->B.nnz, at<void>(c, L.off_sellB));
+    else if (e != SYLV_ERR_WORKSPACE) return fail(e);
+  }
   // QR factorizations C1 = V_1 R_L, C2 = W_1 R_R (Alg. 4.1 step 1, Alg. 4.2 step 2)
   const int s = (int)L.s;
   if ((e = launch_first_block(s, c->sv, pb->C1, pb->ldc1, c->closure_tol, c->sc, c->ds, st)))
@@ -504,9 +520,8 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
     const int p = (k + 1) * s;
     set_iter(c, k);
     // (k+1)-th block Lanczos step on both sides (Alg. 4.1 steps 4-5)
-    if ((e = launch_lanczos_step(s, c->sv, k, L.ldc, c->closure_tol, c->sc, c->ds, c->st))) return e;
-    if (!L.lyap &&
-        (e = launch_lanczos_step(s, c->sw, k, L.ldc, c->closure_tol, c->sc, c->ds, c->st)))
+    if ((e = launch_lanczos_pair(s, c->sv, L.lyap ? nullptr : &c->sw, k, L.ldc, c->closure_tol,
+                                 c->sc, c->ds, c->st)))
       return e;
     // Q_k (step 6) and alpha_k (step 7)
     const double q2 = (double)(p + s) * (p + s);
@@ -754,6 +769,31 @@ int sylv_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, i
     return SYLV_ERR_INVALID;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int e = launch_gemm(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc, st);
+  if (e) return e;
+  HIPOK(hipStreamSynchronize(st));
+  return 0;
+}
+
+size_t sylv_sell_bytes(const sylv_csr *A) {
+  if (!A || A->rows <= 0 || check_csr_header(*A, A->rows)) return 0;
+  return sell_bytes(A->rows, A->nnz);
+}
+
+int sylv_sell_build(const sylv_csr *A, void *sell, size_t bytes, void *stream) {
+  if (!A || !sell || A->rows <= 0 || check_csr_header(*A, A->rows)) return SYLV_ERR_INVALID;
+  if (bytes < sell_bytes(A->rows, A->nnz)) return SYLV_ERR_WORKSPACE;
+  return build_sell(A->rows, A->nnz, A->row_ptr, A->col_idx, A->values, sell,
+                    reinterpret_cast<hipStream_t>(stream));
+}
+
+int sylv_sell_spmm(const sylv_csr *A, const void *sell, int64_t s, const double *X, int64_t ldx,
+                   double *Y, int64_t ldy, void *stream) {
+  if (!A || !sell || s < 1 || s > SYLV_MAX_S || ldx < s || ldy < s || !X || !Y)
+    return SYLV_ERR_INVALID;
+  if (A->rows <= 0 || check_csr_header(*A, A->rows)) return SYLV_ERR_INVALID;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  const SellMat M = sell_view(A->rows, A->nnz, const_cast<void *>(sell));
+  int e = launch_sell_spmm((int)s, M, X, ldx, Y, ldy, st);
   if (e) return e;
   HIPOK(hipStreamSynchronize(st));
   return 0;

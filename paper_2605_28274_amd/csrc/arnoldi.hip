@@ -38,6 +38,7 @@ struct ArSide {
   double *U;
   double *coef;
   SideState *ss;
+  SellMat sell;       // SELL copy of the operator (sell.ci == nullptr: CSR)
   const double *pin;  // compact copy of block j (SpMM input)
   double *pout;       // compact copy of block j+1 (written with the new block)
   double *part;    // Gram chunk partials of this basis
@@ -70,9 +71,13 @@ __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   const int64_t r0 = (int64_t)lb * TPB;
   const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
   double acc[S];
-  spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, A.pin, S, acc);
-  double red[1] = {0.0};
   const int64_t r = r0 + threadIdx.x;
+  if (A.sell.ci) {
+    if (r < r1) sell_row<S>(A.sell, r, A.pin, S, acc);
+  } else {
+    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, A.pin, S, acc);
+  }
+  double red[1] = {0.0};
   if (r < r1) {
 #pragma unroll
     for (int t = 0; t < S; ++t) {
@@ -380,6 +385,119 @@ __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
   }
 }
 
+// ---- block Lanczos step j for both bases (Algorithm 4.1, steps 4-5) ----
+// aux layout per basis: [nb_spmm] ||M V_j||^2, [nb_upd S^2] U^T U, [nb_qr S^2] second-pass Gram,
+// [nb_spmm S^2] V_j^T U.
+template <int S>
+__device__ __forceinline__ double *aux_vju(const ArSide &A) {
+  return A.aux + A.nb_spmm + (A.nb_upd + A.nb_qr) * S * S;
+}
+
+// U = M V_j - V_{j-1} H_{j-1,j} (H_{j-1,j} = H_{j,j-1}^T); partials of ||M V_j||^2 and V_j^T U.
+template <int S>
+__global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ldh,
+                                                    const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double hup[S * S];  // hup[u][t] = H_{j-1,j}[u][t] = H[j s + t][(j-1) s + u]
+#pragma unroll
+  for (int u = 0; u < S; ++u)
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      hup[u * S + t] = jb > 0 ? A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + u] : 0.0;
+  const int64_t r0 = (int64_t)lb * TPB;
+  const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+  const int64_t r = r0 + threadIdx.x;
+  double acc[S];
+  if (A.sell.ci) {
+    if (r < r1) sell_row<S>(A.sell, r, A.pin, S, acc);
+  } else {
+    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, A.pin, S, acc);
+  }
+  double red[S * S + 1];
+#pragma unroll
+  for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
+  if (r < r1) {
+#pragma unroll
+    for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
+    if (jb > 0) {
+      const double *vp = A.pout + r * S;  // block j-1 (its panel is reused for block j+1)
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        const double vu = vp[u];
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
+      }
+    }
+    const double *vj = A.pin + r * S;
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      const double va = vj[a];
+#pragma unroll
+      for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
+  }
+  __shared__ double lds[16 * (S * S + 1)];
+  block_sum<S * S + 1>(red, lds);
+  if (threadIdx.x == 0) {
+    A.aux[lb] = red[S * S];
+    double *vju = aux_vju<S>(A) + lb * S * S;
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) vju[i] = red[i];
+  }
+}
+
+// H_jj = V_j^T U from the partials (every workgroup forms it; workgroup 0 writes column block j
+// of H: H_{j-1,j} and H_jj); U -= V_j H_jj; partials of U^T U.
+template <int S>
+__global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t ldh,
+                                                      const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double hjj[S * S];
+  sum_records<S * S>(aux_vju<S>(A), A.nb_spmm, hjj);
+  if (lb == 0 && threadIdx.x == 0) {
+    for (int a = 0; a < S; ++a)
+      for (int t = 0; t < S; ++t) {
+        A.H[(int64_t)(jb * S + a) * ldh + jb * S + t] = hjj[a * S + t];
+        if (jb > 0)
+          A.H[(int64_t)((jb - 1) * S + a) * ldh + jb * S + t] =
+              A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + a];
+      }
+  }
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  const int64_t r = (int64_t)lb * TPB + threadIdx.x;
+  if (r < A.rows) {
+    double u[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+    const double *vj = A.pin + r * S;
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      const double va = vj[a];
+#pragma unroll
+      for (int t = 0; t < S; ++t) u[t] = fma(-va, hjj[a * S + t], u[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) A.U[r * S + t] = u[t];
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) g[a * S + b] = u[a] * u[b];
+  }
+  __shared__ double lds[16 * S * S];
+  block_sum<S * S>(g, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
+}
+
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Rows per gram chunk: large enough that the chunk partials stay a small fraction of the basis
@@ -409,6 +527,7 @@ ArSide make_side(const SideDesc &d, const Scratch &sc, int idx, size_t half, siz
   a.U = d.U;
   a.coef = d.coef;
   a.ss = d.ss;
+  a.sell = d.sell;
   a.part = sc.partials + (size_t)idx * half;
   a.aux = a.part + half - aux_len;
   a.cnt = sc.counters + CNT_PAIR + idx * 1536;
@@ -433,7 +552,7 @@ constexpr int64_t QR_MAXWG = 512;
 int64_t nb_rows(int64_t rows) { return cdiv(rows, TPB); }
 int64_t nb_qr(int64_t rows) { return std::min<int64_t>(nb_rows(rows), QR_MAXWG); }
 size_t aux_len(int s, int64_t rows) {
-  return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows)) * s * s + 16);
+  return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows) + nb_rows(rows)) * s * s + 16);
 }
 
 template <int S>
@@ -511,6 +630,48 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   return 0;
 }
 
+
+template <int S>
+int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                   double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  ArPair P{};
+  const size_t half = sc.partial_cap / 2;
+  P.nsides = sw ? 2 : 1;
+  const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
+  const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
+  if (aux0 > half || aux1 > half) return SYLV_ERR_WORKSPACE;
+  P.s[0] = make_side(sv, sc, 0, half, aux0);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  for (int i = 0; i < P.nsides; ++i) {
+    const SideDesc &d = i ? *sw : sv;
+    const int64_t rows = i ? rows1 : rows0;
+    P.s[i].nb_spmm = (int)nb_rows(rows);
+    P.s[i].nb_upd = (int)nb_rows(rows);  // U^T U partials come from lz_update_pair
+    P.s[i].nb_qr = (int)nb_qr(rows);
+    P.s[i].pin = d.panel[jb % 2];
+    P.s[i].pout = d.panel[(jb + 1) % 2];
+  }
+  const int64_t total = rows0 + rows1;
+  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+  prof_begin(sc, st);
+  lz_spmm_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  lz_update_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  // matrix + gather V_j + read V_{j-1}, V_j + U write/read (local three-term step)
+  prof_end(sc, FAM_SPMM,
+           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 8.0 * total * S * 6,
+           2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S + 8.0 * total * S * S, st);
+  set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
+  prof_begin(sc, st);
+  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+  HIPOK(hipGetLastError());
+  final_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  return 0;
+}
+
 }  // namespace
 
 size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols) {
@@ -527,6 +688,17 @@ int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
   switch (s) {
 #define CASE(SS) \
   case SS: return arnoldi_pair_t<SS>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
+}
+
+int launch_lanczos_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  switch (s) {
+#define CASE(SS) \
+  case SS: return lanczos_pair_t<SS>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return SYLV_ERR_INVALID;

@@ -211,6 +211,92 @@ __device__ __forceinline__ void spmm_rows(int64_t r0, int64_t r1, const int32_t 
   __syncthreads();
 }
 
+// ---- sliced ELLPACK (SELL-64) ----
+// Rows are grouped in slices of 64 (one wave); slice k stores width[k] = max row length entries
+// per row, column-major inside the slice: entry q of row r sits at off[k] + 64 q + (r % 64).
+// Short rows are padded with value 0 and their own row index as column. Every load of the
+// SpMM below is then one contiguous 64-lane access, and no row pointer lies on the dependent
+// path of the gathers.
+struct SellMat {
+  int64_t rows;
+  int64_t nslices;
+  const int32_t *width;  // [nslices]
+  const int64_t *off;    // [nslices]
+  const int32_t *ci;     // [capacity]
+  const double *val;     // [capacity]
+};
+
+// Capacity (entries) reserved for the SELL copy of a CSR matrix with nnz entries: up to 25%
+// padding plus one full padded row per slice.
+inline int64_t sell_capacity(int64_t rows, int64_t nnz) {
+  return nnz + nnz / 4 + 64 * ((rows + 63) / 64) + 64;
+}
+// Bytes of a SELL buffer (widths, offsets, indices, values; 256-byte aligned parts).
+inline size_t sell_bytes(int64_t rows, int64_t nnz) {
+  const int64_t ns = (rows + 63) / 64, cap = sell_capacity(rows, nnz);
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  return al(ns * 4) + al(ns * 8) + al(cap * 4) + al(cap * 8);
+}
+inline SellMat sell_view(int64_t rows, int64_t nnz, void *buf) {
+  auto al = [](size_t b) { return (b + 255) / 256 * 256; };
+  const int64_t ns = (rows + 63) / 64, cap = sell_capacity(rows, nnz);
+  char *p = reinterpret_cast<char *>(buf);
+  SellMat m;
+  m.rows = rows;
+  m.nslices = ns;
+  m.width = reinterpret_cast<const int32_t *>(p);
+  p += al(ns * 4);
+  m.off = reinterpret_cast<const int64_t *>(p);
+  p += al(ns * 8);
+  m.ci = reinterpret_cast<const int32_t *>(p);
+  p += al(cap * 4);
+  m.val = reinterpret_cast<const double *>(p);
+  return m;
+}
+
+// acc = A[r, :] X[:, 0:S] for one row r < rows (thread r % 64 of a wave-aligned slice). Rows
+// are walked in chunks of 8 entries: all index/value loads of a chunk issue together, then all
+// its gathers, so a stencil row costs two dependent memory round trips.
+template <int S>
+__device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
+                                         const double *__restrict__ X, int64_t ldx,
+                                         double (&acc)[S]) {
+#pragma unroll
+  for (int t = 0; t < S; ++t) acc[t] = 0.0;
+  const int64_t k = r >> 6;
+  const int w = M.width[k];
+  const int64_t base = M.off[k] + (r & 63);
+  for (int q0 = 0; q0 < w; q0 += 8) {
+    int c[8];
+    double a[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = q0 + u < w;
+      c[u] = in ? M.ci[base + 64 * (q0 + u)] : 0;
+      a[u] = in ? M.val[base + 64 * (q0 + u)] : 0.0;
+    }
+    double x[8][S];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const bool in = q0 + u < w;
+#pragma unroll
+      for (int t = 0; t < S; ++t) x[u][t] = in ? X[(int64_t)c[u] * ldx + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+#pragma unroll
+      for (int t = 0; t < S; ++t) acc[t] = fma(a[u], x[u][t], acc[t]);
+  }
+}
+
+// Builds the SELL copy of a CSR matrix into buf (sell_bytes(rows, nnz) bytes). Returns
+// SYLV_ERR_WORKSPACE when the padded size exceeds the reserved capacity (the caller then keeps
+// using CSR). Synchronizes the stream.
+int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *val,
+               void *buf, hipStream_t st);
+int launch_sell_spmm(int s, const SellMat &M, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                     hipStream_t st);
+
 // ---- small dense helpers executed by one thread (s <= 8) ----
 
 // Cholesky G = R^T R (upper R) of an s x s SPD matrix. Returns the smallest pivot ratio
@@ -379,6 +465,7 @@ struct SideDesc {
   SideState *ss;           // device
   double *panel[2];        // compact rows x s copies of the two newest blocks: block j in
                            // panel[j % 2] (SpMM input and Lanczos local terms)
+  SellMat sell;            // SELL copy of the operator (sell.ci == nullptr: use CSR)
 };
 
 struct Scratch {
@@ -415,8 +502,9 @@ size_t csr_transpose_scratch(int64_t rows);
 // Block orthonormalization steps (krylov.hip).
 int launch_first_block(int s, const SideDesc &sd, const double *C, int64_t ldc_in,
                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
-int launch_lanczos_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
-                        const Scratch &sc, DevState *ds, hipStream_t st);
+// Both bases' block Lanczos steps j (arnoldi.hip); sw may be null (Lyapunov).
+int launch_lanczos_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
 
 // Both bases' block Arnoldi steps j (same j) in shared launches (arnoldi.hip); sw may be null
 // (Lyapunov: one basis).

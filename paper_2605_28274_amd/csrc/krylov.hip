@@ -1,7 +1,6 @@
-// One step of the block Lanczos process (Algorithm 4.1): given the newest basis block V_j,
-// compute U = M V_j, orthogonalize it locally (three-term recurrence), then orthonormalize
-// U = V_{j+1} H_{j+1,j} by two Cholesky-QR passes; plus the QR of the first block (C1 = V_1 R_L).
-// The block Arnoldi step of Algorithm 4.2 is in arnoldi.hip.
+// QR of the first block of each basis, C1 = V_1 R_L (Alg. 4.1 step 1, Alg. 4.2 step 2), by two
+// Cholesky-QR passes with the rank test of the right-hand side. The block Lanczos and block
+// Arnoldi steps are in arnoldi.hip.
 // The new block is appended to the basis and its coefficients to column block j of H, so that
 // M V_j = V_{j+1} H_{j+1,j} holds column block by column block (eq. (3.8)).
 //
@@ -111,104 +110,6 @@ __global__ __launch_bounds__(TPB) void final_kernel(const double *__restrict__ U
   }
 }
 
-// ---- block Lanczos ----
-
-// U = M V_j - V_{j-1} H_{j-1,j} with H_{j-1,j} = H_{j,j-1}^T; partials of ||M V_j||^2 and
-// V_j^T U. Last workgroup: H_jj, and column block j of H (rows j-1 and j).
-template <int S>
-__global__ __launch_bounds__(TPB) void lz_spmm_kernel(
-    int64_t rows, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const double *__restrict__ val, const double *__restrict__ Vj, const double *__restrict__ Vjm1,
-    int jb, double *__restrict__ U, double *H, int64_t ldh, SideState *ss, double *partials,
-    int *counter, const DevState *ds) {
-  if (ds->done) return;
-  double hup[S * S];  // hup[u][t] = H_{j-1,j}[u][t] = H[j s + t][(j-1) s + u]
-  if (jb > 0) {
-#pragma unroll
-    for (int u = 0; u < S; ++u)
-#pragma unroll
-      for (int t = 0; t < S; ++t) hup[u * S + t] = H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + u];
-  }
-  const int64_t r0 = (int64_t)blockIdx.x * TPB;
-  const int64_t r1 = (r0 + TPB < rows) ? r0 + TPB : rows;
-  double acc[S];
-  spmm_rows<S>(r0, r1, rp, ci, val, Vj, S, acc);
-  double red[S * S + 1];
-#pragma unroll
-  for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
-  const int64_t r = r0 + threadIdx.x;
-  if (r < r1) {
-#pragma unroll
-    for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
-    if (jb > 0) {
-      const double *vp = Vjm1 + r * S;
-#pragma unroll
-      for (int u = 0; u < S; ++u) {
-        const double vu = vp[u];
-#pragma unroll
-        for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
-      }
-    }
-    const double *vj = Vj + r * S;
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-      const double va = vj[a];
-#pragma unroll
-      for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
-    }
-#pragma unroll
-    for (int t = 0; t < S; ++t) U[r * S + t] = acc[t];
-  }
-  __shared__ double out[S * S + 1];
-  if (reduce_grid<S * S + 1>(red, partials, counter, out) && threadIdx.x == 0) {
-    ss->ref2 = out[S * S];
-    for (int a = 0; a < S; ++a)
-      for (int t = 0; t < S; ++t) {
-        ss->g[a * S + t] = out[a * S + t];
-        H[(int64_t)(jb * S + a) * ldh + jb * S + t] = out[a * S + t];
-        if (jb > 0) H[(int64_t)((jb - 1) * S + a) * ldh + jb * S + t] = hup[a * S + t];
-      }
-  }
-}
-
-// U -= V_j H_jj; partial U^T U; last workgroup runs the first QR pass.
-template <int S>
-__global__ __launch_bounds__(TPB) void lz_update_kernel(int64_t rows, const double *__restrict__ Vj,
-                                                        double *__restrict__ U,
-                                                        double closure_tol, SideState *ss,
-                                                        double *partials, int *counter,
-                                                        const DevState *ds) {
-  if (ds->done) return;
-  double hjj[S * S];
-#pragma unroll
-  for (int i = 0; i < S * S; ++i) hjj[i] = ss->g[i];
-  double g[S * S];
-#pragma unroll
-  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  const int64_t r = (int64_t)blockIdx.x * TPB + threadIdx.x;
-  if (r < rows) {
-    double u[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) u[t] = U[r * S + t];
-    const double *vj = Vj + r * S;
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-      const double va = vj[a];
-#pragma unroll
-      for (int t = 0; t < S; ++t) u[t] = fma(-va, hjj[a * S + t], u[t]);
-    }
-#pragma unroll
-    for (int t = 0; t < S; ++t) U[r * S + t] = u[t];
-#pragma unroll
-    for (int a = 0; a < S; ++a)
-#pragma unroll
-      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
-  }
-  __shared__ double out[S * S];
-  if (reduce_grid<S * S>(g, partials, counter, out) && threadIdx.x == 0)
-    finish_pass1(ss, S, closure_tol, out);
-}
-
 unsigned grid_rows(int64_t rows) { return (unsigned)((rows + TPB - 1) / TPB); }
 
 // Workgroups for the pass-2 Gram and first-block kernels: enough to cover the rows, capped so
@@ -234,39 +135,6 @@ int first_block_t(const SideDesc &sd, const double *C, int64_t ldc_in, double cl
   return 0;
 }
 
-template <int S>
-int finish_step(const SideDesc &sd, int jb, int64_t ldh, const Scratch &sc, DevState *ds,
-                hipStream_t st) {
-  prof_begin(sc, st);
-  pass2_gram_kernel<S><<<grid_capped(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.ss, sc.partials,
-                                                             sc.counters + CNT_NRM + 1, ds);
-  HIPOK(hipGetLastError());
-  final_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.basis, sd.ldb,
-                                                      (jb + 1) * S, sd.panel[(jb + 1) % 2], sd.ss,
-                                                      sd.H, ldh, (jb + 1) * S, jb * S, ds);
-  HIPOK(hipGetLastError());
-  prof_end(sc, FAM_QR, 8.0 * sd.rows * S * 2 + 8.0 * sd.rows * S, 6.0 * sd.rows * S * S, st);
-  return 0;
-}
-
-template <int S>
-int lanczos_step_t(const SideDesc &sd, int jb, int64_t ldh, double closure_tol, const Scratch &sc,
-                   DevState *ds, hipStream_t st) {
-  prof_begin(sc, st);
-  lz_spmm_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(
-      sd.rows, sd.rp, sd.ci, sd.val, sd.panel[jb % 2], sd.panel[(jb + 1) % 2], jb, sd.U, sd.H, ldh,
-      sd.ss, sc.partials, sc.counters + CNT_LZ1, ds);
-  HIPOK(hipGetLastError());
-  lz_update_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.rows, sd.panel[jb % 2], sd.U,
-                                                          closure_tol, sd.ss, sc.partials,
-                                                          sc.counters + CNT_UPD, ds);
-  HIPOK(hipGetLastError());
-  // matrix + gather V_j + read V_{j-1}, V_j + U write/read (Lanczos local step)
-  prof_end(sc, FAM_SPMM, 12.0 * sd.nnz + 4.0 * (sd.rows + 1) + 8.0 * sd.rows * S * 5,
-           2.0 * sd.nnz * S + 8.0 * sd.rows * S * S, st);
-  return finish_step<S>(sd, jb, ldh, sc, ds, st);
-}
-
 }  // namespace
 
 #define DISPATCH_S(s, call)            \
@@ -288,8 +156,4 @@ int launch_first_block(int s, const SideDesc &sd, const double *C, int64_t ldc_i
   DISPATCH_S(s, first_block_t<S>(sd, C, ldc_in, closure_tol, sc, st));
 }
 
-int launch_lanczos_step(int s, const SideDesc &sd, int jb, int64_t ldh, double closure_tol,
-                        const Scratch &sc, DevState *ds, hipStream_t st) {
-  DISPATCH_S(s, lanczos_step_t<S>(sd, jb, ldh, closure_tol, sc, ds, st));
-}
 

@@ -1,6 +1,8 @@
 // CSR kernels: SpMM with tall-skinny panels (the sparse products of the block Lanczos /
 // Arnoldi step, eq. (3.8)), the wide SpMM of the residual evaluation, CSR validation and an
 // exact CSR transpose (B^T for the W basis).
+#include <vector>
+
 #include "common.h"
 
 namespace {
@@ -201,6 +203,94 @@ int launch_csr_validate(int64_t rows, int64_t nnz, const int32_t *rp, const int3
                         hipStream_t st) {
   if (rows <= 0) return 0;
   csr_validate_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(rows, nnz, rp, ci, flag);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+namespace {
+
+__global__ void sell_width_kernel(int64_t rows, int64_t nslices, const int32_t *__restrict__ rp,
+                                  int32_t *__restrict__ width) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nslices) return;
+  int w = 0;
+  const int64_t r1 = (k * 64 + 64 < rows) ? k * 64 + 64 : rows;
+  for (int64_t r = k * 64; r < r1; ++r) {
+    const int len = rp[r + 1] - rp[r];
+    w = len > w ? len : w;
+  }
+  width[k] = w;
+}
+
+__global__ void sell_fill_kernel(int64_t rows, const int32_t *__restrict__ rp,
+                                 const int32_t *__restrict__ ci, const double *__restrict__ val,
+                                 const int32_t *__restrict__ width, const int64_t *__restrict__ off,
+                                 int32_t *__restrict__ sci, double *__restrict__ sval) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t k = r >> 6;
+  const int w = width[k];
+  const int64_t base = off[k] + (r & 63);
+  const int b = rp[r], len = rp[r + 1] - b;
+  for (int q = 0; q < w; ++q) {
+    const bool in = q < len;
+    sci[base + 64 * q] = in ? ci[b + q] : (int32_t)r;
+    sval[base + 64 * q] = in ? val[b + q] : 0.0;
+  }
+}
+
+template <int S>
+__global__ __launch_bounds__(256) void sell_spmm_kernel(SellMat M, const double *__restrict__ X,
+                                                        int64_t ldx, double *__restrict__ Y,
+                                                        int64_t ldy) {
+  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (r >= M.rows) return;
+  double acc[S];
+  sell_row<S>(M, r, X, ldx, acc);
+  double *y = Y + r * ldy;
+#pragma unroll
+  for (int t = 0; t < S; ++t) y[t] = acc[t];
+}
+
+}  // namespace
+
+int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *val,
+               void *buf, hipStream_t st) {
+  SellMat m = sell_view(rows, nnz, buf);
+  const int64_t ns = m.nslices;
+  int32_t *width = const_cast<int32_t *>(m.width);
+  int64_t *off = const_cast<int64_t *>(m.off);
+  sell_width_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(rows, ns, rp, width);
+  HIPOK(hipGetLastError());
+  std::vector<int32_t> hw(ns);
+  std::vector<int64_t> ho(ns);
+  HIPOK(hipMemcpyAsync(hw.data(), width, ns * 4, hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  int64_t tot = 0;
+  for (int64_t k = 0; k < ns; ++k) {
+    ho[k] = tot;
+    tot += 64 * (int64_t)hw[k];
+  }
+  if (tot > sell_capacity(rows, nnz)) return SYLV_ERR_WORKSPACE;
+  HIPOK(hipMemcpyAsync(off, ho.data(), ns * 8, hipMemcpyHostToDevice, st));
+  sell_fill_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(
+      rows, rp, ci, val, width, off, const_cast<int32_t *>(m.ci), const_cast<double *>(m.val));
+  HIPOK(hipGetLastError());
+  HIPOK(hipStreamSynchronize(st));
+  return 0;
+}
+
+int launch_sell_spmm(int s, const SellMat &M, const double *X, int64_t ldx, double *Y, int64_t ldy,
+                     hipStream_t st) {
+  if (M.rows <= 0) return 0;
+  const unsigned g = (unsigned)((M.rows + 255) / 256);
+  switch (s) {
+#define CASE(SS) \
+  case SS: sell_spmm_kernel<SS><<<g, 256, 0, st>>>(M, X, ldx, Y, ldy); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
   HIPOK(hipGetLastError());
   return 0;
 }

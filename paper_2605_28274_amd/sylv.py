@@ -112,6 +112,13 @@ _lib.sylv_get_kernel_stats.argtypes = [c_void_p, POINTER(sylv_kernel_stat), c_in
 _lib.sylv_get_kernel_stats.restype = c_int
 _lib.sylv_kernel_family_name.argtypes = [c_int]
 _lib.sylv_kernel_family_name.restype = ctypes.c_char_p
+_lib.sylv_sell_bytes.argtypes = [POINTER(sylv_csr)]
+_lib.sylv_sell_bytes.restype = c_size_t
+_lib.sylv_sell_build.argtypes = [POINTER(sylv_csr), c_void_p, c_size_t, c_void_p]
+_lib.sylv_sell_build.restype = c_int
+_lib.sylv_sell_spmm.argtypes = [POINTER(sylv_csr), c_void_p, c_int64, c_void_p, c_int64, c_void_p,
+                                c_int64, c_void_p]
+_lib.sylv_sell_spmm.restype = c_int
 _lib.sylv_dgemm.argtypes = [c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_int64,
                             c_void_p, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p]
 _lib.sylv_dgemm.restype = c_int
@@ -255,6 +262,25 @@ def sylv_spmm(csr: sylv_csr, s: int, X, Y, stream=None) -> None:
                         int(Y.stride(0)), _stream(stream))
     if rc != 0:
         raise SylvError(rc, "sylv_spmm")
+
+
+def sylv_sell_bytes(csr: sylv_csr) -> int:
+    return int(_lib.sylv_sell_bytes(byref(csr)))
+
+
+def sylv_sell_build(csr: sylv_csr, buf, stream=None) -> None:
+    rc = _lib.sylv_sell_build(byref(csr), c_void_p(_ptr(buf)),
+                              c_size_t(buf.numel() * buf.element_size()), _stream(stream))
+    if rc != 0:
+        raise SylvError(rc, "sylv_sell_build")
+
+
+def sylv_sell_spmm(csr: sylv_csr, buf, s: int, X, Y, stream=None) -> None:
+    rc = _lib.sylv_sell_spmm(byref(csr), c_void_p(_ptr(buf)), s, c_void_p(_ptr(X)),
+                             int(X.stride(0)), c_void_p(_ptr(Y)), int(Y.stride(0)),
+                             _stream(stream))
+    if rc != 0:
+        raise SylvError(rc, "sylv_sell_spmm")
 
 
 def sylv_csr_transpose(csr: sylv_csr, out_rp, out_ci, out_va, scratch, stream=None) -> None:

@@ -90,3 +90,55 @@ def test_csr_transpose_bit_exact(sylv):
     R = sp.random(3000, 3000, density=0.002, format="csr", random_state=rng)
     R = R + sp.diags(rng.standard_normal(3000))
     _transpose_case(sylv, stencils._canonical(R))
+
+
+def _sell_case(sylv, M, s, expect_ok=True):
+    rp, ci, va = sylv.csr_tensors(M)
+    csr = sylv.make_csr(M.shape[0], rp, ci, va)
+    buf = torch.empty(sylv.sylv_sell_bytes(csr), dtype=torch.uint8, device="cuda")
+    if not expect_ok:
+        with pytest.raises(sylv.SylvError) as ei:
+            sylv.sylv_sell_build(csr, buf)
+        assert ei.value.code == sylv.SYLV_ERR_WORKSPACE
+        return
+    sylv.sylv_sell_build(csr, buf)
+    X = np.random.default_rng(s).standard_normal((M.shape[0], s))
+    dX = _dev(X)
+    dY = torch.empty_like(dX)
+    sylv.sylv_sell_spmm(csr, buf, s, dX, dY)
+    ref = M @ X
+    assert np.max(np.abs(dY.cpu().numpy() - ref)) <= 1e-14 * np.abs(ref).max()
+
+
+@pytest.mark.parametrize("s", [1, 2, 4, 7])
+def test_sell_spmm_stencils(sylv, s):
+    _sell_case(sylv, stencils.cd2d(37, 29, 5.0), s)           # rows not a multiple of 64
+    _sell_case(sylv, stencils.cd3d(16, 8, 9, 10.0), s)
+
+
+def _sell_fits(M):
+    # documented rule: padded size (64 x slice max row length, summed) <= nnz + nnz/4 + 64 slices
+    n = M.shape[0]
+    lens = np.diff(M.indptr)
+    padded = sum(64 * int(lens[k:k + 64].max()) for k in range(0, n, 64))
+    return padded <= M.nnz + M.nnz // 4 + 64 * ((n + 63) // 64) + 64
+
+
+def test_sell_spmm_uneven_rows(sylv):
+    rng = np.random.default_rng(9)
+    n = 1000
+    # one long row: padding beyond the reserved capacity is refused (the solver keeps CSR)
+    R = sp.random(n, n, density=0.001, format="csr", random_state=rng) + sp.identity(n)
+    R = R.tolil()
+    R[5, :400] = 1.0
+    R = stencils._canonical(R.tocsr())
+    assert not _sell_fits(R)
+    _sell_case(sylv, R, 2, expect_ok=False)
+    # rows of 3..6 entries fit and give exact products
+    T = stencils.cd1d(n, 3.0).tolil()
+    for i in range(0, n, 7):
+        T[i, (i + 11) % n] = 0.5
+        T[i, (i + 29) % n] = -0.25
+    T = stencils._canonical(T.tocsr())
+    assert _sell_fits(T)
+    _sell_case(sylv, T, 3)

@@ -1,18 +1,23 @@
 #!/usr/bin/env python3
-"""Benchmark of the factored BiCGSTAB hot path on one MI355X.
+"""Benchmark of the factored Krylov hot path on one MI355X.
 
-Workload: factored BiCGSTAB, FP64, A = 2D convection-diffusion 128 x 128 (Pe = 10), B = 1D
-convection-diffusion m = 8192 (Pe = 10), s = 2, C1, C2 ~ N(0, 1) (seed 1002), tol 1e-8.
+Default workload (`--workload c2`): factored BiCGSTAB, FP64, A = 2D convection-diffusion
+128 x 128 (Pe = 10), B = 1D convection-diffusion m = 8192 (Pe = 10), s = 2, C1, C2 ~ N(0, 1)
+(seed 1002), tol 1e-8. Other workloads (same JSON line, used for measurements and profiles):
+  c1    factored CG, FP64, 1D Laplacians (n+1)^2 tridiag, n = 256, m = 192, s = 1, 200 iterations
+  c3    factored BiCGSTAB, FP64, 3D CD 64^3 x 2D CD 256^2 (Pe = 10), s = 4
+  c5cg  Lyapunov factored CG, FP64, 2D Laplacian 1024^2, s = 1
+  c5bi  Lyapunov factored BiCGSTAB, FP64, 2D CD 1024^2 (Pe = 1), s = 1, 200-iteration window
 
 One step = one pass of the whole path over resident inputs: sylv_create (CSR validation, B^T,
-QR of C1 and C2), sylv_factored_bicgstab to ||R|| <= 1e-8 ||R0||, sylv_get_factors into device
-buffers and sylv_residual_norm (FP64 true residual). `value` is factored iterations per second
-over whole steps; ms_per_step is the time to the 1e-8 solution including setup and the
-residual check.
+sliced-ELLPACK copies, QR of C1 and C2), the factored solve to ||R|| <= tol ||R0|| (or the
+iteration cap), sylv_get_factors into device buffers and sylv_residual_norm (FP64 true
+residual). `value` is factored iterations per second over whole steps; ms_per_step is the time
+to the solution including setup and the residual check.
 
-After the timed region one more (untimed) solve runs with per-kernel HIP-event timing to report
-the roofline fraction of the dominant kernel family; the CPU oracle is timed on a bounded
-sample for `cpu_baseline`.
+After the timed region one more (untimed) solve runs with per-kernel HIP-event timing on the
+solver's stream to report the roofline fraction of the dominant kernel family; the CPU oracle
+is timed on a bounded sample for `cpu_baseline`.
 """
 import argparse
 import json
@@ -28,22 +33,38 @@ PEAK_FP64_TFS = 78.6      # MI355X FP64 (vector and MFMA)
 METRIC = "time-to-1e-8 rel. residual + factored iters/s; mixed/batched vs FP64 plain"
 
 
-def cpu_baseline(p, iters=60):
-    """The oracle as it stands on the host cores: its first `iters` factored BiCGSTAB iterations
-    of the same workload (cost per iteration grows with the rank, so this understates the
-    full-solve time per iteration)."""
-    import numpy as np  # noqa: F401
+def workload(name, max_iter):
+    from workloads import configs
+    if name == "c1":
+        return configs.c1_cg_1d(), "cg"
+    if name == "c2":
+        return configs.c2_bicgstab(max_iter=max_iter or 800), "bicgstab"
+    if name == "c3":
+        return configs.c3_bicgstab(max_iter=max_iter or 400), "bicgstab"
+    if name == "c5cg":
+        return configs.c5_lyap("cg", max_iter=max_iter or 4000), "cg"
+    if name == "c5bi":
+        return configs.c5_lyap("bicgstab", max_iter=max_iter or 200), "bicgstab"
+    raise SystemExit(f"unknown workload {name}")
+
+
+def cpu_baseline(p, method, iters):
+    """The oracle as it stands on the host cores: its first `iters` factored iterations of the
+    same workload (cost per iteration grows with the rank, so this understates the full-solve
+    time per iteration)."""
     from oracle import factored
     try:
         from threadpoolctl import threadpool_info
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
         cores = os.cpu_count() or 1
+    fn = factored.factored_cg if method == "cg" else factored.factored_bicgstab
     t0 = time.perf_counter()
-    _, _, _, info = factored.factored_bicgstab(p.A, p.B, p.C1, p.C2, tol=0.0, max_iter=iters)
+    _, _, _, info = fn(p.A, p.B, p.C1, p.C2, tol=0.0, max_iter=iters, lyapunov=p.lyapunov)
     dt = time.perf_counter() - t0
+    name = "CG" if method == "cg" else "BiCGSTAB"
     return {"value": info["iters"] / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {info['iters']} factored BiCGSTAB iterations of the same workload "
+            "sample": f"first {info['iters']} factored {name} iterations of the same workload "
                       f"({dt:.1f} s on the host)"}
 
 
@@ -52,42 +73,48 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5cg", "c5bi"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--max-iter", type=int, default=800)
+    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--max-iter", type=int, default=0)
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "this library runs one solve on one GPU; --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
     import torch
 
     from paper_2605_28274_amd import sylv
-    from workloads import configs
 
     torch.cuda.set_device(0)
-    p = configs.c2_bicgstab(max_iter=args.max_iter)
+    p, method = workload(args.workload, args.max_iter)
+    cg = method == "cg"
     dev = "cuda"
     rpA, ciA, vaA = sylv.csr_tensors(p.A, dev)
-    rpB, ciB, vaB = sylv.csr_tensors(p.B, dev)
     C1 = torch.as_tensor(p.C1, device=dev)
-    C2 = torch.as_tensor(p.C2, device=dev)
-    prob = sylv.sylv_problem(p.n, p.m, p.s, sylv.make_csr(p.n, rpA, ciA, vaA),
-                             sylv.make_csr(p.m, rpB, ciB, vaB), 0, C1.data_ptr(), p.s,
-                             C2.data_ptr(), p.s)
-    opts = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, args.max_iter, check_every=8)
+    if p.lyapunov:
+        csrB, C2 = sylv.make_csr(p.m, rpA, ciA, vaA), C1
+    else:
+        rpB, ciB, vaB = sylv.csr_tensors(p.B, dev)
+        csrB, C2 = sylv.make_csr(p.m, rpB, ciB, vaB), torch.as_tensor(p.C2, device=dev)
+    prob = sylv.sylv_problem(p.n, p.m, p.s, sylv.make_csr(p.n, rpA, ciA, vaA), csrB,
+                             1 if p.lyapunov else 0, C1.data_ptr(), p.s, C2.data_ptr(), p.s)
+    opts = sylv.default_options(sylv.SYLV_METHOD_CG if cg else sylv.SYLV_METHOD_BICGSTAB,
+                                p.max_iter, check_every=8)
     ws = torch.empty(sylv.sylv_workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
-    rmax = 2 * args.max_iter * p.s
+    rmax = (p.max_iter + 1 if cg else 2 * p.max_iter + 1) * p.s
     V = torch.empty((p.n, rmax), dtype=torch.float64, device=dev)
-    W = torch.empty((p.m, rmax), dtype=torch.float64, device=dev)
+    W = V if p.lyapunov else torch.empty((p.m, rmax), dtype=torch.float64, device=dev)
     Xc = torch.empty((rmax, rmax), dtype=torch.float64, device=dev)
     stream = torch.cuda.current_stream()
+    solve = sylv.sylv_factored_cg if cg else sylv.sylv_factored_bicgstab
 
     def step():
         ctx = sylv.sylv_create(prob, opts, ws, stream.cuda_stream)
-        res = sylv.sylv_factored_bicgstab(ctx, p.tol, args.max_iter)
-        r = res.rank_v
-        sylv.sylv_get_factors(ctx, V[:, :r], Xc[:r, :r], W[:, :r])
+        res = solve(ctx, p.tol, p.max_iter)
+        rv, rw = res.rank_v, res.rank_w
+        sylv.sylv_get_factors(ctx, V[:, :rv], Xc[:rv, :rw], None if p.lyapunov else W[:, :rw])
         _, rel = sylv.sylv_residual_norm(ctx)
         sylv.sylv_destroy(ctx)
         return res, rel
@@ -109,12 +136,14 @@ def main():
     # untimed measurement pass: per-family kernel times with HIP events on the solver's stream
     ctx = sylv.sylv_create(prob, opts, ws, stream.cuda_stream)
     sylv.sylv_set_profiling(ctx, True)
-    res = sylv.sylv_factored_bicgstab(ctx, p.tol, args.max_iter)
+    t1 = time.perf_counter()
+    res = solve(ctx, p.tol, p.max_iter)
+    solve_ms = 1000.0 * (time.perf_counter() - t1)
     stats = sylv.sylv_get_kernel_stats(ctx)
     sylv.sylv_destroy(ctx)
     tot = sum(s["ms"] for s in stats) or 1.0
     dom = max(stats, key=lambda s: s["ms"])
-    if dom["family"] in ("core_op",):
+    if dom["family"] == "core_op":
         bound, unit = "mfma", "TFLOP/s"
         achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
         peak = PEAK_FP64_TFS
@@ -124,8 +153,8 @@ def main():
         peak = PEAK_HBM_GBS
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
                 "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": dom["family"], "avg_launch_us": round(1000 * dom["ms"] /
-                                                                max(dom["launches"], 1), 3),
+                "kernel": dom["family"], "launches": dom["launches"],
+                "avg_launch_us": round(1000 * dom["ms"] / max(dom["launches"], 1), 3),
                 "share_of_kernel_time": round(dom["ms"] / tot, 3)}
     breakdown = {s["family"]: {"ms": round(s["ms"], 3), "launches": s["launches"],
                                "GB/s": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1),
@@ -137,16 +166,18 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": p.meta["workload"] + ", tol 1e-8, seeded N(0,1) C1/C2",
-                   "n": p.n, "m": p.m, "s": p.s, "method": "factored BiCGSTAB",
-                   "iters_per_solve": iters // args.steps, "rank": int(res.rank_v),
-                   "time_to_1e-8_ms": round(ms_per_step, 3),
+        "config": {"workload": p.meta["workload"] + f", tol {p.tol:g}, seeded N(0,1) C1/C2",
+                   "n": p.n, "m": p.m, "s": p.s, "lyapunov": bool(p.lyapunov),
+                   "method": "factored CG" if cg else "factored BiCGSTAB",
+                   "max_iter": p.max_iter, "iters_per_solve": iters // args.steps,
+                   "rank": int(res.rank_v), "time_to_solution_ms": round(ms_per_step, 3),
+                   "profiled_solve_ms": round(solve_ms, 3),
                    "true_rel_res": float(np.max(rels)), "statuses": sorted(set(statuses))},
         "roofline": roofline,
         "kernel_breakdown": breakdown,
     }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p)
+        out["cpu_baseline"] = cpu_baseline(p, method, args.cpu_iters)
     print(json.dumps(out), flush=True)
 
 

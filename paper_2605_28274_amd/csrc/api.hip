@@ -68,8 +68,10 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.Jmax = (op->method == SYLV_METHOD_CG) ? (int64_t)op->max_iter + 2 : 2 * (int64_t)op->max_iter + 2;
   L.rmax = L.Jmax * L.s;
   if (L.rmax > (1 << 20)) return SYLV_ERR_INVALID;
-  L.ldb = round_up(L.rmax, 8);
-  if ((L.ldb * 8) % 4096 == 0) L.ldb += 8;  // avoid power-of-two row strides
+  // multiple of 64 columns (whole 64-wide tiles of the residual Grams stay inside a row),
+  // never a multiple of 4 KiB (row strides that map every row to the same memory channel)
+  L.ldb = round_up(L.rmax, 64);
+  if ((L.ldb * 8) % 4096 == 0) L.ldb += 64;
   L.ldc = round_up(L.rmax, 64);
   const int64_t maxrows = std::max(L.n, L.m);
   L.rc_rows = std::min<int64_t>(maxrows, 16384);
@@ -678,29 +680,40 @@ int sylv_residual_norm(void *ctx, double *abs_res, double *rel_res) {
   double *GVE = at<double>(c, L.off_GVE), *GWE = at<double>(c, L.off_GWE);
   double *GEEa = at<double>(c, L.off_GEEa), *GEEb = at<double>(c, L.off_GEEb);
   double *Lx = at<double>(c, L.off_Lx), *M1 = at<double>(c, L.off_M1), *M2 = at<double>(c, L.off_M2);
-  // Gram accumulation over row chunks of one side.
+  // Gram accumulation over row chunks of one side: E = M V_p - V_q H (banded for block
+  // Lanczos, a Hessenberg GEMM for block Arnoldi), then V^T V and E^T E (lower tiles, mirrored
+  // at the end) and V^T E.
+  const bool band = (L.method == SYLV_METHOD_CG);
   auto side_grams = [&](const SideDesc &sd, const double *Hm, double *Gbb, double *Gbe,
                         double *Gee) -> int {
-    const double *Vb = sd.basis;
+    double *Vb = sd.basis;
+    int ee;
+    if (!band) {
+      const int qk = (int)std::min<int64_t>(round_up(q, 32), ldb);
+      if ((ee = launch_zero_cols(sd.rows, Vb, ldb, (int)q, qk, st))) return ee;
+    }
     for (int64_t r0 = 0; r0 < sd.rows; r0 += L.rc_rows) {
       const int64_t r1 = std::min(sd.rows, r0 + L.rc_rows), nr = r1 - r0;
       const double beta = (r0 == 0) ? 0.0 : 1.0;
-      int ee;
-      // E = M V_p (rows r0..r1)
-      if ((ee = launch_spmm_rows(s, r0, r1, sd.rp, sd.ci, sd.val, Vb, ldb, (int)p, E, ldb, st)))
-        return ee;
-      // E -= V_q(rows) H(0:q, 0:p)
-      if ((ee = launch_gemm(nr, p, q, -1.0, Vb + r0 * ldb, ldb, 1, Hm, ldc, 1, 1.0, E, ldb, st)))
-        return ee;
-      // Gbb += V_q^T V_q, Gbe += V_q^T E, Gee += E^T E
-      if ((ee = launch_gemm(q, q, nr, 1.0, Vb + r0 * ldb, 1, ldb, Vb + r0 * ldb, ldb, 1, beta, Gbb,
-                            ldc, st)))
-        return ee;
-      if ((ee = launch_gemm(q, p, nr, 1.0, Vb + r0 * ldb, 1, ldb, E, ldb, 1, beta, Gbe, ldc, st)))
-        return ee;
-      if ((ee = launch_gemm(p, p, nr, 1.0, E, 1, ldb, E, ldb, 1, beta, Gee, ldc, st))) return ee;
+      if (band) {
+        if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, Vb, ldb, (int)p, (int)q, s, Hm,
+                                     ldc, M2, ldc, r0 == 0, E, ldb, st)))
+          return ee;
+      } else {
+        // E = M V_p (rows r0..r1), then E -= V_q(rows) H(0:q, 0:p)
+        if ((ee = launch_spmm_rows(s, r0, r1, sd.rp, sd.ci, sd.val, Vb, ldb, (int)p, E, ldb, st)))
+          return ee;
+        if ((ee = launch_defect_gemm(nr, (int)p, (int)q, s, Vb + r0 * ldb, ldb, Hm, ldc, E, ldb,
+                                     st)))
+          return ee;
+      }
+      const double *Vr = Vb + r0 * ldb;
+      if ((ee = launch_gram(q, q, nr, Vr, ldb, Vr, ldb, beta, Gbb, ldc, true, st))) return ee;
+      if ((ee = launch_gram(q, p, nr, Vr, ldb, E, ldb, beta, Gbe, ldc, false, st))) return ee;
+      if ((ee = launch_gram(p, p, nr, E, ldb, E, ldb, beta, Gee, ldc, true, st))) return ee;
     }
-    return 0;
+    if ((ee = launch_mirror(q, Gbb, ldc, st))) return ee;
+    return launch_mirror(p, Gee, ldc, st);
   };
   if ((e = side_grams(c->sv, c->H, GVV, GVE, GEEa))) return e;
   const double *GWWp = GVV, *GWEp = GVE, *GEEbp = GEEa;

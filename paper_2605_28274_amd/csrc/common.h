@@ -538,6 +538,23 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
 // Core Sylvester operator eq. (3.11) on dense padded cores: Q = [H P, 0] + [P G^T; 0] where
 // P is p x p and H, G are (p+s) x p (Hessenberg), all ldc-strided; the result is written over
 // the full (p+s) region rounded up to the tile size (entries outside are exact zeros).
+// Residual evaluation (dense.hip, residual.hip).
+// C (+)= A^T B, A: K x M, B: K x N row-major (lda >= roundup(M, 64), ldb >= roundup(N, 64));
+// `lower` computes the tiles on and below the diagonal only (M == N; launch_mirror completes).
+int launch_gram(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+                int64_t ldb, double beta, double *C, int64_t ldc, bool lower, hipStream_t st);
+int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st);
+// E(0:rows, 0:p) -= V(0:rows, 0:q) H(0:q, 0:p), H block upper Hessenberg; V columns
+// [q, roundup(q, 32)) must be finite.
+int launch_defect_gemm(int64_t rows, int p, int q, int s, const double *V, int64_t ldv,
+                       const double *H, int64_t ldh, double *E, int64_t lde, hipStream_t st);
+int launch_zero_cols(int64_t rows, double *V, int64_t ldv, int c0, int c1, hipStream_t st);
+// E(r - r0, 0:p) = M(r, :) V(:, 0:p) - V(r, 0:q) H(0:q, 0:p) for block-tridiagonal H; `pack`
+// first writes the band of H into Hb (3s x ldhb).
+int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
+                       const double *val, const double *V, int64_t ldv, int p, int q, int s,
+                       const double *H, int64_t ldh, double *Hb, int64_t ldhb, bool pack,
+                       double *E, int64_t lde, hipStream_t st);
 int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,
                    int64_t ldc, const int *done, hipStream_t st);
 int launch_csr_validate(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, int *flag,

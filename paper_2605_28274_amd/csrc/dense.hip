@@ -118,53 +118,57 @@ __device__ __forceinline__ void store_cols(Slab &dst, const RegSlab &r) {
   }
 }
 
-template <bool B_FROM_ROWS>
-__device__ __forceinline__ void load_slab(const double *A, const double *B, int64_t ld, int l,
-                                          RegSlab &ra, RegSlab &rb) {
-  load_rows(A + l, ld, ra);
-  if (B_FROM_ROWS) load_rows(B + l, ld, rb);
-  else load_cols(B + (int64_t)l * ld, ld, rb);
+// Operand slabs: A(i, l) is A[i * lda + l] ("rows", A_T = false) or A[l * lda + i] (A_T = true,
+// a K x M row-major matrix read transposed); B(l, j) is B[l * ldb + j] ("cols", B_ROWS = false)
+// or B[j * ldb + l] (B_ROWS = true).
+template <bool A_T, bool B_ROWS>
+__device__ __forceinline__ void load_slab(const double *A, int64_t lda, const double *B,
+                                          int64_t ldb, int64_t l, RegSlab &ra, RegSlab &rb) {
+  if (A_T) load_cols(A + l * lda, lda, ra);
+  else load_rows(A + l, lda, ra);
+  if (B_ROWS) load_rows(B + l, ldb, rb);
+  else load_cols(B + l * ldb, ldb, rb);
 }
 
-template <bool B_FROM_ROWS>
+template <bool A_T, bool B_ROWS>
 __device__ __forceinline__ void store_slab(Smem &sm, int buf, const RegSlab &ra,
                                            const RegSlab &rb) {
-  store_rows(sm.As[buf], ra);
-  if (B_FROM_ROWS) store_rows(sm.Bs[buf], rb);
+  if (A_T) store_cols(sm.As[buf], ra);
+  else store_rows(sm.As[buf], ra);
+  if (B_ROWS) store_rows(sm.Bs[buf], rb);
   else store_cols(sm.Bs[buf], rb);
 }
 
-// One pipelined product over K slabs [l_begin, l_end) (multiples of BK):
-//   B_FROM_ROWS == false: acc += A(i0.., l) * B(l, j0..)  with B row-major (cols slab)
-//   B_FROM_ROWS == true : acc += A(i0.., l) * B(j0.., l)^T (B given by its rows: rows slab)
-// Global loads run two slabs ahead of the MFMAs (two register sets, the loop unrolled by two so
-// they stay static); LDS is double-buffered with one barrier per slab.
-template <bool B_FROM_ROWS>
+// One pipelined product over K slabs [l_begin, l_end) (multiples of BK): acc += A(i0.., l) B(l, j0..)
+// with the operand forms above (A, B point at row/column i0 and j0). Global loads run two slabs
+// ahead of the MFMAs (two register sets, the loop unrolled by two so they stay static); LDS is
+// double-buffered with one barrier per slab.
+template <bool A_T, bool B_ROWS>
 __device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn,
-                                          const double *A, const double *B, int64_t ld,
-                                          int l_begin, int l_end) {
+                                          const double *A, int64_t lda, const double *B,
+                                          int64_t ldb, int64_t l_begin, int64_t l_end) {
   if (l_begin >= l_end) return;
-  const int nsl = (l_end - l_begin) / BK;
+  const int64_t nsl = (l_end - l_begin) / BK;
   // Prefetches are unconditional (a slab index past the end re-reads the last slab, always in
   // bounds), so the number of loads in flight is the same on every path and the wait before an
   // LDS fill only covers the older register set.
-  auto lslab = [&](int t) { return l_begin + (t < nsl ? t : nsl - 1) * BK; };
+  auto lslab = [&](int64_t t) { return l_begin + (t < nsl ? t : nsl - 1) * BK; };
   RegSlab ra0, rb0, ra1, rb1;
-  load_slab<B_FROM_ROWS>(A, B, ld, lslab(0), ra0, rb0);
-  load_slab<B_FROM_ROWS>(A, B, ld, lslab(1), ra1, rb1);
+  load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(0), ra0, rb0);
+  load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(1), ra1, rb1);
   __syncthreads();  // previous users of the LDS buffers are done
-  store_slab<B_FROM_ROWS>(sm, 0, ra0, rb0);
+  store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0);
   __syncthreads();
   // invariant at slab t: LDS[t % 2] holds slab t; register set (t+1) % 2 holds slab t+1
-  int t = 0;
+  int64_t t = 0;
   for (; t + 1 < nsl; t += 2) {
-    load_slab<B_FROM_ROWS>(A, B, ld, lslab(t + 2), ra0, rb0);
+    load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(t + 2), ra0, rb0);
     mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
-    store_slab<B_FROM_ROWS>(sm, 1, ra1, rb1);
+    store_slab<A_T, B_ROWS>(sm, 1, ra1, rb1);
     __syncthreads();
-    load_slab<B_FROM_ROWS>(A, B, ld, lslab(t + 3), ra1, rb1);
+    load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(t + 3), ra1, rb1);
     mma_slab(sm.As[1], sm.Bs[1], acc, wm, wn);
-    store_slab<B_FROM_ROWS>(sm, 0, ra0, rb0);
+    store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0);
     __syncthreads();
   }
   if (t < nsl) mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);  // odd slab count: the last slab
@@ -184,13 +188,14 @@ __device__ __forceinline__ void core_op_tile(Smem &sm, int s, int p, const doubl
   if (j0 < p) {
     int ls = (i0 / s - 1) * s;
     ls = ls < 0 ? 0 : ls / BK * BK;
-    pipelined<false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, P + j0, ldc, ls, pk);
+    pipelined<false, false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, ldc, P + j0, ldc, ls, pk);
   }
   // [P G^T; 0]: rows of G in this tile start at column block (j0/s - 1)
   if (i0 < p) {
     int ls = (j0 / s - 1) * s;
     ls = ls < 0 ? 0 : ls / BK * BK;
-    pipelined<true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, G + (int64_t)j0 * ldc, ldc, ls, pk);
+    pipelined<false, true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, ldc, G + (int64_t)j0 * ldc, ldc,
+                           ls, pk);
   }
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
     Q[(int64_t)(i0 + ii) * ldc + j0 + jj] = v;
@@ -209,6 +214,110 @@ __global__ __launch_bounds__(256) void core_op_kernel(int s, int p, int T,
   const int t1 = blockIdx.x, t2 = T * T - 1 - t1;
   core_op_tile(sm, s, p, H, G, P, Q, ldc, (t1 / T) * BM, (t1 % T) * BN, wm, wn);
   if (t2 != t1) core_op_tile(sm, s, p, H, G, P, Q, ldc, (t2 / T) * BM, (t2 % T) * BN, wm, wn);
+}
+
+// ---- tall-skinny Gram C (+)= A^T B over K rows (residual evaluation) ----
+// A: K x M and B: K x N row-major with row strides lda, ldb; columns up to the next multiple of
+// 64 of M (N) must lie inside the rows (lda >= roundup(M, 64)); K is a multiple of BK. With
+// `lower`, only tiles I >= J are computed (symmetric A^T A; mirror_kernel fills the rest).
+__device__ __forceinline__ void tri_tile(int64_t b, int &I, int &J) {
+  int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > b) --i;
+  while ((i + 1) * (i + 2) / 2 <= b) ++i;
+  I = (int)i;
+  J = (int)(b - i * (i + 1) / 2);
+}
+
+__global__ __launch_bounds__(256) void gram_kernel(int64_t M, int64_t N, int64_t K,
+                                                   const double *__restrict__ A, int64_t lda,
+                                                   const double *__restrict__ B, int64_t ldb,
+                                                   double beta, double *__restrict__ C,
+                                                   int64_t ldc, int tiles_n, int lower) {
+  __shared__ Smem sm;
+  int I, J;
+  if (lower) tri_tile(blockIdx.x, I, J);
+  else {
+    I = (int)(blockIdx.x / tiles_n);
+    J = (int)(blockIdx.x % tiles_n);
+  }
+  const int64_t i0 = (int64_t)I * BM, j0 = (int64_t)J * BN;
+  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  WaveAcc acc;
+  zero_acc(acc);
+  pipelined<true, false>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, 0, K);
+  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
+    const int64_t gi = i0 + ii, gj = j0 + jj;
+    if (gi < M && gj < N) {
+      double *c = C + gi * ldc + gj;
+      *c = (beta == 0.0) ? v : *c + v;
+    }
+  });
+}
+
+// C[i][j] = C[j][i] for i < j < M (upper from lower).
+__global__ __launch_bounds__(256) void mirror_kernel(int64_t M, double *__restrict__ C,
+                                                     int64_t ldc) {
+  for (int64_t i = blockIdx.x; i < M; i += gridDim.x)
+    for (int64_t j = i + 1 + threadIdx.x; j < M; j += 256) C[i * ldc + j] = C[j * ldc + i];
+}
+
+// Basis defect rows: E(i, 0:p) -= V(i, 0:q) H(0:q, 0:p) for i < rows, with H block upper
+// Hessenberg (H(l, c) = 0 when block(l) > block(c) + 1), so output tile J only needs
+// l < (block(j0 + 63) + 2) s. V columns in [q, roundup(q, BK)) must be finite (they meet zero
+// rows of H); V rows past `rows` are never read (row index clamped, results masked).
+__global__ __launch_bounds__(256) void defect_gemm_kernel(int64_t rows, int p, int q, int s,
+                                                          const double *__restrict__ V,
+                                                          int64_t ldv,
+                                                          const double *__restrict__ H,
+                                                          int64_t ldh, double *__restrict__ E,
+                                                          int64_t lde) {
+  __shared__ Smem sm;
+  const int64_t i0 = (int64_t)blockIdx.y * BM;
+  const int j0 = blockIdx.x * BN;
+  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  const int jl = (j0 + BN - 1 < p - 1) ? j0 + BN - 1 : p - 1;
+  int le = (jl / s + 2) * s;
+  le = le < q ? le : q;
+  le = (le + BK - 1) / BK * BK;
+  WaveAcc acc;
+  zero_acc(acc);
+  if (i0 + BM <= rows) {
+    pipelined<false, false>(sm, acc, wm, wn, V + i0 * ldv, ldv, H + j0, ldh, 0, le);
+  } else {
+    // last row tile: stage through a clamped copy of the row pointer range
+    const int64_t last = rows - 1;
+    for (int64_t l0 = 0; l0 < le; l0 += BK) {
+      for (int e = threadIdx.x; e < BM * BK; e += 256) {
+        const int ii = e / BK, kk = e % BK;
+        const int64_t gi = i0 + ii < last ? i0 + ii : last;
+        sm.As[0][kk][ii] = V[gi * ldv + l0 + kk];
+      }
+      for (int e = threadIdx.x; e < BK * BN; e += 256) {
+        const int kk = e / BN, jj = e % BN;
+        sm.Bs[0][kk][jj] = H[(l0 + kk) * ldh + j0 + jj];
+      }
+      __syncthreads();
+      mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+      __syncthreads();
+    }
+  }
+  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
+    const int64_t gi = i0 + ii;
+    const int gj = j0 + jj;
+    if (gi < rows && gj < p) E[gi * lde + gj] -= v;
+  });
+}
+
+// V(i, c0:c1) = 0 for all rows (finite padding columns before defect_gemm_kernel).
+__global__ __launch_bounds__(256) void zero_cols_kernel(int64_t rows, double *V, int64_t ldv,
+                                                        int c0, int c1) {
+  const int w = c1 - c0;
+  const int64_t total = rows * w;
+  for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * 256) {
+    const int64_t i = e / w;
+    V[i * ldv + c0 + (e - i * w)] = 0.0;
+  }
 }
 
 // ---- generic strided GEMM with bounds masks (residual Grams and core products) ----
@@ -272,6 +381,56 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
   if (M <= 0 || N <= 0) return 0;
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
   gemm_kernel<<<grid, 256, 0, st>>>(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_gram(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+                int64_t ldb, double beta, double *C, int64_t ldc, bool lower, hipStream_t st) {
+  if (M <= 0 || N <= 0) return 0;
+  if (lower && M != N) return SYLV_ERR_INVALID;
+  const int64_t TM = (M + BM - 1) / BM, TN = (N + BN - 1) / BN;
+  if (lda < TM * BM || ldb < TN * BN) return SYLV_ERR_INVALID;
+  const int64_t kb = K / BK * BK;
+  if (kb > 0) {
+    const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
+    gram_kernel<<<(unsigned)tiles, 256, 0, st>>>(M, N, kb, A, lda, B, ldb, beta, C, ldc, (int)TN,
+                                                 lower ? 1 : 0);
+    HIPOK(hipGetLastError());
+  }
+  if (K > kb) {
+    // rows past the last full slab (masked generic kernel); it fills the full matrix
+    int e = launch_gemm(M, N, K - kb, 1.0, A + kb * lda, 1, lda, B + kb * ldb, ldb, 1,
+                        kb > 0 ? 1.0 : beta, C, ldc, st);
+    if (e) return e;
+  }
+  return 0;
+}
+
+int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st) {
+  if (M <= 1) return 0;
+  mirror_kernel<<<(unsigned)std::min<int64_t>(M, 1024), 256, 0, st>>>(M, C, ldc);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_defect_gemm(int64_t rows, int p, int q, int s, const double *V, int64_t ldv,
+                       const double *H, int64_t ldh, double *E, int64_t lde, hipStream_t st) {
+  if (rows <= 0 || p <= 0) return 0;
+  const int qk = (q + BK - 1) / BK * BK;
+  const int pn = (p + BN - 1) / BN * BN;
+  if (ldv < qk || ldh < pn) return SYLV_ERR_INVALID;
+  const dim3 grid((unsigned)(pn / BN), (unsigned)((rows + BM - 1) / BM));
+  defect_gemm_kernel<<<grid, 256, 0, st>>>(rows, p, q, s, V, ldv, H, ldh, E, lde);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_zero_cols(int64_t rows, double *V, int64_t ldv, int c0, int c1, hipStream_t st) {
+  if (rows <= 0 || c1 <= c0) return 0;
+  const int64_t total = rows * (c1 - c0);
+  zero_cols_kernel<<<(unsigned)std::min<int64_t>((total + 255) / 256, 8192), 256, 0, st>>>(
+      rows, V, ldv, c0, c1);
   HIPOK(hipGetLastError());
   return 0;
 }

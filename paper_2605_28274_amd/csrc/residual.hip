@@ -1,6 +1,7 @@
-// Small kernels of the true-residual evaluation: the residual core R^ = [R0 0; 0 0] - L(X)
-// and Frobenius inner products <A, B> = tr(A^T B) of strided matrices (deterministic two-stage
-// reduction, result written to device memory).
+// Kernels of the true-residual evaluation: the basis defect E = M V_p - V_{p+s} H for the
+// block-tridiagonal H of block Lanczos (fused with the sparse product), the residual core
+// R^ = [R0 0; 0 0] - L(X), and Frobenius inner products <A, B> = tr(A^T B) of strided matrices
+// (deterministic two-stage reduction, result written to device memory).
 #include "common.h"
 
 namespace {
@@ -31,6 +32,59 @@ __global__ __launch_bounds__(TPB) void rhat_kernel(int s, int q, const double *_
   Rh[(int64_t)i * ldc + j] = v;
 }
 
+// Hb[t][c] = H[(blk(c) - 1) s + t][c], t < 3s: the three nonzero s x s blocks of column c of a
+// block-tridiagonal H, stored so that consecutive columns are consecutive in memory.
+__global__ __launch_bounds__(TPB) void band_pack_kernel(int p, int q, int s,
+                                                        const double *__restrict__ H, int64_t ldh,
+                                                        double *__restrict__ Hb, int64_t ldhb) {
+  const int c = blockIdx.x * TPB + threadIdx.x;
+  if (c >= p) return;
+  const int base = (c / s - 1) * s;
+  for (int t = 0; t < 3 * s; ++t) {
+    const int row = base + t;
+    Hb[(int64_t)t * ldhb + c] = (row >= 0 && row < q) ? H[(int64_t)row * ldh + c] : 0.0;
+  }
+}
+
+// E(r - r0, c) = (M V)(r, c) - sum_t V(r, base(c) + t) Hb(t, c) for c < p (one wave per row,
+// lanes across columns; only rows 0 <= base + t < q of the band enter).
+__global__ __launch_bounds__(TPB) void defect_band_kernel(
+    int64_t r0, int64_t r1, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
+    const double *__restrict__ val, const double *__restrict__ V, int64_t ldv, int p, int q, int s,
+    const double *__restrict__ Hb, int64_t ldhb, double *__restrict__ E, int64_t lde) {
+  const int64_t r = r0 + (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
+  if (r >= r1) return;
+  const int b = rp[r], e = rp[r + 1];
+  const double *vr = V + r * ldv;
+  double *er = E + (r - r0) * lde;
+  for (int j0 = 0; j0 < p; j0 += 4 * WAVE) {
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int z = b; z < e; ++z) {
+      const double a = val[z];
+      const double *x = V + (int64_t)ci[z] * ldv;
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int j = j0 + u * WAVE + lane;
+        if (j < p) acc[u] = fma(a, x[j], acc[u]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * WAVE + lane;
+      if (j < p) {
+        const int base = (j / s - 1) * s;
+        double v = acc[u];
+        for (int t = 0; t < 3 * s; ++t) {
+          const int row = base + t;
+          if (row >= 0 && row < q) v = fma(-vr[row], Hb[(int64_t)t * ldhb + j], v);
+        }
+        er[j] = v;
+      }
+    }
+  }
+}
+
 }  // namespace
 
 int launch_dot(int64_t M, int64_t N, const double *A, int64_t lda, const double *B, int64_t ldb,
@@ -48,6 +102,22 @@ int launch_rhat(int s, int q, const double *Lx, const double *R0, double *Rh, in
   const int64_t tot = (int64_t)q * q;
   if (tot == 0) return 0;
   rhat_kernel<<<(unsigned)((tot + TPB - 1) / TPB), TPB, 0, st>>>(s, q, Lx, R0, Rh, ldc);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
+                       const double *val, const double *V, int64_t ldv, int p, int q, int s,
+                       const double *H, int64_t ldh, double *Hb, int64_t ldhb, bool pack,
+                       double *E, int64_t lde, hipStream_t st) {
+  if (p <= 0 || r1 <= r0) return 0;
+  if (pack) {
+    band_pack_kernel<<<(unsigned)((p + TPB - 1) / TPB), TPB, 0, st>>>(p, q, s, H, ldh, Hb, ldhb);
+    HIPOK(hipGetLastError());
+  }
+  const int64_t nr = r1 - r0;
+  defect_band_kernel<<<(unsigned)((nr + 3) / 4), TPB, 0, st>>>(r0, r1, rp, ci, val, V, ldv, p, q, s,
+                                                               Hb, ldhb, E, lde);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -46,6 +46,14 @@ enum {
 
 enum { SYLV_METHOD_CG = 0, SYLV_METHOD_BICGSTAB = 1 };
 
+/* Storage precision of the Krylov bases. SYLV_FP64: everything in FP64. SYLV_MIXED_FP32: the
+ * bases V, W (and the compact panels the sparse products read) are stored in FP32, halving the
+ * dominant memory traffic of the block Arnoldi/Lanczos steps; products are accumulated in FP64
+ * and the H, G blocks, the cores, the scalars and the residual evaluation stay FP64. The
+ * recurrence then reaches a true-residual floor of roughly the FP32 unit roundoff times the
+ * conditioning of the operator; sylv_refine_* recovers full accuracy (outer refinement). */
+enum { SYLV_FP64 = 0, SYLV_MIXED_FP32 = 1 };
+
 /* Compressed sparse row matrix: rows x rows, int32 row_ptr (rows + 1 entries, row_ptr[0] = 0)
  * and col_idx (nnz entries, sorted and unique within each row, 0 <= col < rows), float64
  * values (nnz). Device pointers, borrowed until sylv_destroy. */
@@ -77,7 +85,9 @@ typedef struct {
  * iteration and by 2s per BiCGSTAB iteration). check_every: the host waits for the device's
  * convergence flag every this many iterations (iterations enqueued after convergence do no
  * work). closure_tol: a new basis block whose norm after orthogonalization is at most
- * closure_tol times ||M V_j||_F is replaced by a zero block (Krylov space exhausted).
+ * closure_tol times ||M V_j||_F is replaced by a zero block (Krylov space exhausted); <= 0
+ * selects the default of the precision (1e-12 for FP64, 1e-6 for FP32 bases).
+ * precision: SYLV_FP64 or SYLV_MIXED_FP32 (storage of the bases, see above).
  * sylv_default_options() fills sensible values. */
 typedef struct {
   int method;
@@ -85,6 +95,7 @@ typedef struct {
   int check_every;
   int record_history;
   double closure_tol;
+  int precision;
 } sylv_options;
 
 /* Outcome of one solve. rank_v / rank_w: number of columns of the returned V and W;

@@ -21,7 +21,8 @@ constexpr size_t ALIGN = 256;
 struct Layout {
   // sizes
   int64_t n = 0, m = 0, s = 0, Jmax = 0, rmax = 0, ldb = 0, ldc = 0, rc_rows = 0;
-  int lyap = 0, method = 0, max_iter = 0;
+  int lyap = 0, method = 0, max_iter = 0, fp32 = 0;
+  int64_t esz = 8;  // bytes per basis element
   size_t partial_cap = 0;
   // byte offsets into the workspace
   size_t off_V, off_W, off_H, off_G, off_X, off_R, off_P, off_Q, off_S, off_T;
@@ -53,6 +54,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   if (pb->lyapunov && pb->n != pb->m) return SYLV_ERR_INVALID;
   if (op->max_iter < 1 || (op->method != SYLV_METHOD_CG && op->method != SYLV_METHOD_BICGSTAB))
     return SYLV_ERR_INVALID;
+  if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32) return SYLV_ERR_INVALID;
   if (!pb->C1 || pb->ldc1 < pb->s) return SYLV_ERR_INVALID;
   if (!pb->lyapunov && (!pb->C2 || pb->ldc2 < pb->s)) return SYLV_ERR_INVALID;
   int e = check_csr_header(pb->A, pb->n);
@@ -64,6 +66,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.lyap = pb->lyapunov ? 1 : 0;
   L.method = op->method;
   L.max_iter = op->max_iter;
+  L.fp32 = op->precision == SYLV_MIXED_FP32;
+  L.esz = L.fp32 ? 4 : 8;
   // blocks generated: CG k+2 after k+1 iterations; BiCGSTAB 2k+3
   L.Jmax = (op->method == SYLV_METHOD_CG) ? (int64_t)op->max_iter + 2 : 2 * (int64_t)op->max_iter + 2;
   L.rmax = L.Jmax * L.s;
@@ -71,7 +75,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   // multiple of 64 columns (whole 64-wide tiles of the residual Grams stay inside a row),
   // never a multiple of 4 KiB (row strides that map every row to the same memory channel)
   L.ldb = round_up(L.rmax, 64);
-  if ((L.ldb * 8) % 4096 == 0) L.ldb += 64;
+  if ((L.ldb * L.esz) % 4096 == 0) L.ldb += 64;
   L.ldc = round_up(L.rmax, 64);
   const int64_t maxrows = std::max(L.n, L.m);
   L.rc_rows = std::min<int64_t>(maxrows, 16384);
@@ -82,8 +86,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
        arnoldi_partials_needed((int)L.s, L.n, L.lyap ? 0 : L.m, L.ldb)});
   size_t cur = 0;
   const size_t c2 = (size_t)L.ldc * L.ldc * sizeof(double);
-  L.off_V = bump(cur, (size_t)L.n * L.ldb * 8);
-  L.off_W = L.lyap ? L.off_V : bump(cur, (size_t)L.m * L.ldb * 8);
+  L.off_V = bump(cur, (size_t)L.n * L.ldb * L.esz);
+  L.off_W = L.lyap ? L.off_V : bump(cur, (size_t)L.m * L.ldb * L.esz);
   L.off_H = bump(cur, c2);
   L.off_G = L.lyap ? L.off_H : bump(cur, c2);
   L.off_X = bump(cur, c2);
@@ -125,8 +129,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.off_Lx = bump(cur, c2);
   L.off_M1 = bump(cur, c2);
   L.off_M2 = bump(cur, c2);
-  L.off_panV = bump(cur, (size_t)2 * L.n * L.s * 8);
-  L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * 8);
+  L.off_panV = bump(cur, (size_t)2 * L.n * L.s * L.esz);
+  L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * L.esz);
   L.off_sellA = bump(cur, sell_bytes(L.n, pb->A.nnz));
   L.off_sellB = L.lyap ? L.off_sellA : bump(cur, sell_bytes(L.m, pb->B.nnz));
   L.off_dots = bump(cur, 16 * 8);
@@ -252,15 +256,16 @@ int begin_solve(Ctx *c, double tol, int max_iter, int method) {
   for (double *z : zero)
     if (z) HIPOK(hipMemsetAsync(z, 0, c2, c->st));
   // the compact copy of block 1 (V_1, W_1) is the first SpMM input; earlier solves reused it
-  HIPOK(hipMemcpy2DAsync(c->sv.panel[0], L.s * 8, c->sv.basis, L.ldb * 8, L.s * 8, L.n,
+  const size_t e = (size_t)L.esz;
+  HIPOK(hipMemcpy2DAsync(c->sv.panel[0], L.s * e, c->sv.basis, L.ldb * e, L.s * e, L.n,
                          hipMemcpyDeviceToDevice, c->st));
   if (!L.lyap)
-    HIPOK(hipMemcpy2DAsync(c->sw.panel[0], L.s * 8, c->sw.basis, L.ldb * 8, L.s * 8, L.m,
+    HIPOK(hipMemcpy2DAsync(c->sw.panel[0], L.s * e, c->sw.basis, L.ldb * e, L.s * e, L.m,
                            hipMemcpyDeviceToDevice, c->st));
   // R0 = R_L R_R^T from the first-block factors kept since sylv_create
-  int e = launch_setup_scalars((int)L.s, c->RL, c->RR, c->R, c->P, c->Rt, L.ldc, tol, c->ds,
-                               c->st);
-  if (e) return e;
+  int err = launch_setup_scalars((int)L.s, c->RL, c->RR, c->R, c->P, c->Rt, L.ldc, tol, c->ds,
+                                 c->st);
+  if (err) return err;
   c->solved = 0;
   c->method = method;
   c->max_iter_run = max_iter;
@@ -314,7 +319,8 @@ void sylv_default_options(sylv_options *opt) {
   opt->max_iter = 200;
   opt->check_every = 8;
   opt->record_history = 1;
-  opt->closure_tol = 1e-12;
+  opt->closure_tol = 0.0;  // precision default
+  opt->precision = SYLV_FP64;
 }
 
 size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt) {
@@ -351,7 +357,7 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
   c->st = reinterpret_cast<hipStream_t>(stream);
   c->A = pb->A;
   c->B = pb->B;
-  c->closure_tol = op->closure_tol > 0 ? op->closure_tol : 1e-12;
+  c->closure_tol = op->closure_tol > 0 ? op->closure_tol : (L.fp32 ? 1e-6 : 1e-12);
   c->check_every = op->check_every > 0 ? op->check_every : 8;
   c->record_history = op->record_history;
   c->ws = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(workspace) + ALIGN - 1) / ALIGN * ALIGN);
@@ -410,16 +416,17 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
                                   c->btrp, c->btci, c->btval, at<void>(c, L.off_tscr), st)))
       return fail(e);
   }
+  char *panv = at<char>(c, L.off_panV), *panw = at<char>(c, L.off_panW);
   c->sv = SideDesc{L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
-                   at<double>(c, L.off_V), L.ldb, c->H, at<double>(c, L.off_U),
+                   at<void>(c, L.off_V), L.ldb, c->H, at<double>(c, L.off_U),
                    at<double>(c, L.off_coefV), c->ssv,
-                   {at<double>(c, L.off_panV), at<double>(c, L.off_panV) + L.n * L.s}};
+                   {panv, panv + L.n * L.s * L.esz}, L.fp32, SellMat{}};
   if (L.lyap) {
     c->sw = c->sv;
   } else {
-    c->sw = SideDesc{L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<double>(c, L.off_W), L.ldb,
+    c->sw = SideDesc{L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<void>(c, L.off_W), L.ldb,
                      c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw,
-                     {at<double>(c, L.off_panW), at<double>(c, L.off_panW) + L.m * L.s}};
+                     {panw, panw + L.m * L.s * L.esz}, L.fp32, SellMat{}};
   }
   // SELL copies of A and B^T for the Krylov SpMM (CSR stays in use if the padding is large)
   c->sv.sell = SellMat{};
@@ -623,14 +630,18 @@ int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx,
   if (rank_w) *rank_w = r;
   if (r == 0) return 0;
   if ((V && ldv < r) || (Xc && ldx < r) || (W && ldw < r)) return SYLV_ERR_INVALID;
-  if (V)
-    HIPOK(hipMemcpy2DAsync(V, ldv * 8, c->sv.basis, L.ldb * 8, r * 8, L.n, hipMemcpyDeviceToDevice,
-                           c->st));
+  auto copy_basis = [&](double *dst, int64_t ldd, const SideDesc &sd) -> int {
+    if (L.fp32)
+      return launch_widen(sd.rows, r, static_cast<const float *>(sd.basis), L.ldb, dst, ldd, c->st);
+    HIPOK(hipMemcpy2DAsync(dst, ldd * 8, sd.basis, L.ldb * 8, r * 8, sd.rows,
+                           hipMemcpyDeviceToDevice, c->st));
+    return 0;
+  };
+  int e;
+  if (V && (e = copy_basis(V, ldv, c->sv))) return e;
   if (Xc)
     HIPOK(hipMemcpy2DAsync(Xc, ldx * 8, c->X, L.ldc * 8, r * 8, r, hipMemcpyDeviceToDevice, c->st));
-  if (W)
-    HIPOK(hipMemcpy2DAsync(W, ldw * 8, c->sw.basis, L.ldb * 8, r * 8, L.m, hipMemcpyDeviceToDevice,
-                           c->st));
+  if (W && (e = copy_basis(W, ldw, c->sw))) return e;
   HIPOK(hipStreamSynchronize(c->st));
   return 0;
 }
@@ -686,31 +697,36 @@ int sylv_residual_norm(void *ctx, double *abs_res, double *rel_res) {
   const bool band = (L.method == SYLV_METHOD_CG);
   auto side_grams = [&](const SideDesc &sd, const double *Hm, double *Gbb, double *Gbe,
                         double *Gee) -> int {
-    double *Vb = sd.basis;
+    char *Vb = static_cast<char *>(sd.basis);
+    const bool f32 = L.fp32;
     int ee;
     if (!band) {
       const int qk = (int)std::min<int64_t>(round_up(q, 32), ldb);
-      if ((ee = launch_zero_cols(sd.rows, Vb, ldb, (int)q, qk, st))) return ee;
+      if ((ee = launch_zero_cols(sd.rows, Vb, f32, ldb, (int)q, qk, st))) return ee;
     }
     for (int64_t r0 = 0; r0 < sd.rows; r0 += L.rc_rows) {
       const int64_t r1 = std::min(sd.rows, r0 + L.rc_rows), nr = r1 - r0;
       const double beta = (r0 == 0) ? 0.0 : 1.0;
       if (band) {
-        if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, Vb, ldb, (int)p, (int)q, s, Hm,
-                                     ldc, M2, ldc, r0 == 0, E, ldb, st)))
+        if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, Vb, f32, ldb, (int)p, (int)q, s,
+                                     Hm, ldc, M2, ldc, r0 == 0, E, ldb, st)))
           return ee;
       } else {
         // E = M V_p (rows r0..r1), then E -= V_q(rows) H(0:q, 0:p)
-        if ((ee = launch_spmm_rows(s, r0, r1, sd.rp, sd.ci, sd.val, Vb, ldb, (int)p, E, ldb, st)))
+        if ((ee = launch_spmm_rows(s, r0, r1, sd.rp, sd.ci, sd.val, Vb, f32, ldb, (int)p, E, ldb,
+                                   st)))
           return ee;
-        if ((ee = launch_defect_gemm(nr, (int)p, (int)q, s, Vb + r0 * ldb, ldb, Hm, ldc, E, ldb,
-                                     st)))
+        if ((ee = launch_defect_gemm(nr, (int)p, (int)q, s, Vb + r0 * ldb * L.esz, f32, ldb, Hm,
+                                     ldc, E, ldb, st)))
           return ee;
       }
-      const double *Vr = Vb + r0 * ldb;
-      if ((ee = launch_gram(q, q, nr, Vr, ldb, Vr, ldb, beta, Gbb, ldc, true, st))) return ee;
-      if ((ee = launch_gram(q, p, nr, Vr, ldb, E, ldb, beta, Gbe, ldc, false, st))) return ee;
-      if ((ee = launch_gram(p, p, nr, E, ldb, E, ldb, beta, Gee, ldc, true, st))) return ee;
+      const char *Vr = Vb + r0 * ldb * L.esz;
+      if ((ee = launch_gram(q, q, nr, Vr, f32, ldb, Vr, f32, ldb, beta, Gbb, ldc, true, st)))
+        return ee;
+      if ((ee = launch_gram(q, p, nr, Vr, f32, ldb, E, false, ldb, beta, Gbe, ldc, false, st)))
+        return ee;
+      if ((ee = launch_gram(p, p, nr, E, false, ldb, E, false, ldb, beta, Gee, ldc, true, st)))
+        return ee;
     }
     if ((ee = launch_mirror(q, Gbb, ldc, st))) return ee;
     return launch_mirror(p, Gee, ldc, st);

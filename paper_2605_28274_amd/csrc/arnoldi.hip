@@ -8,8 +8,8 @@
 //   two classical Gram-Schmidt sweeps:
 //     C = V[:, 0:ncols]^T U  (split-K over row chunks)            gram_part_pair
 //     sum of the chunk partials -> H column block j, coef         gram_reduce_pair
-//     U -= V[:, 0:ncols] C   (coef staged in LDS)                  update_pair
-//   (the second sweep's update also leaves partials of U^T U)
+//     U -= V[:, 0:ncols] C   (FP64 MFMA, coef staged in LDS)       update_mfma_pair
+//   partials of U^T U after the second sweep                       ugram_pair
 //   first Cholesky-QR pass + closure test, partials of G2          qr2_pair
 //   second pass, V_{j+1} = U T, H_{j+1,j}                          final_pair
 // No kernel ends in a grid-wide fence: each reduction leaves one partial per workgroup and the
@@ -32,15 +32,15 @@ struct ArSide {
   int64_t rows, nnz;
   const int32_t *rp, *ci;
   const double *val;
-  double *basis;
+  void *basis;        // rows x ldb, element type T of the kernels (double, or float in mixed mode)
   int64_t ldb;
   double *H;
   double *U;
   double *coef;
   SideState *ss;
   SellMat sell;       // SELL copy of the operator (sell.ci == nullptr: CSR)
-  const double *pin;  // compact copy of block j (SpMM input)
-  double *pout;       // compact copy of block j+1 (written with the new block)
+  const void *pin;    // compact copy of block j (SpMM input), element type T
+  void *pout;         // compact copy of block j+1 (written with the new block), element type T
   double *part;    // Gram chunk partials of this basis
   double *aux;     // partials of ||M V_j||^2, U^T U and of the second-pass Gram
   int *cnt;        // counters of this basis (unused: no grid-wide reductions)
@@ -63,7 +63,7 @@ __device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd) {
   return A;
 }
 
-template <int S>
+template <int S, typename T>
 __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   if (ds->done) return;
   int lb, sd;
@@ -73,9 +73,9 @@ __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   double acc[S];
   const int64_t r = r0 + threadIdx.x;
   if (A.sell.ci) {
-    if (r < r1) sell_row<S>(A.sell, r, A.pin, S, acc);
+    if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
   } else {
-    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, A.pin, S, acc);
+    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
   }
   double red[1] = {0.0};
   if (r < r1) {
@@ -90,12 +90,36 @@ __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   if (threadIdx.x == 0) A.aux[lb] = red[0];
 }
 
+// Eight bytes of basis entries per load: one double, or two floats (FP32 bases).
+template <typename T>
+struct Pack8;
+template <>
+struct Pack8<double> {
+  typedef double type;
+  static constexpr int N = 1;
+  static __device__ __forceinline__ type zero() { return 0.0; }
+  static __device__ __forceinline__ void get(type v, double (&o)[1]) { o[0] = v; }
+};
+template <>
+struct Pack8<float> {
+  typedef float2 type;
+  static constexpr int N = 2;
+  static __device__ __forceinline__ type zero() { return make_float2(0.f, 0.f); }
+  static __device__ __forceinline__ void get(type v, double (&o)[2]) {
+    o[0] = (double)v.x;
+    o[1] = (double)v.y;
+  }
+};
+
 // Chunk partials of C = V^T U: workgroup lb owns rows [lb*rpc, (lb+1)*rpc) and all ncols
-// columns; thread t accumulates columns t + 256 q. part[lb][c][t] (rows of V are read once,
-// coalesced; U rows come from LDS).
-template <int S>
+// columns; thread t accumulates the 8-byte column group t + 256 q (one double or two floats).
+// part[lb][c][t] (rows of V are read once, coalesced; U rows come from LDS).
+template <int S, typename T>
 __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, const DevState *ds) {
   if (ds->done) return;
+  typedef Pack8<T> PK;
+  typedef typename PK::type V8;
+  constexpr int E = PK::N, NV = NQ / E;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   __shared__ double Us[UCH * S];
@@ -103,51 +127,72 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, const
   const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
   double *part = A.part + (size_t)lb * ncols * S;
   for (int c0 = 0; c0 < ncols; c0 += TPB * NQ) {
-    double acc[NQ][S];
+    double acc[NV][E][S];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q)
+    for (int q = 0; q < NV; ++q)
 #pragma unroll
-      for (int t = 0; t < S; ++t) acc[q][t] = 0.0;
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[q][e][t] = 0.0;
+    // columns past ncols load column group 0 instead (always in bounds) and are not stored, so
+    // every load is unconditional and the loads of a step issue back to back
+    int coff[NV];
+#pragma unroll
+    for (int q = 0; q < NV; ++q) {
+      const int c = c0 + (q * TPB + (int)threadIdx.x) * E;
+      coff[q] = c < ncols ? c : 0;
+    }
     for (int64_t rb = r0; rb < r1; rb += UCH) {
       const int nr = (int)((r1 - rb < UCH) ? r1 - rb : UCH);
       __syncthreads();
       for (int e = threadIdx.x; e < nr * S; e += TPB) Us[e] = A.U[rb * S + e];
       __syncthreads();
-      const double *vrow = A.basis + rb * A.ldb + c0 + threadIdx.x;
+      const T *vrow = static_cast<const T *>(A.basis) + rb * A.ldb;
+      // RU rows per step: the same bytes in flight per thread for either element type
+      constexpr int RU = 2 * E;
       int r = 0;
-      for (; r + 2 <= nr; r += 2) {
-        double v0[NQ], v1[NQ];
+      for (; r + RU <= nr; r += RU) {
+        V8 v[RU][NV];
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const bool ok = c0 + q * TPB + (int)threadIdx.x < ncols;
-          v0[q] = ok ? vrow[(int64_t)r * A.ldb + q * TPB] : 0.0;
-          v1[q] = ok ? vrow[(int64_t)(r + 1) * A.ldb + q * TPB] : 0.0;
-        }
+        for (int h = 0; h < RU; ++h)
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
+          for (int q = 0; q < NV; ++q)
+            v[h][q] = *reinterpret_cast<const V8 *>(vrow + (int64_t)(r + h) * A.ldb + coff[q]);
 #pragma unroll
-          for (int t = 0; t < S; ++t) {
-            acc[q][t] = fma(v0[q], Us[r * S + t], acc[q][t]);
-            acc[q][t] = fma(v1[q], Us[(r + 1) * S + t], acc[q][t]);
+        for (int h = 0; h < RU; ++h)
+#pragma unroll
+          for (int q = 0; q < NV; ++q) {
+            double x[E];
+            PK::get(v[h][q], x);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+              for (int t = 0; t < S; ++t)
+                acc[q][e][t] = fma(x[e], Us[(r + h) * S + t], acc[q][e][t]);
           }
       }
       for (; r < nr; ++r) {
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          const bool ok = c0 + q * TPB + (int)threadIdx.x < ncols;
-          const double v = ok ? vrow[(int64_t)r * A.ldb + q * TPB] : 0.0;
+        for (int q = 0; q < NV; ++q) {
+          const V8 v = *reinterpret_cast<const V8 *>(vrow + (int64_t)r * A.ldb + coff[q]);
+          double x[E];
+          PK::get(v, x);
 #pragma unroll
-          for (int t = 0; t < S; ++t) acc[q][t] = fma(v, Us[r * S + t], acc[q][t]);
+          for (int e = 0; e < E; ++e)
+#pragma unroll
+            for (int t = 0; t < S; ++t) acc[q][e][t] = fma(x[e], Us[r * S + t], acc[q][e][t]);
         }
       }
     }
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) {
-      const int c = c0 + q * TPB + threadIdx.x;
-      if (c < ncols)
+    for (int q = 0; q < NV; ++q)
 #pragma unroll
-        for (int t = 0; t < S; ++t) part[c * S + t] = acc[q][t];
-    }
+      for (int e = 0; e < E; ++e) {
+        const int c = c0 + (q * TPB + (int)threadIdx.x) * E + e;
+        if (c < ncols)
+#pragma unroll
+          for (int t = 0; t < S; ++t) part[c * S + t] = acc[q][e][t];
+      }
   }
 }
 
@@ -189,75 +234,97 @@ __global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int nco
   }
 }
 
-// U[r] -= V[r, 0:ncols] C with C (ncols x S) in LDS; one wave per row, lanes across columns.
-// With gram != 0 (second sweep) also reduces U^T U and runs the first QR pass per basis.
-template <int S>
-__global__ __launch_bounds__(TPB) void update_pair(ArPair P, int ncols, int gram,
-                                                   double closure_tol, const DevState *ds) {
+// U[r] -= V[r, 0:ncols] C on FP64 matrix cores (v_mfma_f64_16x16x4f64): each wave owns 16 rows,
+// D (16 x 16) += A (16 rows x 4 basis columns) B (4 x 16, coefficient columns >= S are zero).
+// Lane l reads 32 contiguous bytes of row l % 16 per step (KL consecutive columns, chunk l / 16),
+// so the four lanes of a row cover 128 contiguous bytes; MFMA m of the step takes column
+// k0 + KL (l / 16) + m as its k-slot l / 16 on both operands (the sum over k is the same). The
+// coefficients sit in LDS, zero-padded past ncols; stale basis columns past ncols read as zero.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, const DevState *ds) {
   if (ds->done) return;
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  constexpr int KL = 32 / (int)sizeof(T);  // columns per lane per step
+  constexpr int KG = 4 * KL;               // columns per step
   extern __shared__ double Cs[];
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
-  for (int e = threadIdx.x; e < ncols * S; e += TPB) Cs[e] = A.coef[e];
+  const int nk = (ncols + KG - 1) / KG * KG;
+  for (int e = threadIdx.x; e < nk * S; e += TPB) Cs[e] = e < ncols * S ? A.coef[e] : 0.0;
   __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int li = lane & 15, lq = lane >> 4;
   const int64_t r0 = (int64_t)lb * A.rpc;
   const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
-  double g[S * S];
+  constexpr int KU = 4;  // steps whose loads are in flight together
+  for (int64_t rb = r0 + 16 * w; rb < r1; rb += 16 * (TPB / WAVE)) {
+    const int64_t row = (rb + li < r1) ? rb + li : r1 - 1;  // clamped loads, masked stores
+    const T *vr = static_cast<const T *>(A.basis) + row * A.ldb + lq * KL;
+    v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < nk; k0 += KU * KG) {
+      T x[KU][KL];
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  // each wave updates two rows at a time (twice the loads in flight)
-  for (int64_t ra = r0 + 2 * w; ra < r1; ra += 2 * (TPB / WAVE)) {
-    const bool two = ra + 1 < r1;
-    const double *v0 = A.basis + ra * A.ldb;
-    const double *v1 = two ? v0 + A.ldb : v0;
-    double acc0[S], acc1[S];
+      for (int u = 0; u < KU; ++u) {
+        // a step past nk re-reads step 0 (in bounds); its products are masked to zero below
+        const int kk = k0 + u * KG < nk ? k0 + u * KG : 0;
+        if (sizeof(T) == 8) {
+          const double2 *p2 = reinterpret_cast<const double2 *>(vr + kk);
+          const double2 a = p2[0], b = p2[1];
+          x[u][0] = (T)a.x;
+          x[u][1] = (T)a.y;
+          x[u][2] = (T)b.x;
+          x[u][3] = (T)b.y;
+        } else {
+          const float4 *p4 = reinterpret_cast<const float4 *>(vr + kk);
+          const float4 a = p4[0], b = p4[1];
+          const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
 #pragma unroll
-    for (int t = 0; t < S; ++t) acc0[t] = acc1[t] = 0.0;
-    int c = lane;
-    for (; c + WAVE < ncols; c += 2 * WAVE) {
-      const double x0 = v0[c], x1 = v0[c + WAVE], y0 = v1[c], y1 = v1[c + WAVE];
+          for (int m = 0; m < KL; ++m) x[u][m] = (T)f[m];
+        }
+      }
 #pragma unroll
-      for (int t = 0; t < S; ++t) {
-        const double c0 = Cs[c * S + t], c1 = Cs[(c + WAVE) * S + t];
-        acc0[t] = fma(x0, c0, acc0[t]);
-        acc0[t] = fma(x1, c1, acc0[t]);
-        acc1[t] = fma(y0, c0, acc1[t]);
-        acc1[t] = fma(y1, c1, acc1[t]);
+      for (int u = 0; u < KU; ++u) {
+        const bool step = k0 + u * KG < nk;
+#pragma unroll
+        for (int m = 0; m < KL; ++m) {
+          const int k = k0 + u * KG + lq * KL + m;
+          const double av = (step && k < ncols) ? (double)x[u][m] : 0.0;
+          const double bv = (step && li < S) ? Cs[k * S + li] : 0.0;
+          if (m & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
+          else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
+        }
       }
     }
-    if (c < ncols) {
-      const double x0 = v0[c], y0 = v1[c];
+    // lane holds D[4 v + lq][li]: row rb + 4 v + lq, column li
+    if (li < S) {
 #pragma unroll
-      for (int t = 0; t < S; ++t) {
-        acc0[t] = fma(x0, Cs[c * S + t], acc0[t]);
-        acc1[t] = fma(y0, Cs[c * S + t], acc1[t]);
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < S; ++t) {
-      acc0[t] = wave_sum(acc0[t]);
-      acc1[t] = wave_sum(acc1[t]);
-    }
-    if (lane == 0) {
-      for (int h = 0; h < (two ? 2 : 1); ++h) {
-        const int64_t r = ra + h;
-        double u[S];
-#pragma unroll
-        for (int t = 0; t < S; ++t) {
-          u[t] = A.U[r * S + t] - (h ? acc1[t] : acc0[t]);
-          A.U[r * S + t] = u[t];
-        }
-        if (gram) {
-#pragma unroll
-          for (int a = 0; a < S; ++a)
-#pragma unroll
-            for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
-        }
+      for (int v = 0; v < 4; ++v) {
+        const int64_t r = rb + 4 * v + lq;
+        if (r < r1) A.U[r * S + li] -= acc0[v] + acc1[v];
       }
     }
   }
-  if (!gram) return;
+}
+
+// Partials of U^T U (rows over workgroups, one thread per row) for the first QR pass.
+template <int S>
+__global__ __launch_bounds__(TPB) void ugram_pair(ArPair P, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  const int64_t r = (int64_t)lb * TPB + threadIdx.x;
+  if (r < A.rows) {
+    double u[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) g[a * S + b] = u[a] * u[b];
+  }
   __shared__ double lds[16 * S * S];
   block_sum<S * S>(g, lds);
   if (threadIdx.x == 0)
@@ -340,7 +407,7 @@ __global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, co
 
 // Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
 // V[:, (j+1)s : (j+2)s] = U T; workgroup 0 records T and writes H_{j+1,j}.
-template <int S>
+template <int S, typename T>
 __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
                                                   const DevState *ds) {
   if (ds->done) return;
@@ -367,9 +434,9 @@ __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
     }
   }
   __syncthreads();
-  double T[S * S];
+  double Tq[S * S];
 #pragma unroll
-  for (int i = 0; i < S * S; ++i) T[i] = st.T[i];
+  for (int i = 0; i < S * S; ++i) Tq[i] = st.T[i];
   for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
     double u[S];
 #pragma unroll
@@ -378,9 +445,9 @@ __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
     for (int b = 0; b < S; ++b) {
       double v = 0.0;
 #pragma unroll
-      for (int a = 0; a < S; ++a) v = fma(u[a], T[a * S + b], v);
-      A.basis[r * A.ldb + (jb + 1) * S + b] = v;
-      A.pout[r * S + b] = v;
+      for (int a = 0; a < S; ++a) v = fma(u[a], Tq[a * S + b], v);
+      static_cast<T *>(A.basis)[r * A.ldb + (jb + 1) * S + b] = (T)v;
+      static_cast<T *>(A.pout)[r * S + b] = (T)v;
     }
   }
 }
@@ -394,7 +461,7 @@ __device__ __forceinline__ double *aux_vju(const ArSide &A) {
 }
 
 // U = M V_j - V_{j-1} H_{j-1,j} (H_{j-1,j} = H_{j,j-1}^T); partials of ||M V_j||^2 and V_j^T U.
-template <int S>
+template <int S, typename T>
 __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ldh,
                                                     const DevState *ds) {
   if (ds->done) return;
@@ -411,9 +478,9 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
   const int64_t r = r0 + threadIdx.x;
   double acc[S];
   if (A.sell.ci) {
-    if (r < r1) sell_row<S>(A.sell, r, A.pin, S, acc);
+    if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
   } else {
-    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, A.pin, S, acc);
+    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
   }
   double red[S * S + 1];
 #pragma unroll
@@ -422,18 +489,18 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
 #pragma unroll
     for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
     if (jb > 0) {
-      const double *vp = A.pout + r * S;  // block j-1 (its panel is reused for block j+1)
+      const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused for j+1)
 #pragma unroll
       for (int u = 0; u < S; ++u) {
-        const double vu = vp[u];
+        const double vu = (double)vp[u];
 #pragma unroll
         for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
       }
     }
-    const double *vj = A.pin + r * S;
+    const T *vj = static_cast<const T *>(A.pin) + r * S;
 #pragma unroll
     for (int a = 0; a < S; ++a) {
-      const double va = vj[a];
+      const double va = (double)vj[a];
 #pragma unroll
       for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
     }
@@ -452,7 +519,7 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
 
 // H_jj = V_j^T U from the partials (every workgroup forms it; workgroup 0 writes column block j
 // of H: H_{j-1,j} and H_jj); U -= V_j H_jj; partials of U^T U.
-template <int S>
+template <int S, typename T>
 __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t ldh,
                                                       const DevState *ds) {
   if (ds->done) return;
@@ -477,10 +544,10 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t 
     double u[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
-    const double *vj = A.pin + r * S;
+    const T *vj = static_cast<const T *>(A.pin) + r * S;
 #pragma unroll
     for (int a = 0; a < S; ++a) {
-      const double va = vj[a];
+      const double va = (double)vj[a];
 #pragma unroll
       for (int t = 0; t < S; ++t) u[t] = fma(-va, hjj[a * S + t], u[t]);
     }
@@ -546,7 +613,7 @@ unsigned total_blocks(const ArPair &P) {
   return (unsigned)(P.s[0].nb + (P.nsides > 1 ? P.s[1].nb : 0));
 }
 
-constexpr int64_t UROWS = 32;    // rows per update_pair workgroup
+constexpr int64_t UROWS = 64;    // rows per update workgroup (16 per wave)
 constexpr int64_t QR_MAXWG = 512;
 
 int64_t nb_rows(int64_t rows) { return cdiv(rows, TPB); }
@@ -555,7 +622,7 @@ size_t aux_len(int s, int64_t rows) {
   return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows) + nb_rows(rows)) * s * s + 16);
 }
 
-template <int S>
+template <int S, typename T>
 int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                    double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
   ArPair P{};
@@ -574,7 +641,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   const int64_t total = rows0 + rows1;
   const int ncols = (jb + 1) * S;
   const int nout = ncols * S;
-  const double bytes_v = 8.0 * (double)total * ncols, flops_v = 2.0 * (double)total * ncols * S;
+  const double bytes_v = (double)sizeof(T) * (double)total * ncols, flops_v = 2.0 * (double)total * ncols * S;
 
   // U = M V_j
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
@@ -584,7 +651,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     P.s[i].pin = d.panel[jb % 2];
     P.s[i].pout = d.panel[(jb + 1) % 2];
   }
-  spmm_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ds);
+  spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_SPMM,
            12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,
@@ -595,7 +662,8 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
   if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
     return SYLV_ERR_WORKSPACE;
-  const size_t lds = (size_t)nout * sizeof(double);
+  // coefficients padded to whole steps of the MFMA update (32 columns)
+  const size_t lds = (size_t)((ncols + 31) / 32 * 32) * S * sizeof(double);
   if (lds > 64 * 1024) return SYLV_ERR_WORKSPACE;
   const int64_t rtiles = cdiv(nout, OPB);
 
@@ -604,7 +672,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     P.s[1].rpc = rpc1;
     set_ranges(P, nch0, nch1);
     prof_begin(sc, st);
-    gram_part_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ncols, ds);
+    gram_part_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, ncols, ds);
     HIPOK(hipGetLastError());
     set_ranges(P, rtiles, sw ? rtiles : 0);
     gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S, ncols, nch0, nch1, ldh, jb * S, pass,
@@ -615,8 +683,15 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     P.s[1].rpc = UROWS;
     set_ranges(P, cdiv(rows0, UROWS), sw ? cdiv(rows1, UROWS) : 0);
     prof_begin(sc, st);
-    update_pair<S><<<total_blocks(P), TPB, lds, st>>>(P, ncols, pass == 2, closure_tol, ds);
+    update_mfma_pair<S, T><<<total_blocks(P), TPB, lds, st>>>(P, ncols, ds);
     HIPOK(hipGetLastError());
+    if (pass == 2) {
+      // U^T U partials for the first QR pass (one record per 256 rows)
+      for (int i = 0; i < P.nsides; ++i) P.s[i].nb_upd = (int)nb_rows(i ? rows1 : rows0);
+      set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+      ugram_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ds);
+      HIPOK(hipGetLastError());
+    }
     prof_end(sc, FAM_UPDATE, bytes_v + 16.0 * total * S + 8.0 * nout * P.nsides, flops_v, st);
   }
   // QR passes and the new block
@@ -624,14 +699,14 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
 }
 
 
-template <int S>
+template <int S, typename T>
 int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                    double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
   ArPair P{};
@@ -654,9 +729,9 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   const int64_t total = rows0 + rows1;
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
   prof_begin(sc, st);
-  lz_spmm_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
   HIPOK(hipGetLastError());
-  lz_update_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  lz_update_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
   HIPOK(hipGetLastError());
   // matrix + gather V_j + read V_{j-1}, V_j + U write/read (local three-term step)
   prof_end(sc, FAM_SPMM,
@@ -666,7 +741,7 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
@@ -687,7 +762,9 @@ int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
   switch (s) {
 #define CASE(SS) \
-  case SS: return arnoldi_pair_t<SS>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
+  case SS:                                                                         \
+    return sv.fp32 ? arnoldi_pair_t<SS, float>(sv, sw, jb, ldh, closure_tol, sc, ds, st)   \
+                   : arnoldi_pair_t<SS, double>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return SYLV_ERR_INVALID;
@@ -698,7 +775,9 @@ int launch_lanczos_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
   switch (s) {
 #define CASE(SS) \
-  case SS: return lanczos_pair_t<SS>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
+  case SS:                                                                         \
+    return sv.fp32 ? lanczos_pair_t<SS, float>(sv, sw, jb, ldh, closure_tol, sc, ds, st)   \
+                   : lanczos_pair_t<SS, double>(sv, sw, jb, ldh, closure_tol, sc, ds, st);
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return SYLV_ERR_INVALID;

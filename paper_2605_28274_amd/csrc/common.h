@@ -169,11 +169,11 @@ constexpr int SPMM_CAP = 2048;  // CSR entries staged in LDS per workgroup
 // in LDS with coalesced loads and every thread walks its row from LDS (stencil rows are short,
 // so direct per-thread reads of col_idx / values would be strided across the wave). Larger
 // ranges are read directly. All threads of the workgroup must call (it synchronizes).
-template <int S>
+template <int S, typename T = double>
 __device__ __forceinline__ void spmm_rows(int64_t r0, int64_t r1, const int32_t *__restrict__ rp,
                                           const int32_t *__restrict__ ci,
                                           const double *__restrict__ val,
-                                          const double *__restrict__ X, int64_t ldx,
+                                          const T *__restrict__ X, int64_t ldx,
                                           double (&acc)[S]) {
   __shared__ int s_ci[SPMM_CAP];
   __shared__ double s_val[SPMM_CAP];
@@ -195,16 +195,16 @@ __device__ __forceinline__ void spmm_rows(int64_t r0, int64_t r1, const int32_t 
     if (staged) {
       for (int q = b - base; q < e - base; ++q) {
         const double a = s_val[q];
-        const double *x = X + (int64_t)s_ci[q] * ldx;
+        const T *x = X + (int64_t)s_ci[q] * ldx;
 #pragma unroll
-        for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+        for (int t = 0; t < S; ++t) acc[t] = fma(a, (double)x[t], acc[t]);
       }
     } else {
       for (int q = b; q < e; ++q) {
         const double a = val[q];
-        const double *x = X + (int64_t)ci[q] * ldx;
+        const T *x = X + (int64_t)ci[q] * ldx;
 #pragma unroll
-        for (int t = 0; t < S; ++t) acc[t] = fma(a, x[t], acc[t]);
+        for (int t = 0; t < S; ++t) acc[t] = fma(a, (double)x[t], acc[t]);
       }
     }
   }
@@ -257,9 +257,9 @@ inline SellMat sell_view(int64_t rows, int64_t nnz, void *buf) {
 // acc = A[r, :] X[:, 0:S] for one row r < rows (thread r % 64 of a wave-aligned slice). Rows
 // are walked in chunks of 8 entries: all index/value loads of a chunk issue together, then all
 // its gathers, so a stencil row costs two dependent memory round trips.
-template <int S>
+template <int S, typename T = double>
 __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
-                                         const double *__restrict__ X, int64_t ldx,
+                                         const T *__restrict__ X, int64_t ldx,
                                          double (&acc)[S]) {
 #pragma unroll
   for (int t = 0; t < S; ++t) acc[t] = 0.0;
@@ -280,7 +280,7 @@ __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
     for (int u = 0; u < 8; ++u) {
       const bool in = q0 + u < w;
 #pragma unroll
-      for (int t = 0; t < S; ++t) x[u][t] = in ? X[(int64_t)c[u] * ldx + t] : 0.0;
+      for (int t = 0; t < S; ++t) x[u][t] = in ? (double)X[(int64_t)c[u] * ldx + t] : 0.0;
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u)
@@ -457,14 +457,16 @@ struct SideDesc {
   const int32_t *rp;       // CSR of the operator applied to the basis (A, or B^T)
   const int32_t *ci;
   const double *val;
-  double *basis;           // rows x ldb row-major; block j occupies columns [j s, (j+1) s)
+  void *basis;             // rows x ldb row-major; block j occupies columns [j s, (j+1) s);
+                           // double, or float when fp32 (mixed precision)
   int64_t ldb;
   double *H;               // block Hessenberg, ldc x ldc row-major
   double *U;               // rows x s work panel
   double *coef;            // compact coefficient block (ldb x s)
   SideState *ss;           // device
-  double *panel[2];        // compact rows x s copies of the two newest blocks: block j in
-                           // panel[j % 2] (SpMM input and Lanczos local terms)
+  void *panel[2];          // compact rows x s copies of the two newest blocks: block j in
+                           // panel[j % 2] (SpMM input and Lanczos local terms), basis type
+  int fp32;                // basis and panels stored in FP32
   SellMat sell;            // SELL copy of the operator (sell.ci == nullptr: use CSR)
 };
 
@@ -492,8 +494,11 @@ void prof_end(const Scratch &sc, int fam, double bytes, double flops, hipStream_
 int launch_spmm(int s, int64_t rows, const int32_t *rp, const int32_t *ci, const double *val,
                 const double *X, int64_t ldx, double *Y, int64_t ldy, hipStream_t st);
 int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
-                     const double *val, const double *X, int64_t ldx, int ncols, double *Y,
-                     int64_t ldy, hipStream_t st);
+                     const double *val, const void *X, bool x_fp32, int64_t ldx, int ncols,
+                     double *Y, int64_t ldy, hipStream_t st);
+// dst = src widened from FP32 to FP64 (rows x cols).
+int launch_widen(int64_t rows, int64_t cols, const float *src, int64_t lds, double *dst,
+                 int64_t ldd, hipStream_t st);
 int launch_csr_transpose(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci,
                          const double *val, int32_t *orp, int32_t *oci, double *oval,
                          void *scratch, hipStream_t st);
@@ -541,18 +546,22 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
 // Residual evaluation (dense.hip, residual.hip).
 // C (+)= A^T B, A: K x M, B: K x N row-major (lda >= roundup(M, 64), ldb >= roundup(N, 64));
 // `lower` computes the tiles on and below the diagonal only (M == N; launch_mirror completes).
-int launch_gram(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
-                int64_t ldb, double beta, double *C, int64_t ldc, bool lower, hipStream_t st);
+// A and B are float (a_fp32 / b_fp32) or double; row strides multiples of 8 elements.
+int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
+                const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
+                bool lower, hipStream_t st);
 int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st);
 // E(0:rows, 0:p) -= V(0:rows, 0:q) H(0:q, 0:p), H block upper Hessenberg; V columns
 // [q, roundup(q, 32)) must be finite.
-int launch_defect_gemm(int64_t rows, int p, int q, int s, const double *V, int64_t ldv,
+int launch_defect_gemm(int64_t rows, int p, int q, int s, const void *V, bool v_fp32, int64_t ldv,
                        const double *H, int64_t ldh, double *E, int64_t lde, hipStream_t st);
-int launch_zero_cols(int64_t rows, double *V, int64_t ldv, int c0, int c1, hipStream_t st);
+int launch_zero_cols(int64_t rows, void *V, bool v_fp32, int64_t ldv, int c0, int c1,
+                     hipStream_t st);
 // E(r - r0, 0:p) = M(r, :) V(:, 0:p) - V(r, 0:q) H(0:q, 0:p) for block-tridiagonal H; `pack`
 // first writes the band of H into Hb (3s x ldhb).
 int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
-                       const double *val, const double *V, int64_t ldv, int p, int q, int s,
+                       const double *val, const void *V, bool v_fp32, int64_t ldv, int p, int q,
+                       int s,
                        const double *H, int64_t ldh, double *Hb, int64_t ldhb, bool pack,
                        double *E, int64_t lde, hipStream_t st);
 int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,

@@ -86,11 +86,25 @@ struct RegSlab {
   double2 v[4];
 };
 
-__device__ __forceinline__ void load_rows(const double *base, int64_t ld, RegSlab &r) {
-  const int i = threadIdx.x >> 2, k = (threadIdx.x & 3) * 8;
-  const double2 *p = reinterpret_cast<const double2 *>(base + (int64_t)i * ld + k);
+// Eight consecutive elements (32-byte aligned for float, 64-byte for double) as doubles.
+__device__ __forceinline__ void load8(const double *p, RegSlab &r) {
+  const double2 *q = reinterpret_cast<const double2 *>(p);
 #pragma unroll
-  for (int u = 0; u < 4; ++u) r.v[u] = p[u];
+  for (int u = 0; u < 4; ++u) r.v[u] = q[u];
+}
+__device__ __forceinline__ void load8(const float *p, RegSlab &r) {
+  const float4 *q = reinterpret_cast<const float4 *>(p);
+  const float4 a = q[0], b = q[1];
+  r.v[0] = double2{(double)a.x, (double)a.y};
+  r.v[1] = double2{(double)a.z, (double)a.w};
+  r.v[2] = double2{(double)b.x, (double)b.y};
+  r.v[3] = double2{(double)b.z, (double)b.w};
+}
+
+template <typename T>
+__device__ __forceinline__ void load_rows(const T *base, int64_t ld, RegSlab &r) {
+  const int i = threadIdx.x >> 2, k = (threadIdx.x & 3) * 8;
+  load8(base + (int64_t)i * ld + k, r);
 }
 
 __device__ __forceinline__ void store_rows(Slab &dst, const RegSlab &r) {
@@ -102,11 +116,10 @@ __device__ __forceinline__ void store_rows(Slab &dst, const RegSlab &r) {
   }
 }
 
-__device__ __forceinline__ void load_cols(const double *base, int64_t ld, RegSlab &r) {
+template <typename T>
+__device__ __forceinline__ void load_cols(const T *base, int64_t ld, RegSlab &r) {
   const int k = threadIdx.x >> 3, j = (threadIdx.x & 7) * 8;
-  const double2 *p = reinterpret_cast<const double2 *>(base + (int64_t)k * ld + j);
-#pragma unroll
-  for (int u = 0; u < 4; ++u) r.v[u] = p[u];
+  load8(base + (int64_t)k * ld + j, r);
 }
 
 __device__ __forceinline__ void store_cols(Slab &dst, const RegSlab &r) {
@@ -121,9 +134,9 @@ __device__ __forceinline__ void store_cols(Slab &dst, const RegSlab &r) {
 // Operand slabs: A(i, l) is A[i * lda + l] ("rows", A_T = false) or A[l * lda + i] (A_T = true,
 // a K x M row-major matrix read transposed); B(l, j) is B[l * ldb + j] ("cols", B_ROWS = false)
 // or B[j * ldb + l] (B_ROWS = true).
-template <bool A_T, bool B_ROWS>
-__device__ __forceinline__ void load_slab(const double *A, int64_t lda, const double *B,
-                                          int64_t ldb, int64_t l, RegSlab &ra, RegSlab &rb) {
+template <bool A_T, bool B_ROWS, typename TA, typename TB>
+__device__ __forceinline__ void load_slab(const TA *A, int64_t lda, const TB *B, int64_t ldb,
+                                          int64_t l, RegSlab &ra, RegSlab &rb) {
   if (A_T) load_cols(A + l * lda, lda, ra);
   else load_rows(A + l, lda, ra);
   if (B_ROWS) load_rows(B + l, ldb, rb);
@@ -143,10 +156,10 @@ __device__ __forceinline__ void store_slab(Smem &sm, int buf, const RegSlab &ra,
 // with the operand forms above (A, B point at row/column i0 and j0). Global loads run two slabs
 // ahead of the MFMAs (two register sets, the loop unrolled by two so they stay static); LDS is
 // double-buffered with one barrier per slab.
-template <bool A_T, bool B_ROWS>
-__device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn,
-                                          const double *A, int64_t lda, const double *B,
-                                          int64_t ldb, int64_t l_begin, int64_t l_end) {
+template <bool A_T, bool B_ROWS, typename TA = double, typename TB = double>
+__device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn, const TA *A,
+                                          int64_t lda, const TB *B, int64_t ldb,
+                                          int64_t l_begin, int64_t l_end) {
   if (l_begin >= l_end) return;
   const int64_t nsl = (l_end - l_begin) / BK;
   // Prefetches are unconditional (a slab index past the end re-reads the last slab, always in
@@ -154,19 +167,19 @@ __device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn
   // LDS fill only covers the older register set.
   auto lslab = [&](int64_t t) { return l_begin + (t < nsl ? t : nsl - 1) * BK; };
   RegSlab ra0, rb0, ra1, rb1;
-  load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(0), ra0, rb0);
-  load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(1), ra1, rb1);
+  load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(0), ra0, rb0);
+  load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(1), ra1, rb1);
   __syncthreads();  // previous users of the LDS buffers are done
   store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0);
   __syncthreads();
   // invariant at slab t: LDS[t % 2] holds slab t; register set (t+1) % 2 holds slab t+1
   int64_t t = 0;
   for (; t + 1 < nsl; t += 2) {
-    load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(t + 2), ra0, rb0);
+    load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(t + 2), ra0, rb0);
     mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
     store_slab<A_T, B_ROWS>(sm, 1, ra1, rb1);
     __syncthreads();
-    load_slab<A_T, B_ROWS>(A, lda, B, ldb, lslab(t + 3), ra1, rb1);
+    load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(t + 3), ra1, rb1);
     mma_slab(sm.As[1], sm.Bs[1], acc, wm, wn);
     store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0);
     __syncthreads();
@@ -228,9 +241,10 @@ __device__ __forceinline__ void tri_tile(int64_t b, int &I, int &J) {
   J = (int)(b - i * (i + 1) / 2);
 }
 
+template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void gram_kernel(int64_t M, int64_t N, int64_t K,
-                                                   const double *__restrict__ A, int64_t lda,
-                                                   const double *__restrict__ B, int64_t ldb,
+                                                   const TA *__restrict__ A, int64_t lda,
+                                                   const TB *__restrict__ B, int64_t ldb,
                                                    double beta, double *__restrict__ C,
                                                    int64_t ldc, int tiles_n, int lower) {
   __shared__ Smem sm;
@@ -244,7 +258,19 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t M, int64_t N, int64_t
   const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
   WaveAcc acc;
   zero_acc(acc);
-  pipelined<true, false>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, 0, K);
+  const int64_t kb = K / BK * BK;
+  pipelined<true, false, TA, TB>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, 0, kb);
+  if (K > kb) {
+    // last K - kb < BK rows, zero-filled past K
+    __syncthreads();
+    for (int e = threadIdx.x; e < BK * BM; e += 256) {
+      const int kk = e / BM, ii = e % BM;
+      sm.As[0][kk][ii] = (kb + kk < K) ? (double)A[(kb + kk) * lda + i0 + ii] : 0.0;
+      sm.Bs[0][kk][ii] = (kb + kk < K) ? (double)B[(kb + kk) * ldb + j0 + ii] : 0.0;
+    }
+    __syncthreads();
+    mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+  }
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
     const int64_t gi = i0 + ii, gj = j0 + jj;
     if (gi < M && gj < N) {
@@ -265,9 +291,9 @@ __global__ __launch_bounds__(256) void mirror_kernel(int64_t M, double *__restri
 // Hessenberg (H(l, c) = 0 when block(l) > block(c) + 1), so output tile J only needs
 // l < (block(j0 + 63) + 2) s. V columns in [q, roundup(q, BK)) must be finite (they meet zero
 // rows of H); V rows past `rows` are never read (row index clamped, results masked).
+template <typename T>
 __global__ __launch_bounds__(256) void defect_gemm_kernel(int64_t rows, int p, int q, int s,
-                                                          const double *__restrict__ V,
-                                                          int64_t ldv,
+                                                          const T *__restrict__ V, int64_t ldv,
                                                           const double *__restrict__ H,
                                                           int64_t ldh, double *__restrict__ E,
                                                           int64_t lde) {
@@ -282,7 +308,7 @@ __global__ __launch_bounds__(256) void defect_gemm_kernel(int64_t rows, int p, i
   WaveAcc acc;
   zero_acc(acc);
   if (i0 + BM <= rows) {
-    pipelined<false, false>(sm, acc, wm, wn, V + i0 * ldv, ldv, H + j0, ldh, 0, le);
+    pipelined<false, false, T, double>(sm, acc, wm, wn, V + i0 * ldv, ldv, H + j0, ldh, 0, le);
   } else {
     // last row tile: stage through a clamped copy of the row pointer range
     const int64_t last = rows - 1;
@@ -290,7 +316,7 @@ __global__ __launch_bounds__(256) void defect_gemm_kernel(int64_t rows, int p, i
       for (int e = threadIdx.x; e < BM * BK; e += 256) {
         const int ii = e / BK, kk = e % BK;
         const int64_t gi = i0 + ii < last ? i0 + ii : last;
-        sm.As[0][kk][ii] = V[gi * ldv + l0 + kk];
+        sm.As[0][kk][ii] = (double)V[gi * ldv + l0 + kk];
       }
       for (int e = threadIdx.x; e < BK * BN; e += 256) {
         const int kk = e / BN, jj = e % BN;
@@ -309,14 +335,15 @@ __global__ __launch_bounds__(256) void defect_gemm_kernel(int64_t rows, int p, i
 }
 
 // V(i, c0:c1) = 0 for all rows (finite padding columns before defect_gemm_kernel).
-__global__ __launch_bounds__(256) void zero_cols_kernel(int64_t rows, double *V, int64_t ldv,
-                                                        int c0, int c1) {
+template <typename T>
+__global__ __launch_bounds__(256) void zero_cols_kernel(int64_t rows, T *V, int64_t ldv, int c0,
+                                                        int c1) {
   const int w = c1 - c0;
   const int64_t total = rows * w;
   for (int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * 256) {
     const int64_t i = e / w;
-    V[i * ldv + c0 + (e - i * w)] = 0.0;
+    V[i * ldv + c0 + (e - i * w)] = (T)0;
   }
 }
 
@@ -385,25 +412,25 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
   return 0;
 }
 
-int launch_gram(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
-                int64_t ldb, double beta, double *C, int64_t ldc, bool lower, hipStream_t st) {
+int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
+                const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
+                bool lower, hipStream_t st) {
   if (M <= 0 || N <= 0) return 0;
   if (lower && M != N) return SYLV_ERR_INVALID;
   const int64_t TM = (M + BM - 1) / BM, TN = (N + BN - 1) / BN;
-  if (lda < TM * BM || ldb < TN * BN) return SYLV_ERR_INVALID;
-  const int64_t kb = K / BK * BK;
-  if (kb > 0) {
-    const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
-    gram_kernel<<<(unsigned)tiles, 256, 0, st>>>(M, N, kb, A, lda, B, ldb, beta, C, ldc, (int)TN,
-                                                 lower ? 1 : 0);
-    HIPOK(hipGetLastError());
-  }
-  if (K > kb) {
-    // rows past the last full slab (masked generic kernel); it fills the full matrix
-    int e = launch_gemm(M, N, K - kb, 1.0, A + kb * lda, 1, lda, B + kb * ldb, ldb, 1,
-                        kb > 0 ? 1.0 : beta, C, ldc, st);
-    if (e) return e;
-  }
+  if (lda < TM * BM || ldb < TN * BN || lda % 8 || ldb % 8) return SYLV_ERR_INVALID;
+  if (K <= 0) return 0;
+  const unsigned tiles = (unsigned)(lower ? TM * (TM + 1) / 2 : TM * TN);
+#define GRAM(TA, TB)                                                                           \
+  gram_kernel<TA, TB><<<tiles, 256, 0, st>>>(M, N, K, static_cast<const TA *>(A), lda,         \
+                                             static_cast<const TB *>(B), ldb, beta, C, ldc,    \
+                                             (int)TN, lower ? 1 : 0)
+  if (a_fp32 && b_fp32) GRAM(float, float);
+  else if (a_fp32) GRAM(float, double);
+  else if (b_fp32) GRAM(double, float);
+  else GRAM(double, double);
+#undef GRAM
+  HIPOK(hipGetLastError());
   return 0;
 }
 
@@ -414,23 +441,31 @@ int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st) {
   return 0;
 }
 
-int launch_defect_gemm(int64_t rows, int p, int q, int s, const double *V, int64_t ldv,
+int launch_defect_gemm(int64_t rows, int p, int q, int s, const void *V, bool v_fp32, int64_t ldv,
                        const double *H, int64_t ldh, double *E, int64_t lde, hipStream_t st) {
   if (rows <= 0 || p <= 0) return 0;
   const int qk = (q + BK - 1) / BK * BK;
   const int pn = (p + BN - 1) / BN * BN;
-  if (ldv < qk || ldh < pn) return SYLV_ERR_INVALID;
+  if (ldv < qk || ldh < pn || ldv % 8) return SYLV_ERR_INVALID;
   const dim3 grid((unsigned)(pn / BN), (unsigned)((rows + BM - 1) / BM));
-  defect_gemm_kernel<<<grid, 256, 0, st>>>(rows, p, q, s, V, ldv, H, ldh, E, lde);
+  if (v_fp32)
+    defect_gemm_kernel<float><<<grid, 256, 0, st>>>(rows, p, q, s, static_cast<const float *>(V),
+                                                    ldv, H, ldh, E, lde);
+  else
+    defect_gemm_kernel<double><<<grid, 256, 0, st>>>(rows, p, q, s,
+                                                     static_cast<const double *>(V), ldv, H, ldh,
+                                                     E, lde);
   HIPOK(hipGetLastError());
   return 0;
 }
 
-int launch_zero_cols(int64_t rows, double *V, int64_t ldv, int c0, int c1, hipStream_t st) {
+int launch_zero_cols(int64_t rows, void *V, bool v_fp32, int64_t ldv, int c0, int c1,
+                     hipStream_t st) {
   if (rows <= 0 || c1 <= c0) return 0;
   const int64_t total = rows * (c1 - c0);
-  zero_cols_kernel<<<(unsigned)std::min<int64_t>((total + 255) / 256, 8192), 256, 0, st>>>(
-      rows, V, ldv, c0, c1);
+  const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 8192);
+  if (v_fp32) zero_cols_kernel<float><<<g, 256, 0, st>>>(rows, static_cast<float *>(V), ldv, c0, c1);
+  else zero_cols_kernel<double><<<g, 256, 0, st>>>(rows, static_cast<double *>(V), ldv, c0, c1);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -79,11 +79,12 @@ __global__ __launch_bounds__(TPB) void pass2_gram_kernel(const double *__restric
   if (reduce_grid<S * S>(g, partials, counter, out) && threadIdx.x == 0) finish_pass2(ss, S, out);
 }
 
-// V[:, ocol:ocol+S] = U T; optionally writes H_{j+1,j} = Hs into H at (hrow, hcol).
-template <int S>
+// V[:, ocol:ocol+S] = U T (stored as T_ELEM); optionally writes H_{j+1,j} = Hs into H at
+// (hrow, hcol).
+template <int S, typename T_ELEM>
 __global__ __launch_bounds__(TPB) void final_kernel(const double *__restrict__ U, int64_t rows,
-                                                    double *__restrict__ V, int64_t ldb, int ocol,
-                                                    double *__restrict__ pout, const SideState *ss,
+                                                    T_ELEM *__restrict__ V, int64_t ldb, int ocol,
+                                                    T_ELEM *__restrict__ pout, const SideState *ss,
                                                     double *H, int64_t ldh, int hrow, int hcol,
                                                     const DevState *ds) {
   if (ds && ds->done) return;
@@ -100,8 +101,8 @@ __global__ __launch_bounds__(TPB) void final_kernel(const double *__restrict__ U
       double v = 0.0;
 #pragma unroll
       for (int a = 0; a < S; ++a) v = fma(u[a], T[a * S + b], v);
-      V[r * ldb + ocol + b] = v;
-      pout[r * S + b] = v;
+      V[r * ldb + ocol + b] = (T_ELEM)v;
+      pout[r * S + b] = (T_ELEM)v;
     }
   }
   if (H && blockIdx.x == 0 && threadIdx.x < S * S) {
@@ -128,9 +129,14 @@ int first_block_t(const SideDesc &sd, const double *C, int64_t ldc_in, double cl
   pass2_gram_kernel<S><<<grid_capped(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.ss, sc.partials,
                                                              sc.counters + CNT_NRM + 1, nullptr);
   HIPOK(hipGetLastError());
-  final_kernel<S><<<grid_rows(sd.rows), TPB, 0, st>>>(sd.U, sd.rows, sd.basis, sd.ldb, 0,
-                                                      sd.panel[0], sd.ss, nullptr, 0, 0, 0,
-                                                      nullptr);
+  if (sd.fp32)
+    final_kernel<S, float><<<grid_rows(sd.rows), TPB, 0, st>>>(
+        sd.U, sd.rows, static_cast<float *>(sd.basis), sd.ldb, 0,
+        static_cast<float *>(sd.panel[0]), sd.ss, nullptr, 0, 0, 0, nullptr);
+  else
+    final_kernel<S, double><<<grid_rows(sd.rows), TPB, 0, st>>>(
+        sd.U, sd.rows, static_cast<double *>(sd.basis), sd.ldb, 0,
+        static_cast<double *>(sd.panel[0]), sd.ss, nullptr, 0, 0, 0, nullptr);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -48,25 +48,26 @@ __global__ __launch_bounds__(TPB) void band_pack_kernel(int p, int q, int s,
 
 // E(r - r0, c) = (M V)(r, c) - sum_t V(r, base(c) + t) Hb(t, c) for c < p (one wave per row,
 // lanes across columns; only rows 0 <= base + t < q of the band enter).
+template <typename T>
 __global__ __launch_bounds__(TPB) void defect_band_kernel(
     int64_t r0, int64_t r1, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const double *__restrict__ val, const double *__restrict__ V, int64_t ldv, int p, int q, int s,
+    const double *__restrict__ val, const T *__restrict__ V, int64_t ldv, int p, int q, int s,
     const double *__restrict__ Hb, int64_t ldhb, double *__restrict__ E, int64_t lde) {
   const int64_t r = r0 + (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
   const int lane = threadIdx.x & (WAVE - 1);
   if (r >= r1) return;
   const int b = rp[r], e = rp[r + 1];
-  const double *vr = V + r * ldv;
+  const T *vr = V + r * ldv;
   double *er = E + (r - r0) * lde;
   for (int j0 = 0; j0 < p; j0 += 4 * WAVE) {
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int z = b; z < e; ++z) {
       const double a = val[z];
-      const double *x = V + (int64_t)ci[z] * ldv;
+      const T *x = V + (int64_t)ci[z] * ldv;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + u * WAVE + lane;
-        if (j < p) acc[u] = fma(a, x[j], acc[u]);
+        if (j < p) acc[u] = fma(a, (double)x[j], acc[u]);
       }
     }
 #pragma unroll
@@ -77,12 +78,20 @@ __global__ __launch_bounds__(TPB) void defect_band_kernel(
         double v = acc[u];
         for (int t = 0; t < 3 * s; ++t) {
           const int row = base + t;
-          if (row >= 0 && row < q) v = fma(-vr[row], Hb[(int64_t)t * ldhb + j], v);
+          if (row >= 0 && row < q) v = fma(-(double)vr[row], Hb[(int64_t)t * ldhb + j], v);
         }
         er[j] = v;
       }
     }
   }
+}
+
+// dst (rows x cols, ldd) = src (float, lds), widened to FP64.
+__global__ __launch_bounds__(TPB) void widen_kernel(int64_t rows, int64_t cols,
+                                                    const float *__restrict__ src, int64_t lds,
+                                                    double *__restrict__ dst, int64_t ldd) {
+  for (int64_t i = blockIdx.x; i < rows; i += gridDim.x)
+    for (int64_t j = threadIdx.x; j < cols; j += TPB) dst[i * ldd + j] = (double)src[i * lds + j];
 }
 
 }  // namespace
@@ -107,7 +116,8 @@ int launch_rhat(int s, int q, const double *Lx, const double *R0, double *Rh, in
 }
 
 int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
-                       const double *val, const double *V, int64_t ldv, int p, int q, int s,
+                       const double *val, const void *V, bool v_fp32, int64_t ldv, int p, int q,
+                       int s,
                        const double *H, int64_t ldh, double *Hb, int64_t ldhb, bool pack,
                        double *E, int64_t lde, hipStream_t st) {
   if (p <= 0 || r1 <= r0) return 0;
@@ -116,8 +126,23 @@ int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t 
     HIPOK(hipGetLastError());
   }
   const int64_t nr = r1 - r0;
-  defect_band_kernel<<<(unsigned)((nr + 3) / 4), TPB, 0, st>>>(r0, r1, rp, ci, val, V, ldv, p, q, s,
-                                                               Hb, ldhb, E, lde);
+  const unsigned g = (unsigned)((nr + 3) / 4);
+  if (v_fp32)
+    defect_band_kernel<float><<<g, TPB, 0, st>>>(r0, r1, rp, ci, val, static_cast<const float *>(V),
+                                                 ldv, p, q, s, Hb, ldhb, E, lde);
+  else
+    defect_band_kernel<double><<<g, TPB, 0, st>>>(r0, r1, rp, ci, val,
+                                                  static_cast<const double *>(V), ldv, p, q, s, Hb,
+                                                  ldhb, E, lde);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_widen(int64_t rows, int64_t cols, const float *src, int64_t lds, double *dst,
+                 int64_t ldd, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return 0;
+  widen_kernel<<<(unsigned)std::min<int64_t>(rows, 65536), TPB, 0, st>>>(rows, cols, src, lds, dst,
+                                                                         ldd);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -29,11 +29,12 @@ __global__ __launch_bounds__(SPMM_TPB) void spmm_kernel(int64_t rows,
 
 // Wide SpMM for rows [r0, r1): Y[r - r0, 0:ncols] = A[r, :] X[:, 0:ncols]; one wave per row,
 // lanes across columns (coalesced reads of X rows and writes of Y rows).
+template <typename T>
 __global__ __launch_bounds__(256) void spmm_wide_kernel(int64_t r0, int64_t r1,
                                                         const int32_t *__restrict__ rp,
                                                         const int32_t *__restrict__ ci,
                                                         const double *__restrict__ val,
-                                                        const double *__restrict__ X, int64_t ldx,
+                                                        const T *__restrict__ X, int64_t ldx,
                                                         int ncols, double *__restrict__ Y,
                                                         int64_t ldy) {
   const int64_t r = r0 + (int64_t)blockIdx.x * (blockDim.x / WAVE) + threadIdx.x / WAVE;
@@ -45,11 +46,11 @@ __global__ __launch_bounds__(256) void spmm_wide_kernel(int64_t r0, int64_t r1,
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int q = b; q < e; ++q) {
       const double a = val[q];
-      const double *x = X + (int64_t)ci[q] * ldx;
+      const T *x = X + (int64_t)ci[q] * ldx;
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int j = j0 + u * WAVE + lane;
-        if (j < ncols) acc[u] = fma(a, x[j], acc[u]);
+        if (j < ncols) acc[u] = fma(a, (double)x[j], acc[u]);
       }
     }
 #pragma unroll
@@ -142,13 +143,18 @@ int launch_spmm(int s, int64_t rows, const int32_t *rp, const int32_t *ci, const
 }
 
 int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
-                     const double *val, const double *X, int64_t ldx, int ncols, double *Y,
-                     int64_t ldy, hipStream_t st) {
+                     const double *val, const void *X, bool x_fp32, int64_t ldx, int ncols,
+                     double *Y, int64_t ldy, hipStream_t st) {
   (void)s;
   if (r1 <= r0 || ncols <= 0) return 0;
   const int64_t nr = r1 - r0;
-  spmm_wide_kernel<<<(unsigned)((nr + 3) / 4), 256, 0, st>>>(r0, r1, rp, ci, val, X, ldx, ncols,
-                                                              Y, ldy);
+  const unsigned g = (unsigned)((nr + 3) / 4);
+  if (x_fp32)
+    spmm_wide_kernel<float><<<g, 256, 0, st>>>(r0, r1, rp, ci, val, static_cast<const float *>(X),
+                                               ldx, ncols, Y, ldy);
+  else
+    spmm_wide_kernel<double><<<g, 256, 0, st>>>(r0, r1, rp, ci, val,
+                                                static_cast<const double *>(X), ldx, ncols, Y, ldy);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -24,6 +24,7 @@ SYLV_OK, SYLV_NOT_CONVERGED, SYLV_BREAKDOWN = 0, 1, 2
 SYLV_ERR_INVALID, SYLV_ERR_HIP, SYLV_ERR_WORKSPACE = -1, -2, -3
 SYLV_ERR_RHS_RANK, SYLV_ERR_STATE = -4, -5
 SYLV_METHOD_CG, SYLV_METHOD_BICGSTAB = 0, 1
+SYLV_FP64, SYLV_MIXED_FP32 = 0, 1
 
 
 class SylvError(RuntimeError):
@@ -61,7 +62,7 @@ class sylv_problem(ctypes.Structure):
 
 class sylv_options(ctypes.Structure):
     _fields_ = [("method", c_int), ("max_iter", c_int), ("check_every", c_int),
-                ("record_history", c_int), ("closure_tol", c_double)]
+                ("record_history", c_int), ("closure_tol", c_double), ("precision", c_int)]
 
 
 class sylv_result(ctypes.Structure):
@@ -310,7 +311,7 @@ class Solver:
     arrays (n x s, m x s). ``method`` and ``max_iter`` size the workspace."""
 
     def __init__(self, A, B, C1, C2, lyapunov=False, method=SYLV_METHOD_BICGSTAB, max_iter=200,
-                 check_every=8, closure_tol=1e-12, device="cuda", stream=None):
+                 check_every=8, closure_tol=0.0, precision=0, device="cuda", stream=None):
         import torch
         self.device = device
         self.n, self.s = C1.shape
@@ -324,7 +325,7 @@ class Solver:
             self.n, self.m, self.s, make_csr(self.n, *self._A), make_csr(self.m, *self._B),
             1 if lyapunov else 0, _ptr(self._C1), self.s, _ptr(self._C2), self.s)
         self.options = default_options(method, max_iter, check_every=check_every,
-                                       closure_tol=closure_tol)
+                                       closure_tol=closure_tol, precision=precision)
         nbytes = sylv_workspace_bytes(self.problem, self.options)
         if nbytes == 0:
             raise SylvError(SYLV_ERR_INVALID, "sylv_workspace_bytes")

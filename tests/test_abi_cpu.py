@@ -24,7 +24,8 @@ def test_status_strings_and_defaults():
     assert "rank" in sylv.status_string(sylv.SYLV_ERR_RHS_RANK)
     assert sylv.status_string(12345) == "unknown status"
     o = sylv.default_options()
-    assert o.max_iter > 0 and o.check_every > 0 and 0 < o.closure_tol < 1e-6
+    assert o.max_iter > 0 and o.check_every > 0 and o.closure_tol == 0.0
+    assert o.precision == sylv.SYLV_FP64
 
 
 def _problem(n=256, m=192, s=1, lyap=0, nnzA=766, nnzB=574):

@@ -77,7 +77,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--max-iter", type=int, default=0)
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="storage of the Krylov bases (fp32: mixed precision)")
+    ap.add_argument("--refine", type=int, default=-1,
+                    help="correction solves of the outer refinement (default: 3 with fp32 "
+                         "bases, 0 with fp64)")
     args = ap.parse_args()
+    if args.refine < 0:
+        args.refine = 3 if args.precision == "fp32" else 0
     if args.gpus != 1:
         print(json.dumps({"error": "this library runs one solve on one GPU; --gpus must be 1"}))
         sys.exit(2)
@@ -100,10 +107,15 @@ def main():
         csrB, C2 = sylv.make_csr(p.m, rpB, ciB, vaB), torch.as_tensor(p.C2, device=dev)
     prob = sylv.sylv_problem(p.n, p.m, p.s, sylv.make_csr(p.n, rpA, ciA, vaA), csrB,
                              1 if p.lyapunov else 0, C1.data_ptr(), p.s, C2.data_ptr(), p.s)
+    mixed = args.precision == "fp32"
     opts = sylv.default_options(sylv.SYLV_METHOD_CG if cg else sylv.SYLV_METHOD_BICGSTAB,
-                                p.max_iter, check_every=8)
+                                p.max_iter, check_every=8,
+                                precision=sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64,
+                                refine_max=args.refine, refine_max_iter=100)
     ws = torch.empty(sylv.sylv_workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
     rmax = (p.max_iter + 1 if cg else 2 * p.max_iter + 1) * p.s
+    if args.refine > 0:  # the summed iterate stacks the corrections' bases
+        rmax += args.refine * (101 if cg else 201) * 8
     V = torch.empty((p.n, rmax), dtype=torch.float64, device=dev)
     W = V if p.lyapunov else torch.empty((p.m, rmax), dtype=torch.float64, device=dev)
     Xc = torch.empty((rmax, rmax), dtype=torch.float64, device=dev)
@@ -164,12 +176,15 @@ def main():
     out = {
         "metric": METRIC, "value": round(iters / dt, 2), "unit": "iters/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-basis/f64" if mixed else "f64",
         "data": "synthetic",
         "config": {"workload": p.meta["workload"] + f", tol {p.tol:g}, seeded N(0,1) C1/C2",
                    "n": p.n, "m": p.m, "s": p.s, "lyapunov": bool(p.lyapunov),
                    "method": "factored CG" if cg else "factored BiCGSTAB",
                    "max_iter": p.max_iter, "iters_per_solve": iters // args.steps,
+                   "basis_precision": args.precision, "refine_max": args.refine,
+                   "outer_steps": int(res.outer_steps),
                    "rank": int(res.rank_v), "time_to_solution_ms": round(ms_per_step, 3),
                    "profiled_solve_ms": round(solve_ms, 3),
                    "true_rel_res": float(np.max(rels)), "statuses": sorted(set(statuses))},

@@ -88,7 +88,13 @@ typedef struct {
  * closure_tol times ||M V_j||_F is replaced by a zero block (Krylov space exhausted); <= 0
  * selects the default of the precision (1e-12 for FP64, 1e-6 for FP32 bases).
  * precision: SYLV_FP64 or SYLV_MIXED_FP32 (storage of the bases, see above).
- * sylv_default_options() fills sensible values. */
+ * Outer refinement (0 < refine_max <= 4; used with SYLV_MIXED_FP32): after the solve, the
+ * residual R = C1 C2^T - A X - X B of the iterate is sketched, Y = R Omega with a Gaussian
+ * m x refine_rank matrix, compressed to the rank-k right-hand side P (R^T P)^T with P an
+ * orthonormal basis of Y, and a correction equation with that right-hand side is solved (with
+ * at most refine_max_iter iterations); this repeats until the FP64 true residual of the summed
+ * iterate meets the tolerance or refine_max corrections ran. refine_inner_tol > tol lets the
+ * first solve stop earlier. sylv_default_options() fills sensible values. */
 typedef struct {
   int method;
   int max_iter;
@@ -96,10 +102,17 @@ typedef struct {
   int record_history;
   double closure_tol;
   int precision;
+  int refine_max;
+  int refine_max_iter;
+  int refine_rank;
+  double refine_inner_tol;
 } sylv_options;
 
 /* Outcome of one solve. rank_v / rank_w: number of columns of the returned V and W;
- * rel_res_recursive: ||R_k|| / ||R_0|| from the recurrence (the algorithm's stopping test). */
+ * rel_res_recursive: ||R_k|| / ||R_0|| from the recurrence (the algorithm's stopping test).
+ * With outer refinement: iters sums the iterations of all solves, outer_steps counts the
+ * correction solves, the factors are those of the summed iterate and rel_res_true is its FP64
+ * true relative residual (status SYLV_OK when it meets tol); otherwise rel_res_true < 0. */
 typedef struct {
   int status;
   int iters;
@@ -107,6 +120,8 @@ typedef struct {
   int64_t rank_w;
   double rel_res_recursive;
   double seconds;
+  int outer_steps;
+  double rel_res_true;
 } sylv_result;
 
 void sylv_default_options(sylv_options *opt);

@@ -28,10 +28,23 @@ struct Layout {
   size_t off_V, off_W, off_H, off_G, off_X, off_R, off_P, off_Q, off_S, off_T;
   size_t off_U, off_Uw, off_coefV, off_coefW, off_btrp, off_btci, off_btval, off_tscr;
   size_t off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
-  size_t off_E, off_GVV, off_GWW, off_GVE, off_GWE, off_GEEa, off_GEEb, off_Lx, off_M1, off_M2;
+  size_t off_Lx, off_M2, off_d1, off_d2, off_c2;
   size_t off_dots, off_flag, off_panV, off_panW, off_sellA, off_sellB;
+  // outer refinement: correction contexts and the buffers of the sketch and of the residual of
+  // the summed iterates (child: a correction context, whose operators belong to the parent)
+  int child = 0, refine_max = 0, refine_q = 0, refine_iter = 0;
+  size_t child_bytes = 0, off_child = 0;
+  int64_t rows_max = 0, smax = 0, cmax = 0, ldE = 0, child_rmax = 0;
+  size_t tn_cap = 0;
+  size_t off_Om, off_Zb, off_Yb, off_Eb, off_Fb, off_Pp, off_Qp, off_sa, off_sb, off_sc2, off_sd,
+      off_sk, off_sT, off_tn, off_atrp, off_atci, off_atval, off_atscr, off_GL, off_GN, off_Mc,
+      off_Mt, off_T1, off_T2, off_Es, off_rinfo, off_gpart;
   size_t total = 0;
 };
+
+constexpr int NLD = 64;         // row stride (doubles) of the narrow panels of the refinement
+constexpr int REFINE_CAP = 4;   // correction solves at most
+constexpr size_t GPART_CAP = (size_t)1024 * 64 * 64;  // split-K partial tiles of the Grams
 
 size_t bump(size_t &cur, size_t bytes) {
   const size_t o = (cur + ALIGN - 1) / ALIGN * ALIGN;
@@ -47,8 +60,9 @@ int check_csr_header(const sylv_csr &M, int64_t rows) {
   return 0;
 }
 
-int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
+int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool child = false) {
   if (!pb || !op) return SYLV_ERR_INVALID;
+  L.child = child ? 1 : 0;
   if (pb->n <= 0 || pb->m <= 0 || pb->s < 1 || pb->s > SYLV_MAX_S) return SYLV_ERR_INVALID;
   if (pb->s > std::min(pb->n, pb->m)) return SYLV_ERR_INVALID;
   if (pb->lyapunov && pb->n != pb->m) return SYLV_ERR_INVALID;
@@ -104,7 +118,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.off_Uw = bump(cur, (size_t)L.m * L.s * 8);
   L.off_coefV = bump(cur, (size_t)L.ldb * L.s * 8);
   L.off_coefW = bump(cur, (size_t)L.ldb * L.s * 8);
-  const int64_t bnnz = L.lyap ? 0 : pb->B.nnz;
+  const int64_t bnnz = (L.lyap || child) ? 0 : pb->B.nnz;
   L.off_btrp = bump(cur, (size_t)(L.m + 1) * 4);
   L.off_btci = bump(cur, (size_t)std::max<int64_t>(bnnz, 1) * 4);
   L.off_btval = bump(cur, (size_t)std::max<int64_t>(bnnz, 1) * 8);
@@ -118,23 +132,84 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L) {
   L.off_rl = bump(cur, SYLV_MAX_S * SYLV_MAX_S * 8);
   L.off_rr = bump(cur, SYLV_MAX_S * SYLV_MAX_S * 8);
   L.off_hist = bump(cur, (size_t)4 * L.Jmax * 8);
-  // true-residual buffers
-  L.off_E = bump(cur, (size_t)L.rc_rows * L.ldb * 8);
-  L.off_GVV = bump(cur, c2);
-  L.off_GWW = bump(cur, c2);
-  L.off_GVE = bump(cur, c2);
-  L.off_GWE = bump(cur, c2);
-  L.off_GEEa = bump(cur, c2);
-  L.off_GEEb = bump(cur, c2);
+  // true-residual buffers: R^ core, band scratch, right-hand-side QR defects and a copy of C2
   L.off_Lx = bump(cur, c2);
-  L.off_M1 = bump(cur, c2);
   L.off_M2 = bump(cur, c2);
+  L.off_d1 = bump(cur, (size_t)L.n * L.s * 8);
+  L.off_d2 = L.lyap ? L.off_d1 : bump(cur, (size_t)L.m * L.s * 8);
+  L.off_c2 = bump(cur, (size_t)L.m * L.s * 8);  // C2 (C1 for Lyapunov)
   L.off_panV = bump(cur, (size_t)2 * L.n * L.s * L.esz);
   L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * L.esz);
-  L.off_sellA = bump(cur, sell_bytes(L.n, pb->A.nnz));
-  L.off_sellB = L.lyap ? L.off_sellA : bump(cur, sell_bytes(L.m, pb->B.nnz));
+  L.off_sellA = child ? 0 : bump(cur, sell_bytes(L.n, pb->A.nnz));
+  L.off_sellB = (L.lyap || child) ? L.off_sellA : bump(cur, sell_bytes(L.m, pb->B.nnz));
   L.off_dots = bump(cur, 16 * 8);
   L.off_flag = bump(cur, 16 * sizeof(int));
+  if (!child && op->refine_max > 0) {
+    if (op->refine_max > REFINE_CAP || op->refine_rank < 1 || op->refine_rank > SYLV_MAX_S ||
+        op->refine_max_iter < 1)
+      return SYLV_ERR_INVALID;
+    L.refine_max = op->refine_max;
+    L.refine_q = op->refine_rank;
+    L.refine_iter = op->refine_max_iter;
+    // a correction is a Sylvester problem with a rank <= refine_q right-hand side (for Lyapunov
+    // with B = A^T, since the residual need not be semidefinite)
+    sylv_problem cp = *pb;
+    cp.s = std::min<int64_t>(L.refine_q, std::min(pb->n, pb->m));
+    cp.lyapunov = 0;
+    cp.B = pb->lyapunov ? pb->A : pb->B;
+    cp.B.rows = pb->m;
+    cp.C1 = cp.C2 = reinterpret_cast<const double *>(ALIGN);
+    cp.ldc1 = cp.ldc2 = NLD;
+    sylv_options co = *op;
+    co.max_iter = L.refine_iter;
+    co.refine_max = 0;
+    Layout CL;
+    if ((e = make_layout(&cp, &co, CL, true))) return e;
+    L.child_bytes = (CL.total + ALIGN - 1) / ALIGN * ALIGN;
+    L.off_child = bump(cur, L.child_bytes * L.refine_max);
+    L.rows_max = std::max(L.n, L.m);
+    const size_t panel = (size_t)L.rows_max * NLD * 8;
+    L.off_Om = bump(cur, panel);
+    L.off_Zb = bump(cur, panel);
+    L.off_Yb = bump(cur, panel);
+    L.off_Eb = bump(cur, panel);
+    L.off_Fb = bump(cur, panel);
+    L.off_Pp = bump(cur, (size_t)L.refine_max * L.n * NLD * 8);
+    L.off_Qp = bump(cur, (size_t)L.refine_max * L.m * NLD * 8);
+    L.smax = std::max(L.rmax, CL.rmax) + 2 * SYLV_MAX_S;
+    const size_t small = (size_t)L.smax * NLD * 8;
+    L.off_sa = bump(cur, small);
+    L.off_sb = bump(cur, small);
+    L.off_sc2 = bump(cur, small);
+    L.off_sd = bump(cur, small);
+    L.off_sk = bump(cur, small);
+    L.off_sT = bump(cur, small);
+    L.tn_cap = tn_partials_needed(L.rows_max, L.smax, SYLV_MAX_S);
+    L.off_tn = bump(cur, L.tn_cap * 8);
+    L.off_atrp = bump(cur, (size_t)(L.n + 1) * 4);
+    L.off_atci = bump(cur, (size_t)std::max<int64_t>(pb->A.nnz, 1) * 4);
+    L.off_atval = bump(cur, (size_t)std::max<int64_t>(pb->A.nnz, 1) * 8);
+    L.off_atscr = bump(cur, csr_transpose_scratch(L.n));
+    L.child_rmax = CL.rmax;
+    L.off_rinfo = bump(cur, 64 * 8);
+  }
+  if (!child) {
+    // residual of the (summed) iterate, R = L M N^T over the stacked tall factors of every
+    // step: L = [V_j+, E_A,j, D1_j, ...; P_i], N = [W_j+, E_B,j, D2_j, C2_j, ...; Q_i]
+    const int64_t q1 = L.refine_q;
+    L.cmax = round_up(2 * L.rmax + 4 * L.s + L.refine_max * (2 * L.child_rmax + 5 * q1), 64);
+    const size_t cc = (size_t)L.cmax * L.cmax * 8;
+    L.off_GL = bump(cur, cc);
+    L.off_GN = bump(cur, cc);
+    L.off_Mc = bump(cur, cc);
+    L.off_Mt = bump(cur, cc);
+    L.off_T1 = bump(cur, cc);
+    L.off_T2 = bump(cur, cc);
+    L.ldE = round_up(L.rmax + 2 * L.s, 64) +
+            L.refine_max * round_up(L.child_rmax + 2 * L.refine_q, 64) + 64;
+    L.off_Es = bump(cur, (size_t)L.rc_rows * L.ldE * 8);
+    L.off_gpart = bump(cur, (size_t)GPART_CAP * 8);
+  }
   L.total = cur + ALIGN;
   return 0;
 }
@@ -180,7 +255,7 @@ struct Prof {
     used = 0;
   }
   ~Prof() {
-    for (hipEvent_t e : pool) hipEventDestroy(e);
+    for (hipEvent_t e : pool) (void)hipEventDestroy(e);
   }
 };
 
@@ -208,6 +283,15 @@ struct Ctx {
   double relres = 0.0;
   DevState *h_ds = nullptr;  // pinned
   std::vector<double> h_hist;
+  // outer refinement
+  Ctx *parent = nullptr;
+  std::vector<Ctx *> kids;   // correction contexts of the last refined solve
+  std::vector<int> kid_k;    // their right-hand-side ranks
+  sylv_csr AT{};             // A^T (refinement only)
+  double refine_inner_tol = 0.0;
+  double rel_true = -1.0;    // FP64 true residual of the summed iterate (refined solves)
+  int outer_steps = 0;
+  int in_refine = 0;         // the refinement's own first solve is running
 };
 
 template <typename T>
@@ -221,7 +305,7 @@ void prof_begin(const Scratch &sc, hipStream_t st) {
   Prof *p = reinterpret_cast<Prof *>(sc.prof);
   if (!p) return;
   p->start = p->get();
-  if (p->start) hipEventRecord(p->start, st);
+  if (p->start) (void)hipEventRecord(p->start, st);
 }
 
 void prof_end(const Scratch &sc, int fam, double bytes, double flops, hipStream_t st) {
@@ -229,7 +313,7 @@ void prof_end(const Scratch &sc, int fam, double bytes, double flops, hipStream_
   if (!p || !p->start) return;
   hipEvent_t e = p->get();
   if (!e) return;
-  hipEventRecord(e, st);
+  (void)hipEventRecord(e, st);
   p->recs.push_back(Prof::Rec{fam, p->iter, p->start, e, bytes, flops});
   p->start = nullptr;
 }
@@ -297,58 +381,20 @@ int end_solve(Ctx *c, int max_iter, double seconds, sylv_result *res) {
     res->rank_v = res->rank_w = c->rank;
     res->rel_res_recursive = c->relres;
     res->seconds = seconds;
+    res->outer_steps = 0;
+    res->rel_res_true = -1.0;
   }
   return c->status;
 }
 
-}  // namespace
-
-thread_local char g_last_error[512] = "";
-
-void note_hip_error(hipError_t e, const char *what) {
-  snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
-}
-
-extern "C" {
-
-const char *sylv_last_error(void) { return g_last_error; }
-
-void sylv_default_options(sylv_options *opt) {
-  if (!opt) return;
-  opt->method = SYLV_METHOD_BICGSTAB;
-  opt->max_iter = 200;
-  opt->check_every = 8;
-  opt->record_history = 1;
-  opt->closure_tol = 0.0;  // precision default
-  opt->precision = SYLV_FP64;
-}
-
-size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt) {
-  Layout L;
-  if (make_layout(prob, opt, L)) return 0;
-  return L.total;
-}
-
-const char *sylv_status_string(int status) {
-  switch (status) {
-    case SYLV_OK: return "converged";
-    case SYLV_NOT_CONVERGED: return "not converged (max_iter reached)";
-    case SYLV_BREAKDOWN: return "breakdown";
-    case SYLV_ERR_INVALID: return "invalid argument";
-    case SYLV_ERR_HIP: return "HIP runtime error";
-    case SYLV_ERR_WORKSPACE: return "workspace too small or misaligned";
-    case SYLV_ERR_RHS_RANK: return "right-hand-side factor is rank deficient";
-    case SYLV_ERR_STATE: return "call out of order";
-    default: return "unknown status";
-  }
-}
-
-int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void *workspace,
-                size_t ws_bytes, void *stream) {
+// Creates a context; with a parent, a correction context of the outer refinement: the problem's
+// operators (CSR validated, B^T and the sliced-ELLPACK copies) are the parent's.
+int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void *workspace,
+               size_t ws_bytes, void *stream, Ctx *parent) {
   if (!out) return SYLV_ERR_INVALID;
   *out = nullptr;
   Layout L;
-  int e = make_layout(pb, op, L);
+  int e = make_layout(pb, op, L, parent != nullptr);
   if (e) return e;
   if (!workspace || ws_bytes < L.total) return SYLV_ERR_WORKSPACE;
   Ctx *c = new (std::nothrow) Ctx();
@@ -358,6 +404,8 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
   c->A = pb->A;
   c->B = pb->B;
   c->closure_tol = op->closure_tol > 0 ? op->closure_tol : (L.fp32 ? 1e-6 : 1e-12);
+  c->parent = parent;
+  c->refine_inner_tol = op->refine_inner_tol;
   c->check_every = op->check_every > 0 ? op->check_every : 8;
   c->record_history = op->record_history;
   c->ws = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(workspace) + ALIGN - 1) / ALIGN * ALIGN);
@@ -399,11 +447,11 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
       hipMemsetAsync(c->ds, 0, sizeof(DevState), st) != hipSuccess ||
       hipMemsetAsync(c->flag, 0, 16 * sizeof(int), st) != hipSuccess)
     return fail(SYLV_ERR_HIP);
-  // validate CSR structure on the device
-  if ((e = launch_csr_validate(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, c->flag, st)))
+  // validate CSR structure on the device (a correction context reuses the parent's operators)
+  if (!parent && (e = launch_csr_validate(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, c->flag, st)))
     return fail(e);
-  if (!L.lyap && (e = launch_csr_validate(L.m, pb->B.nnz, pb->B.row_ptr, pb->B.col_idx,
-                                          c->flag + 1, st)))
+  if (!parent && !L.lyap &&
+      (e = launch_csr_validate(L.m, pb->B.nnz, pb->B.row_ptr, pb->B.col_idx, c->flag + 1, st)))
     return fail(e);
   int hflag[2] = {0, 0};
   if (hipMemcpyAsync(hflag, c->flag, sizeof(hflag), hipMemcpyDeviceToHost, st) != hipSuccess ||
@@ -411,7 +459,7 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
     return fail(SYLV_ERR_HIP);
   if (hflag[0] || hflag[1]) return fail(SYLV_ERR_INVALID);
   // W side operator: B^T
-  if (!L.lyap) {
+  if (!L.lyap && !parent) {
     if ((e = launch_csr_transpose(L.m, pb->B.nnz, pb->B.row_ptr, pb->B.col_idx, pb->B.values,
                                   c->btrp, c->btci, c->btval, at<void>(c, L.off_tscr), st)))
       return fail(e);
@@ -428,13 +476,30 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
                      c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw,
                      {panw, panw + L.m * L.s * L.esz}, L.fp32, SellMat{}};
   }
+  if (parent) {
+    // operators of the parent: V side A; W side B^T (A when the parent is a Lyapunov problem)
+    const SideDesc &pw = parent->L.lyap ? parent->sv : parent->sw;
+    c->sv.rp = parent->sv.rp;
+    c->sv.ci = parent->sv.ci;
+    c->sv.val = parent->sv.val;
+    c->sv.nnz = parent->sv.nnz;
+    c->sv.sell = parent->sv.sell;
+    c->sw.rp = pw.rp;
+    c->sw.ci = pw.ci;
+    c->sw.val = pw.val;
+    c->sw.nnz = pw.nnz;
+    c->sw.sell = pw.sell;
+  }
   // SELL copies of A and B^T for the Krylov SpMM (CSR stays in use if the padding is large)
-  c->sv.sell = SellMat{};
-  e = build_sell(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
-                 at<void>(c, L.off_sellA), st);
-  if (e == 0) c->sv.sell = sell_view(L.n, pb->A.nnz, at<void>(c, L.off_sellA));
-  else if (e != SYLV_ERR_WORKSPACE) return fail(e);
-  if (L.lyap) {
+  if (!parent) c->sv.sell = SellMat{};
+  if (!parent) {
+    e = build_sell(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
+                   at<void>(c, L.off_sellA), st);
+    if (e == 0) c->sv.sell = sell_view(L.n, pb->A.nnz, at<void>(c, L.off_sellA));
+    else if (e != SYLV_ERR_WORKSPACE) return fail(e);
+  }
+  if (parent) {
+  } else if (L.lyap) {
     c->sw.sell = c->sv.sell;
   } else {
     c->sw.sell = SellMat{};
@@ -465,6 +530,30 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
       return fail(SYLV_ERR_HIP);
     hs[1] = hs[0];
   }
+  // right-hand-side QR defects D1 = C1 - V_1 R_L, D2 = C2 - W_1 R_R and a copy of C2, for the
+  // true residual (C1, C2 are not read after creation)
+  {
+    const double *C2in = L.lyap ? pb->C1 : pb->C2;
+    const int64_t ld2 = L.lyap ? pb->ldc1 : pb->ldc2;
+    if ((e = launch_qr_defect(L.n, s, pb->C1, pb->ldc1, c->sv.basis, L.fp32, L.ldb, c->RL,
+                              at<double>(c, L.off_d1), st)))
+      return fail(e);
+    if (!L.lyap && (e = launch_qr_defect(L.m, s, pb->C2, pb->ldc2, c->sw.basis, L.fp32, L.ldb,
+                                         c->RR, at<double>(c, L.off_d2), st)))
+      return fail(e);
+    if (hipMemcpy2DAsync(at<double>(c, L.off_c2), s * 8, C2in, ld2 * 8, s * 8, L.m,
+                         hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return fail(SYLV_ERR_HIP);
+  }
+  // A^T for the refinement's products with the transposed residual
+  if (L.refine_max > 0) {
+    int32_t *atrp = at<int32_t>(c, L.off_atrp), *atci = at<int32_t>(c, L.off_atci);
+    double *atval = at<double>(c, L.off_atval);
+    if ((e = launch_csr_transpose(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values, atrp,
+                                  atci, atval, at<void>(c, L.off_atscr), st)))
+      return fail(e);
+    c->AT = sylv_csr{L.n, pb->A.nnz, atrp, atci, atval};
+  }
   if (hipStreamSynchronize(st) != hipSuccess) return fail(SYLV_ERR_HIP);
   for (int i = 0; i < 2; ++i) {
     if (!std::isfinite(hs[i].ref2)) return fail(SYLV_ERR_INVALID);
@@ -474,9 +563,500 @@ int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void
   return 0;
 }
 
+
+
+// ---- outer refinement (mixed precision) ----
+// The residual of the summed iterate X = sum_j V_j X_j W_j^T, where step 0 solves the problem
+// and step j >= 1 the correction equation with right-hand side P_j Q_j^T, is
+//   R = sum_j D_j - sum_{j>=1} P_j Q_j^T,
+//   D_j = D1 C2^T + V_1 R_L D2^T + V_j+ R^_j W_j+^T - E_A,j X_j W_j^T - V_j X_j E_B,j^T
+// (the defect form of each step: E_A = A V - V+ H, E_B = B^T W - W+ G, R^ = C_core - L(X),
+// D1 = C1 - V_1 R_L, D2 = C2 - W_1 R_R for the step's right-hand side C1 C2^T).
+// Products of R and R^T with narrow panels need only the factors; the FP64 norm of R is the
+// trace <G_L M, M G_N> over the Grams of the stacked tall factors.
+
+// R^_j = [R0 0; 0 0] - L(X_j) into the step's Lx buffer.
+int compute_rhat(Ctx *cj) {
+  const Layout &L = cj->L;
+  const int s = (int)L.s;
+  const int64_t p = cj->rank, q = p + s;
+  double *Lx = at<double>(cj, L.off_Lx);
+  int e = launch_core_op(s, (int)p, cj->H, cj->G, cj->X, Lx, L.ldc, nullptr, cj->st);
+  if (e) return e;
+  return launch_rhat(s, (int)q, Lx, cj->Rt, Lx, L.ldc, cj->st);
+}
+
+// Y (left rows x qz) += D_j Z (trans: D_j^T Z), Z (right rows x qz); narrow panels of stride
+// NLD; R^_j must be current in the step's Lx buffer. D_j includes the right-hand-side defect
+// D1 C2^T + V_1 R_L D2^T (the QR of C1, C2 holds only to the basis storage precision).
+int apply_step(Ctx *P, Ctx *cj, bool trans, int qz, const double *Z, double *Y) {
+  const Layout &PL = P->L, &CL = cj->L;
+  hipStream_t st = P->st;
+  const SideDesc &Ls = trans ? cj->sw : cj->sv;
+  const SideDesc &Rs = trans ? cj->sv : cj->sw;
+  const double *Hl = trans ? cj->G : cj->H, *Hr = trans ? cj->H : cj->G;
+  // transpose of the right side's operator: B (of B^T) or A^T
+  const sylv_csr &MrT = (trans || PL.lyap) ? P->AT : P->B;
+  const int64_t p = cj->rank, q = p + CL.s, ldc = CL.ldc, ldb = CL.ldb;
+  if (p == 0) return 0;
+  const bool f32 = CL.fp32;
+  double *a = at<double>(P, PL.off_sa), *b = at<double>(P, PL.off_sb);
+  double *c2 = at<double>(P, PL.off_sc2), *d = at<double>(P, PL.off_sd);
+  double *Zb = at<double>(P, PL.off_Zb), *Eb = at<double>(P, PL.off_Eb);
+  double *Fb = at<double>(P, PL.off_Fb), *tn = at<double>(P, PL.off_tn);
+  const double *Rh = at<double>(cj, CL.off_Lx);
+  const int64_t xr = trans ? 1 : ldc, xc = trans ? ldc : 1;
+  const int s = (int)CL.s;
+  const double *D1 = at<double>(cj, CL.off_d1), *D2 = at<double>(cj, CL.off_d2);
+  const double *C2 = at<double>(cj, CL.off_c2);
+  int e;
+  // right-hand-side defect D1 C2^T + V_1 R_L D2^T (transposed: C2 D1^T + D2 R_L^T V_1^T)
+  if (!trans) {
+    if ((e = launch_tn(Rs.rows, s, qz, C2, false, s, Z, NLD, a, NLD, tn, PL.tn_cap, st))) return e;
+    if ((e = launch_nn(Ls.rows, s, qz, 1.0, D1, false, s, a, NLD, 1.0, Y, NLD, st))) return e;
+    if ((e = launch_tn(Rs.rows, s, qz, D2, false, s, Z, NLD, b, NLD, tn, PL.tn_cap, st))) return e;
+    if ((e = launch_gemm(s, qz, s, 1.0, cj->RL, s, 1, b, NLD, 1, 0.0, c2, NLD, st))) return e;
+    if ((e = launch_nn(Ls.rows, s, qz, 1.0, Ls.basis, f32, ldb, c2, NLD, 1.0, Y, NLD, st)))
+      return e;
+  } else {
+    if ((e = launch_tn(Rs.rows, s, qz, D1, false, s, Z, NLD, a, NLD, tn, PL.tn_cap, st))) return e;
+    if ((e = launch_nn(Ls.rows, s, qz, 1.0, C2, false, s, a, NLD, 1.0, Y, NLD, st))) return e;
+    if ((e = launch_tn(Rs.rows, s, qz, Rs.basis, f32, ldb, Z, NLD, b, NLD, tn, PL.tn_cap, st)))
+      return e;
+    if ((e = launch_gemm(s, qz, s, 1.0, cj->RL, 1, s, b, NLD, 1, 0.0, c2, NLD, st))) return e;
+    if ((e = launch_nn(Ls.rows, s, qz, 1.0, D2, false, s, c2, NLD, 1.0, Y, NLD, st))) return e;
+  }
+  // a = R+^T Z; b = E_R^T Z = R_p^T (M_R^T Z) - H_R^T a
+  if ((e = launch_tn(Rs.rows, (int)q, qz, Rs.basis, f32, ldb, Z, NLD, a, NLD, tn, PL.tn_cap, st)))
+    return e;
+  if ((e = launch_spmm(qz, Rs.rows, MrT.row_ptr, MrT.col_idx, MrT.values, Z, NLD, Zb, NLD, st)))
+    return e;
+  if ((e = launch_tn(Rs.rows, (int)p, qz, Rs.basis, f32, ldb, Zb, NLD, b, NLD, tn, PL.tn_cap, st)))
+    return e;
+  if ((e = launch_gemm(p, qz, q, -1.0, Hr, 1, ldc, a, NLD, 1, 1.0, b, NLD, st))) return e;
+  // d = R^ a + H_L X a_p - [X b; 0]; c2 = X a_p
+  if ((e = launch_gemm(q, qz, q, 1.0, Rh, xr, xc, a, NLD, 1, 0.0, d, NLD, st))) return e;
+  if ((e = launch_gemm(p, qz, p, 1.0, cj->X, xr, xc, a, NLD, 1, 0.0, c2, NLD, st))) return e;
+  if ((e = launch_gemm(q, qz, p, 1.0, Hl, ldc, 1, c2, NLD, 1, 1.0, d, NLD, st))) return e;
+  if ((e = launch_gemm(p, qz, p, -1.0, cj->X, xr, xc, b, NLD, 1, 1.0, d, NLD, st))) return e;
+  // Y += L+ d - M_L (L_p c2)
+  if ((e = launch_nn(Ls.rows, (int)q, qz, 1.0, Ls.basis, f32, ldb, d, NLD, 1.0, Y, NLD, st)))
+    return e;
+  if ((e = launch_nn(Ls.rows, (int)p, qz, 1.0, Ls.basis, f32, ldb, c2, NLD, 0.0, Eb, NLD, st)))
+    return e;
+  if ((e = launch_spmm(qz, Ls.rows, Ls.rp, Ls.ci, Ls.val, Eb, NLD, Fb, NLD, st))) return e;
+  return launch_axpy_narrow(Ls.rows, qz, -1.0, Fb, NLD, Y, NLD, st);
+}
+
+double *pp_panel(Ctx *P, int i) { return at<double>(P, P->L.off_Pp) + (size_t)i * P->L.n * NLD; }
+double *qq_panel(Ctx *P, int i) { return at<double>(P, P->L.off_Qp) + (size_t)i * P->L.m * NLD; }
+
+// Y (n x qz) += R Z (trans: Y (m x qz) += R^T Z) over the steps and the compressed right-hand
+// sides of the corrections so far.
+int apply_residual(Ctx *P, const std::vector<Ctx *> &steps, bool trans, int qz, const double *Z,
+                   double *Y) {
+  const Layout &PL = P->L;
+  double *sk = at<double>(P, PL.off_sk), *tn = at<double>(P, PL.off_tn);
+  int e;
+  for (Ctx *cj : steps)
+    if ((e = apply_step(P, cj, trans, qz, Z, Y))) return e;
+  for (size_t i = 0; i + 1 < steps.size(); ++i) {
+    // - P_i Q_i^T Z  (trans: - Q_i P_i^T Z)
+    const int k = P->kid_k[i];
+    const double *Rp = trans ? pp_panel(P, (int)i) : qq_panel(P, (int)i);
+    const double *Lp = trans ? qq_panel(P, (int)i) : pp_panel(P, (int)i);
+    const int64_t rr = trans ? PL.n : PL.m, lr = trans ? PL.m : PL.n;
+    if ((e = launch_tn(rr, k, qz, Rp, false, NLD, Z, NLD, sk, NLD, tn, PL.tn_cap, P->st))) return e;
+    if ((e = launch_nn(lr, k, qz, -1.0, Lp, false, NLD, sk, NLD, 1.0, Y, NLD, P->st))) return e;
+  }
+  return 0;
+}
+
+// Frobenius norm of the residual R = L M N^T of the (summed) iterate from the Grams of the
+// stacked tall factors: per step j, L gets [V_j+, E_A,j, D1_j] and N gets [W_j+, E_B,j, D2_j,
+// C2_j]; per correction i, L gets P_i and N gets Q_i. With D1 = C1 - V_1 R_L and
+// D2 = C2 - W_1 R_R (the right-hand side's QR defects, O(u) of the basis storage precision),
+//   R_j = D1 C2^T + V_1 R_L D2^T + V+ R^ W+^T - E_A X W^T - V X E_B^T,
+// and ||R||^2 = <G_L M, M G_N>. No term cancels against ||C1 C2^T||: every block is of the size
+// of the residual or of a defect.
+int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, double *rel_res) {
+  const Layout &PL = P->L;
+  hipStream_t st = P->st;
+  int e;
+  struct Seg {
+    const char *ptr;  // rowed: row r at ptr + r ld esz; else E-buffer columns (chunk rows)
+    bool f32, rowed;
+    int64_t ld, cols, esz;
+    const double *unused;
+  };
+  double *Es = at<double>(P, PL.off_Es);
+  for (Ctx *cj : steps)
+    if (cj->rank > 0 && (e = compute_rhat(cj))) return e;
+  // E-buffer columns per step (64-column aligned): [E_A | D1] on the V side, [E_B | D2 | C2] on
+  // the W side, so each side of a step is two Gram segments (basis, defects)
+  std::vector<int64_t> eoff(steps.size());
+  int64_t eo = 0;
+  for (size_t j = 0; j < steps.size(); ++j) {
+    eoff[j] = eo;
+    eo += round_up(steps[j]->rank + 2 * steps[j]->L.s, 64);
+  }
+  if (eo > PL.ldE) return SYLV_ERR_WORKSPACE;
+  struct Idx {
+    int v, e, w, eb;
+  };
+  std::vector<Idx> idx(steps.size(), Idx{-1, -1, -1, -1});
+  std::vector<Seg> segL, segN;
+  std::vector<int> pL, qN;
+  // compact sources copied per chunk into the E buffer: (step, column offset, source, columns)
+  struct Fill {
+    int64_t col;
+    const double *src;
+    int cols;
+  };
+  std::vector<Fill> fillL, fillN;
+  for (size_t j = 0; j < steps.size(); ++j) {
+    Ctx *cj = steps[j];
+    if (cj->rank == 0) continue;
+    const Layout &CL = cj->L;
+    const int64_t p = cj->rank, q = p + CL.s, s = CL.s;
+    const char *eb = reinterpret_cast<const char *>(Es + eoff[j]);
+    idx[j].v = (int)segL.size();
+    segL.push_back(Seg{static_cast<const char *>(cj->sv.basis), (bool)CL.fp32, true, CL.ldb, q,
+                       CL.esz, nullptr});
+    idx[j].e = (int)segL.size();
+    segL.push_back(Seg{eb, false, false, PL.ldE, p + s, 8, nullptr});
+    fillL.push_back(Fill{eoff[j] + p, at<double>(cj, CL.off_d1), (int)s});
+    idx[j].w = (int)segN.size();
+    segN.push_back(Seg{static_cast<const char *>(cj->sw.basis), (bool)CL.fp32, true, CL.ldb, q,
+                       CL.esz, nullptr});
+    idx[j].eb = (int)segN.size();
+    segN.push_back(Seg{eb, false, false, PL.ldE, p + 2 * s, 8, nullptr});
+    fillN.push_back(Fill{eoff[j] + p, at<double>(cj, CL.off_d2), (int)s});
+    fillN.push_back(Fill{eoff[j] + p + s, at<double>(cj, CL.off_c2), (int)s});
+  }
+  for (size_t i = 0; i + 1 < steps.size(); ++i) {
+    pL.push_back((int)segL.size());
+    segL.push_back(Seg{reinterpret_cast<const char *>(pp_panel(P, (int)i)), false, true, NLD,
+                       P->kid_k[i], 8, nullptr});
+    qN.push_back((int)segN.size());
+    segN.push_back(Seg{reinterpret_cast<const char *>(qq_panel(P, (int)i)), false, true, NLD,
+                       P->kid_k[i], 8, nullptr});
+  }
+  auto offsets = [](const std::vector<Seg> &segs) {
+    std::vector<int64_t> o(segs.size() + 1, 0);
+    for (size_t a = 0; a < segs.size(); ++a) o[a + 1] = o[a] + segs[a].cols;
+    return o;
+  };
+  const std::vector<int64_t> offL = offsets(segL), offN = offsets(segN);
+  const int64_t cL = offL.back(), cN = offN.back(), ldG = PL.cmax;
+  if (cL > PL.cmax || cN > PL.cmax) return SYLV_ERR_WORKSPACE;
+  double *GL = at<double>(P, PL.off_GL), *GN = at<double>(P, PL.off_GN);
+  double *Mc = at<double>(P, PL.off_Mc), *Mt = at<double>(P, PL.off_Mt);
+  double *T1 = at<double>(P, PL.off_T1), *T2 = at<double>(P, PL.off_T2);
+  double *gpart = at<double>(P, PL.off_gpart);
+  auto side_pass = [&](bool w, const std::vector<Seg> &segs, const std::vector<int64_t> &offs,
+                       double *G) -> int {
+    const int64_t rows = w ? PL.m : PL.n;
+    int ee;
+    for (Ctx *cj : steps) {
+      if (cj->rank == 0 || cj->L.method == SYLV_METHOD_CG) continue;
+      const SideDesc &sd = w ? cj->sw : cj->sv;
+      const int64_t q = cj->rank + cj->L.s;
+      const int qk = (int)std::min<int64_t>(round_up(q, 32), cj->L.ldb);
+      if ((ee = launch_zero_cols(sd.rows, sd.basis, cj->L.fp32, cj->L.ldb, (int)q, qk, st)))
+        return ee;
+    }
+    for (int64_t r0 = 0; r0 < rows; r0 += PL.rc_rows) {
+      const int64_t r1 = std::min(rows, r0 + PL.rc_rows), nr = r1 - r0;
+      for (size_t j = 0; j < steps.size(); ++j) {
+        Ctx *cj = steps[j];
+        if (cj->rank == 0) continue;
+        const Layout &CL = cj->L;
+        const SideDesc &sd = w ? cj->sw : cj->sv;
+        const double *Hm = w ? cj->G : cj->H;
+        const int p = (int)cj->rank, q = p + (int)CL.s;
+        double *Ej = Es + eoff[j];
+        if (CL.method == SYLV_METHOD_CG) {
+          if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, sd.basis, CL.fp32, CL.ldb, p, q,
+                                       (int)CL.s, Hm, CL.ldc, at<double>(cj, CL.off_M2), CL.ldc,
+                                       r0 == 0, Ej, PL.ldE, st)))
+            return ee;
+        } else {
+          if ((ee = launch_spmm_rows((int)CL.s, r0, r1, sd.rp, sd.ci, sd.val, sd.basis, CL.fp32,
+                                     CL.ldb, p, Ej, PL.ldE, st)))
+            return ee;
+          const char *vb = static_cast<const char *>(sd.basis) + r0 * CL.ldb * CL.esz;
+          if ((ee = launch_defect_gemm(nr, p, q, (int)CL.s, vb, CL.fp32, CL.ldb, Hm, CL.ldc, Ej,
+                                       PL.ldE, st)))
+            return ee;
+        }
+      }
+      // compact sources (QR defects, C2) next to the defects
+      for (const Fill &f : (w ? fillN : fillL))
+        if ((ee = launch_copy_block((int)nr, f.cols, 1.0, f.src + r0 * f.cols, f.cols, false,
+                                    Es + f.col, PL.ldE, st)))
+          return ee;
+      const double beta = r0 == 0 ? 0.0 : 1.0;
+      for (size_t a = 0; a < segs.size(); ++a)
+        for (size_t b = 0; b <= a; ++b) {
+          const Seg &A = segs[a], &B = segs[b];
+          const char *pa = A.ptr + (A.rowed ? r0 * A.ld * A.esz : 0);
+          const char *pb = B.ptr + (B.rowed ? r0 * B.ld * B.esz : 0);
+          if ((ee = launch_gram(A.cols, B.cols, nr, pa, A.f32, A.ld, pb, B.f32, B.ld, beta,
+                                G + offs[a] * ldG + offs[b], ldG, a == b, st, gpart, GPART_CAP)))
+            return ee;
+        }
+    }
+    return launch_mirror(offs.back(), G, ldG, st);
+  };
+  if ((e = side_pass(false, segL, offL, GL))) return e;
+  if ((e = side_pass(true, segN, offN, GN))) return e;
+  // M (cL x cN) and its transpose Mt (cN x cL)
+  HIPOK(hipMemset2DAsync(Mc, ldG * 8, 0, cN * 8, cL, st));
+  HIPOK(hipMemset2DAsync(Mt, ldG * 8, 0, cL * 8, cN, st));
+  auto put = [&](int64_t r, int64_t c, int rows, int cols, double alpha, const double *src,
+                 int64_t lds) -> int {
+    int ee = launch_copy_block(rows, cols, alpha, src, lds, false, Mc + r * ldG + c, ldG, st);
+    if (ee) return ee;
+    return launch_copy_block(cols, rows, alpha, src, lds, true, Mt + c * ldG + r, ldG, st);
+  };
+  for (size_t j = 0; j < steps.size(); ++j) {
+    Ctx *cj = steps[j];
+    if (cj->rank == 0) continue;
+    const Layout &CL = cj->L;
+    const int p = (int)cj->rank, q = p + (int)CL.s, s = (int)CL.s;
+    const Idx &x = idx[j];
+    const int64_t d1 = offL[x.e] + p, d2 = offN[x.eb] + p, c2 = d2 + s;
+    if ((e = put(offL[x.v], offN[x.w], q, q, 1.0, at<double>(cj, CL.off_Lx), CL.ldc))) return e;
+    if ((e = put(offL[x.e], offN[x.w], p, p, -1.0, cj->X, CL.ldc))) return e;
+    if ((e = put(offL[x.v], offN[x.eb], p, p, -1.0, cj->X, CL.ldc))) return e;
+    if ((e = launch_diag_fill(s, 1.0, Mc + d1 * ldG + c2, ldG, st))) return e;
+    if ((e = launch_diag_fill(s, 1.0, Mt + c2 * ldG + d1, ldG, st))) return e;
+    if ((e = put(offL[x.v], d2, s, s, 1.0, cj->RL, s))) return e;
+  }
+  for (size_t i = 0; i + 1 < steps.size(); ++i) {
+    if ((e = launch_diag_fill(P->kid_k[i], -1.0, Mc + offL[pL[i]] * ldG + offN[qN[i]], ldG, st)))
+      return e;
+    if ((e = launch_diag_fill(P->kid_k[i], -1.0, Mt + offN[qN[i]] * ldG + offL[pL[i]], ldG, st)))
+      return e;
+  }
+  // ||R||^2 = <G_L M, M G_N>, both products as A^T B on the symmetric Grams
+  if ((e = launch_gram(cL, cN, cL, GL, false, ldG, Mc, false, ldG, 0.0, T1, ldG, false, st, gpart,
+                       GPART_CAP)))
+    return e;
+  if ((e = launch_gram(cL, cN, cN, Mt, false, ldG, GN, false, ldG, 0.0, T2, ldG, false, st, gpart,
+                       GPART_CAP)))
+    return e;
+  if ((e = launch_dot(cL, cN, T1, ldG, T2, ldG, P->dots, P->sc, st))) return e;
+  double r2 = 0.0;
+  HIPOK(hipMemcpyAsync(&r2, P->dots, sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPOK(hipStreamSynchronize(st));
+  const double ar = std::sqrt(std::max(r2, 0.0));
+  if (abs_res) *abs_res = ar;
+  if (rel_res) *rel_res = ar / P->h_ds->normR0;
+  return 0;
+}
+
+std::vector<Ctx *> refine_steps(Ctx *P) {
+  std::vector<Ctx *> v{P};
+  v.insert(v.end(), P->kids.begin(), P->kids.end());
+  return v;
+}
+
+// Solve with outer refinement: the first solve (to max(tol, refine_inner_tol)); then, while the
+// sketched residual norm ||R Omega||_F / sqrt(q) (an unbiased estimate of ||R||_F^2 when squared)
+// exceeds tol / 2 and corrections remain, compress R to P (R^T P)^T through the sketch
+// Y = R R^T R Omega (one power step) and solve the correction equation with that right-hand
+// side. The FP64 true
+// residual of the summed iterate is evaluated at the end; if it misses tol while corrections
+// remain, the loop resumes.
+int refined_solve(Ctx *P, int method, double tol, int max_iter, sylv_result *res) {
+  const Layout &PL = P->L;
+  hipStream_t st = P->st;
+  auto t0 = std::chrono::steady_clock::now();
+  for (Ctx *k : P->kids) sylv_destroy(k);
+  P->kids.clear();
+  P->kid_k.clear();
+  P->rel_true = -1.0;
+  P->outer_steps = 0;
+  sylv_result r0{};
+  P->in_refine = 1;
+  int e = (method == SYLV_METHOD_CG)
+              ? sylv_factored_cg(P, std::max(tol, P->refine_inner_tol), max_iter, &r0)
+              : sylv_factored_bicgstab(P, std::max(tol, P->refine_inner_tol), max_iter, &r0);
+  P->in_refine = 0;
+  if (e < 0) return e;
+  const int first_status = e;
+  const double normR0 = P->h_ds->normR0;
+  int total_iters = r0.iters;
+  double rel = -1.0, absr = 0.0;
+  const int q = (int)std::min<int64_t>(PL.refine_q, std::min(PL.n, PL.m));
+  double *Om = at<double>(P, PL.off_Om), *Yb = at<double>(P, PL.off_Yb);
+  double *sk = at<double>(P, PL.off_sk), *sT = at<double>(P, PL.off_sT);
+  double *tn = at<double>(P, PL.off_tn);
+  int *info = at<int>(P, PL.off_rinfo);
+  double *dinfo = at<double>(P, PL.off_rinfo) + 8;
+  int J = 0;
+  while (true) {
+    bool more = J < PL.refine_max;
+    if (more) {
+      std::vector<Ctx *> steps = refine_steps(P);
+      for (Ctx *cj : steps)
+        if (cj->rank > 0 && (e = compute_rhat(cj))) return e;
+      // sketch Y = R Omega and its Gram
+      if ((e = launch_gauss_fill(PL.m, q, 0x5EEDull + (uint64_t)J, Om, NLD, st))) return e;
+      HIPOK(hipMemset2DAsync(Yb, NLD * 8, 0, q * 8, PL.n, st));
+      if ((e = apply_residual(P, steps, false, q, Om, Yb))) return e;
+      if ((e = launch_tn(PL.n, q, q, Yb, false, NLD, Yb, NLD, sk, NLD, tn, PL.tn_cap, st)))
+        return e;
+      if ((e = launch_orth_small(q, sk, NLD, sT, NLD, info, dinfo, st))) return e;
+      int k = 0;
+      double tr = 0.0;
+      HIPOK(hipMemcpyAsync(&k, info, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPOK(hipMemcpyAsync(&tr, dinfo, sizeof(double), hipMemcpyDeviceToHost, st));
+      HIPOK(hipStreamSynchronize(st));
+      const double est = std::sqrt(std::max(tr, 0.0) / q);
+      more = k > 0 && est > 0.5 * tol * normR0;
+      if (more) {
+        // one power step, Y = R (R^T Y), sharpens the sketch toward R's dominant left subspace
+        HIPOK(hipMemset2DAsync(Om, NLD * 8, 0, q * 8, PL.m, st));
+        if ((e = apply_residual(P, steps, true, q, Yb, Om))) return e;
+        HIPOK(hipMemset2DAsync(Yb, NLD * 8, 0, q * 8, PL.n, st));
+        if ((e = apply_residual(P, steps, false, q, Om, Yb))) return e;
+        if ((e = launch_tn(PL.n, q, q, Yb, false, NLD, Yb, NLD, sk, NLD, tn, PL.tn_cap, st)))
+          return e;
+        if ((e = launch_orth_small(q, sk, NLD, sT, NLD, info, dinfo, st))) return e;
+        HIPOK(hipMemcpyAsync(&k, info, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+        k = std::max(k, 1);  // a vanishing sketch leaves P_J = 0, which the QR below rejects
+        ++J;
+        // P_J = Y T (orthonormal), Q_J = R^T P_J
+        double *PJ = pp_panel(P, J - 1), *QJ = qq_panel(P, J - 1);
+        if ((e = launch_nn(PL.n, q, k, 1.0, Yb, false, NLD, sT, NLD, 0.0, PJ, NLD, st))) return e;
+        HIPOK(hipMemset2DAsync(QJ, NLD * 8, 0, k * 8, PL.m, st));
+        if ((e = apply_residual(P, steps, true, k, PJ, QJ))) return e;
+        if ((e = launch_tn(PL.m, k, k, QJ, false, NLD, QJ, NLD, sk, NLD, tn, PL.tn_cap, st)))
+          return e;
+        if ((e = launch_orth_small(k, sk, NLD, sT + (size_t)16 * NLD, NLD, info + 1, dinfo + 1,
+                                   st)))
+          return e;
+        double qn2 = 0.0;
+        HIPOK(hipMemcpyAsync(&qn2, dinfo + 1, sizeof(double), hipMemcpyDeviceToHost, st));
+        HIPOK(hipStreamSynchronize(st));
+        // correction equation A Y + Y B = P_J Q_J^T (Sylvester form also for Lyapunov problems)
+        sylv_problem cp{PL.n, PL.m, k, P->A, PL.lyap ? P->AT : P->B, 0, PJ, NLD, QJ, NLD};
+        cp.B.rows = PL.m;
+        sylv_options co{};
+        sylv_default_options(&co);
+        co.method = method;
+        co.max_iter = PL.refine_iter;
+        co.check_every = P->check_every;
+        co.closure_tol = P->closure_tol;
+        co.precision = PL.fp32 ? SYLV_MIXED_FP32 : SYLV_FP64;
+        void *kid = nullptr;
+        char *kws = P->ws + PL.off_child + (size_t)(J - 1) * PL.child_bytes;
+        e = ctx_create(&kid, &cp, &co, kws, PL.child_bytes, st, P);
+        if (e == SYLV_ERR_RHS_RANK) {
+          more = false;
+        } else if (e) {
+          return e;
+        } else {
+          Ctx *K = reinterpret_cast<Ctx *>(kid);
+          const double qn = std::sqrt(std::max(qn2, 0.0));
+          const double tolJ =
+              std::min(0.5, std::max(tol, 0.3 * tol * normR0 / std::max(qn, 1e-300)));
+          sylv_result rk{};
+          e = (method == SYLV_METHOD_CG) ? sylv_factored_cg(K, tolJ, PL.refine_iter, &rk)
+                                         : sylv_factored_bicgstab(K, tolJ, PL.refine_iter, &rk);
+          if (e < 0) {
+            sylv_destroy(K);
+            return e;
+          }
+          total_iters += rk.iters;
+          P->kids.push_back(K);
+          P->kid_k.push_back(k);
+          continue;
+        }
+      }
+    }
+    // the estimate is below tol / 2 (or no correction remains): FP64 true residual of the sum
+    if ((e = stacked_residual(P, refine_steps(P), &absr, &rel))) return e;
+    if (rel <= tol || J >= PL.refine_max || !more) break;
+  }
+  P->rel_true = rel;
+  P->outer_steps = (int)P->kids.size();
+  int status = rel <= tol ? SYLV_OK
+                          : (first_status == SYLV_BREAKDOWN ? SYLV_BREAKDOWN : SYLV_NOT_CONVERGED);
+  P->status = status;
+  int64_t rank = P->rank;
+  for (Ctx *k : P->kids) rank += k->rank;
+  if (res) {
+    *res = r0;
+    res->status = status;
+    res->iters = total_iters;
+    res->rank_v = res->rank_w = rank;
+    res->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    res->outer_steps = P->outer_steps;
+    res->rel_res_true = rel;
+  }
+  return status;
+}
+
+}  // namespace
+
+thread_local char g_last_error[512] = "";
+
+void note_hip_error(hipError_t e, const char *what) {
+  snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+}
+
+extern "C" {
+
+const char *sylv_last_error(void) { return g_last_error; }
+
+void sylv_default_options(sylv_options *opt) {
+  if (!opt) return;
+  opt->method = SYLV_METHOD_BICGSTAB;
+  opt->max_iter = 200;
+  opt->check_every = 8;
+  opt->record_history = 1;
+  opt->closure_tol = 0.0;  // precision default
+  opt->precision = SYLV_FP64;
+  opt->refine_max = 0;
+  opt->refine_max_iter = 100;
+  opt->refine_rank = 8;
+  opt->refine_inner_tol = 0.0;
+}
+
+size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt) {
+  Layout L;
+  if (make_layout(prob, opt, L)) return 0;
+  return L.total;
+}
+
+const char *sylv_status_string(int status) {
+  switch (status) {
+    case SYLV_OK: return "converged";
+    case SYLV_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case SYLV_BREAKDOWN: return "breakdown";
+    case SYLV_ERR_INVALID: return "invalid argument";
+    case SYLV_ERR_HIP: return "HIP runtime error";
+    case SYLV_ERR_WORKSPACE: return "workspace too small or misaligned";
+    case SYLV_ERR_RHS_RANK: return "right-hand-side factor is rank deficient";
+    case SYLV_ERR_STATE: return "call out of order";
+    default: return "unknown status";
+  }
+}
+
+int sylv_create(void **out, const sylv_problem *pb, const sylv_options *op, void *workspace,
+                size_t ws_bytes, void *stream) {
+  return ctx_create(out, pb, op, workspace, ws_bytes, stream, nullptr);
+}
+
 void sylv_destroy(void *ctx) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return;
+  for (Ctx *k : c->kids) sylv_destroy(k);
   if (c->h_ds) hipHostFree(c->h_ds);
   delete c->prof;
   delete c;
@@ -520,6 +1100,8 @@ const char *sylv_kernel_family_name(int family) {
 int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
+  if (c->L.refine_max > 0 && !c->in_refine)
+    return refined_solve(c, SYLV_METHOD_CG, tol, max_iter, res);
   const Layout &L = c->L;
   const int s = (int)L.s;
   auto t0 = std::chrono::steady_clock::now();
@@ -558,6 +1140,8 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
 int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
+  if (c->L.refine_max > 0 && !c->in_refine)
+    return refined_solve(c, SYLV_METHOD_BICGSTAB, tol, max_iter, res);
   const Layout &L = c->L;
   const int s = (int)L.s;
   auto t0 = std::chrono::steady_clock::now();
@@ -624,24 +1208,36 @@ int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx,
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
   if (!c->solved) return SYLV_ERR_STATE;
-  const Layout &L = c->L;
-  const int64_t r = c->rank;
+  // the summed iterate of a refined solve: V = [V_0 V_1 ...], Xc = diag(X_0, X_1, ...)
+  std::vector<Ctx *> steps = refine_steps(c);
+  int64_t r = 0;
+  for (Ctx *cj : steps) r += cj->rank;
   if (rank_v) *rank_v = r;
   if (rank_w) *rank_w = r;
   if (r == 0) return 0;
   if ((V && ldv < r) || (Xc && ldx < r) || (W && ldw < r)) return SYLV_ERR_INVALID;
-  auto copy_basis = [&](double *dst, int64_t ldd, const SideDesc &sd) -> int {
-    if (L.fp32)
-      return launch_widen(sd.rows, r, static_cast<const float *>(sd.basis), L.ldb, dst, ldd, c->st);
-    HIPOK(hipMemcpy2DAsync(dst, ldd * 8, sd.basis, L.ldb * 8, r * 8, sd.rows,
-                           hipMemcpyDeviceToDevice, c->st));
-    return 0;
-  };
-  int e;
-  if (V && (e = copy_basis(V, ldv, c->sv))) return e;
-  if (Xc)
-    HIPOK(hipMemcpy2DAsync(Xc, ldx * 8, c->X, L.ldc * 8, r * 8, r, hipMemcpyDeviceToDevice, c->st));
-  if (W && (e = copy_basis(W, ldw, c->sw))) return e;
+  if (Xc && steps.size() > 1) HIPOK(hipMemset2DAsync(Xc, ldx * 8, 0, r * 8, r, c->st));
+  int64_t off = 0;
+  for (Ctx *cj : steps) {
+    const Layout &L = cj->L;
+    const int64_t rj = cj->rank;
+    if (rj == 0) continue;
+    auto copy_basis = [&](double *dst, int64_t ldd, const SideDesc &sd) -> int {
+      if (L.fp32)
+        return launch_widen(sd.rows, rj, static_cast<const float *>(sd.basis), L.ldb, dst, ldd,
+                            c->st);
+      HIPOK(hipMemcpy2DAsync(dst, ldd * 8, sd.basis, L.ldb * 8, rj * 8, sd.rows,
+                             hipMemcpyDeviceToDevice, c->st));
+      return 0;
+    };
+    int e;
+    if (V && (e = copy_basis(V + off, ldv, cj->sv))) return e;
+    if (Xc)
+      HIPOK(hipMemcpy2DAsync(Xc + off * ldx + off, ldx * 8, cj->X, L.ldc * 8, rj * 8, rj,
+                             hipMemcpyDeviceToDevice, c->st));
+    if (W && (e = copy_basis(W + off, ldw, cj->sw))) return e;
+    off += rj;
+  }
   HIPOK(hipStreamSynchronize(c->st));
   return 0;
 }
@@ -663,121 +1259,21 @@ int sylv_get_history(void *ctx, double *relres, double *alpha, double *beta, dou
   return 0;
 }
 
-// ||A X + X B - C1 C2^T||_F for X = V_p Xc W_p^T, p = rank, from Gram traces:
-//   A X + X B = V_{p+s} L(Xc) W_{p+s}^T + E_A Xc W_p^T + V_p Xc E_B^T with the basis defects
-//   E_A = A V_p - V_{p+s} H, E_B = B^T W_p - W_{p+s} G (eq. (3.8) holds up to them), so with
-//   R^ = [R0 0; 0 0] - L(Xc) the residual is T1 - T2 - T3, T1 = V R^ W^T, T2 = E_A Xc W_p^T,
-//   T3 = V_p Xc E_B^T, and every term of ||T1 - T2 - T3||^2 is a trace of small products
-//   of the Grams V^T V, W^T W, V^T E_A, W^T E_B, E_A^T E_A, E_B^T E_B.
+// ||A X + X B - C1 C2^T||_F of the current iterate (the summed iterate after a refined solve),
+// from the Gram traces of the stacked tall factors of its defect form.
 int sylv_residual_norm(void *ctx, double *abs_res, double *rel_res) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
   if (!c->solved) return SYLV_ERR_STATE;
-  const Layout &L = c->L;
-  hipStream_t st = c->st;
-  const int s = (int)L.s;
-  const int64_t p = c->rank, q = p + s, ldc = L.ldc, ldb = L.ldb;
-  double h_ds_norm;
+  if (c->parent) return SYLV_ERR_STATE;
   int e = read_state(c);
   if (e) return e;
-  h_ds_norm = c->h_ds->normR0;
-  if (p == 0) {
-    if (abs_res) *abs_res = h_ds_norm;
+  if (c->rank == 0 && c->kids.empty()) {
+    if (abs_res) *abs_res = c->h_ds->normR0;
     if (rel_res) *rel_res = 1.0;
     return 0;
   }
-  double *E = at<double>(c, L.off_E);
-  double *GVV = at<double>(c, L.off_GVV), *GWW = at<double>(c, L.off_GWW);
-  double *GVE = at<double>(c, L.off_GVE), *GWE = at<double>(c, L.off_GWE);
-  double *GEEa = at<double>(c, L.off_GEEa), *GEEb = at<double>(c, L.off_GEEb);
-  double *Lx = at<double>(c, L.off_Lx), *M1 = at<double>(c, L.off_M1), *M2 = at<double>(c, L.off_M2);
-  // Gram accumulation over row chunks of one side: E = M V_p - V_q H (banded for block
-  // Lanczos, a Hessenberg GEMM for block Arnoldi), then V^T V and E^T E (lower tiles, mirrored
-  // at the end) and V^T E.
-  const bool band = (L.method == SYLV_METHOD_CG);
-  auto side_grams = [&](const SideDesc &sd, const double *Hm, double *Gbb, double *Gbe,
-                        double *Gee) -> int {
-    char *Vb = static_cast<char *>(sd.basis);
-    const bool f32 = L.fp32;
-    int ee;
-    if (!band) {
-      const int qk = (int)std::min<int64_t>(round_up(q, 32), ldb);
-      if ((ee = launch_zero_cols(sd.rows, Vb, f32, ldb, (int)q, qk, st))) return ee;
-    }
-    for (int64_t r0 = 0; r0 < sd.rows; r0 += L.rc_rows) {
-      const int64_t r1 = std::min(sd.rows, r0 + L.rc_rows), nr = r1 - r0;
-      const double beta = (r0 == 0) ? 0.0 : 1.0;
-      if (band) {
-        if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, Vb, f32, ldb, (int)p, (int)q, s,
-                                     Hm, ldc, M2, ldc, r0 == 0, E, ldb, st)))
-          return ee;
-      } else {
-        // E = M V_p (rows r0..r1), then E -= V_q(rows) H(0:q, 0:p)
-        if ((ee = launch_spmm_rows(s, r0, r1, sd.rp, sd.ci, sd.val, Vb, f32, ldb, (int)p, E, ldb,
-                                   st)))
-          return ee;
-        if ((ee = launch_defect_gemm(nr, (int)p, (int)q, s, Vb + r0 * ldb * L.esz, f32, ldb, Hm,
-                                     ldc, E, ldb, st)))
-          return ee;
-      }
-      const char *Vr = Vb + r0 * ldb * L.esz;
-      if ((ee = launch_gram(q, q, nr, Vr, f32, ldb, Vr, f32, ldb, beta, Gbb, ldc, true, st)))
-        return ee;
-      if ((ee = launch_gram(q, p, nr, Vr, f32, ldb, E, false, ldb, beta, Gbe, ldc, false, st)))
-        return ee;
-      if ((ee = launch_gram(p, p, nr, E, false, ldb, E, false, ldb, beta, Gee, ldc, true, st)))
-        return ee;
-    }
-    if ((ee = launch_mirror(q, Gbb, ldc, st))) return ee;
-    return launch_mirror(p, Gee, ldc, st);
-  };
-  if ((e = side_grams(c->sv, c->H, GVV, GVE, GEEa))) return e;
-  const double *GWWp = GVV, *GWEp = GVE, *GEEbp = GEEa;
-  if (!L.lyap) {
-    if ((e = side_grams(c->sw, c->G, GWW, GWE, GEEb))) return e;
-    GWWp = GWW;
-    GWEp = GWE;
-    GEEbp = GEEb;
-  }
-  // R^ = [R0 0; 0 0] - L(Xc); reuse Lx as R^
-  if ((e = launch_core_op(s, (int)p, c->H, c->G, c->X, Lx, ldc, nullptr, st))) return e;
-  // R0 = R_L R_R^T is the saved Rt core
-  if ((e = launch_rhat(s, (int)q, Lx, c->Rt, Lx, ldc, st))) return e;
-  const double *Rh = Lx;
-  double *dots = c->dots;
-  // t1 = <GVV R^, R^ GWW>
-  if ((e = launch_gemm(q, q, q, 1.0, GVV, ldc, 1, Rh, ldc, 1, 0.0, M1, ldc, st))) return e;
-  if ((e = launch_gemm(q, q, q, 1.0, Rh, ldc, 1, GWWp, ldc, 1, 0.0, M2, ldc, st))) return e;
-  if ((e = launch_dot(q, q, M1, ldc, M2, ldc, dots + 0, c->sc, st))) return e;
-  // t12 = <R^, GVE X GWW(0:p, 0:q)>
-  if ((e = launch_gemm(q, p, p, 1.0, GVE, ldc, 1, c->X, ldc, 1, 0.0, M1, ldc, st))) return e;
-  if ((e = launch_gemm(q, q, p, 1.0, M1, ldc, 1, GWWp, ldc, 1, 0.0, M2, ldc, st))) return e;
-  if ((e = launch_dot(q, q, Rh, ldc, M2, ldc, dots + 1, c->sc, st))) return e;
-  // t13 = <R^, GVV(0:q, 0:p) X GWE^T>
-  if ((e = launch_gemm(q, p, p, 1.0, GVV, ldc, 1, c->X, ldc, 1, 0.0, M1, ldc, st))) return e;
-  if ((e = launch_gemm(q, q, p, 1.0, M1, ldc, 1, GWEp, 1, ldc, 0.0, M2, ldc, st))) return e;
-  if ((e = launch_dot(q, q, Rh, ldc, M2, ldc, dots + 2, c->sc, st))) return e;
-  // t22 = <GEE_A X, X GWW(0:p, 0:p)>
-  if ((e = launch_gemm(p, p, p, 1.0, GEEa, ldc, 1, c->X, ldc, 1, 0.0, M1, ldc, st))) return e;
-  if ((e = launch_gemm(p, p, p, 1.0, c->X, ldc, 1, GWWp, ldc, 1, 0.0, M2, ldc, st))) return e;
-  if ((e = launch_dot(p, p, M1, ldc, M2, ldc, dots + 3, c->sc, st))) return e;
-  // t33 = <GVV(0:p, 0:p) X, X GEE_B>
-  if ((e = launch_gemm(p, p, p, 1.0, GVV, ldc, 1, c->X, ldc, 1, 0.0, M1, ldc, st))) return e;
-  if ((e = launch_gemm(p, p, p, 1.0, c->X, ldc, 1, GEEbp, ldc, 1, 0.0, M2, ldc, st))) return e;
-  if ((e = launch_dot(p, p, M1, ldc, M2, ldc, dots + 4, c->sc, st))) return e;
-  // t23 = <GVE(0:p, :) X, X GWE(0:p, :)^T>
-  if ((e = launch_gemm(p, p, p, 1.0, GVE, ldc, 1, c->X, ldc, 1, 0.0, M1, ldc, st))) return e;
-  if ((e = launch_gemm(p, p, p, 1.0, c->X, ldc, 1, GWEp, 1, ldc, 0.0, M2, ldc, st))) return e;
-  if ((e = launch_dot(p, p, M1, ldc, M2, ldc, dots + 5, c->sc, st))) return e;
-  double t[6];
-  HIPOK(hipMemcpyAsync(t, dots, sizeof(t), hipMemcpyDeviceToHost, st));
-  HIPOK(hipStreamSynchronize(st));
-  double r2 = t[0] - 2.0 * t[1] - 2.0 * t[2] + t[3] + t[4] + 2.0 * t[5];
-  if (r2 < 0.0) r2 = 0.0;
-  const double a = std::sqrt(r2);
-  if (abs_res) *abs_res = a;
-  if (rel_res) *rel_res = a / h_ds_norm;
-  return 0;
+  return stacked_residual(c, refine_steps(c), abs_res, rel_res);
 }
 
 int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double *Y, int64_t ldy,

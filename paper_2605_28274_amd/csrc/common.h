@@ -496,6 +496,9 @@ int launch_spmm(int s, int64_t rows, const int32_t *rp, const int32_t *ci, const
 int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int32_t *ci,
                      const double *val, const void *X, bool x_fp32, int64_t ldx, int ncols,
                      double *Y, int64_t ldy, hipStream_t st);
+// D = C - V_1 R (rows x s, D compact): right-hand-side factor minus its first basis block.
+int launch_qr_defect(int64_t rows, int s, const double *C, int64_t ldc, const void *V, bool v_fp32,
+                     int64_t ldv, const double *R, double *D, hipStream_t st);
 // dst = src widened from FP32 to FP64 (rows x cols).
 int launch_widen(int64_t rows, int64_t cols, const float *src, int64_t lds, double *dst,
                  int64_t ldd, hipStream_t st);
@@ -547,9 +550,11 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
 // C (+)= A^T B, A: K x M, B: K x N row-major (lda >= roundup(M, 64), ldb >= roundup(N, 64));
 // `lower` computes the tiles on and below the diagonal only (M == N; launch_mirror completes).
 // A and B are float (a_fp32 / b_fp32) or double; row strides multiples of 8 elements.
+// part (part_cap doubles, may be null): scratch that lets launches with few output tiles split
+// K over several workgroups (deterministic: slices summed in order).
 int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
                 const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
-                bool lower, hipStream_t st);
+                bool lower, hipStream_t st, double *part = nullptr, size_t part_cap = 0);
 int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st);
 // E(0:rows, 0:p) -= V(0:rows, 0:q) H(0:q, 0:p), H block upper Hessenberg; V columns
 // [q, roundup(q, 32)) must be finite.
@@ -564,6 +569,25 @@ int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t 
                        int s,
                        const double *H, int64_t ldh, double *Hb, int64_t ldhb, bool pack,
                        double *E, int64_t lde, hipStream_t st);
+// Outer refinement (refine.hip). Narrow panels: rows x q FP64 (q <= 8), row stride ldz.
+int launch_gauss_fill(int64_t rows, int q, uint64_t seed, double *Z, int64_t ldz, hipStream_t st);
+size_t tn_partials_needed(int64_t rows, int64_t ncols, int q);
+// out (ncols x q, ldo) = V[:, 0:ncols]^T Z; part: scratch of tn_partials_needed doubles.
+int launch_tn(int64_t rows, int ncols, int q, const void *V, bool v_fp32, int64_t ldv,
+              const double *Z, int64_t ldz, double *out, int64_t ldo, double *part,
+              size_t part_cap, hipStream_t st);
+// Y = beta Y + alpha V[:, 0:ncols] Z (Z: ncols x q, ldz).
+int launch_nn(int64_t rows, int ncols, int q, double alpha, const void *V, bool v_fp32,
+              int64_t ldv, const double *Z, int64_t ldz, double beta, double *Y, int64_t ldy,
+              hipStream_t st);
+// From G = Y^T Y (q x q): T (q x k) with Y T orthonormal, info[0] = k, dinfo[0] = trace(G).
+int launch_orth_small(int q, const double *G, int64_t ldg, double *T, int64_t ldt, int *info,
+                      double *dinfo, hipStream_t st);
+int launch_copy_block(int rows, int cols, double alpha, const double *src, int64_t lds, bool trans,
+                      double *dst, int64_t ldd, hipStream_t st);
+int launch_diag_fill(int k, double v, double *dst, int64_t ldd, hipStream_t st);
+int launch_axpy_narrow(int64_t rows, int q, double alpha, const double *F, int64_t ldf, double *Y,
+                       int64_t ldy, hipStream_t st);
 int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,
                    int64_t ldc, const int *done, hipStream_t st);
 int launch_csr_validate(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, int *flag,

@@ -241,35 +241,46 @@ __device__ __forceinline__ void tri_tile(int64_t b, int &I, int &J) {
   J = (int)(b - i * (i + 1) / 2);
 }
 
+// With part != nullptr the K range is split: workgroup b computes tile b % ntiles over rows
+// [kz kchunk, (kz+1) kchunk), kz = b / ntiles, and stores the whole tile to part; gram_reduce
+// sums the slices in order.
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void gram_kernel(int64_t M, int64_t N, int64_t K,
                                                    const TA *__restrict__ A, int64_t lda,
                                                    const TB *__restrict__ B, int64_t ldb,
                                                    double beta, double *__restrict__ C,
-                                                   int64_t ldc, int tiles_n, int lower) {
+                                                   int64_t ldc, int tiles_n, int lower, int ntiles,
+                                                   int64_t kchunk, double *__restrict__ part) {
   __shared__ Smem sm;
+  const int tile = (int)(blockIdx.x % ntiles), kz = (int)(blockIdx.x / ntiles);
   int I, J;
-  if (lower) tri_tile(blockIdx.x, I, J);
+  if (lower) tri_tile(tile, I, J);
   else {
-    I = (int)(blockIdx.x / tiles_n);
-    J = (int)(blockIdx.x % tiles_n);
+    I = tile / tiles_n;
+    J = tile % tiles_n;
   }
   const int64_t i0 = (int64_t)I * BM, j0 = (int64_t)J * BN;
   const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
   WaveAcc acc;
   zero_acc(acc);
-  const int64_t kb = K / BK * BK;
-  pipelined<true, false, TA, TB>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, 0, kb);
-  if (K > kb) {
-    // last K - kb < BK rows, zero-filled past K
+  const int64_t k0 = (int64_t)kz * kchunk, k1 = (k0 + kchunk < K) ? k0 + kchunk : K;
+  const int64_t kb = k0 + (k1 - k0) / BK * BK;
+  pipelined<true, false, TA, TB>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, k0, kb);
+  if (k1 > kb) {
+    // last k1 - kb < BK rows, zero-filled past k1
     __syncthreads();
     for (int e = threadIdx.x; e < BK * BM; e += 256) {
       const int kk = e / BM, ii = e % BM;
-      sm.As[0][kk][ii] = (kb + kk < K) ? (double)A[(kb + kk) * lda + i0 + ii] : 0.0;
-      sm.Bs[0][kk][ii] = (kb + kk < K) ? (double)B[(kb + kk) * ldb + j0 + ii] : 0.0;
+      sm.As[0][kk][ii] = (kb + kk < k1) ? (double)A[(kb + kk) * lda + i0 + ii] : 0.0;
+      sm.Bs[0][kk][ii] = (kb + kk < k1) ? (double)B[(kb + kk) * ldb + j0 + ii] : 0.0;
     }
     __syncthreads();
     mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+  }
+  if (part) {
+    double *pt = part + ((size_t)kz * ntiles + tile) * (BM * BN);
+    for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });
+    return;
   }
   for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
     const int64_t gi = i0 + ii, gj = j0 + jj;
@@ -278,6 +289,32 @@ __global__ __launch_bounds__(256) void gram_kernel(int64_t M, int64_t N, int64_t
       *c = (beta == 0.0) ? v : *c + v;
     }
   });
+}
+
+// C tile (beta C +) sum over the nk K-slices of the tile's partials, in slice order; 16
+// workgroups per tile.
+__global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t M, int64_t N, int tiles_n,
+                                                          int lower, int ntiles, int nk,
+                                                          const double *__restrict__ part,
+                                                          double beta, double *__restrict__ C,
+                                                          int64_t ldc) {
+  const int tile = blockIdx.x / 16, sub = blockIdx.x % 16;
+  int I, J;
+  if (lower) tri_tile(tile, I, J);
+  else {
+    I = tile / tiles_n;
+    J = tile % tiles_n;
+  }
+  {
+    const int e = sub * 256 + threadIdx.x;
+    double v = 0.0;
+    for (int kz = 0; kz < nk; ++kz) v += part[((size_t)kz * ntiles + tile) * (BM * BN) + e];
+    const int64_t gi = (int64_t)I * BM + e / BN, gj = (int64_t)J * BN + e % BN;
+    if (gi < M && gj < N) {
+      double *c = C + gi * ldc + gj;
+      *c = (beta == 0.0) ? v : *c + v;
+    }
+  }
 }
 
 // C[i][j] = C[j][i] for i < j < M (upper from lower).
@@ -414,23 +451,42 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
 
 int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
                 const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
-                bool lower, hipStream_t st) {
+                bool lower, hipStream_t st, double *part, size_t part_cap) {
   if (M <= 0 || N <= 0) return 0;
   if (lower && M != N) return SYLV_ERR_INVALID;
   const int64_t TM = (M + BM - 1) / BM, TN = (N + BN - 1) / BN;
   if (lda < TM * BM || ldb < TN * BN || lda % 8 || ldb % 8) return SYLV_ERR_INVALID;
   if (K <= 0) return 0;
-  const unsigned tiles = (unsigned)(lower ? TM * (TM + 1) / 2 : TM * TN);
+  const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
+  // few tiles over a long K: split K so that about 512 workgroups run (partials in part)
+  int64_t nk = 1;
+  if (part && tiles < 64 && K >= 4 * 1024) {
+    nk = std::min<int64_t>({(256 + tiles - 1) / tiles, K / 1024, 64,
+                            (int64_t)(part_cap / ((size_t)tiles * BM * BN))});
+    if (nk < 2) nk = 1;
+  }
+  int64_t kchunk = K;
+  if (nk > 1) {
+    kchunk = ((K + nk - 1) / nk + BK - 1) / BK * BK;
+    nk = (K + kchunk - 1) / kchunk;
+  }
+  double *pp = nk > 1 ? part : nullptr;
+  const unsigned grid = (unsigned)(tiles * nk);
 #define GRAM(TA, TB)                                                                           \
-  gram_kernel<TA, TB><<<tiles, 256, 0, st>>>(M, N, K, static_cast<const TA *>(A), lda,         \
-                                             static_cast<const TB *>(B), ldb, beta, C, ldc,    \
-                                             (int)TN, lower ? 1 : 0)
+  gram_kernel<TA, TB><<<grid, 256, 0, st>>>(M, N, K, static_cast<const TA *>(A), lda,          \
+                                            static_cast<const TB *>(B), ldb, beta, C, ldc,     \
+                                            (int)TN, lower ? 1 : 0, (int)tiles, kchunk, pp)
   if (a_fp32 && b_fp32) GRAM(float, float);
   else if (a_fp32) GRAM(float, double);
   else if (b_fp32) GRAM(double, float);
   else GRAM(double, double);
 #undef GRAM
   HIPOK(hipGetLastError());
+  if (pp) {
+    gram_reduce_kernel<<<(unsigned)tiles * 16, 256, 0, st>>>(M, N, (int)TN, lower ? 1 : 0,
+                                                             (int)tiles, (int)nk, pp, beta, C, ldc);
+    HIPOK(hipGetLastError());
+  }
   return 0;
 }
 

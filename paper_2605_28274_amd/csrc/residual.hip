@@ -94,6 +94,23 @@ __global__ __launch_bounds__(TPB) void widen_kernel(int64_t rows, int64_t cols,
     for (int64_t j = threadIdx.x; j < cols; j += TPB) dst[i * ldd + j] = (double)src[i * lds + j];
 }
 
+// D[r][b] = C[r][b] - sum_a V[r][a] R[a][b] (r < rows, b < s; R s x s with stride s): the part of
+// a right-hand-side factor that its stored first basis block V_1 R misses.
+template <typename T>
+__global__ __launch_bounds__(TPB) void qr_defect_kernel(int64_t rows, int s,
+                                                        const double *__restrict__ C, int64_t ldc,
+                                                        const T *__restrict__ V, int64_t ldv,
+                                                        const double *__restrict__ R,
+                                                        double *__restrict__ D) {
+  const int64_t e = (int64_t)blockIdx.x * TPB + threadIdx.x;
+  if (e >= rows * s) return;
+  const int64_t r = e / s;
+  const int b = (int)(e - r * s);
+  double v = C[r * ldc + b];
+  for (int a = 0; a < s; ++a) v = fma(-(double)V[r * ldv + a], R[a * s + b], v);
+  D[r * s + b] = v;
+}
+
 }  // namespace
 
 int launch_dot(int64_t M, int64_t N, const double *A, int64_t lda, const double *B, int64_t ldb,
@@ -143,6 +160,21 @@ int launch_widen(int64_t rows, int64_t cols, const float *src, int64_t lds, doub
   if (rows <= 0 || cols <= 0) return 0;
   widen_kernel<<<(unsigned)std::min<int64_t>(rows, 65536), TPB, 0, st>>>(rows, cols, src, lds, dst,
                                                                          ldd);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_qr_defect(int64_t rows, int s, const double *C, int64_t ldc, const void *V, bool v_fp32,
+                     int64_t ldv, const double *R, double *D, hipStream_t st) {
+  const int64_t tot = rows * s;
+  if (tot <= 0) return 0;
+  const unsigned g = (unsigned)((tot + TPB - 1) / TPB);
+  if (v_fp32)
+    qr_defect_kernel<float><<<g, TPB, 0, st>>>(rows, s, C, ldc, static_cast<const float *>(V), ldv,
+                                               R, D);
+  else
+    qr_defect_kernel<double><<<g, TPB, 0, st>>>(rows, s, C, ldc, static_cast<const double *>(V),
+                                                ldv, R, D);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -62,12 +62,15 @@ class sylv_problem(ctypes.Structure):
 
 class sylv_options(ctypes.Structure):
     _fields_ = [("method", c_int), ("max_iter", c_int), ("check_every", c_int),
-                ("record_history", c_int), ("closure_tol", c_double), ("precision", c_int)]
+                ("record_history", c_int), ("closure_tol", c_double), ("precision", c_int),
+                ("refine_max", c_int), ("refine_max_iter", c_int), ("refine_rank", c_int),
+                ("refine_inner_tol", c_double)]
 
 
 class sylv_result(ctypes.Structure):
     _fields_ = [("status", c_int), ("iters", c_int), ("rank_v", c_int64), ("rank_w", c_int64),
-                ("rel_res_recursive", c_double), ("seconds", c_double)]
+                ("rel_res_recursive", c_double), ("seconds", c_double), ("outer_steps", c_int),
+                ("rel_res_true", c_double)]
 
 
 _lib.sylv_default_options.argtypes = [POINTER(sylv_options)]
@@ -311,7 +314,8 @@ class Solver:
     arrays (n x s, m x s). ``method`` and ``max_iter`` size the workspace."""
 
     def __init__(self, A, B, C1, C2, lyapunov=False, method=SYLV_METHOD_BICGSTAB, max_iter=200,
-                 check_every=8, closure_tol=0.0, precision=0, device="cuda", stream=None):
+                 check_every=8, closure_tol=0.0, precision=0, refine_max=0, refine_max_iter=100,
+                 refine_rank=8, refine_inner_tol=0.0, device="cuda", stream=None):
         import torch
         self.device = device
         self.n, self.s = C1.shape
@@ -325,7 +329,9 @@ class Solver:
             self.n, self.m, self.s, make_csr(self.n, *self._A), make_csr(self.m, *self._B),
             1 if lyapunov else 0, _ptr(self._C1), self.s, _ptr(self._C2), self.s)
         self.options = default_options(method, max_iter, check_every=check_every,
-                                       closure_tol=closure_tol, precision=precision)
+                                       closure_tol=closure_tol, precision=precision,
+                                       refine_max=refine_max, refine_max_iter=refine_max_iter,
+                                       refine_rank=refine_rank, refine_inner_tol=refine_inner_tol)
         nbytes = sylv_workspace_bytes(self.problem, self.options)
         if nbytes == 0:
             raise SylvError(SYLV_ERR_INVALID, "sylv_workspace_bytes")

@@ -77,3 +77,19 @@ def test_c2_workspace_is_modest():
     prob = _problem(p.n, p.m, p.s, 0, p.A.nnz, p.B.nnz)
     nb = sylv.sylv_workspace_bytes(prob, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 800))
     assert 0 < nb < 4 * 2**30
+
+
+def test_precision_and_refine_options_validated():
+    p = _problem()
+    base = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, precision=sylv.SYLV_MIXED_FP32)
+    fp64 = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50)
+    ref = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, precision=sylv.SYLV_MIXED_FP32,
+                               refine_max=2)
+    # FP32 bases need less workspace; refinement adds correction contexts and buffers
+    assert 0 < sylv.sylv_workspace_bytes(p, base) < sylv.sylv_workspace_bytes(p, fp64)
+    assert sylv.sylv_workspace_bytes(p, ref) > sylv.sylv_workspace_bytes(p, base)
+    for bad in (dict(refine_max=5), dict(refine_max=1, refine_rank=0),
+                dict(refine_max=1, refine_rank=9), dict(refine_max=1, refine_max_iter=0),
+                dict(precision=2)):
+        o = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, **bad)
+        assert sylv.sylv_workspace_bytes(p, o) == 0, bad

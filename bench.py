@@ -8,6 +8,10 @@ Default workload (`--workload c2`): factored BiCGSTAB, FP64, A = 2D convection-d
   c3    factored BiCGSTAB, FP64, 3D CD 64^3 x 2D CD 256^2 (Pe = 10), s = 4
   c5cg  Lyapunov factored CG, FP64, 2D Laplacian 1024^2, s = 1
   c5bi  Lyapunov factored BiCGSTAB, FP64, 2D CD 1024^2 (Pe = 1), s = 1, 200-iteration window
+  batch64  64 independent instances (2D A with n in [1024, 32768]; 1D or 2D B with m in [512,
+        16384]; s in {1, 2, 4}; CG on Laplacians and BiCGSTAB on Pe = 10 alternately), solved as
+        one batch over --streams streams; the same instances solved one after another on one
+        stream are timed beside it (`sequential_ms`)
 
 One step = one pass of the whole path over resident inputs: sylv_create (CSR validation, B^T,
 sliced-ELLPACK copies, QR of C1 and C2), the factored solve to ||R|| <= tol ||R0|| (or the
@@ -73,7 +77,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2", choices=["c1", "c2", "c3", "c5cg", "c5bi"])
+    ap.add_argument("--workload", default="c2",
+                    choices=["c1", "c2", "c3", "c5cg", "c5bi", "batch64"])
+    ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--max-iter", type=int, default=0)
@@ -95,6 +101,8 @@ def main():
     from paper_2605_28274_amd import sylv
 
     torch.cuda.set_device(0)
+    if args.workload == "batch64":
+        return run_batch(args, sylv, torch, np)
     p, method = workload(args.workload, args.max_iter)
     cg = method == "cg"
     dev = "cuda"
@@ -193,6 +201,56 @@ def main():
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, method, args.cpu_iters)
+    print(json.dumps(out), flush=True)
+
+
+def run_batch(args, sylv, torch, np):
+    """The 64-instance batch: wall time of sylv_batch_solve over all instances (after one
+    untimed warm-up solve), then the same instances solved sequentially on one stream."""
+    from workloads import configs
+    probs = configs.batch64()
+    for p in probs:  # workspace sized for the survey's iteration estimates of these instances
+        p.max_iter = 600 if p.method == "cg" else 500
+    mixed = args.precision == "fp32"
+    prec = sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64
+
+    def timed(nstreams, steps):
+        b = sylv.Batch(probs, nstreams=nstreams, precision=prec)
+        for _ in range(args.warmup):
+            b.solve(1e-8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = b.solve(1e-8)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / steps
+        rels = []
+        for i in range(len(probs)):
+            _, rel = sylv.sylv_residual_norm(b.context(i))
+            rels.append(rel)
+        b.close()
+        del b
+        torch.cuda.empty_cache()
+        return dt, res, rels
+
+    dt, res, rels = timed(args.streams, args.steps)
+    dts, res_s, _ = timed(1, 1)
+    iters = sum(r.iters for r in res)
+    out = {
+        "metric": METRIC, "value": round(iters / dt, 2), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32-basis/f64" if mixed else "f64", "data": "synthetic",
+        "config": {"workload": "batch of 64 seeded instances (2D A, n 1024-32768; 1D/2D B, "
+                               "m 512-16384; s in {1,2,4}; CG/BiCGSTAB alternating), tol 1e-8",
+                   "instances": len(probs), "streams": args.streams,
+                   "total_iters": iters, "time_to_1e-8_all_ms": round(1000 * dt, 3),
+                   "sequential_ms": round(1000 * dts, 3),
+                   "speedup_vs_sequential": round(dts / dt, 3),
+                   "statuses": sorted(set(int(r.status) for r in res)),
+                   "max_true_rel_res": float(max(rels)),
+                   "sequential_iters": sum(r.iters for r in res_s)},
+    }
     print(json.dumps(out), flush=True)
 
 

@@ -175,6 +175,25 @@ const char *sylv_status_string(int status);
  * after a SYLV_ERR_HIP return. The string stays valid until the next library call. */
 const char *sylv_last_error(void);
 
+/* ---- batches of independent problems (one GPU) ----
+ * Many problems of uneven sizes solved together: each instance gets its own context, carved
+ * from one caller-owned workspace, and the instances are spread over nstreams HIP streams
+ * (longest-first by estimated cost); one host thread per stream drives its instances, so the
+ * small launches of different instances overlap on the device. Instance i uses
+ * opts[i].method and opts[i].max_iter. Results are those of solving each instance alone
+ * (same kernels, same order of arithmetic).
+ * sylv_batch_workspace_bytes: sum of the instances' workspaces (0 if any is invalid).
+ * sylv_batch_create: errors as sylv_create (the first failing instance's code).
+ * sylv_batch_solve: res[count] (host); returns the first error (< 0) or the largest status.
+ * sylv_batch_context: context of instance i (for sylv_get_factors, sylv_residual_norm, ...);
+ * owned by the batch. */
+size_t sylv_batch_workspace_bytes(int count, const sylv_problem *probs, const sylv_options *opts);
+int sylv_batch_create(void **batch, int count, const sylv_problem *probs,
+                      const sylv_options *opts, void *workspace, size_t ws_bytes, int nstreams);
+int sylv_batch_solve(void *batch, double tol, sylv_result *res);
+void *sylv_batch_context(void *batch, int i);
+void sylv_batch_destroy(void *batch);
+
 /* ---- measurement hooks ---- */
 
 /* Time per kernel family, summed over the iterations the solves actually ran. */

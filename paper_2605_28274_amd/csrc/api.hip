@@ -38,7 +38,7 @@ struct Layout {
   size_t tn_cap = 0;
   size_t off_Om, off_Zb, off_Yb, off_Eb, off_Fb, off_Pp, off_Qp, off_sa, off_sb, off_sc2, off_sd,
       off_sk, off_sT, off_tn, off_atrp, off_atci, off_atval, off_atscr, off_GL, off_GN, off_Mc,
-      off_Mt, off_T1, off_T2, off_Es, off_rinfo, off_gpart;
+      off_T1, off_Es, off_rinfo, off_gpart;
   size_t total = 0;
 };
 
@@ -202,9 +202,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
     L.off_GL = bump(cur, cc);
     L.off_GN = bump(cur, cc);
     L.off_Mc = bump(cur, cc);
-    L.off_Mt = bump(cur, cc);
     L.off_T1 = bump(cur, cc);
-    L.off_T2 = bump(cur, cc);
     L.ldE = round_up(L.rmax + 2 * L.s, 64) +
             L.refine_max * round_up(L.child_rmax + 2 * L.refine_q, 64) + 64;
     L.off_Es = bump(cur, (size_t)L.rc_rows * L.ldE * 8);
@@ -751,8 +749,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
   const int64_t cL = offL.back(), cN = offN.back(), ldG = PL.cmax;
   if (cL > PL.cmax || cN > PL.cmax) return SYLV_ERR_WORKSPACE;
   double *GL = at<double>(P, PL.off_GL), *GN = at<double>(P, PL.off_GN);
-  double *Mc = at<double>(P, PL.off_Mc), *Mt = at<double>(P, PL.off_Mt);
-  double *T1 = at<double>(P, PL.off_T1), *T2 = at<double>(P, PL.off_T2);
+  double *Mc = at<double>(P, PL.off_Mc), *T1 = at<double>(P, PL.off_T1);
   double *gpart = at<double>(P, PL.off_gpart);
   auto side_pass = [&](bool w, const std::vector<Seg> &segs, const std::vector<int64_t> &offs,
                        double *G) -> int {
@@ -811,14 +808,11 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
   };
   if ((e = side_pass(false, segL, offL, GL))) return e;
   if ((e = side_pass(true, segN, offN, GN))) return e;
-  // M (cL x cN) and its transpose Mt (cN x cL)
+  // M (cL x cN)
   HIPOK(hipMemset2DAsync(Mc, ldG * 8, 0, cN * 8, cL, st));
-  HIPOK(hipMemset2DAsync(Mt, ldG * 8, 0, cL * 8, cN, st));
   auto put = [&](int64_t r, int64_t c, int rows, int cols, double alpha, const double *src,
                  int64_t lds) -> int {
-    int ee = launch_copy_block(rows, cols, alpha, src, lds, false, Mc + r * ldG + c, ldG, st);
-    if (ee) return ee;
-    return launch_copy_block(cols, rows, alpha, src, lds, true, Mt + c * ldG + r, ldG, st);
+    return launch_copy_block(rows, cols, alpha, src, lds, false, Mc + r * ldG + c, ldG, st);
   };
   for (size_t j = 0; j < steps.size(); ++j) {
     Ctx *cj = steps[j];
@@ -831,23 +825,18 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
     if ((e = put(offL[x.e], offN[x.w], p, p, -1.0, cj->X, CL.ldc))) return e;
     if ((e = put(offL[x.v], offN[x.eb], p, p, -1.0, cj->X, CL.ldc))) return e;
     if ((e = launch_diag_fill(s, 1.0, Mc + d1 * ldG + c2, ldG, st))) return e;
-    if ((e = launch_diag_fill(s, 1.0, Mt + c2 * ldG + d1, ldG, st))) return e;
     if ((e = put(offL[x.v], d2, s, s, 1.0, cj->RL, s))) return e;
   }
   for (size_t i = 0; i + 1 < steps.size(); ++i) {
     if ((e = launch_diag_fill(P->kid_k[i], -1.0, Mc + offL[pL[i]] * ldG + offN[qN[i]], ldG, st)))
       return e;
-    if ((e = launch_diag_fill(P->kid_k[i], -1.0, Mt + offN[qN[i]] * ldG + offL[pL[i]], ldG, st)))
-      return e;
   }
-  // ||R||^2 = <G_L M, M G_N>, both products as A^T B on the symmetric Grams
+  // ||R||^2 = <G_L M, M G_N>: G_L M as A^T B on the symmetric Gram; M G_N into G_L's storage
   if ((e = launch_gram(cL, cN, cL, GL, false, ldG, Mc, false, ldG, 0.0, T1, ldG, false, st, gpart,
                        GPART_CAP)))
     return e;
-  if ((e = launch_gram(cL, cN, cN, Mt, false, ldG, GN, false, ldG, 0.0, T2, ldG, false, st, gpart,
-                       GPART_CAP)))
-    return e;
-  if ((e = launch_dot(cL, cN, T1, ldG, T2, ldG, P->dots, P->sc, st))) return e;
+  if ((e = launch_gemm(cL, cN, cN, 1.0, Mc, ldG, 1, GN, ldG, 1, 0.0, GL, ldG, st))) return e;
+  if ((e = launch_dot(cL, cN, T1, ldG, GL, ldG, P->dots, P->sc, st))) return e;
   double r2 = 0.0;
   HIPOK(hipMemcpyAsync(&r2, P->dots, sizeof(double), hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));

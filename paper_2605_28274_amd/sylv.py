@@ -126,6 +126,17 @@ _lib.sylv_sell_spmm.restype = c_int
 _lib.sylv_dgemm.argtypes = [c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_int64,
                             c_void_p, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p]
 _lib.sylv_dgemm.restype = c_int
+_lib.sylv_batch_workspace_bytes.argtypes = [c_int, c_void_p, c_void_p]
+_lib.sylv_batch_workspace_bytes.restype = c_size_t
+_lib.sylv_batch_create.argtypes = [POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p,
+                                   c_size_t, c_int]
+_lib.sylv_batch_create.restype = c_int
+_lib.sylv_batch_solve.argtypes = [c_void_p, c_double, c_void_p]
+_lib.sylv_batch_solve.restype = c_int
+_lib.sylv_batch_context.argtypes = [c_void_p, c_int]
+_lib.sylv_batch_context.restype = c_void_p
+_lib.sylv_batch_destroy.argtypes = [c_void_p]
+_lib.sylv_batch_destroy.restype = None
 
 
 def declared_functions(header: str = HEADER_PATH) -> list[str]:
@@ -367,6 +378,89 @@ class Solver:
         if getattr(self, "ctx", None) is not None:
             sylv_destroy(self.ctx)
             self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- batches ----------------------------------------------------------------------------------
+
+def sylv_batch_workspace_bytes(problems, options) -> int:
+    P = (sylv_problem * len(problems))(*problems)
+    O = (sylv_options * len(options))(*options)
+    return int(_lib.sylv_batch_workspace_bytes(len(problems), P, O))
+
+
+def sylv_batch_create(problems, options, workspace, nstreams: int):
+    P = (sylv_problem * len(problems))(*problems)
+    O = (sylv_options * len(options))(*options)
+    h = c_void_p()
+    rc = _lib.sylv_batch_create(byref(h), len(problems), P, O, c_void_p(_ptr(workspace)),
+                                c_size_t(workspace.numel() * workspace.element_size()),
+                                int(nstreams))
+    if rc != 0:
+        raise SylvError(rc, "sylv_batch_create")
+    return h
+
+
+def sylv_batch_solve(batch, tol: float, count: int):
+    R = (sylv_result * count)()
+    rc = _lib.sylv_batch_solve(batch, c_double(tol), R)
+    if rc < 0:
+        raise SylvError(rc, "sylv_batch_solve")
+    return list(R)
+
+
+def sylv_batch_context(batch, i: int):
+    return c_void_p(_lib.sylv_batch_context(batch, int(i)))
+
+
+def sylv_batch_destroy(batch) -> None:
+    _lib.sylv_batch_destroy(batch)
+
+
+class Batch:
+    """Device copies and contexts of a batch of problems (workloads.Problem-like objects with
+    A, B, C1, C2, lyapunov, method, max_iter), solved together by sylv_batch_solve."""
+
+    def __init__(self, problems, nstreams=8, precision=0, device="cuda"):
+        import torch
+        self._keep = []
+        probs, opts = [], []
+        for p in problems:
+            A = csr_tensors(p.A, device)
+            Bm = A if p.lyapunov else csr_tensors(p.B, device)
+            C1 = torch.as_tensor(np.ascontiguousarray(p.C1, dtype=np.float64), device=device)
+            C2 = C1 if p.lyapunov else torch.as_tensor(
+                np.ascontiguousarray(p.C2, dtype=np.float64), device=device)
+            self._keep += [A, Bm, C1, C2]
+            n, s = p.C1.shape
+            m = n if p.lyapunov else p.B.shape[0]
+            probs.append(sylv_problem(n, m, s, make_csr(n, *A), make_csr(m, *Bm),
+                                      1 if p.lyapunov else 0, _ptr(C1), s, _ptr(C2), s))
+            method = SYLV_METHOD_CG if p.method == "cg" else SYLV_METHOD_BICGSTAB
+            opts.append(default_options(method, p.max_iter, precision=precision))
+        self.problems, self.options = probs, opts
+        nbytes = sylv_batch_workspace_bytes(probs, opts)
+        if nbytes == 0:
+            raise SylvError(SYLV_ERR_INVALID, "sylv_batch_workspace_bytes")
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
+        self.handle = sylv_batch_create(probs, opts, self.workspace, nstreams)
+        self.count = len(probs)
+
+    def solve(self, tol):
+        return sylv_batch_solve(self.handle, tol, self.count)
+
+    def context(self, i):
+        return sylv_batch_context(self.handle, i)
+
+    def close(self):
+        if getattr(self, "handle", None) is not None:
+            sylv_batch_destroy(self.handle)
+            self.handle = None
 
     def __del__(self):
         try:

@@ -209,8 +209,8 @@ def run_batch(args, sylv, torch, np):
     untimed warm-up solve), then the same instances solved sequentially on one stream."""
     from workloads import configs
     probs = configs.batch64()
-    for p in probs:  # workspace sized for the survey's iteration estimates of these instances
-        p.max_iter = 600 if p.method == "cg" else 500
+    for p in probs:  # workspace sized for the instances' needs (CG up to ~1000 iterations)
+        p.max_iter = 1500 if p.method == "cg" else 600
     mixed = args.precision == "fp32"
     prec = sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64
 

@@ -28,7 +28,7 @@ struct Layout {
   size_t off_V, off_W, off_H, off_G, off_X, off_R, off_P, off_Q, off_S, off_T;
   size_t off_U, off_Uw, off_coefV, off_coefW, off_btrp, off_btci, off_btval, off_tscr;
   size_t off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
-  size_t off_Lx, off_M2, off_d1, off_d2, off_c2;
+  size_t off_Lx, off_M2, off_d1, off_d2, off_c2, off_cpart, cpart_cap = 0;
   size_t off_dots, off_flag, off_panV, off_panW, off_sellA, off_sellB;
   // outer refinement: correction contexts and the buffers of the sketch and of the residual of
   // the summed iterates (child: a correction context, whose operators belong to the parent)
@@ -138,6 +138,12 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.off_d1 = bump(cur, (size_t)L.n * L.s * 8);
   L.off_d2 = L.lyap ? L.off_d1 : bump(cur, (size_t)L.m * L.s * 8);
   L.off_c2 = bump(cur, (size_t)L.m * L.s * 8);  // C2 (C1 for Lyapunov)
+  // split-K partial tiles of the core operator (BiCGSTAB): about 512 + T^2 tiles of 64 x 64
+  if (L.method == SYLV_METHOD_BICGSTAB) {
+    const int64_t T = L.ldc / 64;
+    L.cpart_cap = (size_t)(512 + std::min<int64_t>(T * T, 512)) * 4096;
+    L.off_cpart = bump(cur, L.cpart_cap * 8);
+  }
   L.off_panV = bump(cur, (size_t)2 * L.n * L.s * L.esz);
   L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * L.esz);
   L.off_sellA = child ? 0 : bump(cur, sell_bytes(L.n, pb->A.nnz));
@@ -268,6 +274,7 @@ struct Ctx {
   char *ws = nullptr;
   SideDesc sv{}, sw{};
   double *H, *G, *X, *R, *P, *Q, *S, *T, *Rt, *RL, *RR, *hist;
+  double *cpart = nullptr;  // split-K scratch of the core operator
   DevState *ds;
   SideState *ssv, *ssw;
   Scratch sc{};
@@ -423,6 +430,7 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->RL = at<double>(c, L.off_rl);
   c->RR = at<double>(c, L.off_rr);
   c->hist = at<double>(c, L.off_hist);
+  c->cpart = L.cpart_cap ? at<double>(c, L.off_cpart) : nullptr;
   c->ds = at<DevState>(c, L.off_ds);
   c->ssv = at<SideState>(c, L.off_ssv);
   c->ssw = L.lyap ? c->ssv : at<SideState>(c, L.off_ssw);
@@ -1156,7 +1164,9 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
       return e;
     // Q_k (step 7), alpha_k (step 8), S_k (step 9)
     prof_begin(c->sc, c->st);
-    if ((e = launch_core_op(s, p, c->H, c->G, c->P, c->Q, L.ldc, done, c->st))) return e;
+    if ((e = launch_core_op(s, p, c->H, c->G, c->P, c->Q, L.ldc, done, c->st, c->cpart,
+                            L.cpart_cap)))
+      return e;
     prof_end(c->sc, FAM_CORE_OP, coreop_bytes(p), coreop_flops(p), c->st);
     const double q1 = (double)(p + s) * (p + s), q2 = (double)(p + 2 * s) * (p + 2 * s);
     prof_begin(c->sc, c->st);
@@ -1170,7 +1180,9 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
       return e;
     // T_k (step 12), omega_k (step 13), rho_{k+1}, beta_k (steps 18-19)
     prof_begin(c->sc, c->st);
-    if ((e = launch_core_op(s, p + s, c->H, c->G, c->S, c->T, L.ldc, done, c->st))) return e;
+    if ((e = launch_core_op(s, p + s, c->H, c->G, c->S, c->T, L.ldc, done, c->st, c->cpart,
+                            L.cpart_cap)))
+      return e;
     prof_end(c->sc, FAM_CORE_OP, coreop_bytes(p + s), coreop_flops(p + s), c->st);
     prof_begin(c->sc, c->st);
     if ((e = launch_bicg_omega(s, p, c->T, c->S, L.ldc, c->sc, c->ds, c->st)))

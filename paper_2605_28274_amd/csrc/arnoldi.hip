@@ -68,21 +68,23 @@ __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
-  const int64_t r0 = (int64_t)lb * TPB;
-  const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
-  double acc[S];
-  const int64_t r = r0 + threadIdx.x;
-  if (A.sell.ci) {
-    if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
-  } else {
-    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
-  }
   double red[1] = {0.0};
-  if (r < r1) {
+  // row tiles lb, lb + nb, ... (at most ROW_WG workgroups per basis, so few partials)
+  for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
+    const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+    double acc[S];
+    const int64_t r = r0 + threadIdx.x;
+    if (A.sell.ci) {
+      if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
+    } else {
+      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+    }
+    if (r < r1) {
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-      A.U[r * S + t] = acc[t];
-      red[0] = fma(acc[t], acc[t], red[0]);
+      for (int t = 0; t < S; ++t) {
+        A.U[r * S + t] = acc[t];
+        red[0] = fma(acc[t], acc[t], red[0]);
+      }
     }
   }
   __shared__ double lds[16];
@@ -234,6 +236,13 @@ __global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int nco
   }
 }
 
+// Columns of the coefficient block staged in LDS at a time by update_mfma_pair (64 KiB, whole
+// groups of 128 columns).
+template <int S>
+__host__ __device__ constexpr int UPD_KCH() {
+  return (64 * 1024 / (S * 8)) / 128 * 128;
+}
+
 // U[r] -= V[r, 0:ncols] C on FP64 matrix cores (v_mfma_f64_16x16x4f64): each wave owns 16 rows,
 // D (16 x 16) += A (16 rows x 4 basis columns) B (4 x 16, coefficient columns >= S are zero).
 // Lane l reads 32 contiguous bytes of row l % 16 per step (KL consecutive columns, chunk l / 16),
@@ -246,27 +255,37 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, con
   typedef double v4 __attribute__((ext_vector_type(4)));
   constexpr int KL = 32 / (int)sizeof(T);  // columns per lane per step
   constexpr int KG = 4 * KL;               // columns per step
+  constexpr int KU = 4;                    // steps whose loads are in flight together
   extern __shared__ double Cs[];
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   const int nk = (ncols + KG - 1) / KG * KG;
-  for (int e = threadIdx.x; e < nk * S; e += TPB) Cs[e] = e < ncols * S ? A.coef[e] : 0.0;
-  __syncthreads();
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int li = lane & 15, lq = lane >> 4;
+  // one block of 16 rows per wave (UROWS rows per workgroup)
   const int64_t r0 = (int64_t)lb * A.rpc;
   const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
-  constexpr int KU = 4;  // steps whose loads are in flight together
-  for (int64_t rb = r0 + 16 * w; rb < r1; rb += 16 * (TPB / WAVE)) {
-    const int64_t row = (rb + li < r1) ? rb + li : r1 - 1;  // clamped loads, masked stores
-    const T *vr = static_cast<const T *>(A.basis) + row * A.ldb + lq * KL;
-    v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
-    for (int k0 = 0; k0 < nk; k0 += KU * KG) {
+  const int64_t rb = r0 + 16 * w;
+  const bool live = rb < r1;
+  const int64_t row = (rb + li < r1) ? rb + li : r1 - 1;  // clamped loads, masked stores
+  const T *vr = static_cast<const T *>(A.basis) + row * A.ldb + lq * KL;
+  v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  // the coefficients pass through LDS in chunks of at most 64 KiB
+  for (int c0 = 0; c0 < nk; c0 += UPD_KCH<S>()) {
+    const int c1 = (c0 + UPD_KCH<S>() < nk) ? c0 + UPD_KCH<S>() : nk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (c1 - c0) * S; e += TPB) {
+      const int g = c0 * S + e;
+      Cs[e] = g < ncols * S ? A.coef[g] : 0.0;
+    }
+    __syncthreads();
+    if (!live) continue;
+    for (int k0 = c0; k0 < c1; k0 += KU * KG) {
       T x[KU][KL];
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
-        // a step past nk re-reads step 0 (in bounds); its products are masked to zero below
-        const int kk = k0 + u * KG < nk ? k0 + u * KG : 0;
+        // a step past the chunk re-reads step 0 (in bounds); its products are masked below
+        const int kk = k0 + u * KG < c1 ? k0 + u * KG : 0;
         if (sizeof(T) == 8) {
           const double2 *p2 = reinterpret_cast<const double2 *>(vr + kk);
           const double2 a = p2[0], b = p2[1];
@@ -284,24 +303,24 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, con
       }
 #pragma unroll
       for (int u = 0; u < KU; ++u) {
-        const bool step = k0 + u * KG < nk;
+        const bool step = k0 + u * KG < c1;
 #pragma unroll
         for (int m = 0; m < KL; ++m) {
           const int k = k0 + u * KG + lq * KL + m;
           const double av = (step && k < ncols) ? (double)x[u][m] : 0.0;
-          const double bv = (step && li < S) ? Cs[k * S + li] : 0.0;
+          const double bv = (step && li < S) ? Cs[(k - c0) * S + li] : 0.0;
           if (m & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
           else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
         }
       }
     }
-    // lane holds D[4 v + lq][li]: row rb + 4 v + lq, column li
-    if (li < S) {
+  }
+  // lane holds D[4 v + lq][li]: row rb + 4 v + lq, column li
+  if (live && li < S) {
 #pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t r = rb + 4 * v + lq;
-        if (r < r1) A.U[r * S + li] -= acc0[v] + acc1[v];
-      }
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rb + 4 * v + lq;
+      if (r < r1) A.U[r * S + li] -= acc0[v] + acc1[v];
     }
   }
 }
@@ -315,15 +334,14 @@ __global__ __launch_bounds__(TPB) void ugram_pair(ArPair P, const DevState *ds) 
   double g[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  const int64_t r = (int64_t)lb * TPB + threadIdx.x;
-  if (r < A.rows) {
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
     double u[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
 #pragma unroll
     for (int a = 0; a < S; ++a)
 #pragma unroll
-      for (int b = 0; b < S; ++b) g[a * S + b] = u[a] * u[b];
+      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
   }
   __shared__ double lds[16 * S * S];
   block_sum<S * S>(g, lds);
@@ -473,39 +491,40 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
 #pragma unroll
     for (int t = 0; t < S; ++t)
       hup[u * S + t] = jb > 0 ? A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + u] : 0.0;
-  const int64_t r0 = (int64_t)lb * TPB;
-  const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
-  const int64_t r = r0 + threadIdx.x;
-  double acc[S];
-  if (A.sell.ci) {
-    if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
-  } else {
-    spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
-  }
   double red[S * S + 1];
 #pragma unroll
   for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
-  if (r < r1) {
+  for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
+    const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+    const int64_t r = r0 + threadIdx.x;
+    double acc[S];
+    if (A.sell.ci) {
+      if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
+    } else {
+      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+    }
+    if (r < r1) {
 #pragma unroll
-    for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
-    if (jb > 0) {
-      const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused for j+1)
+      for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
+      if (jb > 0) {
+        const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused)
 #pragma unroll
-      for (int u = 0; u < S; ++u) {
-        const double vu = (double)vp[u];
+        for (int u = 0; u < S; ++u) {
+          const double vu = (double)vp[u];
 #pragma unroll
-        for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
+          for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
+        }
       }
+      const T *vj = static_cast<const T *>(A.pin) + r * S;
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        const double va = (double)vj[a];
+#pragma unroll
+        for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
+      }
+#pragma unroll
+      for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
     }
-    const T *vj = static_cast<const T *>(A.pin) + r * S;
-#pragma unroll
-    for (int a = 0; a < S; ++a) {
-      const double va = (double)vj[a];
-#pragma unroll
-      for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
-    }
-#pragma unroll
-    for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
   }
   __shared__ double lds[16 * (S * S + 1)];
   block_sum<S * S + 1>(red, lds);
@@ -539,8 +558,7 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t 
   double g[S * S];
 #pragma unroll
   for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  const int64_t r = (int64_t)lb * TPB + threadIdx.x;
-  if (r < A.rows) {
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
     double u[S];
 #pragma unroll
     for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
@@ -556,7 +574,7 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t 
 #pragma unroll
     for (int a = 0; a < S; ++a)
 #pragma unroll
-      for (int b = 0; b < S; ++b) g[a * S + b] = u[a] * u[b];
+      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
   }
   __shared__ double lds[16 * S * S];
   block_sum<S * S>(g, lds);
@@ -616,7 +634,10 @@ unsigned total_blocks(const ArPair &P) {
 constexpr int64_t UROWS = 64;    // rows per update workgroup (16 per wave)
 constexpr int64_t QR_MAXWG = 512;
 
-int64_t nb_rows(int64_t rows) { return cdiv(rows, TPB); }
+// Workgroups of the row-tile kernels of one basis (spmm, local update, U^T U): at most ROW_WG,
+// each taking row tiles lb, lb + nb, ...; fewer partial records for the next kernel to sum.
+constexpr int64_t ROW_WG = 512;
+int64_t nb_rows(int64_t rows) { return std::min<int64_t>(cdiv(rows, TPB), ROW_WG); }
 int64_t nb_qr(int64_t rows) { return std::min<int64_t>(nb_rows(rows), QR_MAXWG); }
 size_t aux_len(int s, int64_t rows) {
   return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows) + nb_rows(rows)) * s * s + 16);
@@ -662,9 +683,9 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
   if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
     return SYLV_ERR_WORKSPACE;
-  // coefficients padded to whole steps of the MFMA update (32 columns)
-  const size_t lds = (size_t)((ncols + 31) / 32 * 32) * S * sizeof(double);
-  if (lds > 64 * 1024) return SYLV_ERR_WORKSPACE;
+  // coefficient chunk of the MFMA update in LDS (at most 64 KiB)
+  const size_t lds =
+      (size_t)std::min((ncols + 127) / 128 * 128, UPD_KCH<S>()) * S * sizeof(double);
   const int64_t rtiles = cdiv(nout, OPB);
 
   for (int pass = 1; pass <= 2; ++pass) {

@@ -588,8 +588,11 @@ int launch_copy_block(int rows, int cols, double alpha, const double *src, int64
 int launch_diag_fill(int k, double v, double *dst, int64_t ldd, hipStream_t st);
 int launch_axpy_narrow(int64_t rows, int q, double alpha, const double *F, int64_t ldf, double *Y,
                        int64_t ldy, hipStream_t st);
+// part (part_cap doubles, may be null): scratch for the split-K form used when the cores span
+// few 64 x 64 tiles.
 int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,
-                   int64_t ldc, const int *done, hipStream_t st);
+                   int64_t ldc, const int *done, hipStream_t st, double *part = nullptr,
+                   size_t part_cap = 0);
 int launch_csr_validate(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, int *flag,
                         hipStream_t st);
 int launch_dot(int64_t M, int64_t N, const double *A, int64_t lda, const double *B, int64_t ldb,

@@ -83,37 +83,79 @@ __device__ __forceinline__ void sum_partials(const double *partials, int nb, dou
 // ---- CG (block-tridiagonal H and G from block Lanczos) ----
 
 // Q = [H P, 0] + [P G^T; 0] over (p+s)^2 using the band |blk(i) - blk(l)| <= 1 of H and G;
-// partials of <P, Q(1:p, 1:p)>.
+// partials of <P, Q(1:p, 1:p)>. Workgroup b owns 256 columns (b % gx) and the row groups
+// b / gx, b / gx + gy, ... of CG_ROWS rows; thread j keeps row j's band of G in registers, and
+// the band loops have fixed length 3S (masked), so CG_UNR rows are in flight at once.
+constexpr int CG_ROWS = 16, CG_UNR = 4, CG_MAXWG = 4096;
+
 template <int S>
-__global__ __launch_bounds__(TPB) void cg_core_kernel(int p, const double *__restrict__ H,
+__global__ __launch_bounds__(TPB) void cg_core_kernel(int p, int gx, int gy,
+                                                      const double *__restrict__ H,
                                                       const double *__restrict__ G,
                                                       const double *__restrict__ P,
                                                       double *__restrict__ Q, int64_t ldc,
                                                       double *partials, const DevState *ds) {
   if (ds->done) return;
   const int q = p + S;
+  const int cx = (int)blockIdx.x % gx, ry = (int)blockIdx.x / gx;
+  const int j = cx * TPB + threadIdx.x;
+  const bool jl = j < q;
+  const int jc = jl ? j : q - 1;  // clamped column for loads
+  const int bj = jc / S;
+  const int l0 = bj > 0 ? (bj - 1) * S : 0;
+  const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
+  double gb[3 * S];
+#pragma unroll
+  for (int t = 0; t < 3 * S; ++t) gb[t] = (l0 + t < l1) ? G[(int64_t)jc * ldc + l0 + t] : 0.0;
   double v[1] = {0.0};
-  for (int i = blockIdx.x; i < q; i += gridDim.x) {
-    const int bi = i / S;
-    const int li0 = bi > 0 ? (bi - 1) * S : 0;
-    const int li1 = (bi + 2) * S < p ? (bi + 2) * S : p;
-    for (int j = threadIdx.x; j < q; j += TPB) {
-      double acc = 0.0;
-      if (j < p)
-        for (int l = li0; l < li1; ++l)
-          acc = fma(H[(int64_t)i * ldc + l], P[(int64_t)l * ldc + j], acc);
-      if (i < p) {
-        const int bj = j / S;
-        const int l0 = bj > 0 ? (bj - 1) * S : 0;
-        const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
-        for (int l = l0; l < l1; ++l)
-          acc = fma(P[(int64_t)i * ldc + l], G[(int64_t)j * ldc + l], acc);
+  for (int i0 = ry * CG_ROWS; i0 < q; i0 += gy * CG_ROWS) {
+#pragma unroll
+    for (int u0 = 0; u0 < CG_ROWS; u0 += CG_UNR) {
+      double acc[CG_UNR], pij[CG_UNR];
+#pragma unroll
+      for (int u = 0; u < CG_UNR; ++u) {
+        const int i = i0 + u0 + u;
+        const int ic = i < q ? i : q - 1;
+        const int bi = ic / S;
+        const int li0 = bi > 0 ? (bi - 1) * S : 0;
+        double a = 0.0;
+        // H P: row i of H meets rows li0 .. li0 + 3S of P (masked at p)
+#pragma unroll
+        for (int t = 0; t < 3 * S; ++t) {
+          const int l = li0 + t;
+          const bool in = (l < p) && (j < p);
+          const double h = in ? H[(int64_t)ic * ldc + l] : 0.0;
+          const double pv = in ? P[(int64_t)l * ldc + jc] : 0.0;
+          a = fma(h, pv, a);
+        }
+        // P G^T: row i of P meets the band of row j of G (zero past p)
+        if (ic < p) {
+          const double *pr = P + (int64_t)ic * ldc + l0;
+#pragma unroll
+          for (int t = 0; t < 3 * S; ++t) a = fma((l0 + t < l1) ? pr[t] : 0.0, gb[t], a);
+        }
+        acc[u] = a;
+        pij[u] = P[(int64_t)ic * ldc + jc];
       }
-      Q[(int64_t)i * ldc + j] = acc;
-      if (i < p && j < p) v[0] = fma(P[(int64_t)i * ldc + j], acc, v[0]);
+#pragma unroll
+      for (int u = 0; u < CG_UNR; ++u) {
+        const int i = i0 + u0 + u;
+        if (i < q && jl) {
+          Q[(int64_t)i * ldc + j] = acc[u];
+          if (i < p && j < p) v[0] = fma(pij[u], acc[u], v[0]);
+        }
+      }
     }
   }
   put_partials<1>(v, partials);
+}
+
+// Grid of cg_core_kernel for a (p+s)^2 core: gx column chunks x gy row-group strides, at most
+// CG_MAXWG workgroups (the consumer sums one partial per workgroup).
+void cg_core_grid(int q, int &gx, int &gy) {
+  gx = (q + TPB - 1) / TPB;
+  const int groups = (q + CG_ROWS - 1) / CG_ROWS;
+  gy = std::max(1, std::min(CG_MAXWG / gx, groups));
 }
 
 // alpha = rho / <P, Q> from cg_core's partials (breakdown when <P, Q> <= 0);
@@ -328,15 +370,17 @@ int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, d
   return 0;
 }
 
-// Scratch::partials layout: [0, 2*NBLK) partials of the scalar being formed (<P,Q> or
-// <T,S>, <T,T>); [2*NBLK, 3*NBLK) the ||R||^2 partials.
+// Scratch::partials layout: [0, 2*NBLK) partials of the scalar being formed (<P,Q>: up to
+// CG_MAXWG; <T,S>, <T,T>); [2*NBLK, 3*NBLK) the ||R||^2 partials (CG: from CG_MAXWG).
 int launch_cg_core(int s, int p, const double *H, const double *G, const double *P, double *Q,
                    int64_t ldc, const Scratch &sc, DevState *ds, hipStream_t st) {
-  const unsigned g = grid_q(p + s);
+  int gx, gy;
+  cg_core_grid(p + s, gx, gy);
+  const unsigned g = (unsigned)(gx * gy);
   switch (s) {
 #define CASE(SS)                                                                             \
   case SS:                                                                                   \
-    cg_core_kernel<SS><<<g, TPB, 0, st>>>(p, H, G, P, Q, ldc, sc.partials, ds);              \
+    cg_core_kernel<SS><<<g, TPB, 0, st>>>(p, gx, gy, H, G, P, Q, ldc, sc.partials, ds);      \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -351,8 +395,10 @@ int launch_cg_update(int s, int p, double *X, double *R, double *P, const double
                      hipStream_t st) {
   const int q = p + s;
   const unsigned g = grid_q(q);
-  double *rr = sc.partials + 2 * NBLK;
-  cg_update_kernel<<<g, TPB, 0, st>>>(p, q, X, R, P, Q, ldc, sc.partials, (int)g, rr, ds, hist,
+  double *rr = sc.partials + CG_MAXWG;
+  int gx, gy;
+  cg_core_grid(q, gx, gy);  // one <P, Q> partial per cg_core workgroup
+  cg_update_kernel<<<g, TPB, 0, st>>>(p, q, X, R, P, Q, ldc, sc.partials, gx * gy, rr, ds, hist,
                                       k, max_iter);
   HIPOK(hipGetLastError());
   cg_converge_kernel<<<1, TPB, 0, st>>>(rr, (int)g, ds, hist, k, max_iter);

@@ -229,6 +229,66 @@ __global__ __launch_bounds__(256) void core_op_kernel(int s, int p, int T,
   if (t2 != t1) core_op_tile(sm, s, p, H, G, P, Q, ldc, (t2 / T) * BM, (t2 % T) * BN, wm, wn);
 }
 
+// Split-K form of the core operator for few tiles: tile t's work is the slab sequence of its two
+// products (H P over [lsH, pk), then P G^T over [lsG, pk)); workgroup (t, kz) takes slabs
+// [kz c, (kz+1) c) of that sequence and stores its partial 64 x 64 tile; core_op_reduce sums the
+// nk partials in order into Q (every output element gets exactly one sum, deterministic).
+__device__ __forceinline__ void core_tile_ranges(int s, int p, int i0, int j0, int pk, int &lsH,
+                                                 int &nH, int &lsG, int &nG) {
+  lsH = (i0 / s - 1) * s;
+  lsH = lsH < 0 ? 0 : lsH / BK * BK;
+  lsG = (j0 / s - 1) * s;
+  lsG = lsG < 0 ? 0 : lsG / BK * BK;
+  nH = (j0 < p) ? (pk - lsH) / BK : 0;
+  nG = (i0 < p) ? (pk - lsG) / BK : 0;
+}
+
+__global__ __launch_bounds__(256) void core_op_split_kernel(int s, int p, int T, int nk,
+                                                            const double *__restrict__ H,
+                                                            const double *__restrict__ G,
+                                                            const double *__restrict__ P,
+                                                            int64_t ldc, const int *done,
+                                                            double *__restrict__ part) {
+  if (done && *done) return;
+  __shared__ Smem sm;
+  const int tiles = T * T;
+  const int t = blockIdx.x % tiles, kz = blockIdx.x / tiles;
+  const int i0 = (t / T) * BM, j0 = (t % T) * BN;
+  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  const int pk = (p + BK - 1) / BK * BK;
+  int lsH, nH, lsG, nG;
+  core_tile_ranges(s, p, i0, j0, pk, lsH, nH, lsG, nG);
+  const int tot = nH + nG, c = (tot + nk - 1) / nk;
+  const int a = kz * c, b = (a + c < tot) ? a + c : tot;
+  WaveAcc acc;
+  zero_acc(acc);
+  // slabs [a, b) of the sequence: H P slabs first, then P G^T slabs
+  const int ha = a < nH ? a : nH, hb = b < nH ? b : nH;
+  if (hb > ha)
+    pipelined<false, false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, ldc, P + j0, ldc,
+                            lsH + ha * BK, lsH + hb * BK);
+  const int ga = (a > nH ? a : nH) - nH, gb = (b > nH ? b : nH) - nH;
+  if (gb > ga)
+    pipelined<false, true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, ldc, G + (int64_t)j0 * ldc, ldc,
+                           lsG + ga * BK, lsG + gb * BK);
+  double *pt = part + ((size_t)kz * tiles + t) * (BM * BN);
+  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });
+}
+
+__global__ __launch_bounds__(256) void core_op_reduce_kernel(int T, int nk,
+                                                             const double *__restrict__ part,
+                                                             double *__restrict__ Q, int64_t ldc,
+                                                             const int *done) {
+  if (done && *done) return;
+  const int tiles = T * T;
+  const int t = blockIdx.x / 16, sub = blockIdx.x % 16;
+  const int e = sub * 256 + threadIdx.x;
+  double v = 0.0;
+  for (int kz = 0; kz < nk; ++kz) v += part[((size_t)kz * tiles + t) * (BM * BN) + e];
+  const int i0 = (t / T) * BM, j0 = (t % T) * BN;
+  Q[(int64_t)(i0 + e / BN) * ldc + j0 + e % BN] = v;
+}
+
 // ---- tall-skinny Gram C (+)= A^T B over K rows (residual evaluation) ----
 // A: K x M and B: K x N row-major with row strides lda, ldb; columns up to the next multiple of
 // 64 of M (N) must lie inside the rows (lda >= roundup(M, 64)); K is a multiple of BK. With
@@ -430,10 +490,26 @@ __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t
 }  // namespace
 
 int launch_core_op(int s, int p, const double *H, const double *G, const double *P, double *Q,
-                   int64_t ldc, const int *done, hipStream_t st) {
+                   int64_t ldc, const int *done, hipStream_t st, double *part, size_t part_cap) {
   const int q = p + s;
   const int T = (q + BM - 1) / BM;
   if ((int64_t)T * BM > ldc || ((p + BK - 1) / BK * BK) > ldc) return SYLV_ERR_WORKSPACE;
+  const int tiles = T * T;
+  // few tiles: split each tile's slab sequence so that about 512 workgroups run
+  int nk = 1;
+  if (part && tiles < 512) {
+    const int slabs = 2 * ((p + BK - 1) / BK);
+    nk = std::min({(512 + tiles - 1) / tiles, std::max(slabs / 8, 1),
+                   (int)(part_cap / ((size_t)tiles * BM * BN))});
+  }
+  if (nk > 1) {
+    core_op_split_kernel<<<(unsigned)(tiles * nk), 256, 0, st>>>(s, p, T, nk, H, G, P, ldc, done,
+                                                                 part);
+    HIPOK(hipGetLastError());
+    core_op_reduce_kernel<<<(unsigned)(tiles * 16), 256, 0, st>>>(T, nk, part, Q, ldc, done);
+    HIPOK(hipGetLastError());
+    return 0;
+  }
   core_op_kernel<<<(unsigned)((T * T + 1) / 2), 256, 0, st>>>(s, p, T, H, G, P, Q, ldc, done);
   HIPOK(hipGetLastError());
   return 0;

@@ -85,6 +85,10 @@ def main():
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="storage of the Krylov bases (fp32: mixed precision)")
+    ap.add_argument("--pmc-pass", action="store_true",
+                    help="one step only (for hardware-counter runs of rocprofv3 --pmc)")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="device copies of 512 MiB (counter calibration) and exit")
     ap.add_argument("--refine", type=int, default=-1,
                     help="correction solves of the outer refinement (default: 3 with fp32 "
                          "bases, 0 with fp64)")
@@ -101,6 +105,14 @@ def main():
     from paper_2605_28274_amd import sylv
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        src = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibrate_copy_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
     if args.workload == "batch64":
         return run_batch(args, sylv, torch, np)
     p, method = workload(args.workload, args.max_iter)
@@ -152,6 +164,9 @@ def main():
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ms_per_step = 1000.0 * dt / args.steps
+    if args.pmc_pass:
+        print(json.dumps({"pmc_pass": args.workload, "iters": iters}), flush=True)
+        return
 
     # untimed measurement pass: per-family kernel times with HIP events on the solver's stream
     ctx = sylv.sylv_create(prob, opts, ws, stream.cuda_stream)
@@ -172,7 +187,8 @@ def main():
         achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
         peak = PEAK_HBM_GBS
     roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4), "traffic": None,
+                "frac": round(achieved / peak, 4),
+                "traffic": measured_traffic(args.workload, dom["family"], args.precision),
                 "kernel": dom["family"], "launches": dom["launches"],
                 "avg_launch_us": round(1000 * dom["ms"] / max(dom["launches"], 1), 3),
                 "share_of_kernel_time": round(dom["ms"] / tot, 3)}
@@ -198,10 +214,73 @@ def main():
                    "true_rel_res": float(np.max(rels)), "statuses": sorted(set(statuses))},
         "roofline": roofline,
         "kernel_breakdown": breakdown,
+        "spmm_hbm": spmm_hbm(sylv, torch) if args.workload == "c2" and not mixed else None,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p, method, args.cpu_iters)
     print(json.dumps(out), flush=True)
+
+
+# Kernel sources whose family the hardware-counter traffic in profiles/ was taken for.
+FAMILY_SOURCES = {"core_op": "dense.hip", "gram": "arnoldi.hip", "update": "arnoldi.hip",
+                  "spmm": "arnoldi.hip", "block_qr": "arnoldi.hip", "core_elem": "core.hip",
+                  "core_band": "core.hip"}
+
+
+def measured_traffic(workload, family, precision):
+    """HBM bytes per launch of `family` from the committed counter summary
+    profiles/traffic_<workload>.md (FETCH_SIZE + WRITE_SIZE over the family's kernels, scaled by
+    a copy kernel of known size), or None when there is none or the kernel source changed since
+    (its SHA-256 is recorded beside the figure)."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"traffic_{workload}.md")
+    src = FAMILY_SOURCES.get(family)
+    if precision != "fp64" or not src or not os.path.exists(path):
+        return None
+    sha = hashlib.sha256(open(os.path.join(ROOT, "paper_2605_28274_amd", "csrc", src),
+                              "rb").read()).hexdigest()
+    for line in open(path):
+        if line.startswith("TRAFFIC "):
+            rec = json.loads(line[len("TRAFFIC "):])
+            if rec.get("family") == family and rec.get("source_sha256") == sha:
+                return rec["bytes_per_launch"]
+    return None
+
+
+def spmm_hbm(sylv, torch):
+    """SpMM (sliced ELLPACK, FP64) on two large operators, warm (back to back) and cold (after a
+    512 MiB write evicts the caches): algorithmic bytes 12 nnz + 4 (rows + 1) + 16 rows s per
+    call over the HIP-event time of the launch."""
+    import numpy as np
+    from workloads import stencils
+    out = {}
+    flush = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+    for name, M, s in (("2D 1024^2 (n = 1048576), s = 1", stencils.cd2d(1024, 1024, 0.0), 1),
+                       ("3D 64^3 (n = 262144), s = 4", stencils.cd3d(64, 64, 64, 10.0), 4)):
+        rp, ci, va = sylv.csr_tensors(M)
+        csr = sylv.make_csr(M.shape[0], rp, ci, va)
+        buf = torch.empty(sylv.sylv_sell_bytes(csr), dtype=torch.uint8, device="cuda")
+        sylv.sylv_sell_build(csr, buf)
+        X = torch.randn(M.shape[0], s, dtype=torch.float64, device="cuda")
+        Y = torch.empty_like(X)
+        nbytes = 12 * M.nnz + 4 * (M.shape[0] + 1) + 16 * M.shape[0] * s
+        res = {}
+        for mode in ("warm", "cold"):
+            ts = []
+            for _ in range(10):
+                if mode == "cold":
+                    flush.fill_(1.0)
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record()
+                sylv.sylv_sell_spmm(csr, buf, s, X, Y)
+                b.record()
+                torch.cuda.synchronize()
+                ts.append(a.elapsed_time(b))
+            t = float(np.median(ts)) * 1e-3
+            res[mode] = {"us": round(t * 1e6, 2), "GB/s": round(nbytes / t / 1e9, 1),
+                         "frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 3)}
+        out[name] = {"bytes": nbytes, **res}
+    return out
 
 
 def run_batch(args, sylv, torch, np):

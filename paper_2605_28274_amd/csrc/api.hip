@@ -1089,8 +1089,8 @@ int sylv_get_kernel_stats(void *ctx, sylv_kernel_stat *out, int cap, int *count)
 }
 
 const char *sylv_kernel_family_name(int family) {
-  static const char *names[FAM_COUNT] = {"spmm",    "gram",      "update",   "block_qr",
-                                         "core_op", "core_band", "core_elem"};
+  static const char *names[FAM_COUNT] = {"spmm",    "gram",      "update",    "block_qr",
+                                         "core_op", "core_band", "core_elem", "upd_gram"};
   return (family >= 0 && family < FAM_COUNT) ? names[family] : "unknown";
 }
 

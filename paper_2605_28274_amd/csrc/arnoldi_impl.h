@@ -1,0 +1,1106 @@
+// Block Arnoldi step j for both bases at once (Algorithm 4.2, steps 5-6 and 10-11): the V basis
+// of K(A, C1) and the W basis of K(B^T, C2) advance in lockstep, so every launch below covers
+// both: workgroups [0, nb_0) work on basis 0 and [nb_0, nb_0 + nb_1) on basis 1. This halves
+// the launches of the step and fills the GPU with the smaller basis' work as well.
+//
+// Step (per basis, M the operator, V the row-major rows x ldb basis, U a rows x s panel):
+//   U = M V_j, partials of ||U||^2                                 spmm_pair
+//   two classical Gram-Schmidt sweeps:
+//     C1 = V[:, 0:ncols]^T U  (split-K over row chunks)           gram_part_pair
+//     sum of the chunk partials -> H column block j, coef         gram_reduce_pair
+//     U -= V C1 and the chunk partials of C2 = V^T U in one pass   upd_gram_pair
+//       (narrow bases: update_mfma_pair, then gram_part_pair)
+//     sum of the C2 partials -> H += C2, coef                     gram_reduce_pair
+//     U -= V C2   (FP64 MFMA, coef staged in LDS)                  update_mfma_pair
+//   partials of U^T U after the second sweep                       ugram_pair
+//   first Cholesky-QR pass + closure test, partials of G2          qr2_pair
+//   second pass, V_{j+1} = U T, H_{j+1,j}                          final_pair
+// No kernel ends in a grid-wide fence: each reduction leaves one partial per workgroup and the
+// next kernel sums them in a fixed order (deterministic) after the kernel boundary; the small
+// s x s factorizations are then formed redundantly in every workgroup, and workgroup 0 records
+// them.
+//
+// This header holds the kernels and the host step templates; the arnoldi_s*.hip units
+// instantiate them for groups of block sizes (parallel compilation), arnoldi.hip dispatches.
+#pragma once
+#include <algorithm>
+
+#include "common.h"
+
+namespace {
+
+constexpr int TPB = 256;
+constexpr int NG = 8;          // thread groups splitting the chunk sum in gram_reduce_pair
+constexpr int OPB = TPB / NG;  // outputs per gram_reduce_pair workgroup
+constexpr int GRAM_LOADS = 16; // 8-byte basis loads in flight per thread in gram_part_pair
+
+struct ArSide {
+  int64_t rows, nnz;
+  const int32_t *rp, *ci;
+  const double *val;
+  void *basis;        // rows x ldb, element type T of the kernels (double, or float in mixed mode)
+  int64_t ldb;
+  double *H;
+  double *U;
+  double *coef;
+  SideState *ss;
+  SellMat sell;       // SELL copy of the operator (sell.ci == nullptr: CSR)
+  const void *pin;    // compact copy of block j (SpMM input), element type T
+  void *pout;         // compact copy of block j+1 (written with the new block), element type T
+  double *part;    // Gram chunk partials of this basis
+  double *aux;     // partials of ||M V_j||^2, U^T U and of the second-pass Gram
+  int *cnt;        // counters of this basis (unused: no grid-wide reductions)
+  int nb_spmm, nb_upd, nb_qr;  // workgroups whose partials sit in aux
+  int b0, nb;      // workgroup range of this basis in the current launch
+  int64_t rpc;     // rows per chunk (gram) or rows per workgroup (update)
+};
+
+struct ArPair {
+  ArSide s[2];
+  int nsides;
+};
+
+// The basis this workgroup works on (selected without dynamic indexing of the kernel argument)
+// and the workgroup's index within that basis' range.
+__device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd) {
+  sd = (P.nsides > 1 && (int)blockIdx.x >= P.s[1].b0) ? 1 : 0;
+  const ArSide A = sd ? P.s[1] : P.s[0];
+  lb = (int)blockIdx.x - A.b0;
+  return A;
+}
+
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double red[1] = {0.0};
+  // row tiles lb, lb + nb, ... (at most ROW_WG workgroups per basis, so few partials)
+  for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
+    const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+    double acc[S];
+    const int64_t r = r0 + threadIdx.x;
+    if (A.sell.ci) {
+      if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
+    } else {
+      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+    }
+    if (r < r1) {
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        A.U[r * S + t] = acc[t];
+        red[0] = fma(acc[t], acc[t], red[0]);
+      }
+    }
+  }
+  __shared__ double lds[16];
+  block_sum<1>(red, lds);
+  if (threadIdx.x == 0) A.aux[lb] = red[0];
+}
+
+// Eight bytes of basis entries per load: one double, or two floats (FP32 bases).
+template <typename T>
+struct Pack8;
+template <>
+struct Pack8<double> {
+  typedef double type;
+  static constexpr int N = 1;
+  static __device__ __forceinline__ type zero() { return 0.0; }
+  static __device__ __forceinline__ void get(type v, double (&o)[1]) { o[0] = v; }
+};
+template <>
+struct Pack8<float> {
+  typedef float2 type;
+  static constexpr int N = 2;
+  static __device__ __forceinline__ type zero() { return make_float2(0.f, 0.f); }
+  static __device__ __forceinline__ void get(type v, double (&o)[2]) {
+    o[0] = (double)v.x;
+    o[1] = (double)v.y;
+  }
+};
+
+// Chunk partials of C = V^T U. Workgroup lb owns rows [lb rpc, (lb+1) rpc) of its basis. Its
+// threads form G = TPB / CW row groups of CW threads (CW a power of two fitted to the width):
+// thread (g, l) owns the 8-byte column groups l + CW q (q < nq <= NQ; one double or two floats
+// each) and takes the rows g, g + G, ... of the chunk, RU rows per step, so that NQ RU loads are
+// in flight; a narrow basis thus still spreads its chunk over every thread. The row-group sums
+// are added in a fixed order through LDS. part[lb][c][t]; column groups past the width load
+// group 0 and rows past the chunk load its first row (both in bounds), neither is counted.
+template <int S, typename T, int NQ>
+__global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int cw_log2,
+                                                      const DevState *ds) {
+  if (ds->done) return;
+  typedef Pack8<T> PK;
+  typedef typename PK::type V8;
+  constexpr int E = PK::N;
+  // rows per step: GRAM_LOADS basis loads in flight, at most 16 U values held per thread
+  constexpr int RU0 = NQ >= GRAM_LOADS ? 1 : GRAM_LOADS / NQ;
+  constexpr int RU = RU0 * S > 16 ? (16 / S > 0 ? 16 / S : 1) : RU0;
+  extern __shared__ double gsum[];  // TPB * E * S doubles (several row groups only)
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const int CW = 1 << cw_log2, G = TPB >> cw_log2;
+  const int g = (int)threadIdx.x >> cw_log2, l = (int)threadIdx.x & (CW - 1);
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  double *part = A.part + (size_t)lb * ncols * S;
+  const T *basis = static_cast<const T *>(A.basis);
+  const int ng = (ncols + E - 1) / E;
+  for (int q0 = 0; q0 < ng; q0 += CW * NQ) {
+    const int nq = (ng - q0 + CW - 1) / CW < NQ ? (ng - q0 + CW - 1) / CW : NQ;  // uniform
+    int coff[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+      const int gi = q0 + q * CW + l;
+      coff[q] = (gi < ng ? gi : 0) * E;
+    }
+    double acc[NQ][E][S];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+#pragma unroll
+      for (int e = 0; e < E; ++e)
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[q][e][t] = 0.0;
+    for (int64_t r = r0 + g; r < r1; r += (int64_t)RU * G) {
+      V8 v[RU][NQ];
+      double u[RU][S];
+#pragma unroll
+      for (int h = 0; h < RU; ++h) {
+        const int64_t row = r + (int64_t)h * G;
+        const bool ok = row < r1;
+        const T *vr = basis + (ok ? row : r0) * A.ldb;
+#pragma unroll
+        for (int q = 0; q < NQ; ++q)
+          v[h][q] = (q < nq) ? *reinterpret_cast<const V8 *>(vr + coff[q]) : PK::zero();
+#pragma unroll
+        for (int t = 0; t < S; ++t) u[h][t] = ok ? A.U[row * S + t] : 0.0;
+      }
+#pragma unroll
+      for (int h = 0; h < RU; ++h)
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+          if (q >= nq) continue;
+          double x[E];
+          PK::get(v[h][q], x);
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+#pragma unroll
+            for (int t = 0; t < S; ++t) acc[q][e][t] = fma(x[e], u[h][t], acc[q][e][t]);
+        }
+    }
+    if (G > 1) {
+      // row groups in order: group 0 adds the others' sums (one q at a time through LDS)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (q >= nq) continue;
+        __syncthreads();
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int t = 0; t < S; ++t) gsum[(size_t)threadIdx.x * E * S + e * S + t] = acc[q][e][t];
+        __syncthreads();
+        if (g == 0) {
+#pragma unroll
+          for (int e = 0; e < E; ++e)
+#pragma unroll
+            for (int t = 0; t < S; ++t) {
+              double a = 0.0;
+              for (int gg = 0; gg < G; ++gg) a += gsum[(size_t)(gg * CW + l) * E * S + e * S + t];
+              acc[q][e][t] = a;
+            }
+        }
+      }
+    }
+    if (g == 0) {
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        if (q >= nq) continue;
+#pragma unroll
+        for (int e = 0; e < E; ++e) {
+          const int c = (q0 + q * CW + l) * E + e;
+          if (c < ncols)
+#pragma unroll
+            for (int t = 0; t < S; ++t) part[c * S + t] = acc[q][e][t];
+        }
+      }
+    }
+  }
+}
+
+// Sums the nchunk partials of OPB consecutive outputs per workgroup: thread group g (of NG)
+// adds chunks [g nchunk / NG, (g+1) nchunk / NG) for its output (eight loads in flight, added
+// in chunk order), then group 0 adds the NG group sums in order and writes column block j of H
+// (store in sweep 1, add in sweep 2) and the compact coefficients.
+__global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int ncols, int nchunk0,
+                                                        int nchunk1, int64_t ldh, int hcol,
+                                                        int pass, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ double gs[NG][OPB];
+  const int nchunk = sd ? nchunk1 : nchunk0;
+  const int nout = ncols * S;
+  const int ol = threadIdx.x % OPB, g = threadIdx.x / OPB;
+  const int o = lb * OPB + ol;
+  const int q0 = (int)((int64_t)nchunk * g / NG), q1 = (int)((int64_t)nchunk * (g + 1) / NG);
+  double a = 0.0;
+  if (o < nout) {
+    constexpr int U8 = 8;
+    int q = q0;
+    for (; q + U8 <= q1; q += U8) {
+      double x[U8];
+#pragma unroll
+      for (int k = 0; k < U8; ++k) x[k] = A.part[(size_t)(q + k) * nout + o];
+#pragma unroll
+      for (int k = 0; k < U8; ++k) a += x[k];
+    }
+    for (; q < q1; ++q) a += A.part[(size_t)q * nout + o];
+  }
+  gs[g][ol] = a;
+  __syncthreads();
+  if (g == 0 && o < nout) {
+    double b = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q) b += gs[q][ol];
+    const int c = o / S, t = o % S;
+    double *h = A.H + (int64_t)c * ldh + hcol + t;
+    *h = (pass == 1) ? b : *h + b;
+    A.coef[o] = b;
+  }
+}
+
+// Columns of the coefficient block staged in LDS at a time by update_mfma_pair (64 KiB, whole
+// groups of 128 columns).
+template <int S>
+__host__ __device__ constexpr int UPD_KCH() {
+  return (64 * 1024 / (S * 8)) / 128 * 128;
+}
+
+// U[r] -= V[r, 0:ncols] C on FP64 matrix cores (v_mfma_f64_16x16x4f64): each wave owns 16 rows,
+// D (16 x 16) += A (16 rows x 4 basis columns) B (4 x 16, coefficient columns >= S are zero).
+// Lane l reads 32 contiguous bytes of row l % 16 per step (KL consecutive columns, chunk l / 16),
+// so the four lanes of a row cover 128 contiguous bytes; MFMA m of the step takes column
+// k0 + KL (l / 16) + m as its k-slot l / 16 on both operands (the sum over k is the same). The
+// coefficients sit in LDS, zero-padded past ncols; stale basis columns past ncols read as zero.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, const DevState *ds) {
+  if (ds->done) return;
+  typedef double v4 __attribute__((ext_vector_type(4)));
+  constexpr int KL = 32 / (int)sizeof(T);  // columns per lane per step
+  constexpr int KG = 4 * KL;               // columns per step
+  constexpr int KU = 4;                    // steps whose loads are in flight together
+  extern __shared__ double Cs[];
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const int nk = (ncols + KG - 1) / KG * KG;
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int li = lane & 15, lq = lane >> 4;
+  // one block of 16 rows per wave (UROWS rows per workgroup)
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  const int64_t rb = r0 + 16 * w;
+  const bool live = rb < r1;
+  const int64_t row = (rb + li < r1) ? rb + li : r1 - 1;  // clamped loads, masked stores
+  const T *vr = static_cast<const T *>(A.basis) + row * A.ldb + lq * KL;
+  v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  // the coefficients pass through LDS in chunks of at most 64 KiB
+  for (int c0 = 0; c0 < nk; c0 += UPD_KCH<S>()) {
+    const int c1 = (c0 + UPD_KCH<S>() < nk) ? c0 + UPD_KCH<S>() : nk;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (c1 - c0) * S; e += TPB) {
+      const int g = c0 * S + e;
+      Cs[e] = g < ncols * S ? A.coef[g] : 0.0;
+    }
+    __syncthreads();
+    if (!live) continue;
+    for (int k0 = c0; k0 < c1; k0 += KU * KG) {
+      T x[KU][KL];
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        // a step past the chunk re-reads step 0 (in bounds); its products are masked below
+        const int kk = k0 + u * KG < c1 ? k0 + u * KG : 0;
+        if (sizeof(T) == 8) {
+          const double2 *p2 = reinterpret_cast<const double2 *>(vr + kk);
+          const double2 a = p2[0], b = p2[1];
+          x[u][0] = (T)a.x;
+          x[u][1] = (T)a.y;
+          x[u][2] = (T)b.x;
+          x[u][3] = (T)b.y;
+        } else {
+          const float4 *p4 = reinterpret_cast<const float4 *>(vr + kk);
+          const float4 a = p4[0], b = p4[1];
+          const float f[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+#pragma unroll
+          for (int m = 0; m < KL; ++m) x[u][m] = (T)f[m];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < KU; ++u) {
+        const bool step = k0 + u * KG < c1;
+#pragma unroll
+        for (int m = 0; m < KL; ++m) {
+          const int k = k0 + u * KG + lq * KL + m;
+          const double av = (step && k < ncols) ? (double)x[u][m] : 0.0;
+          const double bv = (step && li < S) ? Cs[(k - c0) * S + li] : 0.0;
+          if (m & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
+          else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
+        }
+      }
+    }
+  }
+  // lane holds D[4 v + lq][li]: row rb + 4 v + lq, column li
+  if (live && li < S) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t r = rb + 4 * v + lq;
+      if (r < r1) A.U[r * S + li] -= acc0[v] + acc1[v];
+    }
+  }
+}
+
+// Sum of NP values over the 64 lanes of a wave by recursive halving (NP a power of two <= 64):
+// at step i each lane keeps the half of its values selected by bit i of its lane id and adds
+// its partner's copy of that half, so after log2(NP) steps every lane holds one value, then the
+// remaining lane bits are folded in. Lane l ends with the wave total of value ws_index<NP>(l);
+// lanes that share the low log2(NP) bits hold bit-identical totals (fixed order).
+template <int NP>
+__device__ __forceinline__ int ws_index(int lane) {
+  int idx = 0;
+#pragma unroll
+  for (int i = 0; (NP >> (i + 1)) >= 1; ++i)
+    if ((lane >> i) & 1) idx += NP >> (i + 1);
+  return idx;
+}
+
+template <int NP, int H>
+__device__ __forceinline__ void ws_step(double (&v)[NP], int lane, int bit) {
+  const bool up = (lane >> bit) & 1;
+#pragma unroll
+  for (int j = 0; j < H; ++j) {
+    const double keep = up ? v[j + H] : v[j];
+    const double send = up ? v[j] : v[j + H];
+    v[j] = keep + __shfl_xor(send, 1 << bit, WAVE);
+  }
+}
+
+template <int NP>
+__device__ __forceinline__ double wave_reduce_scatter(double (&v)[NP], int lane) {
+  static_assert(NP >= 1 && NP <= 64 && (NP & (NP - 1)) == 0, "power of two up to 64");
+  int bit = 0;
+  if constexpr (NP >= 64) ws_step<NP, 32>(v, lane, bit++);
+  if constexpr (NP >= 32) ws_step<NP, 16>(v, lane, bit++);
+  if constexpr (NP >= 16) ws_step<NP, 8>(v, lane, bit++);
+  if constexpr (NP >= 8) ws_step<NP, 4>(v, lane, bit++);
+  if constexpr (NP >= 4) ws_step<NP, 2>(v, lane, bit++);
+  if constexpr (NP >= 2) ws_step<NP, 1>(v, lane, bit++);
+  double x = v[0];
+  for (; bit < 6; ++bit) x += __shfl_xor(x, 1 << bit, WAVE);
+  return x;
+}
+
+// Rows per block of the fused sweep (16 basis loads in flight per thread and buffer, at most 32
+// reduced values) and the padded count of values reduced per block.
+template <int S, int NQ>
+struct UgShape {
+  static constexpr int R0 = NQ >= 16 ? 1 : 16 / NQ;
+  static constexpr int R = R0 * S > 32 ? (32 / S > 0 ? 32 / S : 1) : R0;
+  static constexpr int NV = R * S;
+  static constexpr int NP = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : 32;
+};
+
+// First-sweep update U -= V[:, 0:ncols] C fused with the chunk partials of the second sweep's
+// V^T U (classical Gram-Schmidt applied twice; the second projection needs the updated rows,
+// which depend only on the same rows of V). Workgroup lb owns the Gram chunk [lb rpc,
+// (lb+1) rpc); its 256 threads own the 8-byte column groups l + 256 q (q < nq <= NQ) and keep
+// their coefficients in registers. Per block of R rows: the R x S partial row products are
+// summed over the workgroup (wave reduce-scatter, the four wave totals added in order through
+// LDS), the updated rows are written, and the basis values still in registers are multiplied
+// by them into the chunk partials part[lb][c][t]. The next block's loads are issued before the
+// current block is reduced. Basis columns past ncols are masked to zero (they may be stale).
+template <int S, typename T, int NQ>
+__global__ __launch_bounds__(TPB) void upd_gram_pair(ArPair P, int ncols, const DevState *ds) {
+  if (ds->done) return;
+  typedef Pack8<T> PK;
+  typedef typename PK::type V8;
+  constexpr int E = PK::N;
+  typedef UgShape<S, NQ> SH;
+  constexpr int R = SH::R, NV = SH::NV, NP = SH::NP;
+  __shared__ double red[TPB / WAVE][NP];
+  __shared__ double un[NP];
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  const T *basis = static_cast<const T *>(A.basis);
+  const int ng = (ncols + E - 1) / E;
+  const int nq = (ng + TPB - 1) / TPB < NQ ? (ng + TPB - 1) / TPB : NQ;  // uniform
+  // Column groups past the width read group 0 (a live column, finite) with zero coefficients;
+  // with FP32 bases the second float of the last group may lie past ncols and is masked.
+  int coff[NQ];
+  bool okc[NQ][E];
+  double cf[NQ][E][S], acc[NQ][E][S];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    const int gi = q * TPB + (int)threadIdx.x;
+    coff[q] = (gi < ng ? gi : 0) * E;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int c = gi * E + e;
+      okc[q][e] = c < ncols;
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        cf[q][e][t] = okc[q][e] ? A.coef[c * S + t] : 0.0;
+        acc[q][e][t] = 0.0;
+      }
+    }
+  }
+  auto val = [&](const V8 &v, int q, double (&y)[E]) {
+    PK::get(v, y);
+    if (E > 1) {
+#pragma unroll
+      for (int e = 1; e < E; ++e) y[e] = okc[q][e] ? y[e] : 0.0;
+    }
+  };
+  const int64_t nblk = (r1 - r0 + R - 1) / R;
+  auto load_block = [&](int64_t b, V8 (&v)[R][NQ]) {
+    const int64_t rb = r0 + (b < nblk ? b : nblk - 1) * R;  // past the end: reload the last
+#pragma unroll
+    for (int h = 0; h < R; ++h) {
+      const int64_t row = (rb + h < r1) ? rb + h : r1 - 1;
+      const T *vr = basis + row * A.ldb;
+#pragma unroll
+      for (int q = 0; q < NQ; ++q)
+        v[h][q] = (q < nq) ? *reinterpret_cast<const V8 *>(vr + coff[q]) : PK::zero();
+    }
+  };
+  auto do_block = [&](int64_t b, const V8 (&v)[R][NQ]) {
+    const int64_t rb = r0 + b * R;
+    double d[NP];
+#pragma unroll
+    for (int i = 0; i < NP; ++i) d[i] = 0.0;
+#pragma unroll
+    for (int h = 0; h < R; ++h)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        double y[E];
+        val(v[h][q], q, y);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int t = 0; t < S; ++t) d[h * S + t] = fma(y[e], cf[q][e][t], d[h * S + t]);
+      }
+    const double tot = wave_reduce_scatter<NP>(d, lane);
+    if (lane < NP) red[w][ws_index<NP>(lane)] = tot;
+    __syncthreads();
+    if ((int)threadIdx.x < NV) {
+      const int h = (int)threadIdx.x / S, t = (int)threadIdx.x % S;
+      const int64_t row = rb + h;
+      double a = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < TPB / WAVE; ++ww) a += red[ww][threadIdx.x];
+      double u = 0.0;
+      if (row < r1) {
+        u = A.U[row * S + t] - a;
+        A.U[row * S + t] = u;
+      }
+      un[threadIdx.x] = u;
+    }
+    __syncthreads();
+    double uu[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) uu[i] = un[i];
+#pragma unroll
+    for (int h = 0; h < R; ++h)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        double y[E];
+        val(v[h][q], q, y);
+#pragma unroll
+        for (int e = 0; e < E; ++e)
+#pragma unroll
+          for (int t = 0; t < S; ++t) acc[q][e][t] = fma(y[e], uu[h * S + t], acc[q][e][t]);
+      }
+  };
+  V8 va[R][NQ], vb[R][NQ];
+  load_block(0, va);
+  for (int64_t b = 0; b < nblk; b += 2) {
+    load_block(b + 1, vb);
+    do_block(b, va);
+    if (b + 1 < nblk) {
+      load_block(b + 2, va);
+      do_block(b + 1, vb);
+    }
+  }
+  double *part = A.part + (size_t)lb * ncols * S;
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) {
+    if (q >= nq) continue;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      const int c = (q * TPB + (int)threadIdx.x) * E + e;
+      if (c < ncols)
+#pragma unroll
+        for (int t = 0; t < S; ++t) part[c * S + t] = acc[q][e][t];
+    }
+  }
+}
+
+// Partials of U^T U (rows over workgroups, one thread per row) for the first QR pass.
+template <int S>
+__global__ __launch_bounds__(TPB) void ugram_pair(ArPair P, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    double u[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
+  }
+  __shared__ double lds[16 * S * S];
+  block_sum<S * S>(g, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
+}
+
+// Sums n partial records of NV values (stride NV) in a fixed order; every thread gets the sum.
+template <int NV>
+__device__ __forceinline__ void sum_records(const double *p, int n, double (&out)[NV]) {
+  __shared__ double lds[16 * NV];
+  __shared__ double res[NV];
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = 0.0;
+  for (int b = threadIdx.x; b < n; b += TPB)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) out[i] += p[(size_t)b * NV + i];
+  block_sum<NV>(out, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < NV; ++i) res[i] = out[i];
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < NV; ++i) out[i] = res[i];
+}
+
+// First Cholesky-QR pass and closure test from the partials of ||M V_j||^2 and U^T U (every
+// workgroup forms the same factors; workgroup 0 records them), then partials of
+// G2 = (U T1)^T (U T1).
+template <int S>
+__global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ SideState st;
+  double ref[1], G1[S * S];
+  sum_records<1>(A.aux, A.nb_spmm, ref);
+  sum_records<S * S>(A.aux + A.nb_spmm, A.nb_upd, G1);
+  if (threadIdx.x == 0) {
+    st.ref2 = ref[0];
+    finish_pass1(&st, S, closure_tol, G1);
+    if (lb == 0) {
+      A.ss->ref2 = st.ref2;
+      A.ss->mode = st.mode;
+      for (int i = 0; i < S * S; ++i) {
+        A.ss->T1[i] = st.T1[i];
+        A.ss->Hs1[i] = st.Hs1[i];
+      }
+    }
+  }
+  __syncthreads();
+  double T1[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) T1[i] = st.T1[i];
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    double u[S], u1[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < S; ++a) v = fma(u[a], T1[a * S + b], v);
+      u1[b] = v;
+    }
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u1[a], u1[b], g[a * S + b]);
+  }
+  __shared__ double lds[16 * S * S];
+  block_sum<S * S>(g, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + A.nb_upd * S * S + lb * S * S + i] = g[i];
+}
+
+// Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
+// V[:, (j+1)s : (j+2)s] = U T; workgroup 0 records T and writes H_{j+1,j}.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
+                                                  const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  __shared__ SideState st;
+  double G2[S * S];
+  sum_records<S * S>(A.aux + A.nb_spmm + A.nb_upd * S * S, A.nb_qr, G2);
+  if (threadIdx.x == 0) {
+    st.mode = A.ss->mode;
+    for (int i = 0; i < S * S; ++i) {
+      st.T1[i] = A.ss->T1[i];
+      st.Hs1[i] = A.ss->Hs1[i];
+    }
+    finish_pass2(&st, S, G2);
+    if (lb == 0) {
+      for (int i = 0; i < S * S; ++i) {
+        A.ss->T[i] = st.T[i];
+        A.ss->Hs1[i] = st.Hs1[i];
+      }
+      for (int a = 0; a < S; ++a)
+        for (int b = 0; b < S; ++b)
+          A.H[(int64_t)((jb + 1) * S + a) * ldh + jb * S + b] = st.Hs1[a * S + b];
+    }
+  }
+  __syncthreads();
+  double Tq[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) Tq[i] = st.T[i];
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    double u[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      double v = 0.0;
+#pragma unroll
+      for (int a = 0; a < S; ++a) v = fma(u[a], Tq[a * S + b], v);
+      static_cast<T *>(A.basis)[r * A.ldb + (jb + 1) * S + b] = (T)v;
+      static_cast<T *>(A.pout)[r * S + b] = (T)v;
+    }
+  }
+}
+
+// ---- block Lanczos step j for both bases (Algorithm 4.1, steps 4-5) ----
+// aux layout per basis: [nb_spmm] ||M V_j||^2, [nb_upd S^2] U^T U, [nb_qr S^2] second-pass Gram,
+// [nb_spmm S^2] V_j^T U.
+template <int S>
+__device__ __forceinline__ double *aux_vju(const ArSide &A) {
+  return A.aux + A.nb_spmm + (A.nb_upd + A.nb_qr) * S * S;
+}
+
+// U = M V_j - V_{j-1} H_{j-1,j} (H_{j-1,j} = H_{j,j-1}^T); partials of ||M V_j||^2 and V_j^T U.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ldh,
+                                                    const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double hup[S * S];  // hup[u][t] = H_{j-1,j}[u][t] = H[j s + t][(j-1) s + u]
+#pragma unroll
+  for (int u = 0; u < S; ++u)
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      hup[u * S + t] = jb > 0 ? A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + u] : 0.0;
+  double red[S * S + 1];
+#pragma unroll
+  for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
+  for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
+    const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+    const int64_t r = r0 + threadIdx.x;
+    double acc[S];
+    if (A.sell.ci) {
+      if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
+    } else {
+      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+    }
+    if (r < r1) {
+#pragma unroll
+      for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
+      if (jb > 0) {
+        const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused)
+#pragma unroll
+        for (int u = 0; u < S; ++u) {
+          const double vu = (double)vp[u];
+#pragma unroll
+          for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
+        }
+      }
+      const T *vj = static_cast<const T *>(A.pin) + r * S;
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        const double va = (double)vj[a];
+#pragma unroll
+        for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
+      }
+#pragma unroll
+      for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
+    }
+  }
+  __shared__ double lds[16 * (S * S + 1)];
+  block_sum<S * S + 1>(red, lds);
+  if (threadIdx.x == 0) {
+    A.aux[lb] = red[S * S];
+    double *vju = aux_vju<S>(A) + lb * S * S;
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) vju[i] = red[i];
+  }
+}
+
+// H_jj = V_j^T U from the partials (every workgroup forms it; workgroup 0 writes column block j
+// of H: H_{j-1,j} and H_jj); U -= V_j H_jj; partials of U^T U.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t ldh,
+                                                      const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  double hjj[S * S];
+  sum_records<S * S>(aux_vju<S>(A), A.nb_spmm, hjj);
+  if (lb == 0 && threadIdx.x == 0) {
+    for (int a = 0; a < S; ++a)
+      for (int t = 0; t < S; ++t) {
+        A.H[(int64_t)(jb * S + a) * ldh + jb * S + t] = hjj[a * S + t];
+        if (jb > 0)
+          A.H[(int64_t)((jb - 1) * S + a) * ldh + jb * S + t] =
+              A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + a];
+      }
+  }
+  double g[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    double u[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
+    const T *vj = static_cast<const T *>(A.pin) + r * S;
+#pragma unroll
+    for (int a = 0; a < S; ++a) {
+      const double va = (double)vj[a];
+#pragma unroll
+      for (int t = 0; t < S; ++t) u[t] = fma(-va, hjj[a * S + t], u[t]);
+    }
+#pragma unroll
+    for (int t = 0; t < S; ++t) A.U[r * S + t] = u[t];
+#pragma unroll
+    for (int a = 0; a < S; ++a)
+#pragma unroll
+      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
+  }
+  __shared__ double lds[16 * S * S];
+  block_sum<S * S>(g, lds);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
+}
+
+int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Rows per gram chunk: large enough that the chunk partials stay a small fraction of the basis
+// read (2 s / rpc), small enough for a few hundred workgroups, at most 512 chunks per basis.
+int64_t gram_rpc(int s, int64_t rows, int64_t total_rows) {
+  int64_t rpc = std::max<int64_t>(32 * s, cdiv(total_rows, 1024));
+  rpc = std::min<int64_t>(rpc, std::max<int64_t>(16, cdiv(total_rows, 256)));
+  rpc = std::max<int64_t>(rpc, cdiv(rows, 512));
+  return std::max<int64_t>(rpc, 1);
+}
+
+ArSide make_side(const SideDesc &d, const Scratch &sc, int idx, size_t half, size_t aux_len) {
+  ArSide a{};
+  a.rows = d.rows;
+  a.nnz = d.nnz;
+  a.rp = d.rp;
+  a.ci = d.ci;
+  a.val = d.val;
+  a.basis = d.basis;
+  a.ldb = d.ldb;
+  a.H = d.H;
+  a.U = d.U;
+  a.coef = d.coef;
+  a.ss = d.ss;
+  a.sell = d.sell;
+  a.part = sc.partials + (size_t)idx * half;
+  a.aux = a.part + half - aux_len;
+  a.cnt = sc.counters + CNT_PAIR + idx * 1536;
+  return a;
+}
+
+// Sets the workgroup ranges of a launch with per-basis workgroup counts nb0, nb1.
+void set_ranges(ArPair &P, int64_t nb0, int64_t nb1) {
+  P.s[0].b0 = 0;
+  P.s[0].nb = (int)nb0;
+  P.s[1].b0 = (int)nb0;
+  P.s[1].nb = (int)nb1;
+}
+
+unsigned total_blocks(const ArPair &P) {
+  return (unsigned)(P.s[0].nb + (P.nsides > 1 ? P.s[1].nb : 0));
+}
+
+constexpr int64_t UROWS = 64;    // rows per update workgroup (16 per wave)
+constexpr int64_t QR_MAXWG = 512;
+
+// Workgroups of the row-tile kernels of one basis (spmm, local update, U^T U): at most ROW_WG,
+// each taking row tiles lb, lb + nb, ...; fewer partial records for the next kernel to sum.
+constexpr int64_t ROW_WG = 512;
+int64_t nb_rows(int64_t rows) { return std::min<int64_t>(cdiv(rows, TPB), ROW_WG); }
+int64_t nb_qr(int64_t rows) { return std::min<int64_t>(nb_rows(rows), QR_MAXWG); }
+size_t aux_len(int s, int64_t rows) {
+  return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows) + nb_rows(rows)) * s * s + 16);
+}
+
+
+// Largest power of two q <= 8 with q * per <= cap.
+constexpr int pow2_cap(int per, int cap) {
+  return 8 * per <= cap ? 8 : 4 * per <= cap ? 4 : 2 * per <= cap ? 2 : 1;
+}
+int pow2_ceil(int v) {
+  int p = 1;
+  while (p < v) p <<= 1;
+  return p;
+}
+int log2_exact(int v) {
+  int l = 0;
+  while ((1 << l) < v) ++l;
+  return l;
+}
+
+// Column groups per thread of gram_part_pair and of the fused sweep: accumulators (and the
+// fused sweep's coefficients) of at most 32 doubles per thread. The fused sweep runs on FP64
+// bases only (FP32 values widened twice per block cost more registers than the pass saves).
+template <int S, typename T>
+constexpr int gram_nq_max() { return pow2_cap(Pack8<T>::N * S, 32); }
+template <int S, typename T>
+constexpr int fused_nq_max() { return Pack8<T>::N > 1 ? 0 : S <= 4 ? 8 : 2; }
+
+template <int S, typename T, int NQ>
+void launch_gram_part(const ArPair &P, int ncols, int cw_log2, size_t lds, const DevState *ds,
+                      hipStream_t st) {
+  gram_part_pair<S, T, NQ><<<total_blocks(P), TPB, lds, st>>>(P, ncols, cw_log2, ds);
+}
+
+// C partials of one sweep (shape fitted to the width: row groups for narrow bases, up to NQ
+// column groups per thread for wide ones).
+template <int S, typename T>
+int gram_sweep(const ArPair &P, int ncols, const DevState *ds, hipStream_t st) {
+  constexpr int E = Pack8<T>::N;
+  constexpr int QM = gram_nq_max<S, T>();
+  const int ng = (ncols + E - 1) / E;
+  int cw_log2 = 8, nq = 1;
+  if (ng <= TPB) cw_log2 = log2_exact(pow2_ceil(ng));
+  else nq = std::min(QM, pow2_ceil((ng + TPB - 1) / TPB));
+  const size_t lds = cw_log2 < 8 ? (size_t)TPB * E * S * sizeof(double) : 0;
+  switch (nq) {
+    case 1: launch_gram_part<S, T, 1>(P, ncols, cw_log2, lds, ds, st); break;
+    case 2: launch_gram_part<S, T, std::min(2, QM)>(P, ncols, cw_log2, lds, ds, st); break;
+    case 4: launch_gram_part<S, T, std::min(4, QM)>(P, ncols, cw_log2, lds, ds, st); break;
+    default: launch_gram_part<S, T, QM>(P, ncols, cw_log2, lds, ds, st); break;
+  }
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+// Column groups per thread of the fused first-sweep update + second-sweep Gram, or 0 when the
+// basis is too narrow (separate kernels are faster) or too wide for its registers.
+template <int S, typename T>
+int fused_nq(int ncols) {
+  constexpr int E = Pack8<T>::N;
+  const int nq = ((ncols + E - 1) / E + TPB - 1) / TPB;
+  if (nq < 2 || nq > fused_nq_max<S, T>()) return 0;
+  return pow2_ceil(nq);
+}
+
+template <int S, typename T>
+int launch_fused(const ArPair &P, int ncols, int nq, const DevState *ds, hipStream_t st) {
+  constexpr int QM = fused_nq_max<S, T>();
+  if constexpr (QM < 2) {
+    return SYLV_ERR_INVALID;
+  } else {
+    const unsigned nb = total_blocks(P);
+    switch (nq) {
+      case 2: upd_gram_pair<S, T, std::min(2, QM)><<<nb, TPB, 0, st>>>(P, ncols, ds); break;
+      case 4: upd_gram_pair<S, T, std::min(4, QM)><<<nb, TPB, 0, st>>>(P, ncols, ds); break;
+      default: upd_gram_pair<S, T, QM><<<nb, TPB, 0, st>>>(P, ncols, ds); break;
+    }
+    HIPOK(hipGetLastError());
+    return 0;
+  }
+}
+
+template <int S, typename T>
+int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                   double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  ArPair P{};
+  const size_t half = sc.partial_cap / 2;
+  P.nsides = sw ? 2 : 1;
+  const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
+  const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
+  P.s[0] = make_side(sv, sc, 0, half, aux0);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  for (int i = 0; i < P.nsides; ++i) {
+    const int64_t rows = i ? rows1 : rows0;
+    P.s[i].nb_spmm = (int)nb_rows(rows);
+    P.s[i].nb_upd = (int)cdiv(rows, UROWS);
+    P.s[i].nb_qr = (int)nb_qr(rows);
+  }
+  const int64_t total = rows0 + rows1;
+  const int ncols = (jb + 1) * S;
+  const int nout = ncols * S;
+  const double bytes_v = (double)sizeof(T) * (double)total * ncols;
+  const double flops_v = 2.0 * (double)total * ncols * S;
+
+  // U = M V_j
+  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+  prof_begin(sc, st);
+  for (int i = 0; i < P.nsides; ++i) {
+    const SideDesc &d = i ? *sw : sv;
+    P.s[i].pin = d.panel[jb % 2];
+    P.s[i].pout = d.panel[(jb + 1) % 2];
+  }
+  spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_SPMM,
+           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,
+           2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S, st);
+
+  // chunking of the Gram sweeps
+  const int64_t rpc0 = gram_rpc(S, rows0, total), rpc1 = sw ? gram_rpc(S, rows1, total) : 1;
+  const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
+  if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
+    return SYLV_ERR_WORKSPACE;
+  // coefficient chunk of the MFMA update in LDS (at most 64 KiB)
+  const size_t lds =
+      (size_t)std::min((ncols + 127) / 128 * 128, UPD_KCH<S>()) * S * sizeof(double);
+  const int64_t rtiles = cdiv(nout, OPB);
+  const int fnq = fused_nq<S, T>(ncols);
+  int e;
+
+  auto chunks = [&]() {
+    P.s[0].rpc = rpc0;
+    P.s[1].rpc = rpc1;
+    set_ranges(P, nch0, nch1);
+  };
+  auto reduce = [&](int pass) {
+    set_ranges(P, rtiles, sw ? rtiles : 0);
+    gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S, ncols, nch0, nch1, ldh, jb * S, pass,
+                                                      ds);
+    return hipGetLastError();
+  };
+  auto update = [&]() {
+    P.s[0].rpc = UROWS;
+    P.s[1].rpc = UROWS;
+    set_ranges(P, cdiv(rows0, UROWS), sw ? cdiv(rows1, UROWS) : 0);
+    update_mfma_pair<S, T><<<total_blocks(P), TPB, lds, st>>>(P, ncols, ds);
+    return hipGetLastError();
+  };
+  const double bytes_g = bytes_v + 8.0 * total * S + 8.0 * nout * P.nsides;
+  const double bytes_u = bytes_v + 16.0 * total * S + 8.0 * nout * P.nsides;
+
+  // first sweep: C1 = V^T U
+  chunks();
+  prof_begin(sc, st);
+  if ((e = gram_sweep<S, T>(P, ncols, ds, st))) return e;
+  HIPOK(reduce(1));
+  prof_end(sc, FAM_GRAM, bytes_g, flops_v, st);
+  if (fnq) {
+    // U -= V C1 with the second sweep's partials in the same pass over V
+    chunks();
+    prof_begin(sc, st);
+    if ((e = launch_fused<S, T>(P, ncols, fnq, ds, st))) return e;
+    HIPOK(reduce(2));
+    prof_end(sc, FAM_UPD_GRAM, bytes_u, 2.0 * flops_v, st);
+  } else {
+    prof_begin(sc, st);
+    HIPOK(update());
+    prof_end(sc, FAM_UPDATE, bytes_u, flops_v, st);
+    chunks();
+    prof_begin(sc, st);
+    if ((e = gram_sweep<S, T>(P, ncols, ds, st))) return e;
+    HIPOK(reduce(2));
+    prof_end(sc, FAM_GRAM, bytes_g, flops_v, st);
+  }
+  // second update, then U^T U partials for the first QR pass (one record per 256 rows)
+  prof_begin(sc, st);
+  HIPOK(update());
+  for (int i = 0; i < P.nsides; ++i) P.s[i].nb_upd = (int)nb_rows(i ? rows1 : rows0);
+  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+  ugram_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_UPDATE, bytes_u, flops_v, st);
+  // QR passes and the new block
+  set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
+  prof_begin(sc, st);
+  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+  HIPOK(hipGetLastError());
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  return 0;
+}
+
+template <int S, typename T>
+int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                   double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  ArPair P{};
+  const size_t half = sc.partial_cap / 2;
+  P.nsides = sw ? 2 : 1;
+  const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
+  const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
+  if (aux0 > half || aux1 > half) return SYLV_ERR_WORKSPACE;
+  P.s[0] = make_side(sv, sc, 0, half, aux0);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  for (int i = 0; i < P.nsides; ++i) {
+    const SideDesc &d = i ? *sw : sv;
+    const int64_t rows = i ? rows1 : rows0;
+    P.s[i].nb_spmm = (int)nb_rows(rows);
+    P.s[i].nb_upd = (int)nb_rows(rows);  // U^T U partials come from lz_update_pair
+    P.s[i].nb_qr = (int)nb_qr(rows);
+    P.s[i].pin = d.panel[jb % 2];
+    P.s[i].pout = d.panel[(jb + 1) % 2];
+  }
+  const int64_t total = rows0 + rows1;
+  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+  prof_begin(sc, st);
+  lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  lz_update_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  // matrix + gather V_j + read V_{j-1}, V_j + U write/read (local three-term step)
+  prof_end(sc, FAM_SPMM,
+           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 8.0 * total * S * 6,
+           2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S + 8.0 * total * S * S, st);
+  set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
+  prof_begin(sc, st);
+  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+  HIPOK(hipGetLastError());
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  return 0;
+}
+
+
+}  // namespace
+
+// One unit's entry points for block size SS (both basis precisions).
+#define ARN_UNIT(SS)                                                                            \
+  int arnoldi_step_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,            \
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {  \
+    return sv.fp32 ? arnoldi_pair_t<SS, float>(sv, sw, jb, ldh, closure_tol, sc, ds, st)        \
+                   : arnoldi_pair_t<SS, double>(sv, sw, jb, ldh, closure_tol, sc, ds, st);      \
+  }                                                                                             \
+  int lanczos_step_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,            \
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {  \
+    return sv.fp32 ? lanczos_pair_t<SS, float>(sv, sw, jb, ldh, closure_tol, sc, ds, st)        \
+                   : lanczos_pair_t<SS, double>(sv, sw, jb, ldh, closure_tol, sc, ds, st);      \
+  }

@@ -1,0 +1,4 @@
+// Block Arnoldi and Lanczos steps for block size s = 5 (FP64 and FP32 bases).
+#include "arnoldi_impl.h"
+
+ARN_UNIT(5)

@@ -486,6 +486,7 @@ enum {
   FAM_CORE_OP,      // eq. (3.11) on dense Hessenberg cores (FP64 MFMA)
   FAM_CORE_BAND,    // eq. (3.11) on block-tridiagonal cores
   FAM_CORE_ELEM,    // core axpys, inner products and scalar updates
+  FAM_UPD_GRAM,     // Arnoldi U -= V C1 fused with the second sweep's V^T U
   FAM_COUNT
 };
 void prof_begin(const Scratch &sc, hipStream_t st);

@@ -196,16 +196,19 @@ def test_c2_bicgstab_parity(sylv):
     assert g["res"].status == sylv.SYLV_OK
     it = gold["iters"]
     h = g["hist"]
-    # BiCGSTAB's residual wanders between 1e-6 and 1e-8 for its last ~60 iterations and
-    # plateaus just above 1e-8 before its last drop (the oracle's history sits at 1.3e-8 for
-    # eight iterations); rounding differences (summation order of the core products) move the
-    # end of that phase by tens of iterations (late histories of two implementations part ways,
-    # Section 5.1, Example 2). The count to 1e-6, reached before that phase, is held to 3%; the
-    # final count to 25%.
+    # Section 5.1, Example 2: the histories of two BiCGSTAB implementations coincide early and
+    # part later as their rounding errors propagate differently, with comparable behaviour
+    # overall. Here the relative gap between this run's and the oracle's residual history (same
+    # inputs, FP64 on both sides, different summation orders) grows about tenfold every two
+    # iterations from 1e-13 at iteration 16 and is of order one by iteration 40 (residual
+    # ~3e-3), long before 1e-6; two GPU builds that differ only in the summation order of the
+    # Gram-Schmidt sweeps reach 1e-6 at iterations 231 and 257 (oracle: 266) and stop at 322 and
+    # 316 (oracle: 321). So the first iterations are compared tightly and the rest as overall
+    # behaviour: the counts to 1e-6 and to the tolerance within 20% and 25%.
     def first_below(rr, level):
         return int(np.argmax(np.asarray(rr) <= level)) + 1
     k6, k6o = first_below(h["relres"], 1e-6), first_below(gold["relres"], 1e-6)
-    assert abs(k6 - k6o) <= max(2, round(0.03 * k6o)), (k6, k6o)
+    assert abs(k6 - k6o) <= round(0.20 * k6o), (k6, k6o)
     assert abs(g["res"].iters - it) <= round(0.25 * it), (g["res"].iters, it)
     for key in ("alpha", "omega", "relres"):
         a, b = np.asarray(h[key][:12]), np.asarray(gold[key][:12])
@@ -222,3 +225,22 @@ def test_c2_bicgstab_parity(sylv):
     Sg = g["V"][rows] @ (g["X"] @ (g["W"].T @ Om))
     So = np.asarray(gold["sketch"])
     assert rel(Sg, So) < 1e-4
+
+
+@pytest.mark.parametrize("s,iters", [(2, 180), (4, 130)])
+def test_wide_arnoldi_bases_stay_orthonormal(sylv, s, iters):
+    """Block Arnoldi with classical Gram-Schmidt applied twice keeps V^T V = I to rounding level
+    (Algorithm 4.2's bases) through every sweep shape: narrow bases (row groups), wide ones (up
+    to eight column groups per thread) and the fused first-sweep update with the second sweep's
+    Gram (bases wider than 256 columns); checked up to 720 (s = 2) and 1040 (s = 4) columns.
+    The solve itself must also meet its FP64 true residual."""
+    A, B = stencils.cd2d(64, 64, 10.0), stencils.cd1d(2048, 10.0)
+    p = stencils.make_problem("wide", A, B, s, 21, method="bicgstab", tol=1e-14,
+                              max_iter=iters)
+    g = gpu_solve(sylv, p, "bicgstab", p.tol, p.max_iter)
+    assert g["res"].iters == iters and g["res"].rank_v == 2 * iters * s
+    for F in (g["V"], g["W"]):
+        assert np.linalg.norm(F.T @ F - np.eye(F.shape[1]), 2) < 1e-12
+    _, rr = g["slv"].residual_norm()
+    Xf = g["V"] @ g["X"] @ g["W"].T
+    assert abs(rr - dense_rel_residual(p, Xf)) <= 1e-6 * rr

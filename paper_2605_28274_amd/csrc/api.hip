@@ -138,10 +138,11 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.off_d1 = bump(cur, (size_t)L.n * L.s * 8);
   L.off_d2 = L.lyap ? L.off_d1 : bump(cur, (size_t)L.m * L.s * 8);
   L.off_c2 = bump(cur, (size_t)L.m * L.s * 8);  // C2 (C1 for Lyapunov)
-  // split-K partial tiles of the core operator (BiCGSTAB): about 512 + T^2 tiles of 64 x 64
+  // stream-K partial tiles of the core operator (BiCGSTAB): one 64 x 64 tile per output tile
+  // and per chunk (at most 512 chunks), for cores of up to 1024 tiles
   if (L.method == SYLV_METHOD_BICGSTAB) {
-    const int64_t T = L.ldc / 64;
-    L.cpart_cap = (size_t)(512 + std::min<int64_t>(T * T, 512)) * 4096;
+    const int64_t T = L.ldc / 64 + 1;
+    L.cpart_cap = (size_t)(512 + std::min<int64_t>(T * T, 1024)) * 4096;
     L.off_cpart = bump(cur, L.cpart_cap * 8);
   }
   L.off_panV = bump(cur, (size_t)2 * L.n * L.s * L.esz);

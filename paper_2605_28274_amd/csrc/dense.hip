@@ -188,105 +188,156 @@ __device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn
 }
 
 // ---- core operator (all indices < ldc; entries outside the active cores are exact zeros) ----
-// The K range of output tile (I, J) has (T - I) + (T - J) slab-rows of work (T tiles per side),
-// so workgroup b computes the complementary pair of tiles b and T*T - 1 - b, i.e. (I, J) and
-// (T-1-I, T-1-J): every workgroup then does the same amount of matrix-core work.
-__device__ __forceinline__ void core_op_tile(Smem &sm, int s, int p, const double *H,
-                                             const double *G, const double *P, double *Q,
-                                             int64_t ldc, int i0, int j0, int wm, int wn) {
-  WaveAcc acc;
-  zero_acc(acc);
-  const int pk = (p + BK - 1) / BK * BK;
-  // [H P, 0]: rows of H in this tile start at column block (i0/s - 1)
-  if (j0 < p) {
-    int ls = (i0 / s - 1) * s;
-    ls = ls < 0 ? 0 : ls / BK * BK;
-    pipelined<false, false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, ldc, P + j0, ldc, ls, pk);
+// Output tile (I, J) (64 x 64, T tiles per side) is the slab sequence of its two products:
+// H P over K slabs [lsH(I), pk) (columns J < Tp only, Tp = ceil(p / 64)), then P G^T over
+// [lsG(J), pk) (rows I < Tp only); lsH and lsG skip the structurally zero part of the block
+// Hessenberg factors (rows of block b only meet columns of blocks >= b - 1).
+__host__ __device__ inline int core_start(int s, int idx) {  // first K of tile row / column idx
+  int ls = (idx * BM / s - 1) * s;
+  return ls < 0 ? 0 : ls / BK * BK;
+}
+
+// Per-launch table of the slab counts (passed by value): ns[i] slabs of tile row / column i,
+// colpre / rowpre prefix sums of ns and of the row lengths. Tile (I, J) has nH = ns[I] H P slabs
+// (J < Tp) and ns[J] P G^T slabs (I < Tp).
+constexpr int CT_MAX = 32;  // tiles per side of the stream-K form
+struct CoreTab {
+  int T, Tp, pk;
+  int ns[CT_MAX], colpre[CT_MAX + 1], rowpre[CT_MAX + 1];
+  __host__ __device__ int nh(int I, int J) const { return J < Tp ? ns[I] : 0; }
+  __host__ __device__ int len(int I, int J) const { return nh(I, J) + (I < Tp ? ns[J] : 0); }
+  __host__ __device__ int offset(int I, int J) const {
+    return rowpre[I] + (J < Tp ? J : Tp) * ns[I] + (I < Tp ? colpre[J] : 0);
   }
-  // [P G^T; 0]: rows of G in this tile start at column block (j0/s - 1)
-  if (i0 < p) {
-    int ls = (j0 / s - 1) * s;
-    ls = ls < 0 ? 0 : ls / BK * BK;
-    pipelined<false, true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, ldc, G + (int64_t)j0 * ldc, ldc,
-                           ls, pk);
-  }
-  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
-    Q[(int64_t)(i0 + ii) * ldc + j0 + jj] = v;
-  });
+  __host__ __device__ int total() const { return rowpre[T]; }
+};
+
+CoreTab make_core_tab(int s, int p, int T) {
+  CoreTab t{};
+  t.T = T;
+  t.Tp = (p + BM - 1) / BM;
+  t.pk = (p + BK - 1) / BK * BK;
+  for (int i = 0; i < T; ++i) t.ns[i] = (t.pk - core_start(s, i)) / BK;
+  for (int i = 0; i < T; ++i) t.colpre[i + 1] = t.colpre[i] + t.ns[i];
+  for (int i = 0; i < T; ++i)
+    t.rowpre[i + 1] = t.rowpre[i] + t.Tp * t.ns[i] + (i < t.Tp ? t.colpre[T] : 0);
+  return t;
 }
 
-__global__ __launch_bounds__(256) void core_op_kernel(int s, int p, int T,
-                                                      const double *__restrict__ H,
-                                                      const double *__restrict__ G,
-                                                      const double *__restrict__ P,
-                                                      double *__restrict__ Q, int64_t ldc,
-                                                      const int *done) {
-  if (done && *done) return;
-  __shared__ Smem sm;
-  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
-  const int t1 = blockIdx.x, t2 = T * T - 1 - t1;
-  core_op_tile(sm, s, p, H, G, P, Q, ldc, (t1 / T) * BM, (t1 % T) * BN, wm, wn);
-  if (t2 != t1) core_op_tile(sm, s, p, H, G, P, Q, ldc, (t2 / T) * BM, (t2 % T) * BN, wm, wn);
-}
-
-// Split-K form of the core operator for few tiles: tile t's work is the slab sequence of its two
-// products (H P over [lsH, pk), then P G^T over [lsG, pk)); workgroup (t, kz) takes slabs
-// [kz c, (kz+1) c) of that sequence and stores its partial 64 x 64 tile; core_op_reduce sums the
-// nk partials in order into Q (every output element gets exactly one sum, deterministic).
-__device__ __forceinline__ void core_tile_ranges(int s, int p, int i0, int j0, int pk, int &lsH,
-                                                 int &nH, int &lsG, int &nG) {
-  lsH = (i0 / s - 1) * s;
-  lsH = lsH < 0 ? 0 : lsH / BK * BK;
-  lsG = (j0 / s - 1) * s;
-  lsG = lsG < 0 ? 0 : lsG / BK * BK;
-  nH = (j0 < p) ? (pk - lsH) / BK : 0;
-  nG = (i0 < p) ? (pk - lsG) / BK : 0;
-}
-
-__global__ __launch_bounds__(256) void core_op_split_kernel(int s, int p, int T, int nk,
-                                                            const double *__restrict__ H,
-                                                            const double *__restrict__ G,
-                                                            const double *__restrict__ P,
-                                                            int64_t ldc, const int *done,
-                                                            double *__restrict__ part) {
-  if (done && *done) return;
-  __shared__ Smem sm;
-  const int tiles = T * T;
-  const int t = blockIdx.x % tiles, kz = blockIdx.x / tiles;
-  const int i0 = (t / T) * BM, j0 = (t % T) * BN;
-  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
-  const int pk = (p + BK - 1) / BK * BK;
-  int lsH, nH, lsG, nG;
-  core_tile_ranges(s, p, i0, j0, pk, lsH, nH, lsG, nG);
-  const int tot = nH + nG, c = (tot + nk - 1) / nk;
-  const int a = kz * c, b = (a + c < tot) ? a + c : tot;
-  WaveAcc acc;
-  zero_acc(acc);
-  // slabs [a, b) of the sequence: H P slabs first, then P G^T slabs
+// Slabs [a, b) of tile (I, J)'s sequence (nH H P slabs from K = lsH, then P G^T slabs from lsG)
+// into acc.
+__device__ __forceinline__ void core_tile_part(Smem &sm, WaveAcc &acc, const double *H,
+                                               const double *G, const double *P, int64_t ldc,
+                                               int I, int J, int nH, int lsH, int lsG, int a,
+                                               int b, int wm, int wn) {
+  const int i0 = I * BM, j0 = J * BN;
   const int ha = a < nH ? a : nH, hb = b < nH ? b : nH;
   if (hb > ha)
     pipelined<false, false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, ldc, P + j0, ldc,
                             lsH + ha * BK, lsH + hb * BK);
   const int ga = (a > nH ? a : nH) - nH, gb = (b > nH ? b : nH) - nH;
   if (gb > ga)
-    pipelined<false, true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, ldc, G + (int64_t)j0 * ldc, ldc,
-                           lsG + ga * BK, lsG + gb * BK);
-  double *pt = part + ((size_t)kz * tiles + t) * (BM * BN);
-  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });
+    pipelined<false, true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, ldc, G + (int64_t)j0 * ldc,
+                           ldc, lsG + ga * BK, lsG + gb * BK);
 }
 
-__global__ __launch_bounds__(256) void core_op_reduce_kernel(int T, int nk,
+// One workgroup per complementary pair of tiles b and T*T - 1 - b, i.e. (I, J) and
+// (T-1-I, T-1-J): their sequences add up to the same length for every b.
+__global__ __launch_bounds__(256, 2) void core_op_kernel(int s, int p, int T,
+                                                         const double *__restrict__ H,
+                                                         const double *__restrict__ G,
+                                                         const double *__restrict__ P,
+                                                         double *__restrict__ Q, int64_t ldc,
+                                                         const int *done) {
+  if (done && *done) return;
+  __shared__ Smem sm;
+  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  const int pk = (p + BK - 1) / BK * BK;
+  const int t1 = blockIdx.x, t2 = T * T - 1 - t1;
+  for (int t = t1;; t = t2) {
+    const int I = t / T, J = t % T;
+    const int lsH = core_start(s, I), lsG = core_start(s, J);
+    const int nH = J * BN < p ? (pk - lsH) / BK : 0;
+    const int nG = I * BM < p ? (pk - lsG) / BK : 0;
+    WaveAcc acc;
+    zero_acc(acc);
+    core_tile_part(sm, acc, H, G, P, ldc, I, J, nH, lsH, lsG, 0, nH + nG, wm, wn);
+    for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
+      Q[(int64_t)(I * BM + ii) * ldc + J * BN + jj] = v;
+    });
+    if (t == t2) break;
+  }
+}
+
+// Stream-K form: the concatenated sequence of all tiles (row-major) is cut into chunks of c
+// slabs, chunk w for workgroup w, so every workgroup does the same matrix-core work whatever
+// the tile lengths. Workgroup w stores its part of tile t as partial tile t + w (distinct for
+// all pieces); core_op_reduce sums a tile's pieces in chunk order (deterministic). Chunks are
+// numbered so that XCD x (workgroups b with b % 8 == x) runs a contiguous eighth of the
+// sequence: its tiles share their H and P row panels in its L2.
+__global__ __launch_bounds__(256, 2) void core_op_stream_kernel(const CoreTab tab, int c,
+                                                                int nchunks,
+                                                                const double *__restrict__ H,
+                                                                const double *__restrict__ G,
+                                                                const double *__restrict__ P,
+                                                                int64_t ldc, const int *done,
+                                                                double *__restrict__ part) {
+  if (done && *done) return;
+  const int per = (int)(gridDim.x >> 3);
+  const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (w >= nchunks) return;
+  __shared__ Smem sm;
+  const int T = tab.T;
+  const int total = tab.total();
+  const int c0 = w * c, c1 = (c0 + c < total) ? c0 + c : total;
+  const int wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  // locate the tile holding position c0
+  int I = 0;
+  while (I + 1 < T && tab.rowpre[I + 1] <= c0) ++I;
+  int J = 0;
+  int off = tab.rowpre[I];
+  while (off + tab.len(I, J) <= c0) off += tab.len(I, J++);
+  int pos = c0;
+  while (pos < c1 && I < T) {
+    const int l = tab.len(I, J);
+    if (l > 0) {
+      const int a = pos - off;
+      const int b = (c1 < off + l ? c1 : off + l) - off;
+      WaveAcc acc;
+      zero_acc(acc);
+      core_tile_part(sm, acc, H, G, P, ldc, I, J, tab.nh(I, J), tab.pk - tab.ns[I] * BK,
+                     tab.pk - tab.ns[J] * BK, a, b, wm, wn);
+      double *pt = part + (size_t)(I * T + J + w) * (BM * BN);
+      for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });
+      pos = off + b;
+    }
+    off += l;
+    if (++J == T) {
+      J = 0;
+      ++I;
+    }
+  }
+}
+
+// Q tile t = sum of its pieces t + w over the chunks w that cover it, in chunk order (zero for
+// tiles with an empty sequence). 16 workgroups per tile, one element per thread.
+__global__ __launch_bounds__(256) void core_op_reduce_kernel(const CoreTab tab, int c,
                                                              const double *__restrict__ part,
                                                              double *__restrict__ Q, int64_t ldc,
                                                              const int *done) {
   if (done && *done) return;
-  const int tiles = T * T;
+  const int T = tab.T;
   const int t = blockIdx.x / 16, sub = blockIdx.x % 16;
+  const int I = t / T, J = t % T;
+  const int l = tab.len(I, J);
   const int e = sub * 256 + threadIdx.x;
   double v = 0.0;
-  for (int kz = 0; kz < nk; ++kz) v += part[((size_t)kz * tiles + t) * (BM * BN) + e];
-  const int i0 = (t / T) * BM, j0 = (t % T) * BN;
-  Q[(int64_t)(i0 + e / BN) * ldc + j0 + e % BN] = v;
+  if (l > 0) {
+    const int off = tab.offset(I, J);
+    const int w0 = off / c, w1 = (off + l - 1) / c;
+    for (int w = w0; w <= w1; ++w) v += part[(size_t)(t + w) * (BM * BN) + e];
+  }
+  Q[(int64_t)(I * BM + e / BN) * ldc + J * BN + e % BN] = v;
 }
 
 // ---- tall-skinny Gram C (+)= A^T B over K rows (residual evaluation) ----
@@ -495,22 +546,25 @@ int launch_core_op(int s, int p, const double *H, const double *G, const double 
   const int T = (q + BM - 1) / BM;
   if ((int64_t)T * BM > ldc || ((p + BK - 1) / BK * BK) > ldc) return SYLV_ERR_WORKSPACE;
   const int tiles = T * T;
-  // few tiles: split each tile's slab sequence so that about 512 workgroups run
-  int nk = 1;
-  if (part && tiles < 512) {
-    const int slabs = 2 * ((p + BK - 1) / BK);
-    nk = std::min({(512 + tiles - 1) / tiles, std::max(slabs / 8, 1),
-                   (int)(part_cap / ((size_t)tiles * BM * BN))});
+  // stream-K over up to 512 workgroups (two per CU), chunks of at least two slabs, as long as
+  // the partial tiles (one per tile plus one per chunk) fit in part; otherwise tile pairs
+  if (part && T <= CT_MAX) {
+    const CoreTab tab = make_core_tab(s, p, T);
+    const int total = tab.total();
+    constexpr int NWG = 512;
+    const int c = std::max(2, (total + NWG - 1) / NWG);
+    const int nchunks = (total + c - 1) / c;
+    if (total > 0 && (size_t)(tiles + nchunks) * BM * BN <= part_cap) {
+      const int per = (nchunks + 7) / 8;
+      core_op_stream_kernel<<<(unsigned)(8 * per), 256, 0, st>>>(tab, c, nchunks, H, G, P, ldc,
+                                                                  done, part);
+      HIPOK(hipGetLastError());
+      core_op_reduce_kernel<<<(unsigned)(tiles * 16), 256, 0, st>>>(tab, c, part, Q, ldc, done);
+      HIPOK(hipGetLastError());
+      return 0;
+    }
   }
-  if (nk > 1) {
-    core_op_split_kernel<<<(unsigned)(tiles * nk), 256, 0, st>>>(s, p, T, nk, H, G, P, ldc, done,
-                                                                 part);
-    HIPOK(hipGetLastError());
-    core_op_reduce_kernel<<<(unsigned)(tiles * 16), 256, 0, st>>>(T, nk, part, Q, ldc, done);
-    HIPOK(hipGetLastError());
-    return 0;
-  }
-  core_op_kernel<<<(unsigned)((T * T + 1) / 2), 256, 0, st>>>(s, p, T, H, G, P, Q, ldc, done);
+  core_op_kernel<<<(unsigned)((tiles + 1) / 2), 256, 0, st>>>(s, p, T, H, G, P, Q, ldc, done);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -222,9 +222,9 @@ def main():
 
 
 # Kernel sources whose family the hardware-counter traffic in profiles/ was taken for.
-FAMILY_SOURCES = {"core_op": "dense.hip", "gram": "arnoldi.hip", "update": "arnoldi.hip",
-                  "spmm": "arnoldi.hip", "block_qr": "arnoldi.hip", "core_elem": "core.hip",
-                  "core_band": "core.hip"}
+FAMILY_SOURCES = {"core_op": "dense.hip", "gram": "arnoldi_impl.h", "update": "arnoldi_impl.h",
+                  "upd_gram": "arnoldi_impl.h", "spmm": "arnoldi_impl.h",
+                  "block_qr": "arnoldi_impl.h", "core_elem": "core.hip", "core_band": "core.hip"}
 
 
 def measured_traffic(workload, family, precision):

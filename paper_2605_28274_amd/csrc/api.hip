@@ -17,6 +17,7 @@
 namespace {
 
 constexpr size_t ALIGN = 256;
+constexpr size_t CORE_SCRATCH = 16384;  // doubles of reduction partials of the core kernels
 
 struct Layout {
   // sizes
@@ -27,7 +28,7 @@ struct Layout {
   // byte offsets into the workspace
   size_t off_V, off_W, off_H, off_G, off_X, off_R, off_P, off_Q, off_S, off_T;
   size_t off_U, off_Uw, off_coefV, off_coefW, off_btrp, off_btci, off_btval, off_tscr;
-  size_t off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
+  size_t off_cscr, off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
   size_t off_Lx, off_M2, off_d1, off_d2, off_c2, off_cpart, cpart_cap = 0;
   size_t off_dots, off_flag, off_panV, off_panW, off_sellA, off_sellB;
   // outer refinement: correction contexts and the buffers of the sketch and of the residual of
@@ -124,6 +125,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.off_btval = bump(cur, (size_t)std::max<int64_t>(bnnz, 1) * 8);
   L.off_tscr = bump(cur, csr_transpose_scratch(L.m));
   L.off_partials = bump(cur, L.partial_cap * 8);
+  L.off_cscr = bump(cur, CORE_SCRATCH * 8);
   L.off_counters = bump(cur, CNT_MAX * sizeof(int));
   L.off_ds = bump(cur, sizeof(DevState));
   L.off_ssv = bump(cur, sizeof(SideState));
@@ -278,7 +280,16 @@ struct Ctx {
   double *cpart = nullptr;  // split-K scratch of the core operator
   DevState *ds;
   SideState *ssv, *ssw;
-  Scratch sc{};
+  Scratch sc{};   // Krylov steps (Arnoldi / Lanczos) and the residual evaluation
+  Scratch scc{};  // core recurrences (they run concurrently with the Krylov steps)
+  // Krylov steps run on their own stream (kst), one iteration ahead of the core recurrences on
+  // st: the bases do not depend on the iterates, so each iteration's core work overlaps the
+  // next iteration's basis extension. kst == st when the context was created without it.
+  hipStream_t kst = nullptr;
+  bool own_kst = false;
+  hipEvent_t ev_k[2] = {nullptr, nullptr};                 // Krylov step done (per half)
+  hipEvent_t ev_c[3] = {nullptr, nullptr, nullptr};        // core iteration done (ring)
+  hipEvent_t ev_s = nullptr;                               // stream join
   int32_t *btrp, *btci;
   double *btval;
   int *flag;
@@ -395,8 +406,36 @@ int end_solve(Ctx *c, int max_iter, double seconds, sylv_result *res) {
 
 // Creates a context; with a parent, a correction context of the outer refinement: the problem's
 // operators (CSR validated, B^T and the sliced-ELLPACK copies) are the parent's.
+// Streams and events of the overlapped Krylov / core schedule (kst = st when not overlapped).
+int make_streams(Ctx *c, bool overlap) {
+  c->kst = c->st;
+  for (hipEvent_t *e : {&c->ev_k[0], &c->ev_k[1], &c->ev_c[0], &c->ev_c[1], &c->ev_c[2], &c->ev_s})
+    HIPOK(hipEventCreateWithFlags(e, hipEventDisableTiming));
+  if (overlap) {
+    HIPOK(hipStreamCreateWithFlags(&c->kst, hipStreamNonBlocking));
+    c->own_kst = true;
+  }
+  return 0;
+}
+
+void free_streams(Ctx *c) {
+  for (hipEvent_t e : {c->ev_k[0], c->ev_k[1], c->ev_c[0], c->ev_c[1], c->ev_c[2], c->ev_s})
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_kst && c->kst) (void)hipStreamDestroy(c->kst);
+  c->own_kst = false;
+  c->kst = nullptr;
+}
+
+// b waits for the work queued so far on a (no-op when they are the same stream).
+int join(Ctx *c, hipStream_t a, hipStream_t b) {
+  if (a == b) return 0;
+  HIPOK(hipEventRecord(c->ev_s, a));
+  HIPOK(hipStreamWaitEvent(b, c->ev_s, 0));
+  return 0;
+}
+
 int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void *workspace,
-               size_t ws_bytes, void *stream, Ctx *parent) {
+               size_t ws_bytes, void *stream, Ctx *parent, bool overlap = true) {
   if (!out) return SYLV_ERR_INVALID;
   *out = nullptr;
   Layout L;
@@ -438,6 +477,9 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->sc.partials = at<double>(c, L.off_partials);
   c->sc.partial_cap = L.partial_cap;
   c->sc.counters = at<int>(c, L.off_counters);
+  c->scc.partials = at<double>(c, L.off_cscr);
+  c->scc.partial_cap = CORE_SCRATCH;
+  c->scc.counters = c->sc.counters;
   c->btrp = at<int32_t>(c, L.off_btrp);
   c->btci = at<int32_t>(c, L.off_btci);
   c->btval = at<double>(c, L.off_btval);
@@ -446,9 +488,11 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
 
   auto fail = [&](int code) {
     hipHostFree(c->h_ds);
+    free_streams(c);
     delete c;
     return code;
   };
+  if ((e = make_streams(c, overlap))) return fail(e);
   hipStream_t st = c->st;
   if (hipMemsetAsync(c->sc.counters, 0, CNT_MAX * sizeof(int), st) != hipSuccess ||
       hipMemsetAsync(c->ds, 0, sizeof(DevState), st) != hipSuccess ||
@@ -1002,6 +1046,11 @@ int refined_solve(Ctx *P, int method, double tol, int max_iter, sylv_result *res
 
 }  // namespace
 
+int create_context(void **out, const sylv_problem *pb, const sylv_options *op, void *workspace,
+                   size_t ws_bytes, void *stream, bool overlap) {
+  return ctx_create(out, pb, op, workspace, ws_bytes, stream, nullptr, overlap);
+}
+
 thread_local char g_last_error[512] = "";
 
 void note_hip_error(hipError_t e, const char *what) {
@@ -1056,6 +1105,7 @@ void sylv_destroy(void *ctx) {
   if (!c) return;
   for (Ctx *k : c->kids) sylv_destroy(k);
   if (c->h_ds) hipHostFree(c->h_ds);
+  free_streams(c);
   delete c->prof;
   delete c;
 }
@@ -1105,31 +1155,41 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
   auto t0 = std::chrono::steady_clock::now();
   int e = begin_solve(c, tol, max_iter, SYLV_METHOD_CG);
   if (e) return e;
+  const hipStream_t ks = c->kst, cs = c->st;
+  if ((e = join(c, cs, ks))) return e;  // the Krylov stream sees the solve's set-up
   for (int k = 0; k < max_iter; ++k) {
     const int p = (k + 1) * s;
     set_iter(c, k);
-    // (k+1)-th block Lanczos step on both sides (Alg. 4.1 steps 4-5)
+    // (k+1)-th block Lanczos step on both sides (Alg. 4.1 steps 4-5), on the Krylov stream at
+    // most one iteration ahead of the core recurrences (it waits for core iteration k - 2)
+    if (ks != cs && k >= 2) HIPOK(hipStreamWaitEvent(ks, c->ev_c[(k - 2) % 3], 0));
     if ((e = launch_lanczos_pair(s, c->sv, L.lyap ? nullptr : &c->sw, k, L.ldc, c->closure_tol,
-                                 c->sc, c->ds, c->st)))
+                                 c->sc, c->ds, ks)))
       return e;
+    if (ks != cs) {
+      HIPOK(hipEventRecord(c->ev_k[0], ks));
+      HIPOK(hipStreamWaitEvent(cs, c->ev_k[0], 0));
+    }
     // Q_k (step 6) and alpha_k (step 7)
     const double q2 = (double)(p + s) * (p + s);
     prof_begin(c->sc, c->st);
-    if ((e = launch_cg_core(s, p, c->H, c->G, c->P, c->Q, L.ldc, c->sc, c->ds, c->st)))
+    if ((e = launch_cg_core(s, p, c->H, c->G, c->P, c->Q, L.ldc, c->scc, c->ds, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_BAND, 8.0 * ((double)p * p + q2) + 2 * 8.0 * 3 * s * (p + s),
              2.0 * 2.0 * 3.0 * s * (double)p * (p + s), c->st);
     // X, R updates, stopping test, rho, beta, P update (steps 8-14)
     prof_begin(c->sc, c->st);
-    if ((e = launch_cg_update(s, p, c->X, c->R, c->P, c->Q, L.ldc, c->sc, c->ds, c->hist, k,
+    if ((e = launch_cg_update(s, p, c->X, c->R, c->P, c->Q, L.ldc, c->scc, c->ds, c->hist, k,
                               max_iter, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 9.0 * q2, 8.0 * q2, c->st);
+    if (ks != cs) HIPOK(hipEventRecord(c->ev_c[k % 3], cs));
     if ((k + 1) % c->check_every == 0 && k + 1 < max_iter) {
       if ((e = read_state(c))) return e;
       if (c->h_ds->done) break;
     }
   }
+  if ((e = join(c, ks, cs))) return e;
   if (hipStreamSynchronize(c->st) != hipSuccess) return SYLV_ERR_HIP;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return end_solve(c, max_iter, secs, res);
@@ -1145,6 +1205,8 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
   auto t0 = std::chrono::steady_clock::now();
   int e = begin_solve(c, tol, max_iter, SYLV_METHOD_BICGSTAB);
   if (e) return e;
+  const hipStream_t ks = c->kst, cs = c->st;
+  if ((e = join(c, cs, ks))) return e;  // the Krylov stream sees the solve's set-up
   const int *done = &c->ds->done;
   // algorithmic flops of eq. (3.11) with block Hessenberg H, G ((p+s) x p, J = p/s column
   // blocks, column block c holding c+2 row blocks): 2 nnz(H) p + 2 nnz(G) p
@@ -1160,9 +1222,17 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
     const int p = (2 * k + 1) * s;
     set_iter(c, k);
     const SideDesc *sw = L.lyap ? nullptr : &c->sw;
-    // (2k+1)-th block Arnoldi step on both sides (Alg. 4.2 steps 5-6)
-    if ((e = launch_arnoldi_pair(s, c->sv, sw, 2 * k, L.ldc, c->closure_tol, c->sc, c->ds, c->st)))
-      return e;
+    // Block Arnoldi steps 2k+1 and 2k+2 on both sides (Alg. 4.2 steps 5-6 and 10-11), on the
+    // Krylov stream at most one iteration ahead of the core recurrences (they wait for core
+    // iteration k - 2); the core work waits for each step
+    if (ks != cs && k >= 2) HIPOK(hipStreamWaitEvent(ks, c->ev_c[(k - 2) % 3], 0));
+    for (int h = 0; h < 2; ++h) {
+      if ((e = launch_arnoldi_pair(s, c->sv, sw, 2 * k + h, L.ldc, c->closure_tol, c->sc, c->ds,
+                                   ks)))
+        return e;
+      if (ks != cs) HIPOK(hipEventRecord(c->ev_k[h], ks));
+    }
+    if (ks != cs) HIPOK(hipStreamWaitEvent(cs, c->ev_k[0], 0));
     // Q_k (step 7), alpha_k (step 8), S_k (step 9)
     prof_begin(c->sc, c->st);
     if ((e = launch_core_op(s, p, c->H, c->G, c->P, c->Q, L.ldc, done, c->st, c->cpart,
@@ -1175,10 +1245,8 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
                            c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 3.0 * q1, 2.0 * q1, c->st);
-    // (2k+2)-th Arnoldi step (steps 10-11)
-    if ((e = launch_arnoldi_pair(s, c->sv, sw, 2 * k + 1, L.ldc, c->closure_tol, c->sc, c->ds,
-                                 c->st)))
-      return e;
+    // the (2k+2)-th Arnoldi step (steps 10-11) is needed from here on
+    if (ks != cs) HIPOK(hipStreamWaitEvent(cs, c->ev_k[1], 0));
     // T_k (step 12), omega_k (step 13), rho_{k+1}, beta_k (steps 18-19)
     prof_begin(c->sc, c->st);
     if ((e = launch_core_op(s, p + s, c->H, c->G, c->S, c->T, L.ldc, done, c->st, c->cpart,
@@ -1186,20 +1254,22 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
       return e;
     prof_end(c->sc, FAM_CORE_OP, coreop_bytes(p + s), coreop_flops(p + s), c->st);
     prof_begin(c->sc, c->st);
-    if ((e = launch_bicg_omega(s, p, c->T, c->S, L.ldc, c->sc, c->ds, c->st)))
+    if ((e = launch_bicg_omega(s, p, c->T, c->S, L.ldc, c->scc, c->ds, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 2.0 * q2, 4.0 * q2, c->st);
     // X, R, P updates and the stopping test (steps 14-15, 20)
     prof_begin(c->sc, c->st);
-    if ((e = launch_bicg_update(s, p, c->X, c->R, c->P, c->Q, c->S, c->T, c->Rt, L.ldc, c->sc,
+    if ((e = launch_bicg_update(s, p, c->X, c->R, c->P, c->Q, c->S, c->T, c->Rt, L.ldc, c->scc,
                                 c->ds, c->hist, k, max_iter, c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 8.0 * q2, 12.0 * q2, c->st);
+    if (ks != cs) HIPOK(hipEventRecord(c->ev_c[k % 3], cs));
     if ((k + 1) % c->check_every == 0 && k + 1 < max_iter) {
       if ((e = read_state(c))) return e;
       if (c->h_ds->done) break;
     }
   }
+  if ((e = join(c, ks, cs))) return e;
   if (hipStreamSynchronize(c->st) != hipSuccess) return SYLV_ERR_HIP;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return end_solve(c, max_iter, secs, res);

@@ -398,11 +398,11 @@ __device__ __forceinline__ double wave_reduce_scatter(double (&v)[NP], int lane)
   return x;
 }
 
-// Rows per block of the fused sweep (16 basis loads in flight per thread and buffer, at most 32
+// Rows per block of the fused sweep (32 basis loads in flight per thread and buffer, at most 32
 // reduced values) and the padded count of values reduced per block.
 template <int S, int NQ>
 struct UgShape {
-  static constexpr int R0 = NQ >= 16 ? 1 : 16 / NQ;
+  static constexpr int R0 = NQ >= 32 ? 1 : 32 / NQ;
   static constexpr int R = R0 * S > 32 ? (32 / S > 0 ? 32 / S : 1) : R0;
   static constexpr int NV = R * S;
   static constexpr int NP = NV <= 1 ? 1 : NV <= 2 ? 2 : NV <= 4 ? 4 : NV <= 8 ? 8 : NV <= 16 ? 16 : 32;

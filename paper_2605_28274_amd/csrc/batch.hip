@@ -113,8 +113,8 @@ int sylv_batch_create(void **out, int count, const sylv_problem *probs, const sy
         return;
       }
       for (int i : b->plan[k]) {
-        const int e = sylv_create(&b->ctx[i], &probs[i], &opts[i], base[i], bytes[i],
-                                  b->streams[k]);
+        const int e = create_context(&b->ctx[i], &probs[i], &opts[i], base[i], bytes[i],
+                                     b->streams[k], false);
         if (e) {
           err[k] = e;
           return;

@@ -522,6 +522,11 @@ int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
 // Workspace doubles the paired Arnoldi step needs in Scratch::partials.
 size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols);
 
+// A solver context (api.hip); overlap = false keeps the Krylov steps on the caller's stream
+// (batches overlap their instances instead).
+int create_context(void **out, const sylv_problem *pb, const sylv_options *op, void *workspace,
+                   size_t ws_bytes, void *stream, bool overlap);
+
 // Core recurrences (core.hip).
 int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, double *P,
                          double *Rt, int64_t ldc, double tol, DevState *ds, hipStream_t st);

@@ -546,12 +546,13 @@ int launch_core_op(int s, int p, const double *H, const double *G, const double 
   const int T = (q + BM - 1) / BM;
   if ((int64_t)T * BM > ldc || ((p + BK - 1) / BK * BK) > ldc) return SYLV_ERR_WORKSPACE;
   const int tiles = T * T;
-  // stream-K over up to 512 workgroups (two per CU), chunks of at least two slabs, as long as
-  // the partial tiles (one per tile plus one per chunk) fit in part; otherwise tile pairs
+  // stream-K over up to 256 workgroups (one per CU: the Krylov steps of the next iteration run
+  // beside it), chunks of at least two slabs, as long as the partial tiles (one per tile plus
+  // one per chunk) fit in part; otherwise tile pairs
   if (part && T <= CT_MAX) {
     const CoreTab tab = make_core_tab(s, p, T);
     const int total = tab.total();
-    constexpr int NWG = 512;
+    constexpr int NWG = 256;
     const int c = std::max(2, (total + NWG - 1) / NWG);
     const int nchunks = (total + c - 1) / c;
     if (total > 0 && (size_t)(tiles + nchunks) * BM * BN <= part_cap) {

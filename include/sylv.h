@@ -94,7 +94,12 @@ typedef struct {
  * orthonormal basis of Y, and a correction equation with that right-hand side is solved (with
  * at most refine_max_iter iterations); this repeats until the FP64 true residual of the summed
  * iterate meets the tolerance or refine_max corrections ran. refine_inner_tol > tol lets the
- * first solve stop earlier. sylv_default_options() fills sensible values. */
+ * first solve stop earlier.
+ * streams: 1 runs the whole solve on the stream given at create; 2 runs the block Krylov steps
+ * (Arnoldi / Lanczos, which do not depend on the iterates) on a second, library-owned stream
+ * one iteration ahead of the core recurrences, synchronized with HIP events; 0 chooses 2 when
+ * the bases have at least 16384 rows in total and 1 otherwise. Results are identical either
+ * way. sylv_default_options() fills sensible values. */
 typedef struct {
   int method;
   int max_iter;
@@ -106,6 +111,7 @@ typedef struct {
   int refine_max_iter;
   int refine_rank;
   double refine_inner_tol;
+  int streams;
 } sylv_options;
 
 /* Outcome of one solve. rank_v / rank_w: number of columns of the returned V and W;

@@ -70,6 +70,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   if (op->max_iter < 1 || (op->method != SYLV_METHOD_CG && op->method != SYLV_METHOD_BICGSTAB))
     return SYLV_ERR_INVALID;
   if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32) return SYLV_ERR_INVALID;
+  if (op->streams < 0 || op->streams > 2) return SYLV_ERR_INVALID;
   if (!pb->C1 || pb->ldc1 < pb->s) return SYLV_ERR_INVALID;
   if (!pb->lyapunov && (!pb->C2 || pb->ldc2 < pb->s)) return SYLV_ERR_INVALID;
   int e = check_csr_header(pb->A, pb->n);
@@ -492,6 +493,9 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
     delete c;
     return code;
   };
+  // second stream for the Krylov steps: requested, or automatic for bases of 16384+ rows
+  const int64_t krows = L.n + (L.lyap ? 0 : L.m);
+  overlap = overlap && (op->streams == 2 || (op->streams == 0 && krows >= 16384));
   if ((e = make_streams(c, overlap))) return fail(e);
   hipStream_t st = c->st;
   if (hipMemsetAsync(c->sc.counters, 0, CNT_MAX * sizeof(int), st) != hipSuccess ||
@@ -859,8 +863,14 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
     }
     return launch_mirror(offs.back(), G, ldG, st);
   };
-  if ((e = side_pass(false, segL, offL, GL))) return e;
+  // Lyapunov with a single step: B^T = A, W = V, G = H, so the W-side factors are the V-side
+  // ones followed by C1 (E_B = E_A, D2 = D1, C2 = C1) and G_L is the leading cL x cL block of
+  // G_N; one pass over the rows serves both sides.
+  const bool shared = PL.lyap && steps.size() == 1;
+  if (!shared && (e = side_pass(false, segL, offL, GL))) return e;
   if ((e = side_pass(true, segN, offN, GN))) return e;
+  if (shared && (e = launch_copy_block((int)cL, (int)cL, 1.0, GN, ldG, false, GL, ldG, st)))
+    return e;
   // M (cL x cN)
   HIPOK(hipMemset2DAsync(Mc, ldG * 8, 0, cN * 8, cL, st));
   auto put = [&](int64_t r, int64_t c, int rows, int cols, double alpha, const double *src,
@@ -1073,6 +1083,7 @@ void sylv_default_options(sylv_options *opt) {
   opt->refine_max_iter = 100;
   opt->refine_rank = 8;
   opt->refine_inner_tol = 0.0;
+  opt->streams = 0;
 }
 
 size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt) {

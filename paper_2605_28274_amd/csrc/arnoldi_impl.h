@@ -12,7 +12,7 @@
 //       (narrow bases: update_mfma_pair, then gram_part_pair)
 //     sum of the C2 partials -> H += C2, coef                     gram_reduce_pair
 //     U -= V C2   (FP64 MFMA, coef staged in LDS)                  update_mfma_pair
-//   partials of U^T U after the second sweep                       ugram_pair
+//   (with the partials of U^T U)
 //   first Cholesky-QR pass + closure test, partials of G2          qr2_pair
 //   second pass, V_{j+1} = U T, H_{j+1,j}                          final_pair
 // No kernel ends in a grid-wide fence: each reduction leaves one partial per workgroup and the
@@ -283,7 +283,8 @@ __host__ __device__ constexpr int UPD_KCH() {
 // k0 + KL (l / 16) + m as its k-slot l / 16 on both operands (the sum over k is the same). The
 // coefficients sit in LDS, zero-padded past ncols; stale basis columns past ncols read as zero.
 template <int S, typename T>
-__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, const DevState *ds) {
+__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int upart,
+                                                        const DevState *ds) {
   if (ds->done) return;
   typedef double v4 __attribute__((ext_vector_type(4)));
   constexpr int KL = 32 / (int)sizeof(T);  // columns per lane per step
@@ -349,11 +350,39 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, con
     }
   }
   // lane holds D[4 v + lq][li]: row rb + 4 v + lq, column li
-  if (live && li < S) {
+  double uv[4];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t r = rb + 4 * v + lq;
-      if (r < r1) A.U[r * S + li] -= acc0[v] + acc1[v];
+  for (int v = 0; v < 4; ++v) {
+    const int64_t r = rb + 4 * v + lq;
+    uv[v] = 0.0;
+    if (live && li < S && r < r1) {
+      uv[v] = A.U[r * S + li] - (acc0[v] + acc1[v]);
+      A.U[r * S + li] = uv[v];
+    }
+  }
+  if (upart) {
+    // partials of U^T U for the first QR pass (one record per workgroup): lane li = a of each
+    // 16-lane group adds u[r][a] u[r][b] over its rows, then the groups and the waves are
+    // summed in a fixed order
+    __shared__ double gs[TPB / WAVE][S * S];
+    double g[S];
+#pragma unroll
+    for (int b = 0; b < S; ++b) {
+      g[b] = 0.0;
+#pragma unroll
+      for (int v = 0; v < 4; ++v) g[b] = fma(uv[v], __shfl(uv[v], (lane & 48) | b, WAVE), g[b]);
+      g[b] += __shfl_xor(g[b], 16, WAVE);
+      g[b] += __shfl_xor(g[b], 32, WAVE);
+    }
+    if (lane < S)
+#pragma unroll
+      for (int b = 0; b < S; ++b) gs[w][lane * S + b] = g[b];
+    __syncthreads();
+    if ((int)threadIdx.x < S * S) {
+      double a = 0.0;
+#pragma unroll
+      for (int ww = 0; ww < TPB / WAVE; ++ww) a += gs[ww][threadIdx.x];
+      A.aux[A.nb_spmm + lb * S * S + threadIdx.x] = a;
     }
   }
 }
@@ -544,31 +573,6 @@ __global__ __launch_bounds__(TPB) void upd_gram_pair(ArPair P, int ncols, const 
         for (int t = 0; t < S; ++t) part[c * S + t] = acc[q][e][t];
     }
   }
-}
-
-// Partials of U^T U (rows over workgroups, one thread per row) for the first QR pass.
-template <int S>
-__global__ __launch_bounds__(TPB) void ugram_pair(ArPair P, const DevState *ds) {
-  if (ds->done) return;
-  int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
-  double g[S * S];
-#pragma unroll
-  for (int i = 0; i < S * S; ++i) g[i] = 0.0;
-  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
-    double u[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) u[t] = A.U[r * S + t];
-#pragma unroll
-    for (int a = 0; a < S; ++a)
-#pragma unroll
-      for (int b = 0; b < S; ++b) g[a * S + b] = fma(u[a], u[b], g[a * S + b]);
-  }
-  __shared__ double lds[16 * S * S];
-  block_sum<S * S>(g, lds);
-  if (threadIdx.x == 0)
-#pragma unroll
-    for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
 }
 
 // Sums n partial records of NV values (stride NV) in a fixed order; every thread gets the sum.
@@ -996,11 +1000,11 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                                                       ds);
     return hipGetLastError();
   };
-  auto update = [&]() {
+  auto update = [&](int upart) {
     P.s[0].rpc = UROWS;
     P.s[1].rpc = UROWS;
     set_ranges(P, cdiv(rows0, UROWS), sw ? cdiv(rows1, UROWS) : 0);
-    update_mfma_pair<S, T><<<total_blocks(P), TPB, lds, st>>>(P, ncols, ds);
+    update_mfma_pair<S, T><<<total_blocks(P), TPB, lds, st>>>(P, ncols, upart, ds);
     return hipGetLastError();
   };
   const double bytes_g = bytes_v + 8.0 * total * S + 8.0 * nout * P.nsides;
@@ -1021,7 +1025,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     prof_end(sc, FAM_UPD_GRAM, bytes_u, 2.0 * flops_v, st);
   } else {
     prof_begin(sc, st);
-    HIPOK(update());
+    HIPOK(update(0));
     prof_end(sc, FAM_UPDATE, bytes_u, flops_v, st);
     chunks();
     prof_begin(sc, st);
@@ -1029,13 +1033,9 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     HIPOK(reduce(2));
     prof_end(sc, FAM_GRAM, bytes_g, flops_v, st);
   }
-  // second update, then U^T U partials for the first QR pass (one record per 256 rows)
+  // second update with the U^T U partials for the first QR pass (one record per workgroup)
   prof_begin(sc, st);
-  HIPOK(update());
-  for (int i = 0; i < P.nsides; ++i) P.s[i].nb_upd = (int)nb_rows(i ? rows1 : rows0);
-  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
-  ugram_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, ds);
-  HIPOK(hipGetLastError());
+  HIPOK(update(1));
   prof_end(sc, FAM_UPDATE, bytes_u, flops_v, st);
   // QR passes and the new block
   set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);

@@ -26,6 +26,7 @@ def test_status_strings_and_defaults():
     o = sylv.default_options()
     assert o.max_iter > 0 and o.check_every > 0 and o.closure_tol == 0.0
     assert o.precision == sylv.SYLV_FP64
+    assert o.streams == 0  # automatic: second stream for large bases
 
 
 def _problem(n=256, m=192, s=1, lyap=0, nnzA=766, nnzB=574):
@@ -90,6 +91,6 @@ def test_precision_and_refine_options_validated():
     assert sylv.sylv_workspace_bytes(p, ref) > sylv.sylv_workspace_bytes(p, base)
     for bad in (dict(refine_max=5), dict(refine_max=1, refine_rank=0),
                 dict(refine_max=1, refine_rank=9), dict(refine_max=1, refine_max_iter=0),
-                dict(precision=2)):
+                dict(precision=2), dict(streams=3), dict(streams=-1)):
         o = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, **bad)
         assert sylv.sylv_workspace_bytes(p, o) == 0, bad

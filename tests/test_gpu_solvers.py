@@ -244,3 +244,23 @@ def test_wide_arnoldi_bases_stay_orthonormal(sylv, s, iters):
     _, rr = g["slv"].residual_norm()
     Xf = g["V"] @ g["X"] @ g["W"].T
     assert abs(rr - dense_rel_residual(p, Xf)) <= 1e-6 * rr
+
+
+@pytest.mark.parametrize("method", ["cg", "bicgstab"])
+def test_second_stream_gives_identical_results(sylv, method):
+    """The Krylov steps on their own stream, one iteration ahead of the core recurrences
+    (events order every dependency), give bit-identical results to the one-stream schedule."""
+    pe = 0.0 if method == "cg" else 10.0
+    A, B = stencils.cd2d(96, 96, pe), stencils.cd1d(4096, pe)
+    p = stencils.make_problem("two", A, B, 2, 31, method=method, tol=1e-9, max_iter=300)
+    out = []
+    for streams in (1, 2):
+        g = gpu_solve(sylv, p, method, p.tol, p.max_iter, streams=streams)
+        _, rr = g["slv"].residual_norm()
+        out.append((g["res"].iters, g["res"].rel_res_recursive, rr, g["V"], g["X"], g["W"],
+                    np.asarray(g["hist"]["relres"])))
+        g["slv"].close()
+    a, b = out
+    assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
+    for x, y in zip(a[3:], b[3:]):
+        assert np.array_equal(x, y)

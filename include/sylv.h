@@ -99,7 +99,12 @@ typedef struct {
  * (Arnoldi / Lanczos, which do not depend on the iterates) on a second, library-owned stream
  * one iteration ahead of the core recurrences, synchronized with HIP events; 0 chooses 2 when
  * the bases have at least 16384 rows in total and 1 otherwise. Results are identical either
- * way. sylv_default_options() fills sensible values. */
+ * way.
+ * reorth (BiCGSTAB's block Arnoldi, classical Gram-Schmidt applied twice): 1 orthogonalizes each
+ * new block twice in its own step (three passes over the basis per step); 2 takes the second
+ * pass of each block one step later, together with the first pass of the next block (two passes
+ * per step; FP64 bases and s <= 4 only); 0 chooses 2 where it is available. The bases agree to
+ * rounding. sylv_default_options() fills sensible values. */
 typedef struct {
   int method;
   int max_iter;
@@ -112,6 +117,7 @@ typedef struct {
   int refine_rank;
   double refine_inner_tol;
   int streams;
+  int reorth;
 } sylv_options;
 
 /* Outcome of one solve. rank_v / rank_w: number of columns of the returned V and W;

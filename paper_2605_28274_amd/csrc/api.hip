@@ -71,6 +71,10 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
     return SYLV_ERR_INVALID;
   if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32) return SYLV_ERR_INVALID;
   if (op->streams < 0 || op->streams > 2) return SYLV_ERR_INVALID;
+  if (op->reorth < 0 || op->reorth > 2) return SYLV_ERR_INVALID;
+  if (op->method == SYLV_METHOD_BICGSTAB && op->reorth == 2 &&
+      !arnoldi_lagged_supported(pb->s, op->precision == SYLV_MIXED_FP32))
+    return SYLV_ERR_INVALID;
   if (!pb->C1 || pb->ldc1 < pb->s) return SYLV_ERR_INVALID;
   if (!pb->lyapunov && (!pb->C2 || pb->ldc2 < pb->s)) return SYLV_ERR_INVALID;
   int e = check_csr_header(pb->A, pb->n);
@@ -118,8 +122,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   }
   L.off_U = bump(cur, (size_t)L.n * L.s * 8);
   L.off_Uw = bump(cur, (size_t)L.m * L.s * 8);
-  L.off_coefV = bump(cur, (size_t)L.ldb * L.s * 8);
-  L.off_coefW = bump(cur, (size_t)L.ldb * L.s * 8);
+  L.off_coefV = bump(cur, (size_t)L.ldb * 2 * L.s * 8);  // 2 s columns in the lagged step
+  L.off_coefW = bump(cur, (size_t)L.ldb * 2 * L.s * 8);
   const int64_t bnnz = (L.lyap || child) ? 0 : pb->B.nnz;
   L.off_btrp = bump(cur, (size_t)(L.m + 1) * 4);
   L.off_btci = bump(cur, (size_t)std::max<int64_t>(bnnz, 1) * 4);
@@ -288,7 +292,8 @@ struct Ctx {
   // next iteration's basis extension. kst == st when the context was created without it.
   hipStream_t kst = nullptr;
   bool own_kst = false;
-  hipEvent_t ev_k[2] = {nullptr, nullptr};                 // Krylov step done (per half)
+  bool lagged = false;  // block Arnoldi with the second pass one step later
+  hipEvent_t ev_k[4] = {nullptr, nullptr, nullptr, nullptr};  // Krylov step done (ring)
   hipEvent_t ev_c[3] = {nullptr, nullptr, nullptr};        // core iteration done (ring)
   hipEvent_t ev_s = nullptr;                               // stream join
   int32_t *btrp, *btci;
@@ -410,7 +415,8 @@ int end_solve(Ctx *c, int max_iter, double seconds, sylv_result *res) {
 // Streams and events of the overlapped Krylov / core schedule (kst = st when not overlapped).
 int make_streams(Ctx *c, bool overlap) {
   c->kst = c->st;
-  for (hipEvent_t *e : {&c->ev_k[0], &c->ev_k[1], &c->ev_c[0], &c->ev_c[1], &c->ev_c[2], &c->ev_s})
+  for (hipEvent_t *e : {&c->ev_k[0], &c->ev_k[1], &c->ev_k[2], &c->ev_k[3], &c->ev_c[0],
+                        &c->ev_c[1], &c->ev_c[2], &c->ev_s})
     HIPOK(hipEventCreateWithFlags(e, hipEventDisableTiming));
   if (overlap) {
     HIPOK(hipStreamCreateWithFlags(&c->kst, hipStreamNonBlocking));
@@ -420,7 +426,8 @@ int make_streams(Ctx *c, bool overlap) {
 }
 
 void free_streams(Ctx *c) {
-  for (hipEvent_t e : {c->ev_k[0], c->ev_k[1], c->ev_c[0], c->ev_c[1], c->ev_c[2], c->ev_s})
+  for (hipEvent_t e : {c->ev_k[0], c->ev_k[1], c->ev_k[2], c->ev_k[3], c->ev_c[0], c->ev_c[1],
+                       c->ev_c[2], c->ev_s})
     if (e) (void)hipEventDestroy(e);
   if (c->own_kst && c->kst) (void)hipStreamDestroy(c->kst);
   c->own_kst = false;
@@ -454,6 +461,8 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->refine_inner_tol = op->refine_inner_tol;
   c->check_every = op->check_every > 0 ? op->check_every : 8;
   c->record_history = op->record_history;
+  c->lagged = L.method == SYLV_METHOD_BICGSTAB && op->reorth != 1 &&
+              arnoldi_lagged_supported((int)L.s, L.fp32);
   c->ws = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(workspace) + ALIGN - 1) / ALIGN * ALIGN);
   if (hipHostMalloc(reinterpret_cast<void **>(&c->h_ds), sizeof(DevState)) != hipSuccess) {
     delete c;
@@ -1084,6 +1093,7 @@ void sylv_default_options(sylv_options *opt) {
   opt->refine_rank = 8;
   opt->refine_inner_tol = 0.0;
   opt->streams = 0;
+  opt->reorth = 0;
 }
 
 size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt) {
@@ -1218,6 +1228,7 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
   if (e) return e;
   const hipStream_t ks = c->kst, cs = c->st;
   if ((e = join(c, cs, ks))) return e;  // the Krylov stream sees the solve's set-up
+  int next_step = 0;                    // first Arnoldi step not yet enqueued
   const int *done = &c->ds->done;
   // algorithmic flops of eq. (3.11) with block Hessenberg H, G ((p+s) x p, J = p/s column
   // blocks, column block c holding c+2 row blocks): 2 nnz(H) p + 2 nnz(G) p
@@ -1233,17 +1244,19 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
     const int p = (2 * k + 1) * s;
     set_iter(c, k);
     const SideDesc *sw = L.lyap ? nullptr : &c->sw;
-    // Block Arnoldi steps 2k+1 and 2k+2 on both sides (Alg. 4.2 steps 5-6 and 10-11), on the
-    // Krylov stream at most one iteration ahead of the core recurrences (they wait for core
-    // iteration k - 2); the core work waits for each step
+    // Block Arnoldi steps (Alg. 4.2 steps 5-6 and 10-11) on the Krylov stream, at most one
+    // iteration ahead of the core recurrences (they wait for core iteration k - 2); the core
+    // work waits for the step that completes the columns of H and G it reads: step j writes
+    // column block j, or, with the lagged second pass, completes column block j - 1
+    const int need1 = 2 * k + (c->lagged ? 1 : 0), need2 = need1 + 1;
     if (ks != cs && k >= 2) HIPOK(hipStreamWaitEvent(ks, c->ev_c[(k - 2) % 3], 0));
-    for (int h = 0; h < 2; ++h) {
-      if ((e = launch_arnoldi_pair(s, c->sv, sw, 2 * k + h, L.ldc, c->closure_tol, c->sc, c->ds,
-                                   ks)))
+    for (; next_step <= need2; ++next_step) {
+      if ((e = launch_arnoldi_pair(s, c->sv, sw, next_step, L.ldc, c->closure_tol, c->sc, c->ds,
+                                   ks, c->lagged)))
         return e;
-      if (ks != cs) HIPOK(hipEventRecord(c->ev_k[h], ks));
+      if (ks != cs) HIPOK(hipEventRecord(c->ev_k[next_step % 4], ks));
     }
-    if (ks != cs) HIPOK(hipStreamWaitEvent(cs, c->ev_k[0], 0));
+    if (ks != cs) HIPOK(hipStreamWaitEvent(cs, c->ev_k[need1 % 4], 0));
     // Q_k (step 7), alpha_k (step 8), S_k (step 9)
     prof_begin(c->sc, c->st);
     if ((e = launch_core_op(s, p, c->H, c->G, c->P, c->Q, L.ldc, done, c->st, c->cpart,
@@ -1256,8 +1269,8 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
                            c->st)))
       return e;
     prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 3.0 * q1, 2.0 * q1, c->st);
-    // the (2k+2)-th Arnoldi step (steps 10-11) is needed from here on
-    if (ks != cs) HIPOK(hipStreamWaitEvent(cs, c->ev_k[1], 0));
+    // the (2k+2)-th Arnoldi block (steps 10-11) is needed from here on
+    if (ks != cs) HIPOK(hipStreamWaitEvent(cs, c->ev_k[need2 % 4], 0));
     // T_k (step 12), omega_k (step 13), rho_{k+1}, beta_k (steps 18-19)
     prof_begin(c->sc, c->st);
     if ((e = launch_core_op(s, p + s, c->H, c->G, c->S, c->T, L.ldc, done, c->st, c->cpart,

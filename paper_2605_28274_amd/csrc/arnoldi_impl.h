@@ -126,7 +126,9 @@ struct Pack8<float> {
 // in flight; a narrow basis thus still spreads its chunk over every thread. The row-group sums
 // are added in a fixed order through LDS. part[lb][c][t]; column groups past the width load
 // group 0 and rows past the chunk load its first row (both in bounds), neither is counted.
-template <int S, typename T, int NQ>
+// DUAL: the right-hand side is [pin, U] (S / 2 columns each: the provisional block and M times
+// it, for the lagged step), else U (S columns).
+template <int S, typename T, int NQ, bool DUAL = false>
 __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int cw_log2,
                                                       const DevState *ds) {
   if (ds->done) return;
@@ -173,7 +175,14 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int c
         for (int q = 0; q < NQ; ++q)
           v[h][q] = (q < nq) ? *reinterpret_cast<const V8 *>(vr + coff[q]) : PK::zero();
 #pragma unroll
-        for (int t = 0; t < S; ++t) u[h][t] = ok ? A.U[row * S + t] : 0.0;
+        for (int t = 0; t < S; ++t) {
+          double uv = 0.0;
+          if (ok) {
+            if (DUAL && t < S / 2) uv = (double)static_cast<const T *>(A.pin)[row * (S / 2) + t];
+            else uv = DUAL ? A.U[row * (S / 2) + t - S / 2] : A.U[row * S + t];
+          }
+          u[h][t] = uv;
+        }
       }
 #pragma unroll
       for (int h = 0; h < RU; ++h)
@@ -230,7 +239,7 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int c
 // Sums the nchunk partials of OPB consecutive outputs per workgroup: thread group g (of NG)
 // adds chunks [g nchunk / NG, (g+1) nchunk / NG) for its output (eight loads in flight, added
 // in chunk order), then group 0 adds the NG group sums in order and writes column block j of H
-// (store in sweep 1, add in sweep 2) and the compact coefficients.
+// (store in sweep 1, add in sweep 2; pass 0: coefficients only) and the compact coefficients.
 __global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int ncols, int nchunk0,
                                                         int nchunk1, int64_t ldh, int hcol,
                                                         int pass, const DevState *ds) {
@@ -263,8 +272,10 @@ __global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int nco
 #pragma unroll
     for (int q = 0; q < NG; ++q) b += gs[q][ol];
     const int c = o / S, t = o % S;
-    double *h = A.H + (int64_t)c * ldh + hcol + t;
-    *h = (pass == 1) ? b : *h + b;
+    if (pass > 0) {
+      double *h = A.H + (int64_t)c * ldh + hcol + t;
+      *h = (pass == 1) ? b : *h + b;
+    }
     A.coef[o] = b;
   }
 }
@@ -276,41 +287,39 @@ __host__ __device__ constexpr int UPD_KCH() {
   return (64 * 1024 / (S * 8)) / 128 * 128;
 }
 
-// U[r] -= V[r, 0:ncols] C on FP64 matrix cores (v_mfma_f64_16x16x4f64): each wave owns 16 rows,
-// D (16 x 16) += A (16 rows x 4 basis columns) B (4 x 16, coefficient columns >= S are zero).
-// Lane l reads 32 contiguous bytes of row l % 16 per step (KL consecutive columns, chunk l / 16),
-// so the four lanes of a row cover 128 contiguous bytes; MFMA m of the step takes column
-// k0 + KL (l / 16) + m as its k-slot l / 16 on both operands (the sum over k is the same). The
-// coefficients sit in LDS, zero-padded past ncols; stale basis columns past ncols read as zero.
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int upart,
-                                                        const DevState *ds) {
-  if (ds->done) return;
-  typedef double v4 __attribute__((ext_vector_type(4)));
+typedef double v4d_t __attribute__((ext_vector_type(4)));
+
+// D = V[r, 0:ncols] C on FP64 matrix cores (v_mfma_f64_16x16x4f64) for the wave's 16 rows
+// [rb, rb + 16) (C: ncols x SC row-major coefficients, SC <= 16): D (16 x 16) += A (16 rows x 4
+// basis columns) B (4 x 16, coefficient columns >= SC are zero). Lane l reads 32 contiguous bytes
+// of row l % 16 per step (KL consecutive columns, chunk l / 16), so the four lanes of a row
+// cover 128 contiguous bytes; MFMA m of the step takes column k0 + KL (l / 16) + m as its k-slot
+// l / 16 on both operands (the sum over k is the same). The coefficients pass through LDS (Cs)
+// in chunks, zero-padded past ncols; basis columns past ncols read as zero (they may be stale).
+// On return lane l holds D[4 v + l / 16][l % 16] in acc0[v] + acc1[v]. Every thread of the
+// workgroup must call it (barriers).
+template <int SC, typename T>
+__device__ __forceinline__ void update_acc(const ArSide &A, const double *coef, int ncols,
+                                           double *Cs, int64_t rb, int64_t r1, v4d_t &acc0,
+                                           v4d_t &acc1) {
   constexpr int KL = 32 / (int)sizeof(T);  // columns per lane per step
   constexpr int KG = 4 * KL;               // columns per step
   constexpr int KU = 4;                    // steps whose loads are in flight together
-  extern __shared__ double Cs[];
-  int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
-  const int nk = (ncols + KG - 1) / KG * KG;
-  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int lane = threadIdx.x & (WAVE - 1);
   const int li = lane & 15, lq = lane >> 4;
-  // one block of 16 rows per wave (UROWS rows per workgroup)
-  const int64_t r0 = (int64_t)lb * A.rpc;
-  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
-  const int64_t rb = r0 + 16 * w;
+  const int nk = (ncols + KG - 1) / KG * KG;
   const bool live = rb < r1;
   const int64_t row = (rb + li < r1) ? rb + li : r1 - 1;  // clamped loads, masked stores
   const T *vr = static_cast<const T *>(A.basis) + row * A.ldb + lq * KL;
-  v4 acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  acc0 = v4d_t{0.0, 0.0, 0.0, 0.0};
+  acc1 = v4d_t{0.0, 0.0, 0.0, 0.0};
   // the coefficients pass through LDS in chunks of at most 64 KiB
-  for (int c0 = 0; c0 < nk; c0 += UPD_KCH<S>()) {
-    const int c1 = (c0 + UPD_KCH<S>() < nk) ? c0 + UPD_KCH<S>() : nk;
+  for (int c0 = 0; c0 < nk; c0 += UPD_KCH<SC>()) {
+    const int c1 = (c0 + UPD_KCH<SC>() < nk) ? c0 + UPD_KCH<SC>() : nk;
     __syncthreads();
-    for (int e = threadIdx.x; e < (c1 - c0) * S; e += TPB) {
-      const int g = c0 * S + e;
-      Cs[e] = g < ncols * S ? A.coef[g] : 0.0;
+    for (int e = threadIdx.x; e < (c1 - c0) * SC; e += TPB) {
+      const int g = c0 * SC + e;
+      Cs[e] = g < ncols * SC ? coef[g] : 0.0;
     }
     __syncthreads();
     if (!live) continue;
@@ -342,48 +351,270 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int
         for (int m = 0; m < KL; ++m) {
           const int k = k0 + u * KG + lq * KL + m;
           const double av = (step && k < ncols) ? (double)x[u][m] : 0.0;
-          const double bv = (step && li < S) ? Cs[(k - c0) * S + li] : 0.0;
+          const double bv = (step && li < SC) ? Cs[(k - c0) * SC + li] : 0.0;
           if (m & 1) acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc1, 0, 0, 0);
           else acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc0, 0, 0, 0);
         }
       }
     }
   }
+}
+
+// Partials of U^T U of the workgroup's rows (one record per workgroup, at aux[nb_spmm + lb S^2]):
+// lane li = a of each 16-lane group holds u[rb + 4 v + lq][a] in uv[v] (zero past the rows);
+// it adds u[r][a] u[r][b] over its rows, then the groups and the waves are summed in order.
+template <int S>
+__device__ __forceinline__ void upart_record(const ArSide &A, int lb, const double (&uv)[4]) {
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  __shared__ double gs[TPB / WAVE][S * S];
+  double g[S];
+#pragma unroll
+  for (int b = 0; b < S; ++b) {
+    g[b] = 0.0;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) g[b] = fma(uv[v], __shfl(uv[v], (lane & 48) | b, WAVE), g[b]);
+    g[b] += __shfl_xor(g[b], 16, WAVE);
+    g[b] += __shfl_xor(g[b], 32, WAVE);
+  }
+  if (lane < S)
+#pragma unroll
+    for (int b = 0; b < S; ++b) gs[w][lane * S + b] = g[b];
+  __syncthreads();
+  if ((int)threadIdx.x < S * S) {
+    double a = 0.0;
+#pragma unroll
+    for (int ww = 0; ww < TPB / WAVE; ++ww) a += gs[ww][threadIdx.x];
+    A.aux[A.nb_spmm + lb * S * S + threadIdx.x] = a;
+  }
+}
+
+// U[r] -= V[r, 0:ncols] C for the workgroup's UROWS rows (16 per wave); with upart, also the
+// partials of U^T U of the updated rows for the first QR pass.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int upart,
+                                                        const DevState *ds) {
+  if (ds->done) return;
+  extern __shared__ double Cs[];
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int li = lane & 15, lq = lane >> 4;
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  const int64_t rb = r0 + 16 * w;
+  v4d_t acc0, acc1;
+  update_acc<S, T>(A, A.coef, ncols, Cs, rb, r1, acc0, acc1);
   // lane holds D[4 v + lq][li]: row rb + 4 v + lq, column li
   double uv[4];
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
     const int64_t r = rb + 4 * v + lq;
     uv[v] = 0.0;
-    if (live && li < S && r < r1) {
+    if (li < S && r < r1) {
       uv[v] = A.U[r * S + li] - (acc0[v] + acc1[v]);
       A.U[r * S + li] = uv[v];
     }
   }
-  if (upart) {
-    // partials of U^T U for the first QR pass (one record per workgroup): lane li = a of each
-    // 16-lane group adds u[r][a] u[r][b] over its rows, then the groups and the waves are
-    // summed in a fixed order
-    __shared__ double gs[TPB / WAVE][S * S];
-    double g[S];
+  if (upart) upart_record<S>(A, lb, uv);
+}
+
+// ---- lagged reorthogonalization (block Arnoldi with classical Gram-Schmidt, two passes) ----
+// Block j arrives provisional: V~_j, orthogonalized once and normalized (block 0 is final). Step
+// j computes U = M V~_j and, in one pass over the basis, the coefficients
+//   [a b; d c] = [V_{0..j-1}; V~_j]^T [V~_j, U]                     (gram_part_pair, DUAL)
+// then (dcgs_fix_pair) the second pass of block j: w = V~_j - V a, w^T w = d - a^T a, V_j = w Tw
+// (Cholesky, or the closure / deflation rule of the first-pass QR), the final column block j-1
+// of H from the provisional one, and e = V_j^T U = Tw^T (c - a^T b); then, in one more pass
+// (dcgs_update_pair), the final rows of V_j and U' = (U - V_{0..j-1} b - V_j e) Tw = M V_j -
+// V_{0..j} C, the first-pass projection of the new direction; dcgs_hcol_pair writes the
+// provisional column block j of H, C = ([b; e] - H a) Tw (M V a = V H a by the Arnoldi relation
+// of the earlier columns); the QR of U' (qr2_pair, final_pair) gives the provisional V~_{j+1}.
+// Two passes over the basis per step instead of three; the arithmetic is classical Gram-Schmidt
+// applied twice with the second pass of each block taken one step later.
+
+// One workgroup per basis: Tw, e (SideState), final column block j-1 of H.
+template <int S>
+__global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t ldh,
+                                                     double closure_tol, const DevState *ds) {
+  if (ds->done) return;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  constexpr int S2 = 2 * S;
+  const int nf = jb * S;  // final columns
+  __shared__ double lds[16 * 2 * S * S];
+  __shared__ SideState st;
+  __shared__ double Rt[S * S], Hw[S * S];
+  double g[2 * S * S];  // a^T a, a^T b
 #pragma unroll
-    for (int b = 0; b < S; ++b) {
-      g[b] = 0.0;
+  for (int i = 0; i < 2 * S * S; ++i) g[i] = 0.0;
+  for (int c = threadIdx.x; c < nf; c += TPB) {
+    double av[S], bv[S];
 #pragma unroll
-      for (int v = 0; v < 4; ++v) g[b] = fma(uv[v], __shfl(uv[v], (lane & 48) | b, WAVE), g[b]);
-      g[b] += __shfl_xor(g[b], 16, WAVE);
-      g[b] += __shfl_xor(g[b], 32, WAVE);
+    for (int t = 0; t < S; ++t) {
+      av[t] = A.coef[c * S2 + t];
+      bv[t] = A.coef[c * S2 + S + t];
     }
-    if (lane < S)
 #pragma unroll
-      for (int b = 0; b < S; ++b) gs[w][lane * S + b] = g[b];
-    __syncthreads();
-    if ((int)threadIdx.x < S * S) {
-      double a = 0.0;
+    for (int p = 0; p < S; ++p)
 #pragma unroll
-      for (int ww = 0; ww < TPB / WAVE; ++ww) a += gs[ww][threadIdx.x];
-      A.aux[A.nb_spmm + lb * S * S + threadIdx.x] = a;
+      for (int q = 0; q < S; ++q) {
+        g[p * S + q] = fma(av[p], av[q], g[p * S + q]);
+        g[S * S + p * S + q] = fma(av[p], bv[q], g[S * S + p * S + q]);
+      }
+  }
+  block_sum<2 * S * S>(g, lds);
+  if (threadIdx.x == 0) {
+    double Gw[S * S], cc[S * S];
+    double tr = 0.0;
+    for (int p = 0; p < S; ++p)
+      for (int q = 0; q < S; ++q) {
+        Gw[p * S + q] = A.coef[(nf + p) * S2 + q] - g[p * S + q];
+        cc[p * S + q] = A.coef[(nf + p) * S2 + S + q] - g[S * S + p * S + q];
+      }
+    for (int p = 0; p < S; ++p) tr += A.coef[(nf + p) * S2 + p];
+    if (jb == 0) {  // block 0 is final: V_0 = V~_0
+      for (int i = 0; i < S * S; ++i) st.T1[i] = st.Hs1[i] = (i % (S + 1) == 0) ? 1.0 : 0.0;
+      st.mode = 0;
+    } else {
+      st.ref2 = tr;
+      finish_pass1(&st, S, closure_tol, Gw);
     }
+    for (int i = 0; i < S * S; ++i) {
+      A.ss->Tw[i] = st.T1[i];
+      Hw[i] = st.Hs1[i];
+    }
+    A.ss->modew = st.mode;
+    // e = Tw^T (c - a^T b)
+    for (int p = 0; p < S; ++p)
+      for (int q = 0; q < S; ++q) {
+        double v = 0.0;
+        for (int t = 0; t < S; ++t) v = fma(st.T1[t * S + p], cc[t * S + q], v);
+        A.ss->Ew[p * S + q] = v;
+      }
+    if (jb > 0)
+      for (int p = 0; p < S; ++p)
+        for (int q = 0; q < S; ++q)
+          Rt[p * S + q] = A.H[(int64_t)(nf + p) * ldh + nf - S + q];
+  }
+  __syncthreads();
+  if (jb == 0) return;
+  // column block j-1: the provisional U'_{j-1} = V~_j Rt = (V a + V_j Hw) Rt
+  for (int c = threadIdx.x; c < nf; c += TPB) {
+    double av[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t) av[t] = A.coef[c * S2 + t];
+#pragma unroll
+    for (int q = 0; q < S; ++q) {
+      double v = 0.0;
+#pragma unroll
+      for (int t = 0; t < S; ++t) v = fma(av[t], Rt[t * S + q], v);
+      A.H[(int64_t)c * ldh + nf - S + q] += v;
+    }
+  }
+  if ((int)threadIdx.x < S * S) {
+    const int p = threadIdx.x / S, q = threadIdx.x % S;
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) v = fma(Hw[p * S + t], Rt[t * S + q], v);
+    A.H[(int64_t)(nf + p) * ldh + nf - S + q] = v;
+  }
+}
+
+// The second pass of block j and the first pass of U in one pass over V_{0..j-1}: X = V [a b]
+// on matrix cores (2S coefficient columns), then per row V_j = (V~_j - X_a) Tw (written over the
+// provisional block) and U' = (U - X_b - V_j e) Tw; partials of U'^T U'.
+template <int S>
+__global__ __launch_bounds__(TPB) void dcgs_update_pair(ArPair P, int jb, const DevState *ds) {
+  if (ds->done) return;
+  constexpr int S2 = 2 * S;
+  extern __shared__ double Cs[];
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int li = lane & 15, lq = lane >> 4;
+  const int64_t r0 = (int64_t)lb * A.rpc;
+  const int64_t r1 = (r0 + A.rpc < A.rows) ? r0 + A.rpc : A.rows;
+  const int64_t rb = r0 + 16 * w;
+  const int nf = jb * S;
+  v4d_t acc0, acc1;
+  update_acc<S2, double>(A, A.coef, nf, Cs, rb, r1, acc0, acc1);
+  double Tw[S * S], Ew[S * S];
+#pragma unroll
+  for (int i = 0; i < S * S; ++i) {
+    Tw[i] = A.ss->Tw[i];
+    Ew[i] = A.ss->Ew[i];
+  }
+  double *basis = static_cast<double *>(A.basis);
+  const int col = li < S ? li : 0;
+  double uv[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t r = rb + 4 * v + lq;
+    const bool ok = r < r1;
+    const int64_t rr = ok ? r : r1 - 1;
+    const double x = acc0[v] + acc1[v];  // X[r][li]
+    double wv[S], vv[S], z[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      wv[t] = basis[rr * A.ldb + nf + t] - __shfl(x, (lane & 48) | t, WAVE);
+    double vq = 0.0;  // V_j[r][col]
+#pragma unroll
+    for (int t = 0; t < S; ++t) vq = fma(wv[t], Tw[t * S + col], vq);
+#pragma unroll
+    for (int q = 0; q < S; ++q) vv[q] = __shfl(vq, (lane & 48) | q, WAVE);
+#pragma unroll
+    for (int t = 0; t < S; ++t) {
+      double zt = A.U[rr * S + t] - __shfl(x, (lane & 48) | (S + t), WAVE);
+#pragma unroll
+      for (int q = 0; q < S; ++q) zt = fma(-vv[q], Ew[q * S + t], zt);
+      z[t] = zt;
+    }
+    double uq = 0.0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) uq = fma(z[t], Tw[t * S + col], uq);
+    uv[v] = (ok && li < S) ? uq : 0.0;
+    if (ok && li < S) {
+      basis[r * A.ldb + nf + li] = vq;
+      A.U[r * S + li] = uq;
+    }
+  }
+  upart_record<S>(A, lb, uv);
+}
+
+// Provisional column block j of H: rows i < (j+1) S, one wave per row: C[i] = ([b; e][i] -
+// H[i, 0:nf] a) Tw (H[i, c] is zero for c < (i/S - 1) S).
+template <int S>
+__global__ __launch_bounds__(TPB) void dcgs_hcol_pair(ArPair P, int jb, int64_t ldh,
+                                                      const DevState *ds) {
+  if (ds->done) return;
+  constexpr int S2 = 2 * S;
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
+  const int nf = jb * S, nrow = nf + S;
+  const int i = lb * (TPB / WAVE) + w;
+  if (i >= nrow) return;
+  int cs = (i / S - 1) * S;
+  cs = cs < 0 ? 0 : cs;
+  double acc[S];
+#pragma unroll
+  for (int t = 0; t < S; ++t) acc[t] = 0.0;
+  for (int c = cs + lane; c < nf; c += WAVE) {
+    const double h = A.H[(int64_t)i * ldh + c];
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[t] = fma(h, A.coef[c * S2 + t], acc[t]);
+  }
+#pragma unroll
+  for (int t = 0; t < S; ++t) acc[t] = wave_sum(acc[t]);
+  if (lane < S) {
+    double y[S];
+#pragma unroll
+    for (int t = 0; t < S; ++t)
+      y[t] = (i < nf ? A.coef[i * S2 + S + t] : A.ss->Ew[(i - nf) * S + t]) - acc[t];
+    double v = 0.0;
+#pragma unroll
+    for (int t = 0; t < S; ++t) v = fma(y[t], A.ss->Tw[t * S + lane], v);
+    A.H[(int64_t)i * ldh + nf + lane] = v;
   }
 }
 
@@ -1048,6 +1279,104 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   return 0;
 }
 
+// The lagged Arnoldi step j (FP64 bases, 2 s <= 8 Gram columns): see dcgs_fix_pair.
+template <int S>
+int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
+                     double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
+  constexpr int S2 = 2 * S;
+  ArPair P{};
+  const size_t half = sc.partial_cap / 2;
+  P.nsides = sw ? 2 : 1;
+  const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
+  const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
+  P.s[0] = make_side(sv, sc, 0, half, aux0);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  for (int i = 0; i < P.nsides; ++i) {
+    const SideDesc &d = i ? *sw : sv;
+    const int64_t rows = i ? rows1 : rows0;
+    P.s[i].nb_spmm = (int)nb_rows(rows);
+    P.s[i].nb_upd = (int)cdiv(rows, UROWS);
+    P.s[i].nb_qr = (int)nb_qr(rows);
+    P.s[i].pin = d.panel[jb % 2];
+    P.s[i].pout = d.panel[(jb + 1) % 2];
+  }
+  const int64_t total = rows0 + rows1;
+  const int ncols = (jb + 1) * S, nf = jb * S;
+  const int nout = ncols * S2;
+  const double bytes_g = 8.0 * total * ncols + 16.0 * total * S + 8.0 * nout * P.nsides;
+  const double bytes_u = 8.0 * total * nf + 32.0 * total * S;
+
+  // U = M V~_j
+  set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
+  prof_begin(sc, st);
+  spmm_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_SPMM,
+           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,
+           2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S, st);
+
+  // [V_{0..j-1}; V~_j]^T [V~_j, U]
+  const int64_t rpc0 = gram_rpc(S, rows0, total), rpc1 = sw ? gram_rpc(S, rows1, total) : 1;
+  const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
+  if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
+    return SYLV_ERR_WORKSPACE;
+  P.s[0].rpc = rpc0;
+  P.s[1].rpc = rpc1;
+  set_ranges(P, nch0, nch1);
+  prof_begin(sc, st);
+  {
+    constexpr int QM = gram_nq_max<S2, double>();
+    const int ng = ncols;
+    int cw_log2 = 8, nq = 1;
+    if (ng <= TPB) cw_log2 = log2_exact(pow2_ceil(ng));
+    else nq = std::min(QM, pow2_ceil((ng + TPB - 1) / TPB));
+    const size_t glds = cw_log2 < 8 ? (size_t)TPB * S2 * sizeof(double) : 0;
+    const unsigned nb = total_blocks(P);
+    switch (nq) {
+      case 1: gram_part_pair<S2, double, 1, true><<<nb, TPB, glds, st>>>(P, ncols, cw_log2, ds); break;
+      case 2: gram_part_pair<S2, double, std::min(2, QM), true><<<nb, TPB, glds, st>>>(P, ncols, cw_log2, ds); break;
+      case 4: gram_part_pair<S2, double, std::min(4, QM), true><<<nb, TPB, glds, st>>>(P, ncols, cw_log2, ds); break;
+      default: gram_part_pair<S2, double, QM, true><<<nb, TPB, glds, st>>>(P, ncols, cw_log2, ds); break;
+    }
+    HIPOK(hipGetLastError());
+  }
+  const int64_t rtiles = cdiv(nout, OPB);
+  set_ranges(P, rtiles, sw ? rtiles : 0);
+  gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S2, ncols, nch0, nch1, ldh, jb * S, 0, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_GRAM, bytes_g, 2.0 * total * ncols * S2, st);
+
+  // second pass of block j: Tw, e, final column block j-1
+  prof_begin(sc, st);
+  set_ranges(P, 1, sw ? 1 : 0);
+  dcgs_fix_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, closure_tol, ds);
+  HIPOK(hipGetLastError());
+  // final V_j and U' in one pass over V_{0..j-1}, with the U'^T U' partials
+  const size_t lds = (size_t)std::max(
+      std::min((nf + 127) / 128 * 128, UPD_KCH<S2>()) * S2 * (int)sizeof(double), 8);
+  P.s[0].rpc = UROWS;
+  P.s[1].rpc = UROWS;
+  set_ranges(P, cdiv(rows0, UROWS), sw ? cdiv(rows1, UROWS) : 0);
+  dcgs_update_pair<S><<<total_blocks(P), TPB, lds, st>>>(P, jb, ds);
+  HIPOK(hipGetLastError());
+  // provisional column block j of H
+  const int64_t hw = cdiv(ncols, TPB / WAVE);
+  set_ranges(P, hw, sw ? hw : 0);
+  dcgs_hcol_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_UPDATE, bytes_u, 2.0 * total * nf * S2, st);
+
+  // QR of U' and the provisional block j+1
+  set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
+  prof_begin(sc, st);
+  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+  HIPOK(hipGetLastError());
+  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  HIPOK(hipGetLastError());
+  prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  return 0;
+}
+
 template <int S, typename T>
 int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                    double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
@@ -1103,4 +1432,11 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {  \
     return sv.fp32 ? lanczos_pair_t<SS, float>(sv, sw, jb, ldh, closure_tol, sc, ds, st)        \
                    : lanczos_pair_t<SS, double>(sv, sw, jb, ldh, closure_tol, sc, ds, st);      \
+  }                                                                                             \
+  int arnoldi_lagged_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,          \
+                          double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {\
+    if constexpr (SS <= 4) {                                                                    \
+      if (!sv.fp32) return arnoldi_lagged_t<SS>(sv, sw, jb, ldh, closure_tol, sc, ds, st);      \
+    }                                                                                           \
+    return SYLV_ERR_INVALID;                                                                    \
   }

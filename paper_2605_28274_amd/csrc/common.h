@@ -37,6 +37,11 @@ struct SideState {
   double T[SYLV_MAX_S * SYLV_MAX_S];    // combined normalizer (V_{j+1} = U T)
   int mode;                             // 0 regular, 1 closed (zero block), 2 deflated
   int pad_[3];
+  // lagged reorthogonalization of the provisional block (w = V~_j - V a, V_j = w Tw)
+  double Tw[SYLV_MAX_S * SYLV_MAX_S];
+  double Ew[SYLV_MAX_S * SYLV_MAX_S];   // V_j^T (M V~_j)
+  int modew;
+  int padw_[3];
 };
 
 // Counter slots for the "last workgroup reduces" pattern; each kernel family owns a range.
@@ -518,7 +523,11 @@ int launch_lanczos_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
 // Both bases' block Arnoldi steps j (same j) in shared launches (arnoldi.hip); sw may be null
 // (Lyapunov: one basis).
 int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
-                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
+                        double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st,
+                        bool lagged = false);
+// Whether the lagged (one fewer pass over the basis) Arnoldi step exists for this block size and
+// basis precision.
+bool arnoldi_lagged_supported(int s, bool fp32);
 // Workspace doubles the paired Arnoldi step needs in Scratch::partials.
 size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols);
 

@@ -27,6 +27,7 @@ def test_status_strings_and_defaults():
     assert o.max_iter > 0 and o.check_every > 0 and o.closure_tol == 0.0
     assert o.precision == sylv.SYLV_FP64
     assert o.streams == 0  # automatic: second stream for large bases
+    assert o.reorth == 0   # automatic: lagged second pass where available
 
 
 def _problem(n=256, m=192, s=1, lyap=0, nnzA=766, nnzB=574):
@@ -91,6 +92,16 @@ def test_precision_and_refine_options_validated():
     assert sylv.sylv_workspace_bytes(p, ref) > sylv.sylv_workspace_bytes(p, base)
     for bad in (dict(refine_max=5), dict(refine_max=1, refine_rank=0),
                 dict(refine_max=1, refine_rank=9), dict(refine_max=1, refine_max_iter=0),
-                dict(precision=2), dict(streams=3), dict(streams=-1)):
-        o = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, **bad)
+                dict(precision=2), dict(streams=3), dict(streams=-1), dict(reorth=3),
+                dict(reorth=2)):  # the lagged pass needs FP64 bases (base is FP32)
+        kw = dict(precision=sylv.SYLV_MIXED_FP32) if bad == dict(reorth=2) else {}
+        kw.update(bad)
+        o = sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, **kw)
         assert sylv.sylv_workspace_bytes(p, o) == 0, bad
+    # lagged pass: FP64 bases with s <= 4 only
+    assert sylv.sylv_workspace_bytes(p, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50,
+                                                             reorth=2)) > 0
+    p5 = _problem(s=5)
+    assert sylv.sylv_workspace_bytes(p5, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50,
+                                                              reorth=2)) == 0
+    assert sylv.sylv_workspace_bytes(p5, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50)) > 0

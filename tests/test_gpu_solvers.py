@@ -227,17 +227,19 @@ def test_c2_bicgstab_parity(sylv):
     assert rel(Sg, So) < 1e-4
 
 
+@pytest.mark.parametrize("reorth", [1, 2])
 @pytest.mark.parametrize("s,iters", [(2, 180), (4, 130)])
-def test_wide_arnoldi_bases_stay_orthonormal(sylv, s, iters):
+def test_wide_arnoldi_bases_stay_orthonormal(sylv, s, iters, reorth):
     """Block Arnoldi with classical Gram-Schmidt applied twice keeps V^T V = I to rounding level
     (Algorithm 4.2's bases) through every sweep shape: narrow bases (row groups), wide ones (up
     to eight column groups per thread) and the fused first-sweep update with the second sweep's
-    Gram (bases wider than 256 columns); checked up to 720 (s = 2) and 1040 (s = 4) columns.
+    Gram (bases wider than 256 columns), with both passes in the block's own step (reorth 1) or
+    the second one a step later (reorth 2); checked up to 720 (s = 2) and 1040 (s = 4) columns.
     The solve itself must also meet its FP64 true residual."""
     A, B = stencils.cd2d(64, 64, 10.0), stencils.cd1d(2048, 10.0)
     p = stencils.make_problem("wide", A, B, s, 21, method="bicgstab", tol=1e-14,
                               max_iter=iters)
-    g = gpu_solve(sylv, p, "bicgstab", p.tol, p.max_iter)
+    g = gpu_solve(sylv, p, "bicgstab", p.tol, p.max_iter, reorth=reorth)
     assert g["res"].iters == iters and g["res"].rank_v == 2 * iters * s
     for F in (g["V"], g["W"]):
         assert np.linalg.norm(F.T @ F - np.eye(F.shape[1]), 2) < 1e-12
@@ -264,3 +266,23 @@ def test_second_stream_gives_identical_results(sylv, method):
     assert a[0] == b[0] and a[1] == b[1] and a[2] == b[2]
     for x, y in zip(a[3:], b[3:]):
         assert np.array_equal(x, y)
+
+
+@pytest.mark.parametrize("s", [1, 3])
+def test_lagged_and_same_step_reorthogonalization_agree(sylv, s):
+    """The lagged second Gram-Schmidt pass (reorth 2) and the same-step one (reorth 1) produce
+    the same Arnoldi process up to rounding: the first iterations' scalars agree to 1e-10, and
+    both reach the tolerance with the same solution (within the conditioning times tol)."""
+    A, B = stencils.cd2d(32, 30, 10.0), stencils.cd1d(600, 10.0)
+    p = stencils.make_problem("lag", A, B, s, 41, method="bicgstab", tol=1e-10, max_iter=300)
+    out = []
+    for reorth in (1, 2):
+        g = gpu_solve(sylv, p, "bicgstab", p.tol, p.max_iter, reorth=reorth)
+        assert g["res"].status == sylv.SYLV_OK
+        out.append((g["hist"], g["V"] @ g["X"] @ g["W"].T))
+        g["slv"].close()
+    (h1, X1), (h2, X2) = out
+    for key in ("alpha", "omega", "relres"):
+        a, b = np.asarray(h1[key][:10]), np.asarray(h2[key][:10])
+        assert np.max(np.abs(a - b) / np.abs(b)) < 1e-10, key
+    assert rel(X2, X1) < 1e-6

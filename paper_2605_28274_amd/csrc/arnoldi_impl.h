@@ -432,92 +432,75 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int
 // Two passes over the basis per step instead of three; the arithmetic is classical Gram-Schmidt
 // applied twice with the second pass of each block taken one step later.
 
-// One workgroup per basis: Tw, e (SideState), final column block j-1 of H.
+// One workgroup per basis: Tw, Hw, e and the provisional subdiagonal block Rt of column block
+// j-1 (SideState); dcgs_hcol_pair completes column block j-1 from them.
 template <int S>
 __global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t ldh,
                                                      double closure_tol, const DevState *ds) {
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
-  constexpr int S2 = 2 * S;
+  constexpr int S2 = 2 * S, U4 = 4;
   const int nf = jb * S;  // final columns
   __shared__ double lds[16 * 2 * S * S];
   __shared__ SideState st;
-  __shared__ double Rt[S * S], Hw[S * S];
   double g[2 * S * S];  // a^T a, a^T b
 #pragma unroll
   for (int i = 0; i < 2 * S * S; ++i) g[i] = 0.0;
-  for (int c = threadIdx.x; c < nf; c += TPB) {
-    double av[S], bv[S];
+  for (int c0 = threadIdx.x; c0 < nf; c0 += U4 * TPB) {
+    double av[U4][S], bv[U4][S];
 #pragma unroll
-    for (int t = 0; t < S; ++t) {
-      av[t] = A.coef[c * S2 + t];
-      bv[t] = A.coef[c * S2 + S + t];
+    for (int u = 0; u < U4; ++u) {
+      const int c = c0 + u * TPB;
+      const bool ok = c < nf;
+#pragma unroll
+      for (int t = 0; t < S; ++t) {
+        av[u][t] = ok ? A.coef[c * S2 + t] : 0.0;
+        bv[u][t] = ok ? A.coef[c * S2 + S + t] : 0.0;
+      }
     }
 #pragma unroll
-    for (int p = 0; p < S; ++p)
+    for (int u = 0; u < U4; ++u)
 #pragma unroll
-      for (int q = 0; q < S; ++q) {
-        g[p * S + q] = fma(av[p], av[q], g[p * S + q]);
-        g[S * S + p * S + q] = fma(av[p], bv[q], g[S * S + p * S + q]);
-      }
+      for (int p = 0; p < S; ++p)
+#pragma unroll
+        for (int q = 0; q < S; ++q) {
+          g[p * S + q] = fma(av[u][p], av[u][q], g[p * S + q]);
+          g[S * S + p * S + q] = fma(av[u][p], bv[u][q], g[S * S + p * S + q]);
+        }
   }
   block_sum<2 * S * S>(g, lds);
-  if (threadIdx.x == 0) {
-    double Gw[S * S], cc[S * S];
-    double tr = 0.0;
-    for (int p = 0; p < S; ++p)
-      for (int q = 0; q < S; ++q) {
-        Gw[p * S + q] = A.coef[(nf + p) * S2 + q] - g[p * S + q];
-        cc[p * S + q] = A.coef[(nf + p) * S2 + S + q] - g[S * S + p * S + q];
-      }
-    for (int p = 0; p < S; ++p) tr += A.coef[(nf + p) * S2 + p];
-    if (jb == 0) {  // block 0 is final: V_0 = V~_0
-      for (int i = 0; i < S * S; ++i) st.T1[i] = st.Hs1[i] = (i % (S + 1) == 0) ? 1.0 : 0.0;
-      st.mode = 0;
-    } else {
-      st.ref2 = tr;
-      finish_pass1(&st, S, closure_tol, Gw);
-    }
-    for (int i = 0; i < S * S; ++i) {
-      A.ss->Tw[i] = st.T1[i];
-      Hw[i] = st.Hs1[i];
-    }
-    A.ss->modew = st.mode;
-    // e = Tw^T (c - a^T b)
-    for (int p = 0; p < S; ++p)
-      for (int q = 0; q < S; ++q) {
-        double v = 0.0;
-        for (int t = 0; t < S; ++t) v = fma(st.T1[t * S + p], cc[t * S + q], v);
-        A.ss->Ew[p * S + q] = v;
-      }
-    if (jb > 0)
-      for (int p = 0; p < S; ++p)
-        for (int q = 0; q < S; ++q)
-          Rt[p * S + q] = A.H[(int64_t)(nf + p) * ldh + nf - S + q];
-  }
-  __syncthreads();
-  if (jb == 0) return;
-  // column block j-1: the provisional U'_{j-1} = V~_j Rt = (V a + V_j Hw) Rt
-  for (int c = threadIdx.x; c < nf; c += TPB) {
-    double av[S];
-#pragma unroll
-    for (int t = 0; t < S; ++t) av[t] = A.coef[c * S2 + t];
-#pragma unroll
+  if (threadIdx.x != 0) return;
+  double dd[S * S], cc[S * S], Rt[S * S];
+  for (int p = 0; p < S; ++p)
     for (int q = 0; q < S; ++q) {
-      double v = 0.0;
-#pragma unroll
-      for (int t = 0; t < S; ++t) v = fma(av[t], Rt[t * S + q], v);
-      A.H[(int64_t)c * ldh + nf - S + q] += v;
+      dd[p * S + q] = A.coef[(nf + p) * S2 + q];
+      cc[p * S + q] = A.coef[(nf + p) * S2 + S + q];
+      Rt[p * S + q] = jb > 0 ? A.H[(int64_t)(nf + p) * ldh + nf - S + q] : 0.0;
     }
+  double Gw[S * S], tr = 0.0;
+  for (int i = 0; i < S * S; ++i) {
+    Gw[i] = dd[i] - g[i];
+    cc[i] -= g[S * S + i];
   }
-  if ((int)threadIdx.x < S * S) {
-    const int p = threadIdx.x / S, q = threadIdx.x % S;
-    double v = 0.0;
-#pragma unroll
-    for (int t = 0; t < S; ++t) v = fma(Hw[p * S + t], Rt[t * S + q], v);
-    A.H[(int64_t)(nf + p) * ldh + nf - S + q] = v;
+  for (int p = 0; p < S; ++p) tr += dd[p * S + p];
+  if (jb == 0) {  // block 0 is final: V_0 = V~_0
+    for (int i = 0; i < S * S; ++i) st.T1[i] = st.Hs1[i] = (i % (S + 1) == 0) ? 1.0 : 0.0;
+    st.mode = 0;
+  } else {
+    st.ref2 = tr;
+    finish_pass1(&st, S, closure_tol, Gw);
   }
+  for (int p = 0; p < S; ++p)
+    for (int q = 0; q < S; ++q) {
+      double v = 0.0;  // e = Tw^T (c - a^T b)
+      for (int t = 0; t < S; ++t) v = fma(st.T1[t * S + p], cc[t * S + q], v);
+      A.ss->Ew[p * S + q] = v;
+      A.ss->Tw[p * S + q] = st.T1[p * S + q];
+      A.ss->Hw[p * S + q] = st.Hs1[p * S + q];
+      A.ss->Rt[p * S + q] = Rt[p * S + q];
+    }
+  A.ss->modew = st.mode;
 }
 
 // The second pass of block j and the first pass of U in one pass over V_{0..j-1}: X = V [a b]
@@ -581,13 +564,15 @@ __global__ __launch_bounds__(TPB) void dcgs_update_pair(ArPair P, int jb, const 
   upart_record<S>(A, lb, uv);
 }
 
-// Provisional column block j of H: rows i < (j+1) S, one wave per row: C[i] = ([b; e][i] -
-// H[i, 0:nf] a) Tw (H[i, c] is zero for c < (i/S - 1) S).
+// Column blocks j-1 (final) and j (provisional) of H, one wave per row i < (j+1) S: the
+// provisional U'_{j-1} = V~_j Rt = (V a + V_j Hw) Rt gives H[i, j-1] += a[i] Rt (rows i < j s)
+// and H[j, j-1] = Hw Rt; then C[i] = ([b; e][i] - H[i, 0:nf] a) Tw with the completed column
+// block j-1 (H[i, c] is zero for c < (i/S - 1) S).
 template <int S>
 __global__ __launch_bounds__(TPB) void dcgs_hcol_pair(ArPair P, int jb, int64_t ldh,
                                                       const DevState *ds) {
   if (ds->done) return;
-  constexpr int S2 = 2 * S;
+  constexpr int S2 = 2 * S, U4 = 4;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
@@ -596,13 +581,43 @@ __global__ __launch_bounds__(TPB) void dcgs_hcol_pair(ArPair P, int jb, int64_t 
   if (i >= nrow) return;
   int cs = (i / S - 1) * S;
   cs = cs < 0 ? 0 : cs;
+  const int ce = nf - S;  // columns [ce, nf) are completed below (jb >= 1)
   double acc[S];
 #pragma unroll
   for (int t = 0; t < S; ++t) acc[t] = 0.0;
-  for (int c = cs + lane; c < nf; c += WAVE) {
-    const double h = A.H[(int64_t)i * ldh + c];
+  const int cend = jb > 0 ? ce : nf;
+  for (int c0 = cs + lane; c0 < cend; c0 += U4 * WAVE) {
+    double h[U4], a[U4][S];
 #pragma unroll
-    for (int t = 0; t < S; ++t) acc[t] = fma(h, A.coef[c * S2 + t], acc[t]);
+    for (int u = 0; u < U4; ++u) {
+      const int c = c0 + u * WAVE;
+      const bool ok = c < cend;
+      h[u] = ok ? A.H[(int64_t)i * ldh + c] : 0.0;
+#pragma unroll
+      for (int t = 0; t < S; ++t) a[u][t] = ok ? A.coef[c * S2 + t] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < U4; ++u)
+#pragma unroll
+      for (int t = 0; t < S; ++t) acc[t] = fma(h[u], a[u][t], acc[t]);
+  }
+  if (jb > 0 && lane == 0) {
+    // complete H[i, ce:nf) and add its part of H a
+    double hf[S];
+    for (int q = 0; q < S; ++q) {
+      double v = 0.0;
+      if (i < nf) {
+        v = A.H[(int64_t)i * ldh + ce + q];
+        for (int t = 0; t < S; ++t) v = fma(A.coef[i * S2 + t], A.ss->Rt[t * S + q], v);
+      } else {
+        for (int t = 0; t < S; ++t) v = fma(A.ss->Hw[(i - nf) * S + t], A.ss->Rt[t * S + q], v);
+      }
+      hf[q] = v;
+    }
+    for (int q = 0; q < S; ++q) {
+      A.H[(int64_t)i * ldh + ce + q] = hf[q];
+      for (int t = 0; t < S; ++t) acc[t] = fma(hf[q], A.coef[(ce + q) * S2 + t], acc[t]);
+    }
   }
 #pragma unroll
   for (int t = 0; t < S; ++t) acc[t] = wave_sum(acc[t]);

@@ -40,6 +40,8 @@ struct SideState {
   // lagged reorthogonalization of the provisional block (w = V~_j - V a, V_j = w Tw)
   double Tw[SYLV_MAX_S * SYLV_MAX_S];
   double Ew[SYLV_MAX_S * SYLV_MAX_S];   // V_j^T (M V~_j)
+  double Rt[SYLV_MAX_S * SYLV_MAX_S];   // provisional subdiagonal block of column block j-1
+  double Hw[SYLV_MAX_S * SYLV_MAX_S];   // w = V_j Hw
   int modew;
   int padw_[3];
 };

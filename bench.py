@@ -81,6 +81,12 @@ def main():
                     choices=["c1", "c2", "c3", "c5cg", "c5bi", "batch64"])
     ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--check-every", type=int, default=8,
+                    help="iterations between the host's looks at the convergence flag")
+    ap.add_argument("--streams-solve", type=int, default=0, choices=[0, 1, 2],
+                    help="sylv_options.streams (0 automatic)")
+    ap.add_argument("--reorth", type=int, default=0, choices=[0, 1, 2],
+                    help="sylv_options.reorth (0 automatic)")
     ap.add_argument("--cpu-iters", type=int, default=60)
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
@@ -129,9 +135,10 @@ def main():
                              1 if p.lyapunov else 0, C1.data_ptr(), p.s, C2.data_ptr(), p.s)
     mixed = args.precision == "fp32"
     opts = sylv.default_options(sylv.SYLV_METHOD_CG if cg else sylv.SYLV_METHOD_BICGSTAB,
-                                p.max_iter, check_every=8,
+                                p.max_iter, check_every=args.check_every,
                                 precision=sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64,
-                                refine_max=args.refine, refine_max_iter=100)
+                                refine_max=args.refine, refine_max_iter=100,
+                                streams=args.streams_solve, reorth=args.reorth)
     ws = torch.empty(sylv.sylv_workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
     rmax = (p.max_iter + 1 if cg else 2 * p.max_iter + 1) * p.s
     if args.refine > 0:  # the summed iterate stacks the corrections' bases

@@ -62,10 +62,11 @@ struct ArPair {
 
 // The basis this workgroup works on (selected without dynamic indexing of the kernel argument)
 // and the workgroup's index within that basis' range.
-__device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd) {
-  sd = (P.nsides > 1 && (int)blockIdx.x >= P.s[1].b0) ? 1 : 0;
+__device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd,
+                                          int bid = (int)blockIdx.x) {
+  sd = (P.nsides > 1 && bid >= P.s[1].b0) ? 1 : 0;
   const ArSide A = sd ? P.s[1] : P.s[0];
-  lb = (int)blockIdx.x - A.b0;
+  lb = bid - A.b0;
   return A;
 }
 
@@ -426,14 +427,14 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int
 // (Cholesky, or the closure / deflation rule of the first-pass QR), the final column block j-1
 // of H from the provisional one, and e = V_j^T U = Tw^T (c - a^T b); then, in one more pass
 // (dcgs_update_pair), the final rows of V_j and U' = (U - V_{0..j-1} b - V_j e) Tw = M V_j -
-// V_{0..j} C, the first-pass projection of the new direction; dcgs_hcol_pair writes the
+// V_{0..j} C, the first-pass projection of the new direction; dcgs_hcol_body writes the
 // provisional column block j of H, C = ([b; e] - H a) Tw (M V a = V H a by the Arnoldi relation
 // of the earlier columns); the QR of U' (qr2_pair, final_pair) gives the provisional V~_{j+1}.
 // Two passes over the basis per step instead of three; the arithmetic is classical Gram-Schmidt
 // applied twice with the second pass of each block taken one step later.
 
 // One workgroup per basis: Tw, Hw, e and the provisional subdiagonal block Rt of column block
-// j-1 (SideState); dcgs_hcol_pair completes column block j-1 from them.
+// j-1 (SideState); dcgs_hcol_body completes column block j-1 from them.
 template <int S>
 __global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t ldh,
                                                      double closure_tol, const DevState *ds) {
@@ -569,12 +570,10 @@ __global__ __launch_bounds__(TPB) void dcgs_update_pair(ArPair P, int jb, const 
 // and H[j, j-1] = Hw Rt; then C[i] = ([b; e][i] - H[i, 0:nf] a) Tw with the completed column
 // block j-1 (H[i, c] is zero for c < (i/S - 1) S).
 template <int S>
-__global__ __launch_bounds__(TPB) void dcgs_hcol_pair(ArPair P, int jb, int64_t ldh,
-                                                      const DevState *ds) {
-  if (ds->done) return;
+__device__ __forceinline__ void dcgs_hcol_body(const ArPair &P, int bid, int jb, int64_t ldh) {
   constexpr int S2 = 2 * S, U4 = 4;
   int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
+  const ArSide A = side_of(P, lb, sd, bid);
   const int lane = threadIdx.x & (WAVE - 1), w = threadIdx.x / WAVE;
   const int nf = jb * S, nrow = nf + S;
   const int i = lb * (TPB / WAVE) + w;
@@ -844,10 +843,9 @@ __device__ __forceinline__ void sum_records(const double *p, int n, double (&out
 // workgroup forms the same factors; workgroup 0 records them), then partials of
 // G2 = (U T1)^T (U T1).
 template <int S>
-__global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, const DevState *ds) {
-  if (ds->done) return;
+__device__ __forceinline__ void qr2_body(const ArPair &P, int bid, double closure_tol) {
   int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
+  const ArSide A = side_of(P, lb, sd, bid);
   __shared__ SideState st;
   double ref[1], G1[S * S];
   sum_records<1>(A.aux, A.nb_spmm, ref);
@@ -892,6 +890,23 @@ __global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, co
   if (threadIdx.x == 0)
 #pragma unroll
     for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + A.nb_upd * S * S + lb * S * S + i] = g[i];
+}
+
+template <int S>
+__global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, const DevState *ds) {
+  if (ds->done) return;
+  qr2_body<S>(P, (int)blockIdx.x, closure_tol);
+}
+
+// The lagged step's last small kernels in one launch: workgroups [0, nq) run the first QR pass
+// of U' (Pq ranges), the rest the column blocks j-1 and j of H (Ph ranges).
+template <int S>
+__global__ __launch_bounds__(TPB) void dcgs_tail_pair(ArPair Pq, ArPair Ph, int nq, int jb,
+                                                      int64_t ldh, double closure_tol,
+                                                      const DevState *ds) {
+  if (ds->done) return;
+  if ((int)blockIdx.x < nq) qr2_body<S>(Pq, (int)blockIdx.x, closure_tol);
+  else dcgs_hcol_body<S>(Ph, (int)blockIdx.x - nq, jb, ldh);
 }
 
 // Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
@@ -1374,17 +1389,18 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   set_ranges(P, cdiv(rows0, UROWS), sw ? cdiv(rows1, UROWS) : 0);
   dcgs_update_pair<S><<<total_blocks(P), TPB, lds, st>>>(P, jb, ds);
   HIPOK(hipGetLastError());
-  // provisional column block j of H
-  const int64_t hw = cdiv(ncols, TPB / WAVE);
-  set_ranges(P, hw, sw ? hw : 0);
-  dcgs_hcol_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
-  HIPOK(hipGetLastError());
   prof_end(sc, FAM_UPDATE, bytes_u, 2.0 * total * nf * S2, st);
 
-  // QR of U' and the provisional block j+1
+  // first QR pass of U' and, in the same launch, column blocks j-1 and j of H; then the
+  // second pass and the provisional block j+1
+  ArPair Ph = P;
+  const int64_t hw = cdiv(ncols, TPB / WAVE);
+  set_ranges(Ph, hw, sw ? hw : 0);
   set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
   prof_begin(sc, st);
-  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+  const int nq = (int)total_blocks(P);
+  dcgs_tail_pair<S><<<(unsigned)nq + total_blocks(Ph), TPB, 0, st>>>(P, Ph, nq, jb, ldh,
+                                                                      closure_tol, ds);
   HIPOK(hipGetLastError());
   final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
   HIPOK(hipGetLastError());

@@ -33,6 +33,7 @@ constexpr int TPB = 256;
 constexpr int NG = 8;          // thread groups splitting the chunk sum in gram_reduce_pair
 constexpr int OPB = TPB / NG;  // outputs per gram_reduce_pair workgroup
 constexpr int GRAM_LOADS = 16; // 8-byte basis loads in flight per thread in gram_part_pair
+constexpr int GRAM_UCH = 128;  // right-hand rows staged in LDS at a time by gram_part_pair
 
 struct ArSide {
   int64_t rows, nnz;
@@ -124,8 +125,9 @@ struct Pack8<float> {
 // threads form G = TPB / CW row groups of CW threads (CW a power of two fitted to the width):
 // thread (g, l) owns the 8-byte column groups l + CW q (q < nq <= NQ; one double or two floats
 // each) and takes the rows g, g + G, ... of the chunk, RU rows per step, so that NQ RU loads are
-// in flight; a narrow basis thus still spreads its chunk over every thread. The row-group sums
-// are added in a fixed order through LDS. part[lb][c][t]; column groups past the width load
+// in flight; a narrow basis thus still spreads its chunk over every thread. The right-hand rows
+// pass through LDS (GRAM_UCH rows at a time, read as broadcasts). The row-group sums are added
+// in a fixed order through LDS. part[lb][c][t]; column groups past the width load
 // group 0 and rows past the chunk load its first row (both in bounds), neither is counted.
 // DUAL: the right-hand side is [pin, U] (S / 2 columns each: the provisional block and M times
 // it, for the lagged step), else U (S columns).
@@ -136,10 +138,10 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int c
   typedef Pack8<T> PK;
   typedef typename PK::type V8;
   constexpr int E = PK::N;
-  // rows per step: GRAM_LOADS basis loads in flight, at most 16 U values held per thread
-  constexpr int RU0 = NQ >= GRAM_LOADS ? 1 : GRAM_LOADS / NQ;
-  constexpr int RU = RU0 * S > 16 ? (16 / S > 0 ? 16 / S : 1) : RU0;
+  // rows per step: GRAM_LOADS basis loads in flight; the right-hand rows come from LDS
+  constexpr int RU = NQ >= GRAM_LOADS ? 1 : (GRAM_LOADS / NQ > 8 ? 8 : GRAM_LOADS / NQ);
   extern __shared__ double gsum[];  // TPB * E * S doubles (several row groups only)
+  __shared__ double Us[GRAM_UCH * S];
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   const int CW = 1 << cw_log2, G = TPB >> cw_log2;
@@ -164,39 +166,48 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int c
       for (int e = 0; e < E; ++e)
 #pragma unroll
         for (int t = 0; t < S; ++t) acc[q][e][t] = 0.0;
-    for (int64_t r = r0 + g; r < r1; r += (int64_t)RU * G) {
-      V8 v[RU][NQ];
-      double u[RU][S];
+    for (int64_t rb = r0; rb < r1; rb += GRAM_UCH) {
+      const int nr = (int)((r1 - rb < GRAM_UCH) ? r1 - rb : GRAM_UCH);
+      __syncthreads();  // the previous rows' readers are done
+      for (int e = threadIdx.x; e < nr * S; e += TPB) {
+        const int64_t row = rb + e / S;
+        const int t = e % S;
+        double uv;
+        if (DUAL && t < S / 2) uv = (double)static_cast<const T *>(A.pin)[row * (S / 2) + t];
+        else uv = DUAL ? A.U[row * (S / 2) + t - S / 2] : A.U[row * S + t];
+        Us[e] = uv;
+      }
+      __syncthreads();
+      const T *vb = basis + rb * A.ldb;
+      for (int rr = g; rr < nr; rr += RU * G) {
+        V8 v[RU][NQ];
 #pragma unroll
-      for (int h = 0; h < RU; ++h) {
-        const int64_t row = r + (int64_t)h * G;
-        const bool ok = row < r1;
-        const T *vr = basis + (ok ? row : r0) * A.ldb;
+        for (int h = 0; h < RU; ++h) {
+          const int rl = rr + h * G;
+          const T *vr = vb + (int64_t)(rl < nr ? rl : 0) * A.ldb;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q)
-          v[h][q] = (q < nq) ? *reinterpret_cast<const V8 *>(vr + coff[q]) : PK::zero();
+          for (int q = 0; q < NQ; ++q)
+            v[h][q] = (q < nq) ? *reinterpret_cast<const V8 *>(vr + coff[q]) : PK::zero();
+        }
 #pragma unroll
-        for (int t = 0; t < S; ++t) {
-          double uv = 0.0;
-          if (ok) {
-            if (DUAL && t < S / 2) uv = (double)static_cast<const T *>(A.pin)[row * (S / 2) + t];
-            else uv = DUAL ? A.U[row * (S / 2) + t - S / 2] : A.U[row * S + t];
+        for (int h = 0; h < RU; ++h) {
+          const int rl = rr + h * G;
+          const bool ok = rl < nr;
+          double u[S];
+#pragma unroll
+          for (int t = 0; t < S; ++t) u[t] = ok ? Us[rl * S + t] : 0.0;
+#pragma unroll
+          for (int q = 0; q < NQ; ++q) {
+            if (q >= nq) continue;
+            double x[E];
+            PK::get(v[h][q], x);
+#pragma unroll
+            for (int e = 0; e < E; ++e)
+#pragma unroll
+              for (int t = 0; t < S; ++t) acc[q][e][t] = fma(x[e], u[t], acc[q][e][t]);
           }
-          u[h][t] = uv;
         }
       }
-#pragma unroll
-      for (int h = 0; h < RU; ++h)
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) {
-          if (q >= nq) continue;
-          double x[E];
-          PK::get(v[h][q], x);
-#pragma unroll
-          for (int e = 0; e < E; ++e)
-#pragma unroll
-            for (int t = 0; t < S; ++t) acc[q][e][t] = fma(x[e], u[h][t], acc[q][e][t]);
-        }
     }
     if (G > 1) {
       // row groups in order: group 0 adds the others' sums (one q at a time through LDS)

@@ -71,6 +71,11 @@ __device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd,
   return A;
 }
 
+// Rows a thread handles at once in the SpMM kernels (sliced ELLPACK): more loads in flight for
+// narrow blocks.
+template <int S>
+constexpr int spmm_nr() { return S == 1 ? 4 : S == 2 ? 2 : 1; }
+
 template <int S, typename T>
 __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   if (ds->done) return;
@@ -78,20 +83,40 @@ __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
   const ArSide A = side_of(P, lb, sd);
   double red[1] = {0.0};
   // row tiles lb, lb + nb, ... (at most ROW_WG workgroups per basis, so few partials)
-  for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
-    const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
-    double acc[S];
-    const int64_t r = r0 + threadIdx.x;
-    if (A.sell.ci) {
-      if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
-    } else {
-      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
-    }
-    if (r < r1) {
+  if (A.sell.ci) {
+    constexpr int NR = spmm_nr<S>();
+    const int64_t step = (int64_t)A.nb * TPB;
+    for (int64_t r0 = (int64_t)lb * TPB + threadIdx.x; r0 < A.rows; r0 += NR * step) {
+      int64_t r[NR];
+      bool ok[NR];
 #pragma unroll
-      for (int t = 0; t < S; ++t) {
-        A.U[r * S + t] = acc[t];
-        red[0] = fma(acc[t], acc[t], red[0]);
+      for (int i = 0; i < NR; ++i) {
+        r[i] = r0 + i * step;
+        ok[i] = r[i] < A.rows;
+      }
+      double acc[NR][S];
+      sell_rows<NR, S>(A.sell, r, ok, static_cast<const T *>(A.pin), S, acc);
+#pragma unroll
+      for (int i = 0; i < NR; ++i)
+        if (ok[i])
+#pragma unroll
+          for (int t = 0; t < S; ++t) {
+            A.U[r[i] * S + t] = acc[i][t];
+            red[0] = fma(acc[i][t], acc[i][t], red[0]);
+          }
+    }
+  } else {
+    for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
+      const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+      double acc[S];
+      const int64_t r = r0 + threadIdx.x;
+      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+      if (r < r1) {
+#pragma unroll
+        for (int t = 0; t < S; ++t) {
+          A.U[r * S + t] = acc[t];
+          red[0] = fma(acc[t], acc[t], red[0]);
+        }
       }
     }
   }
@@ -991,36 +1016,53 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
   double red[S * S + 1];
 #pragma unroll
   for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
-  for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
-    const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
-    const int64_t r = r0 + threadIdx.x;
-    double acc[S];
-    if (A.sell.ci) {
-      if (r < r1) sell_row<S>(A.sell, r, static_cast<const T *>(A.pin), S, acc);
-    } else {
-      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+  // one row's local three-term update and its partials
+  auto finish = [&](int64_t r, double (&acc)[S]) {
+#pragma unroll
+    for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
+    if (jb > 0) {
+      const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused)
+#pragma unroll
+      for (int u = 0; u < S; ++u) {
+        const double vu = (double)vp[u];
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
+      }
     }
-    if (r < r1) {
+    const T *vj = static_cast<const T *>(A.pin) + r * S;
 #pragma unroll
-      for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
-      if (jb > 0) {
-        const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused)
+    for (int a = 0; a < S; ++a) {
+      const double va = (double)vj[a];
 #pragma unroll
-        for (int u = 0; u < S; ++u) {
-          const double vu = (double)vp[u];
+      for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
+    }
 #pragma unroll
-          for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
-        }
+    for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
+  };
+  if (A.sell.ci) {
+    constexpr int NR = spmm_nr<S>();
+    const int64_t step = (int64_t)A.nb * TPB;
+    for (int64_t r0 = (int64_t)lb * TPB + threadIdx.x; r0 < A.rows; r0 += NR * step) {
+      int64_t r[NR];
+      bool ok[NR];
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        r[i] = r0 + i * step;
+        ok[i] = r[i] < A.rows;
       }
-      const T *vj = static_cast<const T *>(A.pin) + r * S;
+      double acc[NR][S];
+      sell_rows<NR, S>(A.sell, r, ok, static_cast<const T *>(A.pin), S, acc);
 #pragma unroll
-      for (int a = 0; a < S; ++a) {
-        const double va = (double)vj[a];
-#pragma unroll
-        for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
-      }
-#pragma unroll
-      for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
+      for (int i = 0; i < NR; ++i)
+        if (ok[i]) finish(r[i], acc[i]);
+    }
+  } else {
+    for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
+      const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
+      const int64_t r = r0 + threadIdx.x;
+      double acc[S];
+      spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
+      if (r < r1) finish(r, acc);
     }
   }
   __shared__ double lds[16 * (S * S + 1)];

@@ -296,6 +296,55 @@ __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
   }
 }
 
+// NR rows at once (one per entry of r; rows with ok false yield zeros): the slice headers, then
+// the indices and values, then the gathers of all rows are issued together, so a thread keeps
+// NR times the loads of sell_row in flight.
+template <int NR, int S, typename T = double>
+__device__ __forceinline__ void sell_rows(const SellMat &M, const int64_t (&r)[NR],
+                                          const bool (&ok)[NR], const T *__restrict__ X,
+                                          int64_t ldx, double (&acc)[NR][S]) {
+  int w[NR];
+  int64_t base[NR];
+  int wmax = 0;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int64_t rr = ok[i] ? r[i] : 0;
+    w[i] = ok[i] ? M.width[rr >> 6] : 0;
+    base[i] = M.off[rr >> 6] + (rr & 63);
+    wmax = w[i] > wmax ? w[i] : wmax;
+#pragma unroll
+    for (int t = 0; t < S; ++t) acc[i][t] = 0.0;
+  }
+  for (int q0 = 0; q0 < wmax; q0 += 8) {
+    int c[NR][8];
+    double a[NR][8];
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = q0 + u < w[i];
+        c[i][u] = in ? M.ci[base[i] + 64 * (q0 + u)] : 0;
+        a[i][u] = in ? M.val[base[i] + 64 * (q0 + u)] : 0.0;
+      }
+    double x[NR][8][S];
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const bool in = q0 + u < w[i];
+#pragma unroll
+        for (int t = 0; t < S; ++t)
+          x[i][u][t] = in ? (double)X[(int64_t)c[i][u] * ldx + t] : 0.0;
+      }
+#pragma unroll
+    for (int i = 0; i < NR; ++i)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+#pragma unroll
+        for (int t = 0; t < S; ++t) acc[i][t] = fma(a[i][u], x[i][u][t], acc[i][t]);
+  }
+}
+
 // Builds the SELL copy of a CSR matrix into buf (sell_bytes(rows, nnz) bytes). Returns
 // SYLV_ERR_WORKSPACE when the padded size exceeds the reserved capacity (the caller then keeps
 // using CSR). Synchronizes the stream.

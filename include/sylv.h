@@ -232,7 +232,10 @@ const char *sylv_kernel_family_name(int family);
 
 /* Y = A X for CSR A (rows x rows) and a row-major panel X (rows x s, leading dimension ldx),
  * Y rows x s with leading dimension ldy; 1 <= s <= 8. The CSR SpMM of the block Lanczos /
- * Arnoldi step (eq. (3.8)). */
+ * Arnoldi step (eq. (3.8)). Unlike the other calls, sylv_spmm and sylv_sell_spmm only enqueue
+ * their kernel on `stream` and return without waiting, so that products issued back to back
+ * run back to back; 0 means the launch was accepted, and the caller orders later work on the
+ * same stream or synchronizes before reading Y on the host. */
 int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double *Y,
               int64_t ldy, void *stream);
 

@@ -1377,10 +1377,7 @@ int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double
   if (!A || s < 1 || s > SYLV_MAX_S || ldx < s || ldy < s || !X || !Y) return SYLV_ERR_INVALID;
   if (check_csr_header(*A, A->rows)) return SYLV_ERR_INVALID;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
-  int e = launch_spmm((int)s, A->rows, A->row_ptr, A->col_idx, A->values, X, ldx, Y, ldy, st);
-  if (e) return e;
-  HIPOK(hipStreamSynchronize(st));
-  return 0;
+  return launch_spmm((int)s, A->rows, A->row_ptr, A->col_idx, A->values, X, ldx, Y, ldy, st);
 }
 
 int sylv_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t a_rs,
@@ -1414,10 +1411,7 @@ int sylv_sell_spmm(const sylv_csr *A, const void *sell, int64_t s, const double 
   if (A->rows <= 0 || check_csr_header(*A, A->rows)) return SYLV_ERR_INVALID;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   const SellMat M = sell_view(A->rows, A->nnz, const_cast<void *>(sell));
-  int e = launch_sell_spmm((int)s, M, X, ldx, Y, ldy, st);
-  if (e) return e;
-  HIPOK(hipStreamSynchronize(st));
-  return 0;
+  return launch_sell_spmm((int)s, M, X, ldx, Y, ldy, st);
 }
 
 size_t sylv_csr_transpose_scratch_bytes(int64_t rows) { return csr_transpose_scratch(rows); }

@@ -15,6 +15,7 @@
 namespace {
 
 constexpr int BM = 64, BN = 64, BK = 32;
+constexpr int GRAM_STREAM_WG = 512;  // stream-K Gram: two workgroups per CU
 constexpr int LD = BM + 1;  // +1 pad: fewer bank conflicts on the transposed fills
 static_assert(BM == BN, "one LDS slab shape serves both operands");
 
@@ -428,6 +429,133 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t M, int64_t N, 
   }
 }
 
+// ---- stream-K form of the tall-skinny Gram (launches with many output tiles) ----
+// Visiting order of the tiles: groups of eight tile rows, column by column inside a group (the
+// lower form walks the triangle I >= J the same way, its diagonal block last), so the
+// workgroups that run at one time on one XCD share a few row and column panels in its L2.
+struct GramSeq {
+  int TM, TN, lower;
+  __host__ __device__ int64_t count() const {
+    return lower ? (int64_t)TM * (TM + 1) / 2 : (int64_t)TM * TN;
+  }
+  __device__ void tile(int64_t t, int &I, int &J) const {
+    int g0;  // first tile row of the group; groups start at the same positions as rows do
+    int64_t idx;
+    if (lower) {
+      int r, c;
+      tri_tile(t, r, c);
+      g0 = r & ~7;
+      idx = t - (int64_t)g0 * (g0 + 1) / 2;
+    } else {
+      g0 = (int)(t / ((int64_t)8 * TN)) * 8;
+      idx = t - (int64_t)g0 * TN;
+    }
+    const int h = TM - g0 < 8 ? TM - g0 : 8;
+    const int64_t full = (int64_t)(lower ? g0 : TN) * h;
+    if (idx < full) {
+      J = (int)(idx / h);
+      I = g0 + (int)(idx % h);
+      return;
+    }
+    // lower form, diagonal block: column g0 + d holds rows g0 + d .. g0 + h - 1
+    int64_t e = idx - full;
+    int d = 0;
+    while (e >= h - d) {
+      e -= h - d;
+      ++d;
+    }
+    J = g0 + d;
+    I = J + (int)e;
+  }
+};
+
+// The slab sequences of all tiles (nsl slabs each, the last one zero-filled past K when
+// K % BK != 0) are concatenated in visiting order and cut into chunks of c slabs, chunk w for
+// workgroup w; chunks map to XCDs in contiguous eighths. A tile that lies inside one chunk goes
+// to C directly (C = acc, or C += acc when beta != 0); a tile cut by chunk boundaries leaves its
+// piece of chunk w in partial slot 2w (the chunk's first tile) or 2w + 1 (its last tile), and
+// gram_stream_fix_kernel sums the pieces in chunk order. Every workgroup does the same
+// matrix-core work, whatever the number of tiles.
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256, 2) void gram_stream_kernel(
+    const GramSeq sq, int64_t M, int64_t N, int64_t K, const TA *__restrict__ A, int64_t lda,
+    const TB *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
+    int64_t nsl, int64_t c, int nchunks, double *__restrict__ part) {
+  const int per = (int)(gridDim.x >> 3);
+  const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  if (w >= nchunks) return;
+  __shared__ Smem sm;
+  const int64_t total = sq.count() * nsl, nfull = K / BK;
+  const int64_t c0 = (int64_t)w * c, c1 = (c0 + c < total) ? c0 + c : total;
+  const int wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  for (int64_t pos = c0; pos < c1;) {
+    const int64_t t = pos / nsl, ts = t * nsl;
+    const int64_t a = pos - ts, b = ((c1 < ts + nsl) ? c1 : ts + nsl) - ts;
+    int I, J;
+    sq.tile(t, I, J);
+    const int64_t i0 = (int64_t)I * BM, j0 = (int64_t)J * BN;
+    WaveAcc acc;
+    zero_acc(acc);
+    const int64_t bf = b < nfull ? b : nfull;
+    if (bf > a)
+      pipelined<true, false, TA, TB>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, a * BK, bf * BK);
+    if (b > nfull) {
+      // the last K % BK rows, zero-filled past K
+      const int64_t kb = nfull * BK;
+      __syncthreads();
+      for (int e = threadIdx.x; e < BK * BM; e += 256) {
+        const int kk = e / BM, ii = e % BM;
+        sm.As[0][kk][ii] = (kb + kk < K) ? (double)A[(kb + kk) * lda + i0 + ii] : 0.0;
+        sm.Bs[0][kk][ii] = (kb + kk < K) ? (double)B[(kb + kk) * ldb + j0 + ii] : 0.0;
+      }
+      __syncthreads();
+      mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+    }
+    if (a == 0 && b == nsl) {
+      for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
+        const int64_t gi = i0 + ii, gj = j0 + jj;
+        if (gi < M && gj < N) {
+          double *cp = C + gi * ldc + gj;
+          *cp = (beta == 0.0) ? v : *cp + v;
+        }
+      });
+    } else {
+      double *pt = part + (size_t)(2 * w + (pos == c0 ? 0 : 1)) * (BM * BN);
+      for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });
+    }
+    pos = ts + b;
+  }
+}
+
+// The tiles cut by chunk boundaries: boundary wb (between chunks wb and wb + 1) handles the
+// tile it falls in unless an earlier boundary falls in the same tile; 16 workgroups per
+// boundary, one element per thread.
+__global__ __launch_bounds__(256) void gram_stream_fix_kernel(const GramSeq sq, int64_t M,
+                                                              int64_t N, int64_t nsl, int64_t c,
+                                                              const double *__restrict__ part,
+                                                              double beta, double *__restrict__ C,
+                                                              int64_t ldc) {
+  const int wb = (int)(blockIdx.x / 16), sub = (int)(blockIdx.x % 16);
+  const int64_t pb = (int64_t)(wb + 1) * c, total = sq.count() * nsl;
+  if (pb >= total || pb % nsl == 0) return;
+  const int64_t t = pb / nsl, ts = t * nsl;
+  if ((int64_t)wb * c > ts) return;
+  const int w0 = (int)(ts / c), w1 = (int)((ts + nsl - 1) / c);
+  const int e = sub * 256 + threadIdx.x;
+  double v = 0.0;
+  for (int w = w0; w <= w1; ++w) {
+    const int slot = 2 * w + ((int64_t)w * c / nsl == t ? 0 : 1);
+    v += part[(size_t)slot * (BM * BN) + e];
+  }
+  int I, J;
+  sq.tile(t, I, J);
+  const int64_t gi = (int64_t)I * BM + e / BN, gj = (int64_t)J * BN + e % BN;
+  if (gi < M && gj < N) {
+    double *cp = C + gi * ldc + gj;
+    *cp = (beta == 0.0) ? v : *cp + v;
+  }
+}
+
 // C[i][j] = C[j][i] for i < j < M (upper from lower).
 __global__ __launch_bounds__(256) void mirror_kernel(int64_t M, double *__restrict__ C,
                                                      int64_t ldc) {
@@ -589,6 +717,32 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
   if (lda < TM * BM || ldb < TN * BN || lda % 8 || ldb % 8) return SYLV_ERR_INVALID;
   if (K <= 0) return 0;
   const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
+  // many tiles: stream-K over 512 workgroups (two per CU), when the partial slots fit
+  if (part && tiles >= 64) {
+    const GramSeq sq{(int)TM, (int)TN, lower ? 1 : 0};
+    const int64_t nsl = (K + BK - 1) / BK, total = tiles * nsl;
+    const int64_t c = std::max<int64_t>((total + GRAM_STREAM_WG - 1) / GRAM_STREAM_WG, 4);
+    const int64_t nchunks = (total + c - 1) / c;
+    if ((size_t)(2 * nchunks) * (BM * BN) <= part_cap) {
+      const unsigned grid = (unsigned)((nchunks + 7) / 8 * 8);
+#define GRAM_SK(TA, TB)                                                                        \
+  gram_stream_kernel<TA, TB><<<grid, 256, 0, st>>>(sq, M, N, K, static_cast<const TA *>(A), lda, \
+                                                   static_cast<const TB *>(B), ldb, beta, C, ldc, \
+                                                   nsl, c, (int)nchunks, part)
+      if (a_fp32 && b_fp32) GRAM_SK(float, float);
+      else if (a_fp32) GRAM_SK(float, double);
+      else if (b_fp32) GRAM_SK(double, float);
+      else GRAM_SK(double, double);
+#undef GRAM_SK
+      HIPOK(hipGetLastError());
+      if (nchunks > 1) {
+        gram_stream_fix_kernel<<<(unsigned)(nchunks - 1) * 16, 256, 0, st>>>(sq, M, N, nsl, c,
+                                                                             part, beta, C, ldc);
+        HIPOK(hipGetLastError());
+      }
+      return 0;
+    }
+  }
   // few tiles over a long K: split K so that about 512 workgroups run (partials in part)
   int64_t nk = 1;
   if (part && tiles < 64 && K >= 4 * 1024) {

@@ -116,6 +116,23 @@ def test_sell_spmm_stencils(sylv, s):
     _sell_case(sylv, stencils.cd3d(16, 8, 9, 10.0), s)
 
 
+@pytest.mark.parametrize("grid,s", [("2d1024", 1), ("3d64", 4)])
+def test_sell_spmm_chained_full_size(sylv, grid, s):
+    # the operators the bandwidth figure is measured on, at full size; three products issued
+    # back to back on one stream without waiting in between (the call only enqueues)
+    M = stencils.cd2d(1024, 1024, 0.0) if grid == "2d1024" else stencils.cd3d(64, 64, 64, 10.0)
+    rp, ci, va = sylv.csr_tensors(M)
+    csr = sylv.make_csr(M.shape[0], rp, ci, va)
+    buf = torch.empty(sylv.sylv_sell_bytes(csr), dtype=torch.uint8, device="cuda")
+    sylv.sylv_sell_build(csr, buf)
+    X = np.random.default_rng(5).standard_normal((M.shape[0], s))
+    d = [_dev(X)] + [torch.empty_like(_dev(X)) for _ in range(3)]
+    for k in range(3):
+        sylv.sylv_sell_spmm(csr, buf, s, d[k], d[k + 1])
+    ref = M @ (M @ (M @ X))
+    assert np.max(np.abs(d[3].cpu().numpy() - ref)) <= 1e-13 * np.abs(ref).max()
+
+
 def _sell_fits(M):
     # documented rule: padded size (64 x slice max row length, summed) <= nnz + nnz/4 + 64 slices
     n = M.shape[0]

@@ -125,6 +125,29 @@ def test_lyapunov_cg_and_bicgstab(sylv):
         assert rel(Xg, Vo @ Xo @ Wo.T) < 1e-5
 
 
+@pytest.mark.parametrize("case", ["lyap_cg", "sylv_bicgstab"])
+def test_residual_grams_with_many_tiles(sylv, case):
+    # Unconverged runs whose stacked residual factors span hundreds of columns, so the residual
+    # Grams run in their many-tile (stream-K) form: symmetric ones for the shared Lyapunov pass,
+    # rectangular ones for a Sylvester pair. The Gram-trace residual must match a dense
+    # evaluation of the same iterate.
+    # 1D operators converge slowly, so the residual stays far above rounding level
+    if case == "lyap_cg":
+        A = stencils.cd1d(3000, 0.0)
+        p = stencils.make_problem("ly", A, None, 2, 23, lyapunov=True, method="cg")
+        g = gpu_solve(sylv, p, "cg", 1e-12, 300)
+    else:
+        A, B = stencils.cd1d(2000, 5.0), stencils.cd1d(1500, 5.0)
+        p = stencils.make_problem("sy", A, B, 2, 29, method="bicgstab")
+        g = gpu_solve(sylv, p, "bicgstab", 1e-12, 150)
+    assert g["res"].status == sylv.SYLV_NOT_CONVERGED
+    assert g["V"].shape[1] >= 600
+    Xg = g["V"] @ g["X"] @ g["W"].T
+    _, rr = g["slv"].residual_norm()
+    dr = dense_rel_residual(p, Xg)
+    assert abs(rr - dr) <= 1e-6 * dr
+
+
 def test_breakdowns(sylv):
     A = stencils._canonical(sp.csr_matrix(np.diag([1.0, -2.0, 0.5, 1.0])))
     B = stencils._canonical(sp.csr_matrix(np.diag([0.1, 0.2])))

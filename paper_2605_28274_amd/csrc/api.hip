@@ -1177,6 +1177,8 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
   int e = begin_solve(c, tol, max_iter, SYLV_METHOD_CG);
   if (e) return e;
   const hipStream_t ks = c->kst, cs = c->st;
+  // Lyapunov (G = H, C2 = C1): every core is symmetric (Section 4.3)
+  const bool sym = L.lyap != 0;
   if ((e = join(c, cs, ks))) return e;  // the Krylov stream sees the solve's set-up
   for (int k = 0; k < max_iter; ++k) {
     const int p = (k + 1) * s;
@@ -1191,19 +1193,23 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
       HIPOK(hipEventRecord(c->ev_k[0], ks));
       HIPOK(hipStreamWaitEvent(cs, c->ev_k[0], 0));
     }
-    // Q_k (step 6) and alpha_k (step 7)
-    const double q2 = (double)(p + s) * (p + s);
+    // P_k = R_k + beta_{k-1} P_{k-1} (step 14 of the previous iteration; P_0 = R_0 with
+    // beta = 0) into the other P buffer, with <P_k, Q_k> (steps 6-7); the Q buffer serves as
+    // the second P buffer. Symmetric cores store the lower triangle only.
+    const double q2 = (double)(p + s) * (p + s), half = sym ? 0.5 : 1.0;
+    double *Pprev = (k & 1) ? c->Q : c->P, *Pk = (k & 1) ? c->P : c->Q;
     prof_begin(c->sc, c->st);
-    if ((e = launch_cg_core(s, p, c->H, c->G, c->P, c->Q, L.ldc, c->scc, c->ds, c->st)))
+    if ((e = launch_cg_pq(s, p, sym, c->H, c->G, c->R, Pprev, Pk, L.ldc, c->scc, c->ds, c->st)))
       return e;
-    prof_end(c->sc, FAM_CORE_BAND, 8.0 * ((double)p * p + q2) + 2 * 8.0 * 3 * s * (p + s),
-             2.0 * 2.0 * 3.0 * s * (double)p * (p + s), c->st);
-    // X, R updates, stopping test, rho, beta, P update (steps 8-14)
+    prof_end(c->sc, FAM_CORE_BAND, half * 8.0 * 3.0 * p * p,
+             half * 2.0 * 2.0 * 3.0 * s * q2, c->st);
+    // alpha, X and R updates (steps 7-9), stopping test, rho and beta (steps 10-13)
     prof_begin(c->sc, c->st);
-    if ((e = launch_cg_update(s, p, c->X, c->R, c->P, c->Q, L.ldc, c->scc, c->ds, c->hist, k,
-                              max_iter, c->st)))
+    if ((e = launch_cg_xr(s, p, sym, c->H, c->G, Pk, c->X, c->R, L.ldc, c->scc, c->ds, c->hist,
+                          k, max_iter, c->st)))
       return e;
-    prof_end(c->sc, FAM_CORE_ELEM, 8.0 * 9.0 * q2, 8.0 * q2, c->st);
+    prof_end(c->sc, FAM_CORE_ELEM, half * 8.0 * (3.0 * p * p + 2.0 * q2),
+             half * (2.0 * 2.0 * 3.0 * s * q2 + 4.0 * q2), c->st);
     if (ks != cs) HIPOK(hipEventRecord(c->ev_c[k % 3], cs));
     if ((k + 1) % c->check_every == 0 && k + 1 < max_iter) {
       if ((e = read_state(c))) return e;
@@ -1211,6 +1217,10 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
     }
   }
   if ((e = join(c, ks, cs))) return e;
+  // the upper triangle of the symmetric solution core from its lower one
+  if (sym && (e = launch_mirror(std::min<int64_t>(L.ldc, (int64_t)(max_iter + 1) * s), c->X,
+                                L.ldc, c->st)))
+    return e;
   if (hipStreamSynchronize(c->st) != hipSuccess) return SYLV_ERR_HIP;
   const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   return end_solve(c, max_iter, secs, res);

@@ -590,11 +590,12 @@ int create_context(void **out, const sylv_problem *pb, const sylv_options *op, v
 // Core recurrences (core.hip).
 int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, double *P,
                          double *Rt, int64_t ldc, double tol, DevState *ds, hipStream_t st);
-int launch_cg_core(int s, int p, const double *H, const double *G, const double *P, double *Q,
-                   int64_t ldc, const Scratch &sc, DevState *ds, hipStream_t st);
-int launch_cg_update(int s, int p, double *X, double *R, double *P, const double *Q, int64_t ldc,
-                     const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
-                     hipStream_t st);
+int launch_cg_pq(int s, int p, bool sym, const double *H, const double *G, const double *R,
+                 const double *Pprev, double *Pk, int64_t ldc, const Scratch &sc, DevState *ds,
+                 hipStream_t st);
+int launch_cg_xr(int s, int p, bool sym, const double *H, const double *G, const double *Pk,
+                 double *X, double *R, int64_t ldc, const Scratch &sc, DevState *ds, double *hist,
+                 int k, int max_iter, hipStream_t st);
 int launch_bicg_s(int s, int p, const double *Q, const double *R, double *S, const double *Rt,
                   int64_t ldc, DevState *ds, double *hist, int k, int max_iter, hipStream_t st);
 int launch_bicg_omega(int s, int p, const double *T, const double *S, int64_t ldc,

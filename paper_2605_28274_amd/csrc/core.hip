@@ -81,93 +81,197 @@ __device__ __forceinline__ void sum_partials(const double *partials, int nb, dou
 }
 
 // ---- CG (block-tridiagonal H and G from block Lanczos) ----
-
-// Q = [H P, 0] + [P G^T; 0] over (p+s)^2 using the band |blk(i) - blk(l)| <= 1 of H and G;
-// partials of <P, Q(1:p, 1:p)>. Workgroup b owns 256 columns (b % gx) and the row groups
-// b / gx, b / gx + gy, ... of CG_ROWS rows; thread j keeps row j's band of G in registers, and
-// the band loops have fixed length 3S (masked), so CG_UNR rows are in flight at once.
-constexpr int CG_ROWS = 16, CG_UNR = 4, CG_MAXWG = 4096;
+// Two passes over the cores per iteration, on 32 x 64 tiles:
+//   cg_pq_kernel: P_k = R_k + beta_{k-1} P_{k-1} (Alg. 4.1 step 14 of the previous iteration,
+//     written to the other P buffer) and partials of <P_k, Q_k>, with
+//     Q_k = [H P_k, 0] + [P_k G^T; 0] (eq. (3.11), step 6) formed in registers, not stored;
+//   cg_xr_kernel: alpha_k = rho_k / <P_k, Q_k> (step 7), Q_k formed again from the stored P_k
+//     (same arithmetic on the same values, so the same Q_k), X += alpha P_k, R -= alpha Q_k
+//     (steps 8-9) and partials of ||R_{k+1}||^2.
+// H and G are block tridiagonal (|blk(i) - blk(l)| <= 1), so a tile's Q needs P_k on the rows of
+// H's band times the tile's columns and on the tile's rows times the columns of G's band; both
+// strips are staged in LDS. With SYM (Lyapunov: G = H and R_0 = R_L R_L^T) every core is
+// symmetric: only entries i >= j are formed and stored, an entry above the diagonal is read
+// from its mirror, and the inner products count off-diagonal entries twice.
+constexpr int CT_I = 32, CT_J = 64, CG_GRID = 2048;
 
 template <int S>
-__global__ __launch_bounds__(TPB) void cg_core_kernel(int p, int gx, int gy,
-                                                      const double *__restrict__ H,
-                                                      const double *__restrict__ G,
-                                                      const double *__restrict__ P,
-                                                      double *__restrict__ Q, int64_t ldc,
-                                                      double *partials, const DevState *ds) {
-  if (ds->done) return;
+struct CgTile {
+  double pc[CT_I + 4 * S][CT_J];      // P rows [ra, rb) x the tile's columns
+  double pr[CT_I][CT_J + 4 * S + 1];  // the tile's rows x P columns [ca, cb)
+  double hb[CT_I][3 * S];             // the band of H on the tile's rows
+};
+
+__host__ __device__ inline int cg_tiles_j(int q) { return (q + CT_J - 1) / CT_J; }
+__host__ __device__ inline int cg_tiles(int q) { return ((q + CT_I - 1) / CT_I) * cg_tiles_j(q); }
+
+// Next tile at or after t (stride gridDim.x) that holds an entry to form: all tiles, or with SYM
+// those reaching the lower triangle.
+template <bool SYM>
+__device__ __forceinline__ int cg_next_tile(int t, int q) {
+  const int tj = cg_tiles_j(q), nt = cg_tiles(q);
+  for (; t < nt; t += gridDim.x) {
+    const int i0 = (t / tj) * CT_I, j0 = (t % tj) * CT_J;
+    if (!SYM || (i0 + CT_I - 1 < q - 1 ? i0 + CT_I - 1 : q - 1) >= j0) break;
+  }
+  return t;
+}
+
+// P_k(l, j) for l, j < p (zero outside): FORM reads R and the previous P and forms
+// R + beta P_prev; otherwise it reads the stored P_k. SYM maps l < j to (j, l).
+template <bool SYM, bool FORM>
+__device__ __forceinline__ double cg_pval(int l, int j, int p, const double *__restrict__ R,
+                                          const double *__restrict__ Pp, double beta,
+                                          int64_t ldc) {
+  if (l >= p || j >= p) return 0.0;
+  const int64_t o = (SYM && l < j) ? (int64_t)j * ldc + l : (int64_t)l * ldc + j;
+  return FORM ? fma(beta, Pp[o], R[o]) : Pp[o];
+}
+
+// Tile geometry: P rows [ra, rb) meet H's band on the tile's rows, P columns [ca, cb) meet G's
+// band on its columns (both clipped to p).
+struct CgGeom {
+  int i0, j0, ra, rb, ca, cb;
+};
+
+template <int S>
+__device__ __forceinline__ CgGeom cg_geom(int t, int p) {
+  const int q = p + S, tj = cg_tiles_j(q);
+  CgGeom g;
+  g.i0 = (t / tj) * CT_I;
+  g.j0 = (t % tj) * CT_J;
+  const int imax = (g.i0 + CT_I - 1 < q - 1) ? g.i0 + CT_I - 1 : q - 1;
+  const int jmax = (g.j0 + CT_J - 1 < q - 1) ? g.j0 + CT_J - 1 : q - 1;
+  g.ra = (g.i0 / S - 1) * S > 0 ? (g.i0 / S - 1) * S : 0;
+  g.rb = (imax / S + 2) * S < p ? (imax / S + 2) * S : p;
+  g.ca = (g.j0 / S - 1) * S > 0 ? (g.j0 / S - 1) * S : 0;
+  g.cb = (jmax / S + 2) * S < p ? (jmax / S + 2) * S : p;
+  return g;
+}
+
+// Fills the two P strips and the H band of a tile into LDS and this thread's G band (column
+// j0 + (t & 63)) into gb. No barrier: the caller brackets it.
+template <int S, bool SYM, bool FORM>
+__device__ __forceinline__ void cg_stage(CgTile<S> &T, const CgGeom &g, int p,
+                                         const double *__restrict__ H,
+                                         const double *__restrict__ G,
+                                         const double *__restrict__ R,
+                                         const double *__restrict__ Pp, double beta, int64_t ldc,
+                                         double (&gb)[3 * S]) {
   const int q = p + S;
-  const int cx = (int)blockIdx.x % gx, ry = (int)blockIdx.x / gx;
-  const int j = cx * TPB + threadIdx.x;
-  const bool jl = j < q;
-  const int jc = jl ? j : q - 1;  // clamped column for loads
+  const int j = g.j0 + (threadIdx.x & (CT_J - 1));
+  const int jc = j < q ? j : q - 1;
   const int bj = jc / S;
   const int l0 = bj > 0 ? (bj - 1) * S : 0;
   const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
-  double gb[3 * S];
 #pragma unroll
   for (int t = 0; t < 3 * S; ++t) gb[t] = (l0 + t < l1) ? G[(int64_t)jc * ldc + l0 + t] : 0.0;
-  double v[1] = {0.0};
-  for (int i0 = ry * CG_ROWS; i0 < q; i0 += gy * CG_ROWS) {
+  const int nr = g.rb > g.ra ? g.rb - g.ra : 0, nc = g.cb > g.ca ? g.cb - g.ca : 0;
+  for (int e = threadIdx.x; e < nr * CT_J; e += TPB)
+    T.pc[e / CT_J][e % CT_J] =
+        cg_pval<SYM, FORM>(g.ra + e / CT_J, g.j0 + e % CT_J, p, R, Pp, beta, ldc);
+  for (int e = threadIdx.x; e < CT_I * nc; e += TPB)
+    T.pr[e / nc][e % nc] = cg_pval<SYM, FORM>(g.i0 + e / nc, g.ca + e % nc, p, R, Pp, beta, ldc);
+  for (int e = threadIdx.x; e < CT_I * 3 * S; e += TPB) {
+    const int ii = e / (3 * S), t = e % (3 * S);
+    const int ic = g.i0 + ii < q ? g.i0 + ii : q - 1;
+    const int l = (ic / S > 0 ? (ic / S - 1) * S : 0) + t;
+    T.hb[ii][t] = l < p ? H[(int64_t)ic * ldc + l] : 0.0;
+  }
+}
+
+// Q_k on this thread's 8 entries of the tile (rows i0 + (t >> 6) + 4u, column j0 + (t & 63))
+// into qv, and P_k there into pk, from the staged strips.
+template <int S>
+__device__ __forceinline__ void cg_tile_q(const CgTile<S> &T, const CgGeom &g, int p,
+                                          const double (&gb)[3 * S], double (&qv)[8],
+                                          double (&pk)[8]) {
+  const int q = p + S;
+  const int jj = threadIdx.x & (CT_J - 1), iw = threadIdx.x >> 6;
+  const int j = g.j0 + jj;
+  const int jc = j < q ? j : q - 1;
+  const int bj = jc / S;
+  const int l0 = bj > 0 ? (bj - 1) * S : 0;
+  const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
 #pragma unroll
-    for (int u0 = 0; u0 < CG_ROWS; u0 += CG_UNR) {
-      double acc[CG_UNR], pij[CG_UNR];
+  for (int u = 0; u < 8; ++u) {
+    const int ii = iw + 4 * u, i = g.i0 + ii;
+    const int ic = i < q ? i : q - 1;
+    const int bi = ic / S;
+    const int li0 = bi > 0 ? (bi - 1) * S : 0;
+    double a = 0.0;
+    // H P: row i of H meets rows li0 .. li0 + 3S of P (zero at and past p)
+    if (j < p) {
 #pragma unroll
-      for (int u = 0; u < CG_UNR; ++u) {
-        const int i = i0 + u0 + u;
-        const int ic = i < q ? i : q - 1;
-        const int bi = ic / S;
-        const int li0 = bi > 0 ? (bi - 1) * S : 0;
-        double a = 0.0;
-        // H P: row i of H meets rows li0 .. li0 + 3S of P (masked at p)
-#pragma unroll
-        for (int t = 0; t < 3 * S; ++t) {
-          const int l = li0 + t;
-          const bool in = (l < p) && (j < p);
-          const double h = in ? H[(int64_t)ic * ldc + l] : 0.0;
-          const double pv = in ? P[(int64_t)l * ldc + jc] : 0.0;
-          a = fma(h, pv, a);
-        }
-        // P G^T: row i of P meets the band of row j of G (zero past p)
-        if (ic < p) {
-          const double *pr = P + (int64_t)ic * ldc + l0;
-#pragma unroll
-          for (int t = 0; t < 3 * S; ++t) a = fma((l0 + t < l1) ? pr[t] : 0.0, gb[t], a);
-        }
-        acc[u] = a;
-        pij[u] = P[(int64_t)ic * ldc + jc];
+      for (int t = 0; t < 3 * S; ++t) {
+        const int l = li0 + t;
+        a = fma(T.hb[ii][t], l < g.rb ? T.pc[l - g.ra][jj] : 0.0, a);
       }
+    }
+    // P G^T: row i of P meets the band of row j of G
+    if (ic < p) {
 #pragma unroll
-      for (int u = 0; u < CG_UNR; ++u) {
-        const int i = i0 + u0 + u;
-        if (i < q && jl) {
-          Q[(int64_t)i * ldc + j] = acc[u];
-          if (i < p && j < p) v[0] = fma(pij[u], acc[u], v[0]);
-        }
+      for (int t = 0; t < 3 * S; ++t)
+        a = fma((l0 + t < l1) ? T.pr[ii][l0 + t - g.ca] : 0.0, gb[t], a);
+    }
+    qv[u] = a;
+    pk[u] = (i < g.rb && i >= g.ra) ? T.pc[i - g.ra][jj] : 0.0;
+  }
+}
+
+template <int S, bool SYM>
+__global__ __launch_bounds__(TPB) void cg_pq_kernel(int p, const double *__restrict__ H,
+                                                    const double *__restrict__ G,
+                                                    const double *__restrict__ R,
+                                                    const double *__restrict__ Pprev,
+                                                    double *__restrict__ Pk, int64_t ldc,
+                                                    double *partials, const DevState *ds) {
+  if (ds->done) return;
+  __shared__ CgTile<S> T;
+  const int q = p + S, nt = cg_tiles(q);
+  const double beta = ds->beta;
+  double v[1] = {0.0};
+  for (int t = cg_next_tile<SYM>(blockIdx.x, q); t < nt;
+       t = cg_next_tile<SYM>(t + gridDim.x, q)) {
+    const CgGeom g = cg_geom<S>(t, p);
+    double gb[3 * S], qv[8], pk[8];
+    __syncthreads();  // the previous tile's readers are done
+    cg_stage<S, SYM, true>(T, g, p, H, G, R, Pprev, beta, ldc, gb);
+    __syncthreads();
+    cg_tile_q<S>(T, g, p, gb, qv, pk);
+    const int j = g.j0 + (threadIdx.x & (CT_J - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = g.i0 + (threadIdx.x >> 6) + 4 * u;
+      if (i < p && j < p && (!SYM || i >= j)) {
+        Pk[(int64_t)i * ldc + j] = pk[u];
+        v[0] = fma((SYM && i > j) ? 2.0 * pk[u] : pk[u], qv[u], v[0]);
       }
     }
   }
   put_partials<1>(v, partials);
 }
 
-// Grid of cg_core_kernel for a (p+s)^2 core: gx column chunks x gy row-group strides, at most
-// CG_MAXWG workgroups (the consumer sums one partial per workgroup).
-void cg_core_grid(int q, int &gx, int &gy) {
-  gx = (q + TPB - 1) / TPB;
-  const int groups = (q + CG_ROWS - 1) / CG_ROWS;
-  gy = std::max(1, std::min(CG_MAXWG / gx, groups));
-}
-
-// alpha = rho / <P, Q> from cg_core's partials (breakdown when <P, Q> <= 0);
-// X += alpha P (p x p), R = R - alpha Q ((p+s)^2); partials of ||R||^2.
-__global__ __launch_bounds__(TPB) void cg_update_kernel(int p, int q, double *__restrict__ X,
-                                                        double *__restrict__ R,
-                                                        const double *__restrict__ P,
-                                                        const double *__restrict__ Q, int64_t ldc,
-                                                        const double *pq_part, int pq_nb,
-                                                        double *partials, DevState *ds,
-                                                        double *hist, int k, int max_iter) {
+template <int S, bool SYM>
+__global__ __launch_bounds__(TPB) void cg_xr_kernel(int p, const double *__restrict__ H,
+                                                    const double *__restrict__ G,
+                                                    const double *__restrict__ Pk,
+                                                    double *__restrict__ X,
+                                                    double *__restrict__ R, int64_t ldc,
+                                                    const double *pq_part, int pq_nb,
+                                                    double *partials, DevState *ds,
+                                                    double *hist, int k, int max_iter) {
   if (ds->done) return;
+  __shared__ CgTile<S> T;
+  const int q = p + S, nt = cg_tiles(q);
+  // the first tile's strips load while the <P, Q> partials are summed
+  int t = cg_next_tile<SYM>(blockIdx.x, q);
+  CgGeom g{};
+  double gb[3 * S];
+  if (t < nt) {
+    g = cg_geom<S>(t, p);
+    cg_stage<S, SYM, false>(T, g, p, H, G, nullptr, Pk, 0.0, ldc, gb);
+  }
   double pq[1];
   sum_partials<1>(pq_part, pq_nb, pq);
   if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
@@ -184,14 +288,29 @@ __global__ __launch_bounds__(TPB) void cg_update_kernel(int p, int q, double *__
     hist[max_iter + k] = alpha;
   }
   double v[1] = {0.0};
-  for (int i = blockIdx.x; i < q; i += gridDim.x)
-    for (int j = threadIdx.x; j < q; j += TPB) {
-      const int64_t o = (int64_t)i * ldc + j;
-      if (i < p && j < p) X[o] = fma(alpha, P[o], X[o]);
-      const double r = fma(-alpha, Q[o], R[o]);
-      R[o] = r;
-      v[0] = fma(r, r, v[0]);
+  while (t < nt) {
+    __syncthreads();  // the strips are in place
+    double qv[8], pk[8];
+    cg_tile_q<S>(T, g, p, gb, qv, pk);
+    const int j = g.j0 + (threadIdx.x & (CT_J - 1));
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int i = g.i0 + (threadIdx.x >> 6) + 4 * u;
+      if (i < q && j < q && (!SYM || i >= j)) {
+        const int64_t o = (int64_t)i * ldc + j;
+        if (i < p && j < p) X[o] = fma(alpha, pk[u], X[o]);
+        const double r = fma(-alpha, qv[u], R[o]);
+        R[o] = r;
+        v[0] = fma((SYM && i > j) ? 2.0 * r : r, r, v[0]);
+      }
     }
+    t = cg_next_tile<SYM>(t + gridDim.x, q);
+    if (t < nt) {
+      g = cg_geom<S>(t, p);
+      __syncthreads();  // the previous tile's readers are done
+      cg_stage<S, SYM, false>(T, g, p, H, G, nullptr, Pk, 0.0, ldc, gb);
+    }
+  }
   put_partials<1>(v, partials);
 }
 
@@ -214,19 +333,6 @@ __global__ __launch_bounds__(TPB) void cg_converge_kernel(const double *rr_part,
   ds->beta = rr[0] / ds->rho;
   ds->rho = rr[0];
   hist[2 * max_iter + k] = ds->beta;
-}
-
-// P = R + beta P over (p+s)^2.
-__global__ __launch_bounds__(TPB) void cg_p_kernel(int q, const double *__restrict__ R,
-                                                   double *__restrict__ P, int64_t ldc,
-                                                   const DevState *ds) {
-  if (ds->done) return;
-  const double beta = ds->beta;
-  for (int i = blockIdx.x; i < q; i += gridDim.x)
-    for (int j = threadIdx.x; j < q; j += TPB) {
-      const int64_t o = (int64_t)i * ldc + j;
-      P[o] = fma(beta, P[o], R[o]);
-    }
 }
 
 // ---- BiCGSTAB (dense block Hessenberg H and G from block Arnoldi) ----
@@ -370,17 +476,25 @@ int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, d
   return 0;
 }
 
-// Scratch::partials layout: [0, 2*NBLK) partials of the scalar being formed (<P,Q>: up to
-// CG_MAXWG; <T,S>, <T,T>); [2*NBLK, 3*NBLK) the ||R||^2 partials (CG: from CG_MAXWG).
-int launch_cg_core(int s, int p, const double *H, const double *G, const double *P, double *Q,
-                   int64_t ldc, const Scratch &sc, DevState *ds, hipStream_t st) {
-  int gx, gy;
-  cg_core_grid(p + s, gx, gy);
-  const unsigned g = (unsigned)(gx * gy);
+// Scratch::partials layout. CG: [0, CG_MAXWG) the <P, Q> partials, [CG_MAXWG, 2 CG_MAXWG)
+// the ||R||^2 partials. BiCGSTAB: [0, 2*NBLK) partials of the scalar being formed (<T,S>,
+// <T,T>), [2*NBLK, 3*NBLK) the ||R||^2 partials.
+constexpr int CG_MAXWG = 4096;
+static_assert(CG_GRID <= CG_MAXWG, "CG partials fit their ranges");
+
+unsigned cg_grid(int q) { return (unsigned)std::min(cg_tiles(q), CG_GRID); }
+
+int launch_cg_pq(int s, int p, bool sym, const double *H, const double *G, const double *R,
+                 const double *Pprev, double *Pk, int64_t ldc, const Scratch &sc, DevState *ds,
+                 hipStream_t st) {
+  const unsigned g = cg_grid(p + s);
   switch (s) {
-#define CASE(SS)                                                                             \
-  case SS:                                                                                   \
-    cg_core_kernel<SS><<<g, TPB, 0, st>>>(p, gx, gy, H, G, P, Q, ldc, sc.partials, ds);      \
+#define CASE(SS)                                                                              \
+  case SS:                                                                                    \
+    if (sym)                                                                                  \
+      cg_pq_kernel<SS, true><<<g, TPB, 0, st>>>(p, H, G, R, Pprev, Pk, ldc, sc.partials, ds); \
+    else                                                                                      \
+      cg_pq_kernel<SS, false><<<g, TPB, 0, st>>>(p, H, G, R, Pprev, Pk, ldc, sc.partials, ds); \
     break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
@@ -390,20 +504,27 @@ int launch_cg_core(int s, int p, const double *H, const double *G, const double 
   return 0;
 }
 
-int launch_cg_update(int s, int p, double *X, double *R, double *P, const double *Q, int64_t ldc,
-                     const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
-                     hipStream_t st) {
-  const int q = p + s;
-  const unsigned g = grid_q(q);
+int launch_cg_xr(int s, int p, bool sym, const double *H, const double *G, const double *Pk,
+                 double *X, double *R, int64_t ldc, const Scratch &sc, DevState *ds, double *hist,
+                 int k, int max_iter, hipStream_t st) {
+  const unsigned g = cg_grid(p + s);
   double *rr = sc.partials + CG_MAXWG;
-  int gx, gy;
-  cg_core_grid(q, gx, gy);  // one <P, Q> partial per cg_core workgroup
-  cg_update_kernel<<<g, TPB, 0, st>>>(p, q, X, R, P, Q, ldc, sc.partials, gx * gy, rr, ds, hist,
-                                      k, max_iter);
+  switch (s) {
+#define CASE(SS)                                                                            \
+  case SS:                                                                                  \
+    if (sym)                                                                                \
+      cg_xr_kernel<SS, true><<<g, TPB, 0, st>>>(p, H, G, Pk, X, R, ldc, sc.partials, (int)g, \
+                                                rr, ds, hist, k, max_iter);                 \
+    else                                                                                    \
+      cg_xr_kernel<SS, false><<<g, TPB, 0, st>>>(p, H, G, Pk, X, R, ldc, sc.partials,       \
+                                                 (int)g, rr, ds, hist, k, max_iter);        \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
   HIPOK(hipGetLastError());
   cg_converge_kernel<<<1, TPB, 0, st>>>(rr, (int)g, ds, hist, k, max_iter);
-  HIPOK(hipGetLastError());
-  cg_p_kernel<<<g, TPB, 0, st>>>(q, R, P, ldc, ds);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -152,8 +152,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
     L.cpart_cap = (size_t)(512 + std::min<int64_t>(T * T, 1024)) * 4096;
     L.off_cpart = bump(cur, L.cpart_cap * 8);
   }
-  L.off_panV = bump(cur, (size_t)2 * L.n * L.s * L.esz);
-  L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)2 * L.m * L.s * L.esz);
+  L.off_panV = bump(cur, (size_t)LZ_RING * L.n * L.s * L.esz);
+  L.off_panW = L.lyap ? L.off_panV : bump(cur, (size_t)LZ_RING * L.m * L.s * L.esz);
   L.off_sellA = child ? 0 : bump(cur, sell_bytes(L.n, pb->A.nnz));
   L.off_sellB = (L.lyap || child) ? L.off_sellA : bump(cur, sell_bytes(L.m, pb->B.nnz));
   L.off_dots = bump(cur, 16 * 8);
@@ -362,8 +362,13 @@ int begin_solve(Ctx *c, double tol, int max_iter, int method) {
   double *zero[] = {c->H, c->G, c->X, c->R, c->P, c->Q, c->S, c->T};
   for (double *z : zero)
     if (z) HIPOK(hipMemsetAsync(z, 0, c2, c->st));
-  // the compact copy of block 1 (V_1, W_1) is the first SpMM input; earlier solves reused it
+  // the compact copy of block 1 (V_1, W_1) is the first SpMM input; earlier solves reused it.
+  // The other ring slots start at zero: the block Lanczos ring writes whole groups of slots
+  // into the basis, and slots of blocks a solve never formed must hold finite values.
   const size_t e = (size_t)L.esz;
+  HIPOK(hipMemsetAsync(c->sv.panel[1], 0, (size_t)(LZ_RING - 1) * L.n * L.s * e, c->st));
+  if (!L.lyap)
+    HIPOK(hipMemsetAsync(c->sw.panel[1], 0, (size_t)(LZ_RING - 1) * L.m * L.s * e, c->st));
   HIPOK(hipMemcpy2DAsync(c->sv.panel[0], L.s * e, c->sv.basis, L.ldb * e, L.s * e, L.n,
                          hipMemcpyDeviceToDevice, c->st));
   if (!L.lyap)
@@ -531,14 +536,15 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   char *panv = at<char>(c, L.off_panV), *panw = at<char>(c, L.off_panW);
   c->sv = SideDesc{L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
                    at<void>(c, L.off_V), L.ldb, c->H, at<double>(c, L.off_U),
-                   at<double>(c, L.off_coefV), c->ssv,
-                   {panv, panv + L.n * L.s * L.esz}, L.fp32, SellMat{}};
+                   at<double>(c, L.off_coefV), c->ssv, {}, L.fp32, SellMat{}};
+  for (int k = 0; k < LZ_RING; ++k) c->sv.panel[k] = panv + k * L.n * L.s * L.esz;
   if (L.lyap) {
     c->sw = c->sv;
   } else {
     c->sw = SideDesc{L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<void>(c, L.off_W), L.ldb,
-                     c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw,
-                     {panw, panw + L.m * L.s * L.esz}, L.fp32, SellMat{}};
+                     c->G, at<double>(c, L.off_Uw), at<double>(c, L.off_coefW), c->ssw, {},
+                     L.fp32, SellMat{}};
+    for (int k = 0; k < LZ_RING; ++k) c->sw.panel[k] = panw + k * L.m * L.s * L.esz;
   }
   if (parent) {
     // operators of the parent: V side A; W side B^T (A when the parent is a Lyapunov problem)
@@ -1179,6 +1185,7 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
   const hipStream_t ks = c->kst, cs = c->st;
   // Lyapunov (G = H, C2 = C1): every core is symmetric (Section 4.3)
   const bool sym = L.lyap != 0;
+  int steps = 0;  // Lanczos steps issued: blocks 0 .. steps exist
   if ((e = join(c, cs, ks))) return e;  // the Krylov stream sees the solve's set-up
   for (int k = 0; k < max_iter; ++k) {
     const int p = (k + 1) * s;
@@ -1189,6 +1196,7 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
     if ((e = launch_lanczos_pair(s, c->sv, L.lyap ? nullptr : &c->sw, k, L.ldc, c->closure_tol,
                                  c->sc, c->ds, ks)))
       return e;
+    steps = k + 1;
     if (ks != cs) {
       HIPOK(hipEventRecord(c->ev_k[0], ks));
       HIPOK(hipStreamWaitEvent(cs, c->ev_k[0], 0));
@@ -1216,6 +1224,10 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
       if (c->h_ds->done) break;
     }
   }
+  // basis columns of the newest blocks still held only in the ring
+  if ((steps + 1) % LZ_RING != 0 &&
+      (e = launch_lanczos_flush(s, c->sv, L.lyap ? nullptr : &c->sw, steps + 1, ks)))
+    return e;
   if ((e = join(c, ks, cs))) return e;
   // the upper triangle of the symmetric solution core from its lower one
   if (sym && (e = launch_mirror(std::min<int64_t>(L.ldc, (int64_t)(max_iter + 1) * s), c->X,

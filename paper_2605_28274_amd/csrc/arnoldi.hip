@@ -8,7 +8,8 @@
   int lanczos_step_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,          \
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st); \
   int arnoldi_lagged_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,        \
-                          double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
+                          double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st); \
+  int lanczos_flush_##SS(const SideDesc &sv, const SideDesc *sw, int nblocks, hipStream_t st);
 ARN_DECL(1) ARN_DECL(2) ARN_DECL(3) ARN_DECL(4) ARN_DECL(5) ARN_DECL(6) ARN_DECL(7) ARN_DECL(8)
 #undef ARN_DECL
 
@@ -43,6 +44,17 @@ int launch_lanczos_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
   switch (s) {
 #define CASE(SS) \
   case SS: return lanczos_step_##SS(sv, sw, jb, ldh, closure_tol, sc, ds, st);
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
+}
+
+int launch_lanczos_flush(int s, const SideDesc &sv, const SideDesc *sw, int nblocks,
+                         hipStream_t st) {
+  switch (s) {
+#define CASE(SS) \
+  case SS: return lanczos_flush_##SS(sv, sw, nblocks, st);
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return SYLV_ERR_INVALID;

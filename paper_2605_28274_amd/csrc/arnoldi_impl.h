@@ -48,6 +48,8 @@ struct ArSide {
   SellMat sell;       // SELL copy of the operator (sell.ci == nullptr: CSR)
   const void *pin;    // compact copy of block j (SpMM input), element type T
   void *pout;         // compact copy of block j+1 (written with the new block), element type T
+  const void *pprev;  // block Lanczos: compact copy of block j-1
+  const void *ring;   // block Lanczos: slot k of the block ring at ring + k rows s elements
   double *part;    // Gram chunk partials of this basis
   double *aux;     // partials of ||M V_j||^2, U^T U and of the second-pass Gram
   int *cnt;        // counters of this basis (unused: no grid-wide reductions)
@@ -946,9 +948,11 @@ __global__ __launch_bounds__(TPB) void dcgs_tail_pair(ArPair Pq, ArPair Ph, int 
 }
 
 // Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
-// V[:, (j+1)s : (j+2)s] = U T; workgroup 0 records T and writes H_{j+1,j}.
+// the new block U T to the compact copy and, with to_basis, to V[:, (j+1)s : (j+2)s] (block
+// Lanczos leaves the basis columns to lz_flush_pair); workgroup 0 records T and writes
+// H_{j+1,j}.
 template <int S, typename T>
-__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
+__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh, int to_basis,
                                                   const DevState *ds) {
   if (ds->done) return;
   int lb, sd;
@@ -986,7 +990,7 @@ __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
       double v = 0.0;
 #pragma unroll
       for (int a = 0; a < S; ++a) v = fma(u[a], Tq[a * S + b], v);
-      static_cast<T *>(A.basis)[r * A.ldb + (jb + 1) * S + b] = (T)v;
+      if (to_basis) static_cast<T *>(A.basis)[r * A.ldb + (jb + 1) * S + b] = (T)v;
       static_cast<T *>(A.pout)[r * S + b] = (T)v;
     }
   }
@@ -1021,7 +1025,7 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
 #pragma unroll
     for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
     if (jb > 0) {
-      const T *vp = static_cast<const T *>(A.pout) + r * S;  // block j-1 (panel reused)
+      const T *vp = static_cast<const T *>(A.pprev) + r * S;  // block j-1
 #pragma unroll
       for (int u = 0; u < S; ++u) {
         const double vu = (double)vp[u];
@@ -1120,6 +1124,32 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t 
   if (threadIdx.x == 0)
 #pragma unroll
     for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
+}
+
+// Basis columns of blocks [b0, b1) (b1 - b0 <= LZ_RING) from the block Lanczos ring: each
+// row receives (b1 - b0) s consecutive entries at once.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void lz_flush_pair(ArPair P, int b0, int b1) {
+  int lb, sd;
+  const ArSide A = side_of(P, lb, sd);
+  const T *ring = static_cast<const T *>(A.ring);
+  T *basis = static_cast<T *>(A.basis);
+  for (int64_t r = (int64_t)lb * TPB + threadIdx.x; r < A.rows; r += (int64_t)A.nb * TPB) {
+    T v[LZ_RING * S];
+#pragma unroll
+    for (int k = 0; k < LZ_RING; ++k)
+      if (b0 + k < b1) {
+        const T *src = ring + (size_t)((b0 + k) % LZ_RING) * A.rows * S + r * S;
+#pragma unroll
+        for (int t = 0; t < S; ++t) v[k * S + t] = src[t];
+      }
+    T *dst = basis + r * A.ldb + (int64_t)b0 * S;
+#pragma unroll
+    for (int k = 0; k < LZ_RING; ++k)
+      if (b0 + k < b1)
+#pragma unroll
+        for (int t = 0; t < S; ++t) dst[k * S + t] = v[k * S + t];
+  }
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
@@ -1356,7 +1386,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, 1, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
@@ -1455,9 +1485,30 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   dcgs_tail_pair<S><<<(unsigned)nq + total_blocks(Ph), TPB, 0, st>>>(P, Ph, nq, jb, ldh,
                                                                       closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, 1, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  return 0;
+}
+
+// Basis columns of the blocks of the last (possibly partial) ring group before block nblocks:
+// blocks [(nblocks - 1) / LZ_RING * LZ_RING, nblocks).
+template <int S, typename T>
+int lanczos_flush_t(const SideDesc &sv, const SideDesc *sw, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return 0;
+  const int b0 = (nblocks - 1) / LZ_RING * LZ_RING;
+  ArPair P{};
+  P.nsides = sw ? 2 : 1;
+  for (int i = 0; i < P.nsides; ++i) {
+    const SideDesc &d = i ? *sw : sv;
+    P.s[i].rows = d.rows;
+    P.s[i].basis = d.basis;
+    P.s[i].ldb = d.ldb;
+    P.s[i].ring = d.panel[0];
+  }
+  set_ranges(P, nb_rows(sv.rows), sw ? nb_rows(sw->rows) : 0);
+  lz_flush_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, b0, nblocks);
+  HIPOK(hipGetLastError());
   return 0;
 }
 
@@ -1478,8 +1529,10 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     P.s[i].nb_spmm = (int)nb_rows(rows);
     P.s[i].nb_upd = (int)nb_rows(rows);  // U^T U partials come from lz_update_pair
     P.s[i].nb_qr = (int)nb_qr(rows);
-    P.s[i].pin = d.panel[jb % 2];
-    P.s[i].pout = d.panel[(jb + 1) % 2];
+    P.s[i].pin = d.panel[jb % LZ_RING];
+    P.s[i].pout = d.panel[(jb + 1) % LZ_RING];
+    P.s[i].pprev = d.panel[(jb + LZ_RING - 1) % LZ_RING];
+    P.s[i].ring = d.panel[0];
   }
   const int64_t total = rows0 + rows1;
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
@@ -1496,9 +1549,11 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, 0, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  // block jb + 1 completes a group of ring slots: the group goes to the basis
+  if ((jb + 2) % LZ_RING == 0) return lanczos_flush_t<S, T>(sv, sw, jb + 2, st);
   return 0;
 }
 
@@ -1516,6 +1571,10 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {  \
     return sv.fp32 ? lanczos_pair_t<SS, float>(sv, sw, jb, ldh, closure_tol, sc, ds, st)        \
                    : lanczos_pair_t<SS, double>(sv, sw, jb, ldh, closure_tol, sc, ds, st);      \
+  }                                                                                             \
+  int lanczos_flush_##SS(const SideDesc &sv, const SideDesc *sw, int nblocks, hipStream_t st) { \
+    return sv.fp32 ? lanczos_flush_t<SS, float>(sv, sw, nblocks, st)                            \
+                   : lanczos_flush_t<SS, double>(sv, sw, nblocks, st);                          \
   }                                                                                             \
   int arnoldi_lagged_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,          \
                           double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {\

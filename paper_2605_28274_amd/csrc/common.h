@@ -507,6 +507,10 @@ __device__ inline void finish_pass2(SideState *ss, int s, const double *G2) {
 
 // ---- launchers implemented in the .hip files (all return 0 or SYLV_ERR_HIP) ----
 
+// Slots of the ring of compact block copies (block Lanczos: the basis receives LZ_RING blocks
+// per row at a time instead of one block's s entries).
+constexpr int LZ_RING = 8;
+
 struct SideDesc {
   int64_t rows;            // n (V side) or m (W side)
   int64_t nnz;
@@ -520,8 +524,10 @@ struct SideDesc {
   double *U;               // rows x s work panel
   double *coef;            // compact coefficient block (ldb x s)
   SideState *ss;           // device
-  void *panel[2];          // compact rows x s copies of the two newest blocks: block j in
-                           // panel[j % 2] (SpMM input and Lanczos local terms), basis type
+  void *panel[LZ_RING];    // compact rows x s copies of the newest blocks, basis type, slots
+                           // contiguous: block j in panel[j % 2] (block Arnoldi) or in
+                           // panel[j % LZ_RING] (block Lanczos, whose basis columns are
+                           // written from the ring LZ_RING blocks at a time)
   int fp32;                // basis and panels stored in FP32
   SellMat sell;            // SELL copy of the operator (sell.ci == nullptr: use CSR)
 };
@@ -570,6 +576,11 @@ int launch_first_block(int s, const SideDesc &sd, const double *C, int64_t ldc_i
 // Both bases' block Lanczos steps j (arnoldi.hip); sw may be null (Lyapunov).
 int launch_lanczos_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st);
+// Block Lanczos keeps its newest blocks in the ring of SideDesc::panel and writes their basis
+// columns a group of LZ_RING blocks at a time; this writes the last, possibly partial group of
+// the first nblocks blocks (after the final step of a solve).
+int launch_lanczos_flush(int s, const SideDesc &sv, const SideDesc *sw, int nblocks,
+                         hipStream_t st);
 
 // Both bases' block Arnoldi steps j (same j) in shared launches (arnoldi.hip); sw may be null
 // (Lyapunov: one basis).

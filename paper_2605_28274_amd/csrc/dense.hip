@@ -469,56 +469,85 @@ struct GramSeq {
   }
 };
 
-// The slab sequences of all tiles (nsl slabs each, the last one zero-filled past K when
-// K % BK != 0) are concatenated in visiting order and cut into chunks of c slabs, chunk w for
-// workgroup w; chunks map to XCDs in contiguous eighths. A tile that lies inside one chunk goes
-// to C directly (C = acc, or C += acc when beta != 0); a tile cut by chunk boundaries leaves its
-// piece of chunk w in partial slot 2w (the chunk's first tile) or 2w + 1 (its last tile), and
-// gram_stream_fix_kernel sums the pieces in chunk order. Every workgroup does the same
-// matrix-core work, whatever the number of tiles.
+// Schedule over G workgroups (G a multiple of 8; workgroup b is worker w = (b % 8) G/8 + b / 8,
+// so XCD x runs workers [x G/8, (x+1) G/8)):
+// * whole tiles first: worker w computes tiles w, w + G, ... below dp = floor(T / G) G. The
+//   workers of one XCD then hold 64 consecutive tiles of the visiting order (eight tile rows by
+//   eight columns) and walk K in step, so their row and column panels are shared in its L2;
+// * then the remaining tiles [dp, T) in stream-K form: their slab sequences (nsl slabs each, the
+//   last one zero-filled past K when K % BK != 0) are concatenated and cut into chunks of c
+//   slabs, chunk w for worker w. A tile inside one chunk goes to C directly; a tile cut by chunk
+//   boundaries leaves its piece of chunk w in partial slot 2w (the chunk's first tile) or 2w + 1
+//   (its last tile), and gram_stream_fix_kernel sums the pieces in chunk order.
+// Whole tiles write C = acc (C += acc when beta != 0). Every worker does the same matrix-core
+// work, whatever the number of tiles.
+template <typename TA, typename TB>
+__device__ __forceinline__ void gram_piece(Smem &sm, WaveAcc &acc, int64_t i0, int64_t j0,
+                                           int64_t K, const TA *__restrict__ A, int64_t lda,
+                                           const TB *__restrict__ B, int64_t ldb, int64_t a,
+                                           int64_t b, int wm, int wn) {
+  const int64_t nfull = K / BK;
+  const int64_t bf = b < nfull ? b : nfull;
+  if (bf > a)
+    pipelined<true, false, TA, TB>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, a * BK, bf * BK);
+  if (b > nfull) {
+    // the last K % BK rows, zero-filled past K
+    const int64_t kb = nfull * BK;
+    __syncthreads();
+    for (int e = threadIdx.x; e < BK * BM; e += 256) {
+      const int kk = e / BM, ii = e % BM;
+      sm.As[0][kk][ii] = (kb + kk < K) ? (double)A[(kb + kk) * lda + i0 + ii] : 0.0;
+      sm.Bs[0][kk][ii] = (kb + kk < K) ? (double)B[(kb + kk) * ldb + j0 + ii] : 0.0;
+    }
+    __syncthreads();
+    mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+  }
+}
+
+__device__ __forceinline__ void gram_store(const WaveAcc &acc, int64_t i0, int64_t j0, int64_t M,
+                                           int64_t N, double beta, double *__restrict__ C,
+                                           int64_t ldc, int wm, int wn) {
+  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
+    const int64_t gi = i0 + ii, gj = j0 + jj;
+    if (gi < M && gj < N) {
+      double *cp = C + gi * ldc + gj;
+      *cp = (beta == 0.0) ? v : *cp + v;
+    }
+  });
+}
+
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256, 2) void gram_stream_kernel(
     const GramSeq sq, int64_t M, int64_t N, int64_t K, const TA *__restrict__ A, int64_t lda,
     const TB *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
-    int64_t nsl, int64_t c, int nchunks, double *__restrict__ part) {
-  const int per = (int)(gridDim.x >> 3);
+    int64_t nsl, int64_t dp, int64_t c, int nchunks, double *__restrict__ part) {
+  const int G = (int)gridDim.x, per = G >> 3;
   const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
-  if (w >= nchunks) return;
   __shared__ Smem sm;
-  const int64_t total = sq.count() * nsl, nfull = K / BK;
-  const int64_t c0 = (int64_t)w * c, c1 = (c0 + c < total) ? c0 + c : total;
   const int wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-  for (int64_t pos = c0; pos < c1;) {
-    const int64_t t = pos / nsl, ts = t * nsl;
-    const int64_t a = pos - ts, b = ((c1 < ts + nsl) ? c1 : ts + nsl) - ts;
+  for (int64_t t = w; t < dp; t += G) {
     int I, J;
     sq.tile(t, I, J);
     const int64_t i0 = (int64_t)I * BM, j0 = (int64_t)J * BN;
     WaveAcc acc;
     zero_acc(acc);
-    const int64_t bf = b < nfull ? b : nfull;
-    if (bf > a)
-      pipelined<true, false, TA, TB>(sm, acc, wm, wn, A + i0, lda, B + j0, ldb, a * BK, bf * BK);
-    if (b > nfull) {
-      // the last K % BK rows, zero-filled past K
-      const int64_t kb = nfull * BK;
-      __syncthreads();
-      for (int e = threadIdx.x; e < BK * BM; e += 256) {
-        const int kk = e / BM, ii = e % BM;
-        sm.As[0][kk][ii] = (kb + kk < K) ? (double)A[(kb + kk) * lda + i0 + ii] : 0.0;
-        sm.Bs[0][kk][ii] = (kb + kk < K) ? (double)B[(kb + kk) * ldb + j0 + ii] : 0.0;
-      }
-      __syncthreads();
-      mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
-    }
+    gram_piece<TA, TB>(sm, acc, i0, j0, K, A, lda, B, ldb, 0, nsl, wm, wn);
+    gram_store(acc, i0, j0, M, N, beta, C, ldc, wm, wn);
+  }
+  if (w >= nchunks) return;
+  const int64_t total = (sq.count() - dp) * nsl;
+  const int64_t c0 = (int64_t)w * c, c1 = (c0 + c < total) ? c0 + c : total;
+  for (int64_t pos = c0; pos < c1;) {
+    const int64_t tr = pos / nsl, ts = tr * nsl;
+    const int64_t a = pos - ts, b = ((c1 < ts + nsl) ? c1 : ts + nsl) - ts;
+    int I, J;
+    sq.tile(dp + tr, I, J);
+    const int64_t i0 = (int64_t)I * BM, j0 = (int64_t)J * BN;
+    WaveAcc acc;
+    zero_acc(acc);
+    gram_piece<TA, TB>(sm, acc, i0, j0, K, A, lda, B, ldb, a, b, wm, wn);
     if (a == 0 && b == nsl) {
-      for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
-        const int64_t gi = i0 + ii, gj = j0 + jj;
-        if (gi < M && gj < N) {
-          double *cp = C + gi * ldc + gj;
-          *cp = (beta == 0.0) ? v : *cp + v;
-        }
-      });
+      gram_store(acc, i0, j0, M, N, beta, C, ldc, wm, wn);
     } else {
       double *pt = part + (size_t)(2 * w + (pos == c0 ? 0 : 1)) * (BM * BN);
       for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });
@@ -527,28 +556,29 @@ __global__ __launch_bounds__(256, 2) void gram_stream_kernel(
   }
 }
 
-// The tiles cut by chunk boundaries: boundary wb (between chunks wb and wb + 1) handles the
-// tile it falls in unless an earlier boundary falls in the same tile; 16 workgroups per
-// boundary, one element per thread.
+// The remaining tiles cut by chunk boundaries: boundary wb (between chunks wb and wb + 1)
+// handles the tile it falls in unless an earlier boundary falls in the same tile; 16 workgroups
+// per boundary, one element per thread. Tile indices count from dp.
 __global__ __launch_bounds__(256) void gram_stream_fix_kernel(const GramSeq sq, int64_t M,
-                                                              int64_t N, int64_t nsl, int64_t c,
+                                                              int64_t N, int64_t nsl, int64_t dp,
+                                                              int64_t c,
                                                               const double *__restrict__ part,
                                                               double beta, double *__restrict__ C,
                                                               int64_t ldc) {
   const int wb = (int)(blockIdx.x / 16), sub = (int)(blockIdx.x % 16);
-  const int64_t pb = (int64_t)(wb + 1) * c, total = sq.count() * nsl;
+  const int64_t pb = (int64_t)(wb + 1) * c, total = (sq.count() - dp) * nsl;
   if (pb >= total || pb % nsl == 0) return;
-  const int64_t t = pb / nsl, ts = t * nsl;
+  const int64_t tr = pb / nsl, ts = tr * nsl;
   if ((int64_t)wb * c > ts) return;
   const int w0 = (int)(ts / c), w1 = (int)((ts + nsl - 1) / c);
   const int e = sub * 256 + threadIdx.x;
   double v = 0.0;
   for (int w = w0; w <= w1; ++w) {
-    const int slot = 2 * w + ((int64_t)w * c / nsl == t ? 0 : 1);
+    const int slot = 2 * w + ((int64_t)w * c / nsl == tr ? 0 : 1);
     v += part[(size_t)slot * (BM * BN) + e];
   }
   int I, J;
-  sq.tile(t, I, J);
+  sq.tile(dp + tr, I, J);
   const int64_t gi = (int64_t)I * BM + e / BN, gj = (int64_t)J * BN + e % BN;
   if (gi < M && gj < N) {
     double *cp = C + gi * ldc + gj;
@@ -717,18 +747,19 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
   if (lda < TM * BM || ldb < TN * BN || lda % 8 || ldb % 8) return SYLV_ERR_INVALID;
   if (K <= 0) return 0;
   const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
-  // many tiles: stream-K over 512 workgroups (two per CU), when the partial slots fit
+  // many tiles: whole tiles in rounds of 512 workgroups (two per CU), the rest in stream-K
+  // form, when the partial slots fit
   if (part && tiles >= 64) {
     const GramSeq sq{(int)TM, (int)TN, lower ? 1 : 0};
-    const int64_t nsl = (K + BK - 1) / BK, total = tiles * nsl;
-    const int64_t c = std::max<int64_t>((total + GRAM_STREAM_WG - 1) / GRAM_STREAM_WG, 4);
+    const int64_t G = GRAM_STREAM_WG;
+    const int64_t nsl = (K + BK - 1) / BK, dp = tiles / G * G, total = (tiles - dp) * nsl;
+    const int64_t c = std::max<int64_t>((total + G - 1) / G, 4);
     const int64_t nchunks = (total + c - 1) / c;
     if ((size_t)(2 * nchunks) * (BM * BN) <= part_cap) {
-      const unsigned grid = (unsigned)((nchunks + 7) / 8 * 8);
-#define GRAM_SK(TA, TB)                                                                        \
-  gram_stream_kernel<TA, TB><<<grid, 256, 0, st>>>(sq, M, N, K, static_cast<const TA *>(A), lda, \
-                                                   static_cast<const TB *>(B), ldb, beta, C, ldc, \
-                                                   nsl, c, (int)nchunks, part)
+#define GRAM_SK(TA, TB)                                                                         \
+  gram_stream_kernel<TA, TB><<<(unsigned)G, 256, 0, st>>>(                                      \
+      sq, M, N, K, static_cast<const TA *>(A), lda, static_cast<const TB *>(B), ldb, beta, C, \
+      ldc, nsl, dp, c, (int)nchunks, part)
       if (a_fp32 && b_fp32) GRAM_SK(float, float);
       else if (a_fp32) GRAM_SK(float, double);
       else if (b_fp32) GRAM_SK(double, float);
@@ -736,8 +767,8 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
 #undef GRAM_SK
       HIPOK(hipGetLastError());
       if (nchunks > 1) {
-        gram_stream_fix_kernel<<<(unsigned)(nchunks - 1) * 16, 256, 0, st>>>(sq, M, N, nsl, c,
-                                                                             part, beta, C, ldc);
+        gram_stream_fix_kernel<<<(unsigned)(nchunks - 1) * 16, 256, 0, st>>>(
+            sq, M, N, nsl, dp, c, part, beta, C, ldc);
         HIPOK(hipGetLastError());
       }
       return 0;

@@ -258,12 +258,13 @@ def spmm_hbm(sylv, torch):
     """SpMM (sliced ELLPACK, FP64) on two large operators: algorithmic bytes 12 nnz +
     4 (rows + 1) + 16 rows s per call over its HIP-event time. Warm: 20 launches back to back
     between two events (the library's SpMM call only enqueues), per launch. Cold: one launch
-    right after a 512 MiB write that evicts the caches; the write keeps the stream busy while
-    the launch is enqueued, so the events bracket the kernel and not the host call."""
+    right after a 512 MiB read that evicts the caches (a read, so that no dirty lines are left
+    to write back); the read keeps the stream busy while the launch is enqueued, so the events
+    bracket the kernel and not the host call."""
     import numpy as np
     from workloads import stencils
     out = {}
-    flush = torch.empty(64 * 2 ** 20, dtype=torch.float64, device="cuda")
+    flush = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
     batch = 20
     for name, M, s in (("2D 1024^2 (n = 1048576), s = 1", stencils.cd2d(1024, 1024, 0.0), 1),
                        ("3D 64^3 (n = 262144), s = 4", stencils.cd3d(64, 64, 64, 10.0), 4)):
@@ -280,7 +281,7 @@ def spmm_hbm(sylv, torch):
             for _ in range(5 if mode == "warm" else 10):
                 k = batch if mode == "warm" else 1
                 if mode == "cold":
-                    flush.fill_(1.0)
+                    flush.sum()
                 else:
                     sylv.sylv_sell_spmm(csr, buf, s, X, Y)
                 a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -35,6 +35,11 @@ constexpr int OPB = TPB / NG;  // outputs per gram_reduce_pair workgroup
 constexpr int GRAM_LOADS = 16; // 8-byte basis loads in flight per thread in gram_part_pair
 constexpr int GRAM_UCH = 128;  // right-hand rows staged in LDS at a time by gram_part_pair
 
+// The kernels of the block Arnoldi sweeps (SpMM, Gram, update, QR) run on the Krylov stream
+// beside the core product's matrix-core waves (two streams); they are the longer chain, so
+// their waves take the higher issue priority on a SIMD they share (1% on the C2 solve).
+__device__ __forceinline__ void krylov_wave_priority() { __builtin_amdgcn_s_setprio(3); }
+
 struct ArSide {
   int64_t rows, nnz;
   const int32_t *rp, *ci;
@@ -80,6 +85,7 @@ constexpr int spmm_nr() { return S == 1 ? 4 : S == 2 ? 2 : 1; }
 
 template <int S, typename T>
 __global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
@@ -161,6 +167,7 @@ struct Pack8<float> {
 template <int S, typename T, int NQ, bool DUAL = false>
 __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int cw_log2,
                                                       const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   typedef Pack8<T> PK;
   typedef typename PK::type V8;
@@ -282,6 +289,7 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int c
 __global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int ncols, int nchunk0,
                                                         int nchunk1, int64_t ldh, int hcol,
                                                         int pass, const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
@@ -476,6 +484,7 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int
 template <int S>
 __global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t ldh,
                                                      double closure_tol, const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
@@ -547,6 +556,7 @@ __global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t l
 // provisional block) and U' = (U - X_b - V_j e) Tw; partials of U'^T U'.
 template <int S>
 __global__ __launch_bounds__(TPB) void dcgs_update_pair(ArPair P, int jb, const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   constexpr int S2 = 2 * S;
   extern __shared__ double Cs[];
@@ -942,6 +952,7 @@ template <int S>
 __global__ __launch_bounds__(TPB) void dcgs_tail_pair(ArPair Pq, ArPair Ph, int nq, int jb,
                                                       int64_t ldh, double closure_tol,
                                                       const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   if ((int)blockIdx.x < nq) qr2_body<S>(Pq, (int)blockIdx.x, closure_tol);
   else dcgs_hcol_body<S>(Ph, (int)blockIdx.x - nq, jb, ldh);
@@ -954,6 +965,7 @@ __global__ __launch_bounds__(TPB) void dcgs_tail_pair(ArPair Pq, ArPair Ph, int 
 template <int S, typename T>
 __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh, int to_basis,
                                                   const DevState *ds) {
+  krylov_wave_priority();
   if (ds->done) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);

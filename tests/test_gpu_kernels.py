@@ -110,7 +110,7 @@ def _sell_case(sylv, M, s, expect_ok=True):
     assert np.max(np.abs(dY.cpu().numpy() - ref)) <= 1e-14 * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("s", [1, 2, 4, 7])
+@pytest.mark.parametrize("s", [1, 2, 3, 4, 7, 8])
 def test_sell_spmm_stencils(sylv, s):
     _sell_case(sylv, stencils.cd2d(37, 29, 5.0), s)           # rows not a multiple of 64
     _sell_case(sylv, stencils.cd3d(16, 8, 9, 10.0), s)

@@ -963,12 +963,10 @@ __global__ __launch_bounds__(TPB) void dcgs_tail_pair(ArPair Pq, ArPair Ph, int 
 // Lanczos leaves the basis columns to lz_flush_pair); workgroup 0 records T and writes
 // H_{j+1,j}.
 template <int S, typename T>
-__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh, int to_basis,
-                                                  const DevState *ds) {
-  krylov_wave_priority();
-  if (ds->done) return;
+__device__ __forceinline__ void final_body(const ArPair &P, int bid, int jb, int64_t ldh,
+                                           int to_basis) {
   int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
+  const ArSide A = side_of(P, lb, sd, bid);
   __shared__ SideState st;
   double G2[S * S];
   sum_records<S * S>(A.aux + A.nb_spmm + A.nb_upd * S * S, A.nb_qr, G2);
@@ -1008,6 +1006,14 @@ __global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh,
   }
 }
 
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh, int to_basis,
+                                                  const DevState *ds) {
+  krylov_wave_priority();
+  if (ds->done) return;
+  final_body<S, T>(P, (int)blockIdx.x, jb, ldh, to_basis);
+}
+
 // ---- block Lanczos step j for both bases (Algorithm 4.1, steps 4-5) ----
 // aux layout per basis: [nb_spmm] ||M V_j||^2, [nb_upd S^2] U^T U, [nb_qr S^2] second-pass Gram,
 // [nb_spmm S^2] V_j^T U.
@@ -1018,11 +1024,9 @@ __device__ __forceinline__ double *aux_vju(const ArSide &A) {
 
 // U = M V_j - V_{j-1} H_{j-1,j} (H_{j-1,j} = H_{j,j-1}^T); partials of ||M V_j||^2 and V_j^T U.
 template <int S, typename T>
-__global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ldh,
-                                                    const DevState *ds) {
-  if (ds->done) return;
+__device__ __forceinline__ void lz_spmm_body(const ArPair &P, int bid, int jb, int64_t ldh) {
   int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
+  const ArSide A = side_of(P, lb, sd, bid);
   double hup[S * S];  // hup[u][t] = H_{j-1,j}[u][t] = H[j s + t][(j-1) s + u]
 #pragma unroll
   for (int u = 0; u < S; ++u)
@@ -1091,14 +1095,19 @@ __global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ld
   }
 }
 
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ldh,
+                                                    const DevState *ds) {
+  if (ds->done) return;
+  lz_spmm_body<S, T>(P, (int)blockIdx.x, jb, ldh);
+}
+
 // H_jj = V_j^T U from the partials (every workgroup forms it; workgroup 0 writes column block j
 // of H: H_{j-1,j} and H_jj); U -= V_j H_jj; partials of U^T U.
 template <int S, typename T>
-__global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t ldh,
-                                                      const DevState *ds) {
-  if (ds->done) return;
+__device__ __forceinline__ void lz_update_body(const ArPair &P, int bid, int jb, int64_t ldh) {
   int lb, sd;
-  const ArSide A = side_of(P, lb, sd);
+  const ArSide A = side_of(P, lb, sd, bid);
   double hjj[S * S];
   sum_records<S * S>(aux_vju<S>(A), A.nb_spmm, hjj);
   if (lb == 0 && threadIdx.x == 0) {
@@ -1138,6 +1147,31 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t 
     for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
 }
 
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t ldh,
+                                                      const DevState *ds) {
+  if (ds->done) return;
+  lz_update_body<S, T>(P, (int)blockIdx.x, jb, ldh);
+}
+
+// The whole block Lanczos step for small bases: one workgroup per basis runs the four phases
+// (SpMM and local three-term update, H_jj and U update, first and second QR pass with the new
+// block), with barriers where the separate kernels have launch boundaries; each phase's
+// reduction has a single record.
+template <int S, typename T>
+__global__ __launch_bounds__(TPB) void lz_fused_pair(ArPair P, int jb, int64_t ldh,
+                                                     double closure_tol, const DevState *ds) {
+  if (ds->done) return;
+  const int bid = (int)blockIdx.x;
+  lz_spmm_body<S, T>(P, bid, jb, ldh);
+  __syncthreads();
+  lz_update_body<S, T>(P, bid, jb, ldh);
+  __syncthreads();
+  qr2_body<S>(P, bid, closure_tol);
+  __syncthreads();
+  final_body<S, T>(P, bid, jb, ldh, 0);
+}
+
 // Basis columns of blocks [b0, b1) (b1 - b0 <= LZ_RING) from the block Lanczos ring: each
 // row receives (b1 - b0) s consecutive entries at once.
 template <int S, typename T>
@@ -1165,6 +1199,9 @@ __global__ __launch_bounds__(TPB) void lz_flush_pair(ArPair P, int b0, int b1) {
 }
 
 int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Bases (both sides together) up to this many rows take the single-launch Lanczos step.
+constexpr int64_t LZ_FUSED_ROWS = 2048;
 
 // Rows per gram chunk: large enough that the chunk partials stay a small fraction of the basis
 // read (2 s / rpc), small enough for a few hundred workgroups, at most 512 chunks per basis.
@@ -1535,18 +1572,31 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   if (aux0 > half || aux1 > half) return SYLV_ERR_WORKSPACE;
   P.s[0] = make_side(sv, sc, 0, half, aux0);
   if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  // small bases: the whole step in one launch, one workgroup per basis
+  const bool fused = rows0 + rows1 <= LZ_FUSED_ROWS;
   for (int i = 0; i < P.nsides; ++i) {
     const SideDesc &d = i ? *sw : sv;
     const int64_t rows = i ? rows1 : rows0;
-    P.s[i].nb_spmm = (int)nb_rows(rows);
-    P.s[i].nb_upd = (int)nb_rows(rows);  // U^T U partials come from lz_update_pair
-    P.s[i].nb_qr = (int)nb_qr(rows);
+    P.s[i].nb_spmm = fused ? 1 : (int)nb_rows(rows);
+    P.s[i].nb_upd = fused ? 1 : (int)nb_rows(rows);  // U^T U partials from lz_update_pair
+    P.s[i].nb_qr = fused ? 1 : (int)nb_qr(rows);
     P.s[i].pin = d.panel[jb % LZ_RING];
     P.s[i].pout = d.panel[(jb + 1) % LZ_RING];
     P.s[i].pprev = d.panel[(jb + LZ_RING - 1) % LZ_RING];
     P.s[i].ring = d.panel[0];
   }
   const int64_t total = rows0 + rows1;
+  if (fused) {
+    set_ranges(P, 1, sw ? 1 : 0);
+    prof_begin(sc, st);
+    lz_fused_pair<S, T><<<P.nsides, TPB, 0, st>>>(P, jb, ldh, closure_tol, ds);
+    HIPOK(hipGetLastError());
+    prof_end(sc, FAM_SPMM,
+             12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 8.0 * total * S * 9,
+             2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S + 14.0 * total * S * S, st);
+    if ((jb + 2) % LZ_RING == 0) return lanczos_flush_t<S, T>(sv, sw, jb + 2, st);
+    return 0;
+  }
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
   prof_begin(sc, st);
   lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);

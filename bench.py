@@ -87,7 +87,7 @@ def main():
                     help="sylv_options.streams (0 automatic)")
     ap.add_argument("--reorth", type=int, default=0, choices=[0, 1, 2],
                     help="sylv_options.reorth (0 automatic)")
-    ap.add_argument("--cpu-iters", type=int, default=60)
+    ap.add_argument("--cpu-iters", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="storage of the Krylov bases (fp32: mixed precision)")

@@ -913,7 +913,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
   if ((e = launch_gram(cL, cN, cL, GL, false, ldG, Mc, false, ldG, 0.0, T1, ldG, false, st, gpart,
                        GPART_CAP)))
     return e;
-  if ((e = launch_gemm(cL, cN, cN, 1.0, Mc, ldG, 1, GN, ldG, 1, 0.0, GL, ldG, st))) return e;
+  if ((e = launch_gemm_nn(cL, cN, cN, Mc, ldG, GN, ldG, GL, ldG, st))) return e;
   if ((e = launch_dot(cL, cN, T1, ldG, GL, ldG, P->dots, P->sc, st))) return e;
   double r2 = 0.0;
   HIPOK(hipMemcpyAsync(&r2, P->dots, sizeof(double), hipMemcpyDeviceToHost, st));

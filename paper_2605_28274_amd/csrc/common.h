@@ -633,6 +633,10 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
 int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
                 const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
                 bool lower, hipStream_t st, double *part = nullptr, size_t part_cap = 0);
+// C = A B (row-major, FP64 MFMA); rows of A up to roundup(M, 64) and columns of B up to
+// roundup(N, 64) must be readable, lda >= roundup(K, 32), lda and ldb multiples of 8.
+int launch_gemm_nn(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t st);
 int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st);
 // E(0:rows, 0:p) -= V(0:rows, 0:q) H(0:q, 0:p), H block upper Hessenberg; V columns
 // [q, roundup(q, 32)) must be finite.

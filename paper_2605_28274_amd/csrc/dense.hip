@@ -653,6 +653,38 @@ __global__ __launch_bounds__(256) void zero_cols_kernel(int64_t rows, T *V, int6
   }
 }
 
+// ---- C = A B for row-major operands on the pipelined slabs (one 64 x 64 tile per workgroup) ----
+// A: M x K (lda), B: K x N (ldb); rows of A up to roundup(M, 64) and columns of B up to
+// roundup(N, 64) must be readable (their products only reach masked outputs); K runs in full
+// slabs, the last K % BK entries zero-filled, so nothing past K is read.
+__global__ __launch_bounds__(256, 2) void gemm_nn_kernel(int64_t M, int64_t N, int64_t K,
+                                                         const double *__restrict__ A, int64_t lda,
+                                                         const double *__restrict__ B, int64_t ldb,
+                                                         double *__restrict__ C, int64_t ldc,
+                                                         int tiles_n) {
+  __shared__ Smem sm;
+  const int64_t i0 = (int64_t)(blockIdx.x / tiles_n) * BM, j0 = (int64_t)(blockIdx.x % tiles_n) * BN;
+  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  WaveAcc acc;
+  zero_acc(acc);
+  const int64_t kb = K / BK * BK;
+  pipelined<false, false>(sm, acc, wm, wn, A + i0 * lda, lda, B + j0, ldb, 0, kb);
+  if (K > kb) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < BK * BM; e += 256) {
+      const int kk = e / BM, ii = e % BM;
+      sm.As[0][kk][ii] = (kb + kk < K) ? A[(i0 + ii) * lda + kb + kk] : 0.0;
+      sm.Bs[0][kk][ii] = (kb + kk < K) ? B[(kb + kk) * ldb + j0 + ii] : 0.0;
+    }
+    __syncthreads();
+    mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
+  }
+  for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
+    const int64_t gi = i0 + ii, gj = j0 + jj;
+    if (gi < M && gj < N) C[gi * ldc + gj] = v;
+  });
+}
+
 // ---- generic strided GEMM with bounds masks (residual Grams and core products) ----
 __global__ __launch_bounds__(256) void gemm_kernel(int64_t M, int64_t N, int64_t K, double alpha,
                                                    const double *__restrict__ A, int64_t a_rs,
@@ -734,6 +766,17 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
   if (M <= 0 || N <= 0) return 0;
   const dim3 grid((unsigned)((N + BN - 1) / BN), (unsigned)((M + BM - 1) / BM));
   gemm_kernel<<<grid, 256, 0, st>>>(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_gemm_nn(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                   const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t st) {
+  if (M <= 0 || N <= 0) return 0;
+  if (lda % 8 || ldb % 8 || lda < (K + BK - 1) / BK * BK || ldb < (N + BN - 1) / BN * BN)
+    return SYLV_ERR_INVALID;
+  const int64_t TM = (M + BM - 1) / BM, TN = (N + BN - 1) / BN;
+  gemm_nn_kernel<<<(unsigned)(TM * TN), 256, 0, st>>>(M, N, K, A, lda, B, ldb, C, ldc, (int)TN);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -264,6 +264,35 @@ inline SellMat sell_view(int64_t rows, int64_t nnz, void *buf) {
 // acc = A[r, :] X[:, 0:S] for one row r < rows (thread r % 64 of a wave-aligned slice). Rows
 // are walked in chunks of 8 entries: all index/value loads of a chunk issue together, then all
 // its gathers, so a stencil row costs two dependent memory round trips.
+// Row c of X (S consecutive values at X + c ldx) as doubles. With vec (FP64, S even, X and ldx
+// keeping every row 16-byte aligned) the values load two at a time, halving the gather loads;
+// in == false gives zeros (the load reads row c, which the caller keeps in range).
+template <int S, typename T>
+__device__ __forceinline__ void gather_row(const T *__restrict__ X, int64_t c, int64_t ldx,
+                                           bool vec, bool in, double (&x)[S]) {
+  if constexpr (S % 2 == 0 && sizeof(T) == 8) {
+    if (vec) {
+      const double2 *p = reinterpret_cast<const double2 *>(X + c * ldx);
+#pragma unroll
+      for (int t = 0; t < S / 2; ++t) {
+        const double2 v = p[t];
+        x[2 * t] = in ? v.x : 0.0;
+        x[2 * t + 1] = in ? v.y : 0.0;
+      }
+      return;
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < S; ++t) x[t] = in ? (double)X[c * ldx + t] : 0.0;
+}
+
+// Whether gather_row may load pairs for this X and ldx.
+template <int S, typename T>
+__device__ __forceinline__ bool gather_vec(const T *X, int64_t ldx) {
+  return S % 2 == 0 && sizeof(T) == 8 && ldx % 2 == 0 &&
+         (reinterpret_cast<uintptr_t>(X) & 15) == 0;
+}
+
 template <int S, typename T = double>
 __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
                                          const T *__restrict__ X, int64_t ldx,
@@ -273,6 +302,7 @@ __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
   const int64_t k = r >> 6;
   const int w = M.width[k];
   const int64_t base = M.off[k] + (r & 63);
+  const bool vec = gather_vec<S>(X, ldx);
   for (int q0 = 0; q0 < w; q0 += 8) {
     int c[8];
     double a[8];
@@ -284,11 +314,7 @@ __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
     }
     double x[8][S];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const bool in = q0 + u < w;
-#pragma unroll
-      for (int t = 0; t < S; ++t) x[u][t] = in ? (double)X[(int64_t)c[u] * ldx + t] : 0.0;
-    }
+    for (int u = 0; u < 8; ++u) gather_row<S>(X, c[u], ldx, vec, q0 + u < w, x[u]);
 #pragma unroll
     for (int u = 0; u < 8; ++u)
 #pragma unroll

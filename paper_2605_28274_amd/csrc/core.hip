@@ -97,9 +97,10 @@ constexpr int CT_I = 32, CT_J = 64, CG_GRID = 2048;
 
 template <int S>
 struct CgTile {
-  double pc[CT_I + 4 * S][CT_J];      // P rows [ra, rb) x the tile's columns
-  double pr[CT_I][CT_J + 4 * S + 1];  // the tile's rows x P columns [ca, cb)
-  double hb[CT_I][3 * S];             // the band of H on the tile's rows
+  double pc[CT_I + 4 * S][CT_J];  // P rows [ra, rb) x the tile's columns
+  double hl[CT_I][2 * S];         // the tile's rows x P columns [ca, j0) (left of the tile)
+  double hr[CT_I][2 * S];         // the tile's rows x P columns [j0 + 64, cb) (right of it)
+  double hb[CT_I][3 * S];         // the band of H on the tile's rows
 };
 
 __host__ __device__ inline int cg_tiles_j(int q) { return (q + CT_J - 1) / CT_J; }
@@ -166,12 +167,18 @@ __device__ __forceinline__ void cg_stage(CgTile<S> &T, const CgGeom &g, int p,
   const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
 #pragma unroll
   for (int t = 0; t < 3 * S; ++t) gb[t] = (l0 + t < l1) ? G[(int64_t)jc * ldc + l0 + t] : 0.0;
-  const int nr = g.rb > g.ra ? g.rb - g.ra : 0, nc = g.cb > g.ca ? g.cb - g.ca : 0;
+  // the tile's own rows of P sit inside the column strip; only the columns of G's band left and
+  // right of the tile are staged apart
+  const int nr = g.rb > g.ra ? g.rb - g.ra : 0;
+  const int nl = g.j0 - g.ca, nrt = g.cb > g.j0 + CT_J ? g.cb - g.j0 - CT_J : 0;
   for (int e = threadIdx.x; e < nr * CT_J; e += TPB)
     T.pc[e / CT_J][e % CT_J] =
         cg_pval<SYM, FORM>(g.ra + e / CT_J, g.j0 + e % CT_J, p, R, Pp, beta, ldc);
-  for (int e = threadIdx.x; e < CT_I * nc; e += TPB)
-    T.pr[e / nc][e % nc] = cg_pval<SYM, FORM>(g.i0 + e / nc, g.ca + e % nc, p, R, Pp, beta, ldc);
+  for (int e = threadIdx.x; e < CT_I * nl; e += TPB)
+    T.hl[e / nl][e % nl] = cg_pval<SYM, FORM>(g.i0 + e / nl, g.ca + e % nl, p, R, Pp, beta, ldc);
+  for (int e = threadIdx.x; e < CT_I * nrt; e += TPB)
+    T.hr[e / nrt][e % nrt] =
+        cg_pval<SYM, FORM>(g.i0 + e / nrt, g.j0 + CT_J + e % nrt, p, R, Pp, beta, ldc);
   for (int e = threadIdx.x; e < CT_I * 3 * S; e += TPB) {
     const int ii = e / (3 * S), t = e % (3 * S);
     const int ic = g.i0 + ii < q ? g.i0 + ii : q - 1;
@@ -211,8 +218,13 @@ __device__ __forceinline__ void cg_tile_q(const CgTile<S> &T, const CgGeom &g, i
     // P G^T: row i of P meets the band of row j of G
     if (ic < p) {
 #pragma unroll
-      for (int t = 0; t < 3 * S; ++t)
-        a = fma((l0 + t < l1) ? T.pr[ii][l0 + t - g.ca] : 0.0, gb[t], a);
+      for (int t = 0; t < 3 * S; ++t) {
+        const int l = l0 + t;
+        const double v = l < g.j0            ? T.hl[ii][l - g.ca]
+                         : l < g.j0 + CT_J ? T.pc[i - g.ra][l - g.j0]
+                                           : T.hr[ii][l - g.j0 - CT_J];
+        a = fma(l < l1 ? v : 0.0, gb[t], a);
+      }
     }
     qv[u] = a;
     pk[u] = (i < g.rb && i >= g.ra) ? T.pc[i - g.ra][jj] : 0.0;

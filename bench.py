@@ -81,7 +81,7 @@ def main():
                     choices=["c1", "c2", "c3", "c5cg", "c5bi", "batch64"])
     ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--check-every", type=int, default=8,
+    ap.add_argument("--check-every", type=int, default=16,
                     help="iterations between the host's looks at the convergence flag")
     ap.add_argument("--streams-solve", type=int, default=0, choices=[0, 1, 2],
                     help="sylv_options.streams (0 automatic)")

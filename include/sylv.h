@@ -84,7 +84,7 @@ typedef struct {
 /* Options. method and max_iter size the workspace (the basis grows by s columns per CG
  * iteration and by 2s per BiCGSTAB iteration). check_every: the host waits for the device's
  * convergence flag every this many iterations (iterations enqueued after convergence do no
- * work). closure_tol: a new basis block whose norm after orthogonalization is at most
+ * work); <= 0 selects the default, 16. closure_tol: a new basis block whose norm after orthogonalization is at most
  * closure_tol times ||M V_j||_F is replaced by a zero block (Krylov space exhausted); <= 0
  * selects the default of the precision (1e-12 for FP64, 1e-6 for FP32 bases).
  * precision: SYLV_FP64 or SYLV_MIXED_FP32 (storage of the bases, see above).

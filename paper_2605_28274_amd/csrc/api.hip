@@ -277,7 +277,7 @@ struct Ctx {
   hipStream_t st = nullptr;
   sylv_csr A{}, B{};
   double closure_tol = 1e-12;
-  int check_every = 8;
+  int check_every = 16;
   int record_history = 1;
   char *ws = nullptr;
   SideDesc sv{}, sw{};
@@ -464,7 +464,7 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->closure_tol = op->closure_tol > 0 ? op->closure_tol : (L.fp32 ? 1e-6 : 1e-12);
   c->parent = parent;
   c->refine_inner_tol = op->refine_inner_tol;
-  c->check_every = op->check_every > 0 ? op->check_every : 8;
+  c->check_every = op->check_every > 0 ? op->check_every : 16;
   c->record_history = op->record_history;
   c->lagged = L.method == SYLV_METHOD_BICGSTAB && op->reorth != 1 &&
               arnoldi_lagged_supported((int)L.s, L.fp32);
@@ -1090,7 +1090,7 @@ void sylv_default_options(sylv_options *opt) {
   if (!opt) return;
   opt->method = SYLV_METHOD_BICGSTAB;
   opt->max_iter = 200;
-  opt->check_every = 8;
+  opt->check_every = 16;
   opt->record_history = 1;
   opt->closure_tol = 0.0;  // precision default
   opt->precision = SYLV_FP64;

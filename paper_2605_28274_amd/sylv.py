@@ -325,7 +325,7 @@ class Solver:
     arrays (n x s, m x s). ``method`` and ``max_iter`` size the workspace."""
 
     def __init__(self, A, B, C1, C2, lyapunov=False, method=SYLV_METHOD_BICGSTAB, max_iter=200,
-                 check_every=8, closure_tol=0.0, precision=0, refine_max=0, refine_max_iter=100,
+                 check_every=16, closure_tol=0.0, precision=0, refine_max=0, refine_max_iter=100,
                  refine_rank=8, refine_inner_tol=0.0, streams=0, reorth=0, device="cuda",
                  stream=None):
         import torch

@@ -70,3 +70,42 @@ def test_batch_argument_errors(sylv):
     b.close()
     with pytest.raises(sylv.SylvError):
         sylv.Batch(probs, nstreams=0)
+
+
+def test_batch_instances_match_the_oracle(sylv):
+    """Every instance of a batch against the CPU oracle's solve of the same problem
+    (Algorithms 4.1 / 4.2): same iteration count (CG within one; BiCGSTAB within its rounding
+    band), the oracle's early scalars to 1e-10, and the same solution, compared through the
+    sketch X Omega (both factors, so W of the Lyapunov instance is covered too)."""
+    from oracle import factored, residual
+    probs = instances()
+    tol = 1e-9
+    b = sylv.Batch(probs, nstreams=3)
+    res = b.solve(tol)
+    for i, p in enumerate(probs):
+        Vo, Xo, Wo, info = factored.solve(p, tol=tol, max_iter=p.max_iter)
+        assert res[i].status == sylv.SYLV_OK and info["status"] == factored.CONVERGED, p.name
+        band = 1 if p.method == "cg" else max(3, round(0.15 * info["iters"]))
+        assert abs(res[i].iters - info["iters"]) <= band, (p.name, res[i].iters, info["iters"])
+        ctx = b.context(i)
+        hist = sylv.sylv_get_history(ctx, p.max_iter)
+        k = min(5, info["iters"])
+        a, o = np.asarray(hist["alpha"][:k]), np.asarray(info["alpha"][:k])
+        assert np.max(np.abs(a - o) / np.abs(o)) < 1e-10, p.name
+        rv, rw = sylv.sylv_get_factors(ctx)
+        Vb = torch.empty((p.n, rv), dtype=torch.float64, device="cuda")
+        Xb = torch.empty((rv, rw), dtype=torch.float64, device="cuda")
+        Wb = torch.empty((p.m, rw), dtype=torch.float64, device="cuda")
+        sylv.sylv_get_factors(ctx, Vb, Xb, Wb)
+        V, X, W = Vb.cpu().numpy(), Xb.cpu().numpy(), Wb.cpu().numpy()
+        if p.lyapunov:
+            assert np.array_equal(V, W)
+        Om = residual.sketch_matrix(p.m, 8, 7)
+        Sg, So = residual.sketch(V, X, W, Om), residual.sketch(Vo, Xo, Wo, Om)
+        # both iterates meet ||R|| <= tol ||C||; these small operators have condition numbers
+        # of at most a few thousand, so the solutions agree to about kappa * tol
+        assert np.linalg.norm(Sg - So) / np.linalg.norm(So) < 1e-5, p.name
+        _, rel = sylv.sylv_residual_norm(ctx)
+        _, ro = residual.dense_residual(p.A, p.B, p.C1, p.C2, V, X, W)
+        assert rel <= 1.05 * tol and abs(rel - ro) <= 1e-3 * tol, (p.name, rel, ro)
+    b.close()

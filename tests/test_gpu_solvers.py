@@ -220,19 +220,23 @@ def test_c2_bicgstab_parity(sylv):
     it = gold["iters"]
     h = g["hist"]
     # Section 5.1, Example 2: the histories of two BiCGSTAB implementations coincide early and
-    # part later as their rounding errors propagate differently, with comparable behaviour
-    # overall. Here the relative gap between this run's and the oracle's residual history (same
-    # inputs, FP64 on both sides, different summation orders) grows about tenfold every two
-    # iterations from 1e-13 at iteration 16 and is of order one by iteration 40 (residual
-    # ~3e-3), long before 1e-6; two GPU builds that differ only in the summation order of the
-    # Gram-Schmidt sweeps reach 1e-6 at iterations 231 and 257 (oracle: 266) and stop at 322 and
-    # 316 (oracle: 321). So the first iterations are compared tightly and the rest as overall
-    # behaviour: the counts to 1e-6 and to the tolerance within 20% and 25%.
+    # part later as their rounding errors propagate differently. The bands for the iteration
+    # counts come from the oracle itself: reruns with every entry of C1 moved by about one unit
+    # in its last place (tests/golden/c2_bicgstab_spread.json, written by make_golden.py and
+    # re-checked on the CPU by test_oracle_spread.py) move the count to 1e-6 by up to ~40 and
+    # the final count by up to ~16 iterations. This run must stay within 1.5 times that spread.
+    with open(os.path.join(GOLDEN, "c2_bicgstab_spread.json")) as f:
+        spread = json.load(f)
+    base = spread["base"]
+    d6 = max(abs(r["k6"] - base["k6"]) for r in spread["runs"])
+    d8 = max(abs(r["k8"] - base["k8"]) for r in spread["runs"])
+
     def first_below(rr, level):
         return int(np.argmax(np.asarray(rr) <= level)) + 1
     k6, k6o = first_below(h["relres"], 1e-6), first_below(gold["relres"], 1e-6)
-    assert abs(k6 - k6o) <= round(0.20 * k6o), (k6, k6o)
-    assert abs(g["res"].iters - it) <= round(0.25 * it), (g["res"].iters, it)
+    assert k6o == base["k6"] and it == base["k8"]
+    assert abs(k6 - k6o) <= int(np.ceil(1.5 * d6)), (k6, k6o, d6)
+    assert abs(g["res"].iters - it) <= int(np.ceil(1.5 * d8)), (g["res"].iters, it, d8)
     for key in ("alpha", "omega", "relres"):
         a, b = np.asarray(h[key][:12]), np.asarray(gold[key][:12])
         assert np.max(np.abs(a - b) / np.abs(b)) < 1e-10, key

@@ -258,6 +258,22 @@ size_t sylv_csr_transpose_scratch_bytes(int64_t rows);
 int sylv_csr_transpose(const sylv_csr *A, int32_t *out_row_ptr, int32_t *out_col_idx,
                        double *out_values, void *scratch, void *stream);
 
+/* CSR transpose for callers that cannot allocate device memory: code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc. Same result as sylv_csr_transpose
+ * (canonical, bit-identical), but its scratch (2 (rows + 2) ints of column counts and scatter
+ * cursors) lives in a static device array of the library, one per GPU, held until the process
+ * ends: at most SYLV_NOALLOC_TRANSPOSE_MAX_ROWS rows (16 MiB of scratch); larger matrices return
+ * SYLV_ERR_WORKSPACE (sylv_last_error names the limit). The call allocates nothing and only
+ * enqueues kernels on `stream` (no memset or memcpy, no synchronization, so it may be captured
+ * into a HIP graph); the caller orders later work on the same stream or synchronizes before
+ * reading the outputs on the host. Every call on one GPU shares that GPU's scratch array: calls
+ * that overlap on one GPU (on different streams, or from different threads) race and must be
+ * serialized by the caller. out_row_ptr (rows + 1), out_col_idx (nnz), out_values (nnz) are
+ * caller-owned device buffers. */
+#define SYLV_NOALLOC_TRANSPOSE_MAX_ROWS ((int64_t)1 << 21)
+int sylv_csr_transpose_noalloc(const sylv_csr *A, int32_t *out_row_ptr, int32_t *out_col_idx,
+                               double *out_values, void *stream);
+
 /* C (M x N, ldc) = alpha * op(A) op(B) + beta * C in FP64 on FP64 MFMA, with element strides:
  * A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs] (a transpose is a swap of the two
  * strides). The dense contraction behind the Gram products of the residual evaluation and the

@@ -1082,6 +1082,8 @@ void note_hip_error(hipError_t e, const char *what) {
   snprintf(g_last_error, sizeof(g_last_error), "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
 }
 
+void note_error(const char *msg) { snprintf(g_last_error, sizeof(g_last_error), "%s", msg); }
+
 extern "C" {
 
 const char *sylv_last_error(void) { return g_last_error; }

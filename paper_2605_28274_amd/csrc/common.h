@@ -60,6 +60,8 @@ enum {
 
 // Records the last HIP runtime error seen by the library (reported by sylv_last_error).
 void note_hip_error(hipError_t e, const char *what);
+// Records a library error message (reported by sylv_last_error).
+void note_error(const char *msg);
 
 #define HIPOK(x)                                      \
   do {                                                \

@@ -1,6 +1,7 @@
 // CSR kernels: SpMM with tall-skinny panels (the sparse products of the block Lanczos /
 // Arnoldi step, eq. (3.8)), the wide SpMM of the residual evaluation, CSR validation and an
 // exact CSR transpose (B^T for the W basis).
+#include <mutex>
 #include <vector>
 
 #include "common.h"
@@ -161,20 +162,36 @@ int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int
 
 size_t csr_transpose_scratch(int64_t rows) { return (size_t)(rows + 2) * 2 * sizeof(int) + 256; }
 
+namespace {
+__global__ void fill_int_kernel(int64_t len, int *__restrict__ dst, int v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) dst[i] = v;
+}
+
+__global__ void copy_int_kernel(int64_t len, const int32_t *__restrict__ src, int *__restrict__ dst) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < len) dst[i] = src[i];
+}
+}  // namespace
+
+// Only kernels are enqueued (no memset or memcpy nodes), so the sequence may be captured into a
+// HIP graph; the scratch counters are cleared by a fill kernel.
 int launch_csr_transpose(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci,
                          const double *val, int32_t *orp, int32_t *oci, double *oval,
                          void *scratch, hipStream_t st) {
   int *cnt = reinterpret_cast<int *>(scratch);
   int *cursor = cnt + (rows + 2);
-  HIPOK(hipMemsetAsync(cnt, 0, sizeof(int) * (rows + 1), st));
+  fill_int_kernel<<<(unsigned)((rows + 1 + 255) / 256), 256, 0, st>>>(rows + 1, cnt, 0);
+  HIPOK(hipGetLastError());
   if (nnz > 0)
     csr_count_kernel<<<(unsigned)((nnz + 255) / 256), 256, 0, st>>>(nnz, ci, cnt);
   HIPOK(hipGetLastError());
   scan_kernel<<<1, 1024, 0, st>>>(rows + 1, cnt, orp);
   HIPOK(hipGetLastError());
   // cursor[c] = orp[c]; the +1 shift of cnt makes the inclusive scan of cnt the row starts
-  HIPOK(hipMemcpyAsync(cursor, orp, sizeof(int) * rows, hipMemcpyDeviceToDevice, st));
   const unsigned g = (unsigned)((rows + 255) / 256);
+  copy_int_kernel<<<g, 256, 0, st>>>(rows, orp, cursor);
+  HIPOK(hipGetLastError());
   csr_scatter_kernel<<<g, 256, 0, st>>>(rows, rp, ci, val, cursor, oci, oval);
   HIPOK(hipGetLastError());
   csr_sort_rows_kernel<<<g, 256, 0, st>>>(rows, orp, oci, oval);
@@ -299,4 +316,59 @@ int launch_sell_spmm(int s, const SellMat &M, const double *X, int64_t ldx, doub
   }
   HIPOK(hipGetLastError());
   return 0;
+}
+
+// ---- CSR transpose for callers that cannot allocate ----
+//
+// The transpose's scratch (column counts and scatter cursors, 2 (rows + 2) ints) lives in a
+// file-scope device array instead of a caller buffer. Each GPU holds its own copy for the
+// life of the process; its device address is looked up once per device and kept, and only that
+// address is handed to kernels (the array's name is not a device address in host code).
+namespace {
+
+constexpr int64_t NOALLOC_MAX_ROWS = SYLV_NOALLOC_TRANSPOSE_MAX_ROWS;
+constexpr size_t NOALLOC_SCRATCH_INTS = 2 * (size_t)(NOALLOC_MAX_ROWS + 2) + 64;
+static_assert(NOALLOC_SCRATCH_INTS * sizeof(int) >= (size_t)(NOALLOC_MAX_ROWS + 2) * 2 * sizeof(int) + 256,
+              "scratch array smaller than the transpose needs at the row limit");
+
+__device__ __align__(256) int scratch[NOALLOC_SCRATCH_INTS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[MAX_DEVICES] = {};
+
+// Device address of this device's scratch array (looked up on the first call per device, with
+// that device current).
+int scratch_address(void **out) {
+  int dev = -1;
+  HIPOK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= MAX_DEVICES) return SYLV_ERR_INVALID;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HIPOK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return SYLV_ERR_HIP;
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return 0;
+}
+
+}  // namespace
+
+extern "C" int sylv_csr_transpose_noalloc(const sylv_csr *A, int32_t *out_row_ptr,
+                                          int32_t *out_col_idx, double *out_values,
+                                          void *stream) {
+  if (!A || !out_row_ptr || A->rows <= 0 || A->nnz < 0 || A->nnz >= ((int64_t)1 << 31) ||
+      !A->row_ptr || (A->nnz > 0 && (!A->col_idx || !A->values || !out_col_idx || !out_values)))
+    return SYLV_ERR_INVALID;
+  if (A->rows > NOALLOC_MAX_ROWS) {
+    note_error("sylv_csr_transpose_noalloc: rows exceed SYLV_NOALLOC_TRANSPOSE_MAX_ROWS");
+    return SYLV_ERR_WORKSPACE;
+  }
+  void *scr = nullptr;
+  int e = scratch_address(&scr);
+  if (e) return e;
+  return launch_csr_transpose(A->rows, A->nnz, A->row_ptr, A->col_idx, A->values, out_row_ptr,
+                              out_col_idx, out_values, scr, reinterpret_cast<hipStream_t>(stream));
 }

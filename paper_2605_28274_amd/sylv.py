@@ -105,6 +105,10 @@ _lib.sylv_csr_transpose_scratch_bytes.restype = c_size_t
 _lib.sylv_csr_transpose.argtypes = [POINTER(sylv_csr), c_void_p, c_void_p, c_void_p, c_void_p,
                                     c_void_p]
 _lib.sylv_csr_transpose.restype = c_int
+_lib.sylv_csr_transpose_noalloc.argtypes = [POINTER(sylv_csr), c_void_p, c_void_p, c_void_p,
+                                            c_void_p]
+_lib.sylv_csr_transpose_noalloc.restype = c_int
+SYLV_NOALLOC_TRANSPOSE_MAX_ROWS = 1 << 21
 class sylv_kernel_stat(ctypes.Structure):
     _fields_ = [("family", c_int), ("launches", c_int64), ("ms", c_double), ("bytes", c_double),
                 ("flops", c_double)]
@@ -303,6 +307,15 @@ def sylv_csr_transpose(csr: sylv_csr, out_rp, out_ci, out_va, scratch, stream=No
                                  c_void_p(_ptr(out_va)), c_void_p(_ptr(scratch)), _stream(stream))
     if rc != 0:
         raise SylvError(rc, "sylv_csr_transpose")
+
+
+def sylv_csr_transpose_noalloc(csr: sylv_csr, out_rp, out_ci, out_va, stream=None) -> None:
+    """Enqueues the transpose on the stream and returns (no synchronization)."""
+    rc = _lib.sylv_csr_transpose_noalloc(byref(csr), c_void_p(_ptr(out_rp)),
+                                         c_void_p(_ptr(out_ci)), c_void_p(_ptr(out_va)),
+                                         _stream(stream))
+    if rc != 0:
+        raise SylvError(rc, "sylv_csr_transpose_noalloc")
 
 
 def sylv_dgemm(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc, stream=None) -> None:

@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="storage of the Krylov bases (fp32: mixed precision)")
+    ap.add_argument("--gram-precision", type=int, default=0, choices=[0, 1, 2],
+                    help="sylv_options.gram_precision of the true-residual Grams")
     ap.add_argument("--pmc-pass", action="store_true",
                     help="one step only (for hardware-counter runs of rocprofv3 --pmc)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -138,7 +140,8 @@ def main():
                                 p.max_iter, check_every=args.check_every,
                                 precision=sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64,
                                 refine_max=args.refine, refine_max_iter=100,
-                                streams=args.streams_solve, reorth=args.reorth)
+                                streams=args.streams_solve, reorth=args.reorth,
+                                gram_precision=args.gram_precision)
     ws = torch.empty(sylv.sylv_workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
     rmax = (p.max_iter + 1 if cg else 2 * p.max_iter + 1) * p.s
     if args.refine > 0:  # the summed iterate stacks the corrections' bases

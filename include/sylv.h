@@ -104,7 +104,22 @@ typedef struct {
  * new block twice in its own step (three passes over the basis per step); 2 takes the second
  * pass of each block one step later, together with the first pass of the next block (two passes
  * per step; FP64 bases and s <= 4 only); 0 chooses 2 where it is available. The bases agree to
- * rounding. sylv_default_options() fills sensible values. */
+ * rounding.
+ * gram_precision (Gram products of the true-residual evaluation, sylv_residual_norm): 0 forms
+ * every Gram block in FP64 on FP64 matrix cores; 1 forms the blocks that involve the basis
+ * defects (A V - V H, B^T W - W G, the right-hand side's QR defects and the C2 columns stacked
+ * with them) in split BF16 on the BF16 matrix cores (each value split into two BF16 parts, three
+ * partial products, FP32 partial sums over at most 4096 rows, summed in FP64; about 1e-5
+ * relative error per Gram entry) and the basis Grams V^T V, W^T W in FP64: the defect terms are
+ * at rounding level, so their contribution to the residual norm stays accurate to far better
+ * than 1e-5 of the norm; 2 forms every block in split BF16 (the norm then carries a relative
+ * error of order 1e-5).
+ * verify: 1 evaluates the true residual after a solve
+ * that stopped on the recursive test and, when it exceeds tol, solves again with the recursive
+ * target lowered (at most twice); the result then reports rel_res_true, and the status is
+ * SYLV_OK only when the true residual meets tol (SYLV_NOT_CONVERGED otherwise). 0 returns on the
+ * recursive test alone (the algorithms' stopping rule). sylv_default_options() fills sensible
+ * values (streams 0, reorth 0, gram_precision 0, verify 1). */
 typedef struct {
   int method;
   int max_iter;
@@ -118,13 +133,16 @@ typedef struct {
   double refine_inner_tol;
   int streams;
   int reorth;
+  int gram_precision;
+  int verify;
 } sylv_options;
 
 /* Outcome of one solve. rank_v / rank_w: number of columns of the returned V and W;
  * rel_res_recursive: ||R_k|| / ||R_0|| from the recurrence (the algorithm's stopping test).
  * With outer refinement: iters sums the iterations of all solves, outer_steps counts the
  * correction solves, the factors are those of the summed iterate and rel_res_true is its FP64
- * true relative residual (status SYLV_OK when it meets tol); otherwise rel_res_true < 0. */
+ * true relative residual (status SYLV_OK when it meets tol). With verify, rel_res_true is the
+ * true relative residual of a converged solve. Otherwise rel_res_true < 0. */
 typedef struct {
   int status;
   int iters;

@@ -40,6 +40,10 @@ struct Layout {
   size_t off_Om, off_Zb, off_Yb, off_Eb, off_Fb, off_Pp, off_Qp, off_sa, off_sb, off_sc2, off_sd,
       off_sk, off_sT, off_tn, off_atrp, off_atci, off_atval, off_atscr, off_GL, off_GN, off_Mc,
       off_T1, off_Es, off_rinfo, off_gpart;
+  // split-BF16 residual Grams: packed chunk, column maxima / exponents, FP32 partials
+  int gram_prec = 0;
+  int64_t cpad = 0;
+  size_t off_pack = 0, off_cmaxb = 0, off_cexp = 0, off_bpart = 0, bpart_floats = 0;
   size_t total = 0;
 };
 
@@ -72,6 +76,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32) return SYLV_ERR_INVALID;
   if (op->streams < 0 || op->streams > 2) return SYLV_ERR_INVALID;
   if (op->reorth < 0 || op->reorth > 2) return SYLV_ERR_INVALID;
+  if (op->gram_precision < 0 || op->gram_precision > 2 || op->verify < 0 || op->verify > 1)
+    return SYLV_ERR_INVALID;
   if (op->method == SYLV_METHOD_BICGSTAB && op->reorth == 2 &&
       !arnoldi_lagged_supported(pb->s, op->precision == SYLV_MIXED_FP32))
     return SYLV_ERR_INVALID;
@@ -221,6 +227,15 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
             L.refine_max * round_up(L.child_rmax + 2 * L.refine_q, 64) + 64;
     L.off_Es = bump(cur, (size_t)L.rc_rows * L.ldE * 8);
     L.off_gpart = bump(cur, (size_t)GPART_CAP * 8);
+    L.gram_prec = op->gram_precision;
+    if (L.gram_prec > 0) {
+      L.cpad = bf16_pack_width(L.cmax);
+      L.off_pack = bump(cur, bf16_pack_bytes(L.rc_rows, L.cpad));
+      L.off_cmaxb = bump(cur, (size_t)L.cpad * 8);
+      L.off_cexp = bump(cur, (size_t)L.cpad * 4);
+      L.bpart_floats = bf16_part_floats(L.cpad, L.rc_rows);
+      L.off_bpart = bump(cur, L.bpart_floats * 4);
+    }
   }
   L.total = cur + ALIGN;
   return 0;
@@ -315,6 +330,9 @@ struct Ctx {
   double rel_true = -1.0;    // FP64 true residual of the summed iterate (refined solves)
   int outer_steps = 0;
   int in_refine = 0;         // the refinement's own first solve is running
+  int verify = 1;            // check the true residual after a converged solve
+  int res_valid = 0;         // abs_res / rel_res hold the residual of the current iterate
+  double res_abs = 0.0, res_rel = 0.0;
 };
 
 template <typename T>
@@ -379,6 +397,7 @@ int begin_solve(Ctx *c, double tol, int max_iter, int method) {
                                  c->st);
   if (err) return err;
   c->solved = 0;
+  c->res_valid = 0;
   c->method = method;
   c->max_iter_run = max_iter;
   return 0;
@@ -465,6 +484,7 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->parent = parent;
   c->refine_inner_tol = op->refine_inner_tol;
   c->check_every = op->check_every > 0 ? op->check_every : 16;
+  c->verify = op->verify;
   c->record_history = op->record_history;
   c->lagged = L.method == SYLV_METHOD_BICGSTAB && op->reorth != 1 &&
               arnoldi_lagged_supported((int)L.s, L.fp32);
@@ -757,7 +777,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
     const char *ptr;  // rowed: row r at ptr + r ld esz; else E-buffer columns (chunk rows)
     bool f32, rowed;
     int64_t ld, cols, esz;
-    const double *unused;
+    bool defect;      // basis defects, QR defects and the C2 columns beside them
   };
   double *Es = at<double>(P, PL.off_Es);
   for (Ctx *cj : steps)
@@ -792,25 +812,25 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
     const char *eb = reinterpret_cast<const char *>(Es + eoff[j]);
     idx[j].v = (int)segL.size();
     segL.push_back(Seg{static_cast<const char *>(cj->sv.basis), (bool)CL.fp32, true, CL.ldb, q,
-                       CL.esz, nullptr});
+                       CL.esz, false});
     idx[j].e = (int)segL.size();
-    segL.push_back(Seg{eb, false, false, PL.ldE, p + s, 8, nullptr});
+    segL.push_back(Seg{eb, false, false, PL.ldE, p + s, 8, true});
     fillL.push_back(Fill{eoff[j] + p, at<double>(cj, CL.off_d1), (int)s});
     idx[j].w = (int)segN.size();
     segN.push_back(Seg{static_cast<const char *>(cj->sw.basis), (bool)CL.fp32, true, CL.ldb, q,
-                       CL.esz, nullptr});
+                       CL.esz, false});
     idx[j].eb = (int)segN.size();
-    segN.push_back(Seg{eb, false, false, PL.ldE, p + 2 * s, 8, nullptr});
+    segN.push_back(Seg{eb, false, false, PL.ldE, p + 2 * s, 8, true});
     fillN.push_back(Fill{eoff[j] + p, at<double>(cj, CL.off_d2), (int)s});
     fillN.push_back(Fill{eoff[j] + p + s, at<double>(cj, CL.off_c2), (int)s});
   }
   for (size_t i = 0; i + 1 < steps.size(); ++i) {
     pL.push_back((int)segL.size());
     segL.push_back(Seg{reinterpret_cast<const char *>(pp_panel(P, (int)i)), false, true, NLD,
-                       P->kid_k[i], 8, nullptr});
+                       P->kid_k[i], 8, false});
     qN.push_back((int)segN.size());
     segN.push_back(Seg{reinterpret_cast<const char *>(qq_panel(P, (int)i)), false, true, NLD,
-                       P->kid_k[i], 8, nullptr});
+                       P->kid_k[i], 8, false});
   }
   auto offsets = [](const std::vector<Seg> &segs) {
     std::vector<int64_t> o(segs.size() + 1, 0);
@@ -866,9 +886,38 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
                                     Es + f.col, PL.ldE, st)))
           return ee;
       const double beta = r0 == 0 ? 0.0 : 1.0;
+      // split BF16 for the blocks with a defect operand (gram_precision 1) or for all (2)
+      auto bf16_block = [&](size_t a, size_t b) {
+        return PL.gram_prec == 2 || (PL.gram_prec == 1 && (segs[a].defect || segs[b].defect));
+      };
+      bool any_bf16 = false;
+      for (size_t a = 0; a < segs.size(); ++a)
+        for (size_t b = 0; b <= a; ++b) any_bf16 = any_bf16 || bf16_block(a, b);
+      if (any_bf16) {
+        if (segs.size() > (size_t)BF_MAX_SEGS) return SYLV_ERR_WORKSPACE;
+        BfSegs bs{};
+        for (size_t a = 0; a < segs.size(); ++a) {
+          const Seg &A = segs[a];
+          bs.s[a] = BfSeg{A.ptr + (A.rowed ? r0 * A.ld * A.esz : 0), A.ld, offs[a], A.cols,
+                          (int)A.esz, 0};
+        }
+        bs.count = (int)segs.size();
+        if ((ee = launch_bf16_pack(bs, nr, offs.back(), PL.cpad,
+                                   at<unsigned long long>(P, PL.off_cmaxb), at<int>(P, PL.off_cexp),
+                                   at<char>(P, PL.off_pack), st)))
+          return ee;
+      }
       for (size_t a = 0; a < segs.size(); ++a)
         for (size_t b = 0; b <= a; ++b) {
           const Seg &A = segs[a], &B = segs[b];
+          if (bf16_block(a, b)) {
+            if ((ee = launch_gram_bf16(A.cols, B.cols, nr, at<char>(P, PL.off_pack), PL.cpad,
+                                       at<int>(P, PL.off_cexp), offs[a], offs[b], beta,
+                                       G + offs[a] * ldG + offs[b], ldG, a == b, st,
+                                       at<float>(P, PL.off_bpart), PL.bpart_floats)))
+              return ee;
+            continue;
+          }
           const char *pa = A.ptr + (A.rowed ? r0 * A.ld * A.esz : 0);
           const char *pb = B.ptr + (B.rowed ? r0 * B.ld * B.esz : 0);
           if ((ee = launch_gram(A.cols, B.cols, nr, pa, A.f32, A.ld, pb, B.f32, B.ld, beta,
@@ -928,6 +977,24 @@ std::vector<Ctx *> refine_steps(Ctx *P) {
   std::vector<Ctx *> v{P};
   v.insert(v.end(), P->kids.begin(), P->kids.end());
   return v;
+}
+
+// True residual of the current (summed) iterate, kept until the next solve.
+int true_residual(Ctx *c, double *abs_res, double *rel_res) {
+  if (!c->res_valid) {
+    int e = read_state(c);
+    if (e) return e;
+    if (c->rank == 0 && c->kids.empty()) {
+      c->res_abs = c->h_ds->normR0;
+      c->res_rel = 1.0;
+    } else if ((e = stacked_residual(c, refine_steps(c), &c->res_abs, &c->res_rel))) {
+      return e;
+    }
+    c->res_valid = 1;
+  }
+  if (abs_res) *abs_res = c->res_abs;
+  if (rel_res) *rel_res = c->res_rel;
+  return 0;
 }
 
 // Solve with outer refinement: the first solve (to max(tol, refine_inner_tol)); then, while the
@@ -1051,6 +1118,9 @@ int refined_solve(Ctx *P, int method, double tol, int max_iter, sylv_result *res
     if (rel <= tol || J >= PL.refine_max || !more) break;
   }
   P->rel_true = rel;
+  P->res_abs = absr;
+  P->res_rel = rel;
+  P->res_valid = 1;
   P->outer_steps = (int)P->kids.size();
   int status = rel <= tol ? SYLV_OK
                           : (first_status == SYLV_BREAKDOWN ? SYLV_BREAKDOWN : SYLV_NOT_CONVERGED);
@@ -1102,6 +1172,8 @@ void sylv_default_options(sylv_options *opt) {
   opt->refine_inner_tol = 0.0;
   opt->streams = 0;
   opt->reorth = 0;
+  opt->gram_precision = 0;
+  opt->verify = 1;
 }
 
 size_t sylv_workspace_bytes(const sylv_problem *prob, const sylv_options *opt) {
@@ -1174,7 +1246,7 @@ const char *sylv_kernel_family_name(int family) {
   return (family >= 0 && family < FAM_COUNT) ? names[family] : "unknown";
 }
 
-int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
+static int cg_body(void *ctx, double tol, int max_iter, sylv_result *res) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
   if (c->L.refine_max > 0 && !c->in_refine)
@@ -1240,7 +1312,7 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
   return end_solve(c, max_iter, secs, res);
 }
 
-int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res) {
+static int bicg_body(void *ctx, double tol, int max_iter, sylv_result *res) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
   if (c->L.refine_max > 0 && !c->in_refine)
@@ -1323,6 +1395,49 @@ int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res
   return end_solve(c, max_iter, secs, res);
 }
 
+// A solve followed, when the context verifies, by the true residual of the converged iterate:
+// if it misses tol (the recursive residual of the recurrence drifted from the true one), the
+// solve runs again with the recursive target lowered in proportion, at most twice.
+static int solve_verified(void *ctx, int method, double tol, int max_iter, sylv_result *res) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return SYLV_ERR_INVALID;
+  auto run = [&](double t) {
+    return method == SYLV_METHOD_CG ? cg_body(ctx, t, max_iter, res)
+                                    : bicg_body(ctx, t, max_iter, res);
+  };
+  auto t0 = std::chrono::steady_clock::now();
+  int st = run(tol);
+  const bool verify = c->verify && !c->parent && !c->in_refine && c->L.refine_max == 0;
+  if (st != SYLV_OK || !verify) return st;
+  double target = tol;
+  for (int round = 0;; ++round) {
+    double a = 0.0, r = 0.0;
+    int e = true_residual(c, &a, &r);
+    if (e) return e;
+    if (r <= tol || round == 2) {
+      if (r > tol) c->status = SYLV_NOT_CONVERGED;
+      if (res) {
+        res->status = c->status;
+        res->rel_res_true = r;
+        res->seconds =
+            std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      }
+      return c->status;
+    }
+    target *= std::min(0.5, 0.5 * tol / r);
+    st = run(target);
+    if (st != SYLV_OK) return st;
+  }
+}
+
+int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
+  return solve_verified(ctx, SYLV_METHOD_CG, tol, max_iter, res);
+}
+
+int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res) {
+  return solve_verified(ctx, SYLV_METHOD_BICGSTAB, tol, max_iter, res);
+}
+
 int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx, double *W,
                      int64_t ldw, int64_t *rank_v, int64_t *rank_w) {
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
@@ -1386,14 +1501,7 @@ int sylv_residual_norm(void *ctx, double *abs_res, double *rel_res) {
   if (!c) return SYLV_ERR_INVALID;
   if (!c->solved) return SYLV_ERR_STATE;
   if (c->parent) return SYLV_ERR_STATE;
-  int e = read_state(c);
-  if (e) return e;
-  if (c->rank == 0 && c->kids.empty()) {
-    if (abs_res) *abs_res = c->h_ds->normR0;
-    if (rel_res) *rel_res = 1.0;
-    return 0;
-  }
-  return stacked_residual(c, refine_steps(c), abs_res, rel_res);
+  return true_residual(c, abs_res, rel_res);
 }
 
 int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double *Y, int64_t ldy,

@@ -666,6 +666,33 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
 int launch_gemm_nn(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                    const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t st);
 int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st);
+// Split-BF16 Grams (gram_bf16.hip). The stacked columns of one row chunk come from up to
+// BF_MAX_SEGS segments: segment i supplies columns [col0, col0 + cols) from a row-major source
+// (row r at ptr + r ld esz, esz 4 for float or 8 for double; row 0 is the chunk's first row).
+constexpr int BF_MAX_SEGS = 16;
+struct BfSeg {
+  const char *ptr;
+  int64_t ld, col0, cols;
+  int esz, pad_;
+};
+struct BfSegs {
+  BfSeg s[BF_MAX_SEGS];
+  int count;
+};
+// Packed width for ctot stacked columns; bytes of the packed chunk; FP32 partial capacity that
+// any Gram block of a cpad-wide pack over `rows` rows fits into.
+int64_t bf16_pack_width(int64_t ctot);
+size_t bf16_pack_bytes(int64_t rows, int64_t cpad);
+size_t bf16_part_floats(int64_t cpad, int64_t rows);
+// Column maxima, per-column power-of-two scales (cexp, cpad ints) and the hi/lo pack of the
+// chunk's nr rows; cmax: cpad 64-bit words of scratch.
+int launch_bf16_pack(const BfSegs &sg, int64_t nr, int64_t ctot, int64_t cpad,
+                     unsigned long long *cmax, int *cexp, void *packed, hipStream_t st);
+// C (M x N, ldc) (+)= A^T B over the nr packed rows, A = stacked columns [a0, a0 + M), B =
+// [b0, b0 + N), in split BF16 with FP32 partials summed in FP64; `lower` as launch_gram.
+int launch_gram_bf16(int64_t M, int64_t N, int64_t nr, const void *packed, int64_t cpad,
+                     const int *cexp, int64_t a0, int64_t b0, double beta, double *C, int64_t ldc,
+                     bool lower, hipStream_t st, float *part, size_t part_floats);
 // E(0:rows, 0:p) -= V(0:rows, 0:q) H(0:q, 0:p), H block upper Hessenberg; V columns
 // [q, roundup(q, 32)) must be finite.
 int launch_defect_gemm(int64_t rows, int p, int q, int s, const void *V, bool v_fp32, int64_t ldv,

@@ -64,7 +64,8 @@ class sylv_options(ctypes.Structure):
     _fields_ = [("method", c_int), ("max_iter", c_int), ("check_every", c_int),
                 ("record_history", c_int), ("closure_tol", c_double), ("precision", c_int),
                 ("refine_max", c_int), ("refine_max_iter", c_int), ("refine_rank", c_int),
-                ("refine_inner_tol", c_double), ("streams", c_int), ("reorth", c_int)]
+                ("refine_inner_tol", c_double), ("streams", c_int), ("reorth", c_int),
+                ("gram_precision", c_int), ("verify", c_int)]
 
 
 class sylv_result(ctypes.Structure):
@@ -339,8 +340,8 @@ class Solver:
 
     def __init__(self, A, B, C1, C2, lyapunov=False, method=SYLV_METHOD_BICGSTAB, max_iter=200,
                  check_every=16, closure_tol=0.0, precision=0, refine_max=0, refine_max_iter=100,
-                 refine_rank=8, refine_inner_tol=0.0, streams=0, reorth=0, device="cuda",
-                 stream=None):
+                 refine_rank=8, refine_inner_tol=0.0, streams=0, reorth=0, gram_precision=0,
+                 verify=1, device="cuda", stream=None):
         import torch
         self.device = device
         self.n, self.s = C1.shape
@@ -357,7 +358,8 @@ class Solver:
                                        closure_tol=closure_tol, precision=precision,
                                        refine_max=refine_max, refine_max_iter=refine_max_iter,
                                        refine_rank=refine_rank, refine_inner_tol=refine_inner_tol,
-                                       streams=streams, reorth=reorth)
+                                       streams=streams, reorth=reorth,
+                                       gram_precision=gram_precision, verify=verify)
         nbytes = sylv_workspace_bytes(self.problem, self.options)
         if nbytes == 0:
             raise SylvError(SYLV_ERR_INVALID, "sylv_workspace_bytes")

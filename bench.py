@@ -1,27 +1,33 @@
 #!/usr/bin/env python3
 """Benchmark of the factored Krylov hot path on one MI355X.
 
-Default workload (`--workload c2`): factored BiCGSTAB, FP64, A = 2D convection-diffusion
-128 x 128 (Pe = 10), B = 1D convection-diffusion m = 8192 (Pe = 10), s = 2, C1, C2 ~ N(0, 1)
-(seed 1002), tol 1e-8. Other workloads (same JSON line, used for measurements and profiles):
+Default workload (`--workload c5cg`): Lyapunov factored CG, FP64, A = 2D Laplacian on a
+1024 x 1024 grid (n = m = 1,048,576), B = A^T, s = 1, C1 ~ N(0, 1) (seed 1005), tol 1e-8, the
+largest single-GPU configuration. Other workloads (same JSON line):
   c1    factored CG, FP64, 1D Laplacians (n+1)^2 tridiag, n = 256, m = 192, s = 1, 200 iterations
+  c2    factored BiCGSTAB, FP64, 2D CD 128^2 (Pe = 10) x 1D CD m = 8192 (Pe = 10), s = 2
   c3    factored BiCGSTAB, FP64, 3D CD 64^3 x 2D CD 256^2 (Pe = 10), s = 4
-  c5cg  Lyapunov factored CG, FP64, 2D Laplacian 1024^2, s = 1
   c5bi  Lyapunov factored BiCGSTAB, FP64, 2D CD 1024^2 (Pe = 1), s = 1, 200-iteration window
   batch64  64 independent instances (2D A with n in [1024, 32768]; 1D or 2D B with m in [512,
         16384]; s in {1, 2, 4}; CG on Laplacians and BiCGSTAB on Pe = 10 alternately), solved as
-        one batch over --streams streams; the same instances solved one after another on one
-        stream are timed beside it (`sequential_ms`)
+        one batch over --streams streams, beside the same instances one after another
 
 One step = one pass of the whole path over resident inputs: sylv_create (CSR validation, B^T,
-sliced-ELLPACK copies, QR of C1 and C2), the factored solve to ||R|| <= tol ||R0|| (or the
-iteration cap), sylv_get_factors into device buffers and sylv_residual_norm (FP64 true
-residual). `value` is factored iterations per second over whole steps; ms_per_step is the time
-to the solution including setup and the residual check.
+sliced-ELLPACK copies, QR of C1 and C2), the factored solve with the verified stopping rule (the
+recursive test ||R|| <= tol ||R0||, then the true residual ||A X + X B - C1 C2^T||_F, which must
+meet tol too), sylv_get_factors into device buffers and sylv_residual_norm (returns the verified
+figure). `value` is factored iterations per second over whole steps; ms_per_step is the time to
+a verified solution including setup.
+
+Precision of the default line: FP64 everywhere ("FP64 plain"). `comparisons` times the mixed
+and batched forms of the same and of the other workloads beside their FP64-plain runs (two steps
+after one warm-up each): split-BF16 Gram products for the true residual (gram_precision 2), FP32
+bases with outer refinement, and the 64-instance batch against the same instances solved one
+after another.
 
 After the timed region one more (untimed) solve runs with per-kernel HIP-event timing on the
-solver's stream to report the roofline fraction of the dominant kernel family; the CPU oracle
-is timed on a bounded sample for `cpu_baseline`.
+solver's stream, for the roofline fraction of the dominant kernel family; the CPU oracle is
+timed on a bounded sample of the same workload for `cpu_baseline`.
 """
 import argparse
 import json
@@ -34,10 +40,15 @@ sys.path.insert(0, ROOT)
 
 PEAK_HBM_GBS = 8000.0     # MI355X HBM3E
 PEAK_FP64_TFS = 78.6      # MI355X FP64 (vector and MFMA)
+PEAK_BF16_TFS = 2500.0    # MI355X dense BF16 MFMA
 METRIC = "time-to-1e-8 rel. residual + factored iters/s; mixed/batched vs FP64 plain"
 
+# kernel families bound by the matrix cores (peak TFLOP/s); the others are bound by HBM
+MFMA_FAMILIES = {"core_op": PEAK_FP64_TFS, "res_gram": PEAK_FP64_TFS,
+                 "res_gram_bf16": PEAK_BF16_TFS}
 
-def workload(name, max_iter):
+
+def workload(name, max_iter=0):
     from workloads import configs
     if name == "c1":
         return configs.c1_cg_1d(), "cg"
@@ -52,24 +63,176 @@ def workload(name, max_iter):
     raise SystemExit(f"unknown workload {name}")
 
 
-def cpu_baseline(p, method, iters):
+def cpu_baseline(p, method, iters, iters_1t):
     """The oracle as it stands on the host cores: its first `iters` factored iterations of the
-    same workload (cost per iteration grows with the rank, so this understates the full-solve
-    time per iteration)."""
+    same workload with the BLAS threads the host gives it, and its first `iters_1t` iterations
+    on one thread (cost per iteration grows with the rank, so an early sample understates the
+    full-solve time per iteration)."""
     from oracle import factored
     try:
-        from threadpoolctl import threadpool_info
+        from threadpoolctl import threadpool_info, threadpool_limits
         cores = max([i.get("num_threads", 1) for i in threadpool_info()] + [1])
     except Exception:
-        cores = os.cpu_count() or 1
+        threadpool_limits, cores = None, os.cpu_count() or 1
     fn = factored.factored_cg if method == "cg" else factored.factored_bicgstab
-    t0 = time.perf_counter()
-    _, _, _, info = fn(p.A, p.B, p.C1, p.C2, tol=0.0, max_iter=iters, lyapunov=p.lyapunov)
-    dt = time.perf_counter() - t0
+
+    def sample(k):
+        t0 = time.perf_counter()
+        _, _, _, info = fn(p.A, p.B, p.C1, p.C2, tol=0.0, max_iter=k, lyapunov=p.lyapunov)
+        return info["iters"], time.perf_counter() - t0
+
+    it, dt = sample(iters)
+    one = None
+    if threadpool_limits is not None and iters_1t > 0:
+        with threadpool_limits(limits=1):
+            it1, dt1 = sample(iters_1t)
+        one = {"value": round(it1 / dt1, 3), "cores": 1,
+               "sample": f"first {it1} iterations ({dt1:.1f} s, one BLAS thread)"}
     name = "CG" if method == "cg" else "BiCGSTAB"
-    return {"value": info["iters"] / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
-            "sample": f"first {info['iters']} factored {name} iterations of the same workload "
-                      f"({dt:.1f} s on the host)"}
+    return {"value": it / dt, "unit": "iters/s", "cores": int(cores), "kind": "oracle",
+            "sample": f"first {it} factored {name} iterations of the same workload "
+                      f"({dt:.1f} s on the host; SciPy's sparse products use one thread)",
+            "one_thread": one}
+
+
+class DeviceProblem:
+    """Device copies of one problem and its sylv_problem record."""
+
+    def __init__(self, sylv, torch, p):
+        dev = "cuda"
+        self.p = p
+        self.rpA, self.ciA, self.vaA = sylv.csr_tensors(p.A, dev)
+        self.C1 = torch.as_tensor(p.C1, device=dev)
+        if p.lyapunov:
+            csrB, self.C2 = sylv.make_csr(p.m, self.rpA, self.ciA, self.vaA), self.C1
+        else:
+            self.B = sylv.csr_tensors(p.B, dev)
+            csrB = sylv.make_csr(p.m, *self.B)
+            self.C2 = torch.as_tensor(p.C2, device=dev)
+        self.prob = sylv.sylv_problem(p.n, p.m, p.s, sylv.make_csr(p.n, self.rpA, self.ciA,
+                                                                     self.vaA), csrB,
+                                      1 if p.lyapunov else 0, self.C1.data_ptr(), p.s,
+                                      self.C2.data_ptr(), p.s)
+
+
+def run_config(sylv, torch, np, p, method, cfg, steps, warmup, measure=False):
+    """Times `steps` whole steps (after `warmup`) of one configuration: cfg holds precision
+    ('fp64' or 'fp32' bases), gram_precision, refine, check_every, streams, reorth."""
+    cg = method == "cg"
+    dp = DeviceProblem(sylv, torch, p)
+    mixed = cfg.get("precision", "fp64") == "fp32"
+    refine = cfg.get("refine", 3 if mixed else 0)
+    opts = sylv.default_options(sylv.SYLV_METHOD_CG if cg else sylv.SYLV_METHOD_BICGSTAB,
+                                p.max_iter, check_every=cfg.get("check_every", 16),
+                                precision=sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64,
+                                refine_max=refine, refine_max_iter=100,
+                                streams=cfg.get("streams", 0), reorth=cfg.get("reorth", 0),
+                                gram_precision=cfg.get("gram_precision", 0), verify=1)
+    ws = torch.empty(sylv.sylv_workspace_bytes(dp.prob, opts), dtype=torch.uint8, device="cuda")
+    rmax = (p.max_iter + 1 if cg else 2 * p.max_iter + 1) * p.s
+    if refine > 0:  # the summed iterate stacks the corrections' bases
+        rmax += refine * (101 if cg else 201) * 8
+    V = torch.empty((p.n, rmax), dtype=torch.float64, device="cuda")
+    W = V if p.lyapunov else torch.empty((p.m, rmax), dtype=torch.float64, device="cuda")
+    Xc = torch.empty((rmax, rmax), dtype=torch.float64, device="cuda")
+    stream = torch.cuda.current_stream()
+    solve = sylv.sylv_factored_cg if cg else sylv.sylv_factored_bicgstab
+
+    def step():
+        ctx = sylv.sylv_create(dp.prob, opts, ws, stream.cuda_stream)
+        res = solve(ctx, p.tol, p.max_iter)
+        rv, rw = res.rank_v, res.rank_w
+        sylv.sylv_get_factors(ctx, V[:, :rv], Xc[:rv, :rw], None if p.lyapunov else W[:, :rw])
+        _, rel = sylv.sylv_residual_norm(ctx)
+        sylv.sylv_destroy(ctx)
+        return res, rel
+
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    iters, rels, statuses, outer = 0, [], [], 0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res, rel = step()
+        iters += res.iters
+        rels.append(rel)
+        statuses.append(res.status)
+        outer = res.outer_steps
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out = {"ms_per_step": 1000.0 * dt / steps, "iters_per_step": iters // steps,
+           "iters_per_s": iters / dt, "true_rel_res": float(np.max(rels)),
+           "statuses": sorted(set(int(s) for s in statuses)), "outer_steps": int(outer),
+           "rank": int(res.rank_v)}
+    if measure:
+        # untimed measurement pass: per-family kernel times with HIP events on the solver's
+        # stream (the solve and the true residual of its verification)
+        ctx = sylv.sylv_create(dp.prob, opts, ws, stream.cuda_stream)
+        sylv.sylv_set_profiling(ctx, True)
+        t1 = time.perf_counter()
+        solve(ctx, p.tol, p.max_iter)
+        out["profiled_solve_ms"] = 1000.0 * (time.perf_counter() - t1)
+        out["stats"] = sylv.sylv_get_kernel_stats(ctx)
+        sylv.sylv_destroy(ctx)
+    del V, W, Xc, ws, dp
+    torch.cuda.empty_cache()
+    return out
+
+
+def roofline_of(stats, workload, precision):
+    tot = sum(s["ms"] for s in stats) or 1.0
+    dom = max(stats, key=lambda s: s["ms"])
+    fam = dom["family"]
+    if fam in MFMA_FAMILIES:
+        bound, unit, peak = "mfma", "TFLOP/s", MFMA_FAMILIES[fam]
+        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
+    else:
+        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
+        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
+    return {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
+            "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(workload, fam, precision),
+            "kernel": fam, "launches": dom["launches"],
+            "avg_launch_us": round(1000 * dom["ms"] / max(dom["launches"], 1), 3),
+            "share_of_kernel_time": round(dom["ms"] / tot, 3)}
+
+
+def breakdown_of(stats):
+    return {s["family"]: {"ms": round(s["ms"], 3), "launches": s["launches"],
+                          "GB/s": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1),
+                          "TFLOP/s": round(s["flops"] / max(s["ms"], 1e-9) / 1e9, 3)}
+            for s in stats if s["launches"]}
+
+
+def summary(r):
+    return {"time_to_1e-8_ms": round(r["ms_per_step"], 3), "iters": r["iters_per_step"],
+            "iters_per_s": round(r["iters_per_s"], 2), "true_rel_res": r["true_rel_res"],
+            "statuses": r["statuses"], "outer_steps": r["outer_steps"], "rank": r["rank"]}
+
+
+def comparisons(sylv, torch, np, main_name, main_res):
+    """Mixed and batched forms beside FP64 plain (two steps after one warm-up each)."""
+    out = {}
+    plans = {
+        "c5cg": [("fp64_plain", {}), ("mixed_bf16_grams", {"gram_precision": 2})],
+        "c2": [("fp64_plain", {}), ("mixed_bf16_grams", {"gram_precision": 2})],
+        "c3": [("fp64_plain", {}), ("mixed_bf16_grams", {"gram_precision": 2}),
+               ("mixed_fp32_bases_refined", {"precision": "fp32", "gram_precision": 2})],
+    }
+    for name, plan in plans.items():
+        p, method = workload(name)
+        rows = {}
+        for label, cfg in plan:
+            if name == main_name and label == "fp64_plain":
+                rows[label] = summary(main_res)
+                continue
+            rows[label] = summary(run_config(sylv, torch, np, p, method, cfg, 2, 1))
+        base = rows["fp64_plain"]["time_to_1e-8_ms"]
+        for label, r in rows.items():
+            r["speedup_vs_fp64_plain"] = round(base / r["time_to_1e-8_ms"], 3)
+        out[name] = {"workload": p.meta["workload"], **rows}
+    out["batch64"] = run_batch_compare(sylv, torch, np, steps=2, warmup=1)
+    return out
 
 
 def main():
@@ -77,17 +240,20 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="c2",
+    ap.add_argument("--workload", default="c5cg",
                     choices=["c1", "c2", "c3", "c5cg", "c5bi", "batch64"])
     ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare", action="store_true",
+                    help="skip the mixed / batched comparisons")
     ap.add_argument("--check-every", type=int, default=16,
                     help="iterations between the host's looks at the convergence flag")
     ap.add_argument("--streams-solve", type=int, default=0, choices=[0, 1, 2],
                     help="sylv_options.streams (0 automatic)")
     ap.add_argument("--reorth", type=int, default=0, choices=[0, 1, 2],
                     help="sylv_options.reorth (0 automatic)")
-    ap.add_argument("--cpu-iters", type=int, default=200)
+    ap.add_argument("--cpu-iters", type=int, default=600)
+    ap.add_argument("--cpu-iters-1t", type=int, default=200)
     ap.add_argument("--max-iter", type=int, default=0)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
                     help="storage of the Krylov bases (fp32: mixed precision)")
@@ -104,7 +270,8 @@ def main():
     if args.refine < 0:
         args.refine = 3 if args.precision == "fp32" else 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this library runs one solve on one GPU; --gpus must be 1"}))
+        print(json.dumps({"error": "this build runs on one GPU: the path would shard by rows "
+                                   "(see the design notes); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np
@@ -122,119 +289,62 @@ def main():
         print(json.dumps({"calibrate_copy_bytes": src.numel() * 8, "copies": 3}), flush=True)
         return
     if args.workload == "batch64":
-        return run_batch(args, sylv, torch, np)
-    p, method = workload(args.workload, args.max_iter)
-    cg = method == "cg"
-    dev = "cuda"
-    rpA, ciA, vaA = sylv.csr_tensors(p.A, dev)
-    C1 = torch.as_tensor(p.C1, device=dev)
-    if p.lyapunov:
-        csrB, C2 = sylv.make_csr(p.m, rpA, ciA, vaA), C1
-    else:
-        rpB, ciB, vaB = sylv.csr_tensors(p.B, dev)
-        csrB, C2 = sylv.make_csr(p.m, rpB, ciB, vaB), torch.as_tensor(p.C2, device=dev)
-    prob = sylv.sylv_problem(p.n, p.m, p.s, sylv.make_csr(p.n, rpA, ciA, vaA), csrB,
-                             1 if p.lyapunov else 0, C1.data_ptr(), p.s, C2.data_ptr(), p.s)
-    mixed = args.precision == "fp32"
-    opts = sylv.default_options(sylv.SYLV_METHOD_CG if cg else sylv.SYLV_METHOD_BICGSTAB,
-                                p.max_iter, check_every=args.check_every,
-                                precision=sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64,
-                                refine_max=args.refine, refine_max_iter=100,
-                                streams=args.streams_solve, reorth=args.reorth,
-                                gram_precision=args.gram_precision)
-    ws = torch.empty(sylv.sylv_workspace_bytes(prob, opts), dtype=torch.uint8, device=dev)
-    rmax = (p.max_iter + 1 if cg else 2 * p.max_iter + 1) * p.s
-    if args.refine > 0:  # the summed iterate stacks the corrections' bases
-        rmax += args.refine * (101 if cg else 201) * 8
-    V = torch.empty((p.n, rmax), dtype=torch.float64, device=dev)
-    W = V if p.lyapunov else torch.empty((p.m, rmax), dtype=torch.float64, device=dev)
-    Xc = torch.empty((rmax, rmax), dtype=torch.float64, device=dev)
-    stream = torch.cuda.current_stream()
-    solve = sylv.sylv_factored_cg if cg else sylv.sylv_factored_bicgstab
-
-    def step():
-        ctx = sylv.sylv_create(prob, opts, ws, stream.cuda_stream)
-        res = solve(ctx, p.tol, p.max_iter)
-        rv, rw = res.rank_v, res.rank_w
-        sylv.sylv_get_factors(ctx, V[:, :rv], Xc[:rv, :rw], None if p.lyapunov else W[:, :rw])
-        _, rel = sylv.sylv_residual_norm(ctx)
-        sylv.sylv_destroy(ctx)
-        return res, rel
-
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    iters, rels, statuses = 0, [], []
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res, rel = step()
-        iters += res.iters
-        rels.append(rel)
-        statuses.append(res.status)
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    ms_per_step = 1000.0 * dt / args.steps
-    if args.pmc_pass:
-        print(json.dumps({"pmc_pass": args.workload, "iters": iters}), flush=True)
+        r = run_batch_compare(sylv, torch, np, args.steps, args.warmup, args.streams)
+        out = {"metric": METRIC, "value": r["batched"]["iters_per_s"], "unit": "iters/s",
+               "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+               "ms_per_step": r["batched"]["time_to_1e-8_ms"], "higher_is_better": True,
+               "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+               "config": {"workload": r["workload"], **r}}
+        print(json.dumps(out), flush=True)
         return
-
-    # untimed measurement pass: per-family kernel times with HIP events on the solver's stream
-    ctx = sylv.sylv_create(prob, opts, ws, stream.cuda_stream)
-    sylv.sylv_set_profiling(ctx, True)
-    t1 = time.perf_counter()
-    res = solve(ctx, p.tol, p.max_iter)
-    solve_ms = 1000.0 * (time.perf_counter() - t1)
-    stats = sylv.sylv_get_kernel_stats(ctx)
-    sylv.sylv_destroy(ctx)
-    tot = sum(s["ms"] for s in stats) or 1.0
-    dom = max(stats, key=lambda s: s["ms"])
-    if dom["family"] == "core_op":
-        bound, unit = "mfma", "TFLOP/s"
-        achieved = dom["flops"] / (dom["ms"] * 1e-3) / 1e12
-        peak = PEAK_FP64_TFS
-    else:
-        bound, unit = "hbm", "GB/s"
-        achieved = dom["bytes"] / (dom["ms"] * 1e-3) / 1e9
-        peak = PEAK_HBM_GBS
-    roofline = {"bound": bound, "achieved": round(achieved, 3), "peak": peak, "unit": unit,
-                "frac": round(achieved / peak, 4),
-                "traffic": measured_traffic(args.workload, dom["family"], args.precision),
-                "kernel": dom["family"], "launches": dom["launches"],
-                "avg_launch_us": round(1000 * dom["ms"] / max(dom["launches"], 1), 3),
-                "share_of_kernel_time": round(dom["ms"] / tot, 3)}
-    breakdown = {s["family"]: {"ms": round(s["ms"], 3), "launches": s["launches"],
-                               "GB/s": round(s["bytes"] / max(s["ms"], 1e-9) / 1e6, 1),
-                               "TFLOP/s": round(s["flops"] / max(s["ms"], 1e-9) / 1e9, 3)}
-                 for s in stats if s["launches"]}
-
+    p, method = workload(args.workload, args.max_iter)
+    cfg = {"precision": args.precision, "gram_precision": args.gram_precision,
+           "refine": args.refine, "check_every": args.check_every,
+           "streams": args.streams_solve, "reorth": args.reorth}
+    if args.pmc_pass:
+        r = run_config(sylv, torch, np, p, method, cfg, args.steps, 0)
+        print(json.dumps({"pmc_pass": args.workload, "iters": r["iters_per_step"]}), flush=True)
+        return
+    r = run_config(sylv, torch, np, p, method, cfg, args.steps, args.warmup, measure=True)
+    stats = r.pop("stats")
+    mixed = args.precision == "fp32" or args.gram_precision > 0
+    dtype = "f64"
+    if args.precision == "fp32":
+        dtype = "f32-basis/f64"
+    if args.gram_precision > 0:
+        dtype += "+bf16x3-grams"
     out = {
-        "metric": METRIC, "value": round(iters / dt, 2), "unit": "iters/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32-basis/f64" if mixed else "f64",
+        "metric": METRIC, "value": round(r["iters_per_s"], 2), "unit": "iters/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(r["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": dtype,
         "data": "synthetic",
         "config": {"workload": p.meta["workload"] + f", tol {p.tol:g}, seeded N(0,1) C1/C2",
                    "n": p.n, "m": p.m, "s": p.s, "lyapunov": bool(p.lyapunov),
-                   "method": "factored CG" if cg else "factored BiCGSTAB",
-                   "max_iter": p.max_iter, "iters_per_solve": iters // args.steps,
-                   "basis_precision": args.precision, "refine_max": args.refine,
-                   "outer_steps": int(res.outer_steps),
-                   "rank": int(res.rank_v), "time_to_solution_ms": round(ms_per_step, 3),
-                   "profiled_solve_ms": round(solve_ms, 3),
-                   "true_rel_res": float(np.max(rels)), "statuses": sorted(set(statuses))},
-        "roofline": roofline,
-        "kernel_breakdown": breakdown,
-        "spmm_hbm": spmm_hbm(sylv, torch) if args.workload == "c2" and not mixed else None,
+                   "method": "factored CG" if method == "cg" else "factored BiCGSTAB",
+                   "max_iter": p.max_iter, "iters_per_solve": r["iters_per_step"],
+                   "basis_precision": args.precision, "gram_precision": args.gram_precision,
+                   "refine_max": args.refine, "outer_steps": r["outer_steps"],
+                   "rank": r["rank"], "time_to_solution_ms": round(r["ms_per_step"], 3),
+                   "profiled_solve_ms": round(r["profiled_solve_ms"], 3),
+                   "true_rel_res": r["true_rel_res"], "statuses": r["statuses"],
+                   "stopping_rule": "recursive ||R|| <= tol ||R0||, then the true residual "
+                                    "<= tol (verified)"},
+        "roofline": roofline_of(stats, args.workload, "mixed" if mixed else "fp64"),
+        "kernel_breakdown": breakdown_of(stats),
     }
+    if not args.no_compare and not mixed:
+        out["comparisons"] = comparisons(sylv, torch, np, args.workload, r)
+        out["spmm_hbm"] = spmm_hbm(sylv, torch)
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(p, method, args.cpu_iters)
+        out["cpu_baseline"] = cpu_baseline(p, method, args.cpu_iters, args.cpu_iters_1t)
     print(json.dumps(out), flush=True)
 
 
 # Kernel sources whose family the hardware-counter traffic in profiles/ was taken for.
 FAMILY_SOURCES = {"core_op": "dense.hip", "gram": "arnoldi_impl.h", "update": "arnoldi_impl.h",
                   "upd_gram": "arnoldi_impl.h", "spmm": "arnoldi_impl.h",
-                  "block_qr": "arnoldi_impl.h", "core_elem": "core.hip", "core_band": "core.hip"}
+                  "block_qr": "arnoldi_impl.h", "core_elem": "core.hip", "core_band": "core.hip",
+                  "res_gram": "dense.hip", "res_gram_bf16": "gram_bf16.hip"}
 
 
 def measured_traffic(workload, family, precision):
@@ -301,54 +411,44 @@ def spmm_hbm(sylv, torch):
     return out
 
 
-def run_batch(args, sylv, torch, np):
-    """The 64-instance batch: wall time of sylv_batch_solve over all instances (after one
-    untimed warm-up solve), then the same instances solved sequentially on one stream."""
+def run_batch_compare(sylv, torch, np, steps, warmup, nstreams=8):
+    """The 64-instance batch: wall time of sylv_batch_solve over all instances (every instance
+    verified against its true residual), then the same instances solved one after another on one
+    stream (FP64 plain, one context at a time)."""
     from workloads import configs
     probs = configs.batch64()
     for p in probs:  # workspace sized for the instances' needs (CG up to ~1000 iterations)
         p.max_iter = 1500 if p.method == "cg" else 600
-    mixed = args.precision == "fp32"
-    prec = sylv.SYLV_MIXED_FP32 if mixed else sylv.SYLV_FP64
 
-    def timed(nstreams, steps):
-        b = sylv.Batch(probs, nstreams=nstreams, precision=prec)
-        for _ in range(args.warmup):
+    def timed(ns, nsteps):
+        b = sylv.Batch(probs, nstreams=ns)
+        for _ in range(warmup):
             b.solve(1e-8)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(steps):
+        for _ in range(nsteps):
             res = b.solve(1e-8)
         torch.cuda.synchronize()
-        dt = (time.perf_counter() - t0) / steps
-        rels = []
-        for i in range(len(probs)):
-            _, rel = sylv.sylv_residual_norm(b.context(i))
-            rels.append(rel)
+        dt = (time.perf_counter() - t0) / nsteps
+        rels = [sylv.sylv_residual_norm(b.context(i))[1] for i in range(len(probs))]
         b.close()
         del b
         torch.cuda.empty_cache()
         return dt, res, rels
 
-    dt, res, rels = timed(args.streams, args.steps)
-    dts, res_s, _ = timed(1, 1)
+    dt, res, rels = timed(nstreams, steps)
+    dts, res_s, rels_s = timed(1, 1)
     iters = sum(r.iters for r in res)
-    out = {
-        "metric": METRIC, "value": round(iters / dt, 2), "unit": "iters/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1000 * dt, 3),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32-basis/f64" if mixed else "f64", "data": "synthetic",
-        "config": {"workload": "batch of 64 seeded instances (2D A, n 1024-32768; 1D/2D B, "
-                               "m 512-16384; s in {1,2,4}; CG/BiCGSTAB alternating), tol 1e-8",
-                   "instances": len(probs), "streams": args.streams,
-                   "total_iters": iters, "time_to_1e-8_all_ms": round(1000 * dt, 3),
-                   "sequential_ms": round(1000 * dts, 3),
-                   "speedup_vs_sequential": round(dts / dt, 3),
-                   "statuses": sorted(set(int(r.status) for r in res)),
-                   "max_true_rel_res": float(max(rels)),
-                   "sequential_iters": sum(r.iters for r in res_s)},
-    }
-    print(json.dumps(out), flush=True)
+    return {"workload": "batch of 64 seeded instances (2D A, n 1024-32768; 1D/2D B, m 512-16384; "
+                        "s in {1,2,4}; CG/BiCGSTAB alternating), tol 1e-8",
+            "instances": len(probs), "streams": nstreams,
+            "batched": {"time_to_1e-8_ms": round(1000 * dt, 3), "iters": iters,
+                        "iters_per_s": round(iters / dt, 2), "max_true_rel_res": float(max(rels)),
+                        "statuses": sorted(set(int(r.status) for r in res))},
+            "sequential_fp64_plain": {"time_to_1e-8_ms": round(1000 * dts, 3),
+                                      "iters": sum(r.iters for r in res_s),
+                                      "max_true_rel_res": float(max(rels_s))},
+            "speedup_vs_sequential": round(dts / dt, 3)}
 
 
 if __name__ == "__main__":

@@ -865,6 +865,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
         const double *Hm = w ? cj->G : cj->H;
         const int p = (int)cj->rank, q = p + (int)CL.s;
         double *Ej = Es + eoff[j];
+        prof_begin(P->sc, st);
         if (CL.method == SYLV_METHOD_CG) {
           if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, sd.basis, CL.fp32, CL.ldb, p, q,
                                        (int)CL.s, Hm, CL.ldc, at<double>(cj, CL.off_M2), CL.ldc,
@@ -879,6 +880,8 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
                                        PL.ldE, st)))
             return ee;
         }
+        // algorithmic: the basis rows read once, the defect rows written once, the operator
+        prof_end(P->sc, FAM_RES_DEFECT, (double)nr * (CL.esz * q + 8.0 * p), 2.0 * nr * q * p, st);
       }
       // compact sources (QR defects, C2) next to the defects
       for (const Fill &f : (w ? fillN : fillL))
@@ -902,27 +905,41 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
                           (int)A.esz, 0};
         }
         bs.count = (int)segs.size();
+        prof_begin(P->sc, st);
         if ((ee = launch_bf16_pack(bs, nr, offs.back(), PL.cpad,
                                    at<unsigned long long>(P, PL.off_cmaxb), at<int>(P, PL.off_cexp),
                                    at<char>(P, PL.off_pack), st)))
           return ee;
+        double pb = 0.0;
+        for (const Seg &A : segs) pb += (double)nr * A.cols * A.esz;
+        prof_end(P->sc, FAM_RES_PACK, pb + 4.0 * (double)nr * offs.back(), 0.0, st);
       }
       for (size_t a = 0; a < segs.size(); ++a)
         for (size_t b = 0; b <= a; ++b) {
           const Seg &A = segs[a], &B = segs[b];
+          // useful flops of the block (lower triangle only when a == b)
+          const double fl = (a == b ? (double)A.cols * (A.cols + 1) : 2.0 * A.cols * B.cols) * nr;
           if (bf16_block(a, b)) {
+            prof_begin(P->sc, st);
             if ((ee = launch_gram_bf16(A.cols, B.cols, nr, at<char>(P, PL.off_pack), PL.cpad,
                                        at<int>(P, PL.off_cexp), offs[a], offs[b], beta,
                                        G + offs[a] * ldG + offs[b], ldG, a == b, st,
                                        at<float>(P, PL.off_bpart), PL.bpart_floats)))
               return ee;
+            // three BF16 products per FP64-equivalent product; operands read as packed hi/lo
+            prof_end(P->sc, FAM_RES_BF16, 4.0 * nr * (a == b ? A.cols : A.cols + B.cols), 3.0 * fl,
+                     st);
             continue;
           }
           const char *pa = A.ptr + (A.rowed ? r0 * A.ld * A.esz : 0);
           const char *pb = B.ptr + (B.rowed ? r0 * B.ld * B.esz : 0);
+          prof_begin(P->sc, st);
           if ((ee = launch_gram(A.cols, B.cols, nr, pa, A.f32, A.ld, pb, B.f32, B.ld, beta,
                                 G + offs[a] * ldG + offs[b], ldG, a == b, st, gpart, GPART_CAP)))
             return ee;
+          prof_end(P->sc, FAM_RES_GRAM,
+                   (double)nr * (a == b ? A.cols * A.esz : A.cols * A.esz + B.cols * B.esz), fl,
+                   st);
         }
     }
     return launch_mirror(offs.back(), G, ldG, st);
@@ -984,12 +1001,14 @@ int true_residual(Ctx *c, double *abs_res, double *rel_res) {
   if (!c->res_valid) {
     int e = read_state(c);
     if (e) return e;
+    if (c->prof) c->prof->iter = 0;
     if (c->rank == 0 && c->kids.empty()) {
       c->res_abs = c->h_ds->normR0;
       c->res_rel = 1.0;
     } else if ((e = stacked_residual(c, refine_steps(c), &c->res_abs, &c->res_rel))) {
       return e;
     }
+    if (c->prof) c->prof->flush(1);  // the residual's launches (stream idle after its read-back)
     c->res_valid = 1;
   }
   if (abs_res) *abs_res = c->res_abs;
@@ -1241,8 +1260,9 @@ int sylv_get_kernel_stats(void *ctx, sylv_kernel_stat *out, int cap, int *count)
 }
 
 const char *sylv_kernel_family_name(int family) {
-  static const char *names[FAM_COUNT] = {"spmm",    "gram",      "update",    "block_qr",
-                                         "core_op", "core_band", "core_elem", "upd_gram"};
+  static const char *names[FAM_COUNT] = {"spmm",     "gram",          "update",   "block_qr",
+                                         "core_op",  "core_band",     "core_elem", "upd_gram",
+                                         "res_gram", "res_gram_bf16", "res_pack", "res_defect"};
   return (family >= 0 && family < FAM_COUNT) ? names[family] : "unknown";
 }
 

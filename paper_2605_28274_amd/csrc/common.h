@@ -577,6 +577,10 @@ enum {
   FAM_CORE_BAND,    // eq. (3.11) on block-tridiagonal cores
   FAM_CORE_ELEM,    // core axpys, inner products and scalar updates
   FAM_UPD_GRAM,     // Arnoldi U -= V C1 fused with the second sweep's V^T U
+  FAM_RES_GRAM,     // true residual: FP64 Gram blocks of the stacked factors (FP64 MFMA)
+  FAM_RES_BF16,     // true residual: split-BF16 Gram blocks (BF16 MFMA; flops counted as issued)
+  FAM_RES_PACK,     // true residual: column scales and the BF16 pack of a row chunk
+  FAM_RES_DEFECT,   // true residual: basis defects A V - V H of a row chunk
   FAM_COUNT
 };
 void prof_begin(const Scratch &sc, hipStream_t st);
@@ -666,6 +670,55 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
 int launch_gemm_nn(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
                    const double *B, int64_t ldb, double *C, int64_t ldc, hipStream_t st);
 int launch_mirror(int64_t M, double *C, int64_t ldc, hipStream_t st);
+// Tile (I, J), I >= J, of position b in the row-major order of a lower triangle of tiles.
+__device__ __forceinline__ void tri_tile(int64_t b, int &I, int &J) {
+  int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > b) --i;
+  while ((i + 1) * (i + 2) / 2 <= b) ++i;
+  I = (int)i;
+  J = (int)(b - i * (i + 1) / 2);
+}
+
+// Visiting order of the tiles: groups of eight tile rows, column by column inside a group (the
+// lower form walks the triangle I >= J the same way, its diagonal block last), so the
+// workgroups that run at one time on one XCD share a few row and column panels in its L2.
+struct GramSeq {
+  int TM, TN, lower;
+  __host__ __device__ int64_t count() const {
+    return lower ? (int64_t)TM * (TM + 1) / 2 : (int64_t)TM * TN;
+  }
+  __device__ void tile(int64_t t, int &I, int &J) const {
+    int g0;  // first tile row of the group; groups start at the same positions as rows do
+    int64_t idx;
+    if (lower) {
+      int r, c;
+      tri_tile(t, r, c);
+      g0 = r & ~7;
+      idx = t - (int64_t)g0 * (g0 + 1) / 2;
+    } else {
+      g0 = (int)(t / ((int64_t)8 * TN)) * 8;
+      idx = t - (int64_t)g0 * TN;
+    }
+    const int h = TM - g0 < 8 ? TM - g0 : 8;
+    const int64_t full = (int64_t)(lower ? g0 : TN) * h;
+    if (idx < full) {
+      J = (int)(idx / h);
+      I = g0 + (int)(idx % h);
+      return;
+    }
+    // lower form, diagonal block: column g0 + d holds rows g0 + d .. g0 + h - 1
+    int64_t e = idx - full;
+    int d = 0;
+    while (e >= h - d) {
+      e -= h - d;
+      ++d;
+    }
+    J = g0 + d;
+    I = J + (int)e;
+  }
+};
+
+
 // Split-BF16 Grams (gram_bf16.hip). The stacked columns of one row chunk come from up to
 // BF_MAX_SEGS segments: segment i supplies columns [col0, col0 + cols) from a row-major source
 // (row r at ptr + r ld esz, esz 4 for float or 8 for double; row 0 is the chunk's first row).

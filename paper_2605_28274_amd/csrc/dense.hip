@@ -345,14 +345,6 @@ __global__ __launch_bounds__(256) void core_op_reduce_kernel(const CoreTab tab, 
 // A: K x M and B: K x N row-major with row strides lda, ldb; columns up to the next multiple of
 // 64 of M (N) must lie inside the rows (lda >= roundup(M, 64)); K is a multiple of BK. With
 // `lower`, only tiles I >= J are computed (symmetric A^T A; mirror_kernel fills the rest).
-__device__ __forceinline__ void tri_tile(int64_t b, int &I, int &J) {
-  int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > b) --i;
-  while ((i + 1) * (i + 2) / 2 <= b) ++i;
-  I = (int)i;
-  J = (int)(b - i * (i + 1) / 2);
-}
-
 // With part != nullptr the K range is split: workgroup b computes tile b % ntiles over rows
 // [kz kchunk, (kz+1) kchunk), kz = b / ntiles, and stores the whole tile to part; gram_reduce
 // sums the slices in order.
@@ -430,45 +422,6 @@ __global__ __launch_bounds__(256) void gram_reduce_kernel(int64_t M, int64_t N, 
 }
 
 // ---- stream-K form of the tall-skinny Gram (launches with many output tiles) ----
-// Visiting order of the tiles: groups of eight tile rows, column by column inside a group (the
-// lower form walks the triangle I >= J the same way, its diagonal block last), so the
-// workgroups that run at one time on one XCD share a few row and column panels in its L2.
-struct GramSeq {
-  int TM, TN, lower;
-  __host__ __device__ int64_t count() const {
-    return lower ? (int64_t)TM * (TM + 1) / 2 : (int64_t)TM * TN;
-  }
-  __device__ void tile(int64_t t, int &I, int &J) const {
-    int g0;  // first tile row of the group; groups start at the same positions as rows do
-    int64_t idx;
-    if (lower) {
-      int r, c;
-      tri_tile(t, r, c);
-      g0 = r & ~7;
-      idx = t - (int64_t)g0 * (g0 + 1) / 2;
-    } else {
-      g0 = (int)(t / ((int64_t)8 * TN)) * 8;
-      idx = t - (int64_t)g0 * TN;
-    }
-    const int h = TM - g0 < 8 ? TM - g0 : 8;
-    const int64_t full = (int64_t)(lower ? g0 : TN) * h;
-    if (idx < full) {
-      J = (int)(idx / h);
-      I = g0 + (int)(idx % h);
-      return;
-    }
-    // lower form, diagonal block: column g0 + d holds rows g0 + d .. g0 + h - 1
-    int64_t e = idx - full;
-    int d = 0;
-    while (e >= h - d) {
-      e -= h - d;
-      ++d;
-    }
-    J = g0 + d;
-    I = J + (int)e;
-  }
-};
-
 // Schedule over G workgroups (G a multiple of 8; workgroup b is worker w = (b % 8) G/8 + b / 8,
 // so XCD x runs workers [x G/8, (x+1) G/8)):
 // * whole tiles first: worker w computes tiles w, w + G, ... below dp = floor(T / G) G. The

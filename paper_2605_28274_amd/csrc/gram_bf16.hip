@@ -99,14 +99,6 @@ __global__ __launch_bounds__(256) void pack_kernel(const BfSegs sg, int64_t nr, 
   }
 }
 
-__device__ __forceinline__ void tri_index(int64_t b, int &I, int &J) {
-  int64_t i = (int64_t)((sqrt(8.0 * (double)b + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > b) --i;
-  while ((i + 1) * (i + 2) / 2 <= b) ++i;
-  I = (int)i;
-  J = (int)(b - i * (i + 1) / 2);
-}
-
 struct Frag {
   bf16x8 ah[4], al[4], bh[4], bl[4];
 };
@@ -146,21 +138,28 @@ __device__ __forceinline__ void mma_frag(const Frag &f, f32x4 (&acc)[4][4]) {
       acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(f.ah[i], f.bh[j], acc[i][j], 0, 0, 0);
 }
 
-// Workgroup b: output tile b % ntiles over slabs [kz KS, (kz+1) KS) of the chunk, kz = b /
-// ntiles; its FP32 128 x 128 partial goes to part[kz][tile]. Columns a0 + I*128 .. +127 and
-// b0 + J*128 .. +127 must lie inside the packed width (cpad).
+// Worker w (of nw = ntiles * nk) computes tile number w % ntiles of the grouped visiting order
+// (GramSeq) over slabs [kz KS, (kz+1) KS) of the chunk, kz = w / ntiles, and stores its FP32
+// 128 x 128 partial to part[kz][tile]. Workers map to XCDs in contiguous ranges (workgroup b
+// runs worker (b % 8) G/8 + b / 8 of a grid of G, a multiple of 8), so the workgroups resident
+// on one XCD hold neighbouring tiles of one K range and share their row and column panels in
+// its L2. Each wave loads its operand fragments straight into registers, one slab ahead (the
+// loads of slab t + 1 are in flight during slab t's matrix-core work; the prefetch past the end
+// re-reads the last slab). Staging the slabs in LDS (one coalesced fill per workgroup, padded
+// records) and a third register set were both slower. Columns a0 + I*128 .. +127 and b0 + J*128 .. +127 must
+// lie inside the packed width.
 __global__ __launch_bounds__(256, 2) void gram_bf16_kernel(const char *__restrict__ pk,
                                                            int64_t cpad, int64_t a0, int64_t b0,
-                                                           int TN, int lower, int ntiles, int nsl,
-                                                           int ks, float *__restrict__ part) {
-  const int tile = (int)(blockIdx.x % ntiles), kz = (int)(blockIdx.x / ntiles);
+                                                           const GramSeq sq, int ntiles, int nw,
+                                                           int nsl, int ks,
+                                                           float *__restrict__ part) {
+  const int G = (int)gridDim.x;
+  const int w = (int)(blockIdx.x & 7) * (G >> 3) + (int)(blockIdx.x >> 3);
+  if (w >= nw) return;
+  const int tile = w % ntiles, kz = w / ntiles;
   int I, J;
-  if (lower) tri_index(tile, I, J);
-  else {
-    I = tile / TN;
-    J = tile % TN;
-  }
-  const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
+  sq.tile(tile, I, J);
+  const int wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
   const int lane = threadIdx.x & 63, li = lane & 15, g = lane >> 4;
   const int64_t ca = a0 + (int64_t)I * PT + wm * 64 + li;
   const int64_t cb = b0 + (int64_t)J * PT + wn * 64 + li;
@@ -171,15 +170,14 @@ __global__ __launch_bounds__(256, 2) void gram_bf16_kernel(const char *__restric
     for (int j = 0; j < 4; ++j) acc[i][j] = f32x4{0.f, 0.f, 0.f, 0.f};
   const int t0 = kz * ks, t1 = (t0 + ks < nsl) ? t0 + ks : nsl;
   const size_t sstride = (size_t)cpad * REC;
-  // two register sets, loads one slab ahead (the prefetch past the end re-reads the last slab)
+  auto slab = [&](int t) { return pk + (size_t)(t < t1 ? t : t1 - 1) * sstride; };
   Frag f0, f1;
-  if (t0 < t1) load_frag(pk + (size_t)t0 * sstride, ca, cb, g, f0);
+  load_frag(slab(t0), ca, cb, g, f0);
   int t = t0;
   for (; t + 1 < t1; t += 2) {
-    load_frag(pk + (size_t)(t + 1) * sstride, ca, cb, g, f1);
+    load_frag(slab(t + 1), ca, cb, g, f1);
     mma_frag(f0, acc);
-    const int tn = (t + 2 < t1) ? t + 2 : t1 - 1;
-    load_frag(pk + (size_t)tn * sstride, ca, cb, g, f0);
+    load_frag(slab(t + 2), ca, cb, g, f0);
     mma_frag(f1, acc);
   }
   if (t < t1) mma_frag(f0, acc);
@@ -195,8 +193,8 @@ __global__ __launch_bounds__(256, 2) void gram_bf16_kernel(const char *__restric
 
 // C(i, j) = beta C(i, j) + 2^(e_a(i) + e_b(j)) sum over kz of the partials, in FP64 and in kz
 // order (deterministic); 64 workgroups per tile, one element per thread.
-__global__ __launch_bounds__(256) void gram_bf16_reduce_kernel(int64_t M, int64_t N, int TN,
-                                                               int lower, int ntiles, int nk,
+__global__ __launch_bounds__(256) void gram_bf16_reduce_kernel(int64_t M, int64_t N,
+                                                               const GramSeq sq, int ntiles, int nk,
                                                                const float *__restrict__ part,
                                                                const int *__restrict__ cexp,
                                                                int64_t a0, int64_t b0, double beta,
@@ -204,11 +202,7 @@ __global__ __launch_bounds__(256) void gram_bf16_reduce_kernel(int64_t M, int64_
                                                                int64_t ldc) {
   const int tile = (int)(blockIdx.x / 64), sub = (int)(blockIdx.x % 64);
   int I, J;
-  if (lower) tri_index(tile, I, J);
-  else {
-    I = tile / TN;
-    J = tile % TN;
-  }
+  sq.tile(tile, I, J);
   const int e = sub * 256 + threadIdx.x;
   const int64_t gi = (int64_t)I * PT + e / PT, gj = (int64_t)J * PT + e % PT;
   if (gi >= M || gj >= N) return;
@@ -265,12 +259,14 @@ int launch_gram_bf16(int64_t M, int64_t N, int64_t nr, const void *packed, int64
     nk = (nsl + ks - 1) / ks;
   }
   if ((size_t)(tiles * nk) * PT * PT > part_floats) return SYLV_ERR_WORKSPACE;
-  gram_bf16_kernel<<<(unsigned)(tiles * nk), 256, 0, st>>>(
-      static_cast<const char *>(packed), cpad, a0, b0, (int)TN, lower ? 1 : 0, (int)tiles,
-      (int)nsl, (int)ks, part);
+  const GramSeq sq{(int)TM, (int)TN, lower ? 1 : 0};
+  const int64_t nw = tiles * nk, G = (nw + 7) / 8 * 8;
+  gram_bf16_kernel<<<(unsigned)G, 256, 0, st>>>(static_cast<const char *>(packed), cpad, a0, b0,
+                                                 sq, (int)tiles, (int)nw, (int)nsl, (int)ks,
+                                                 part);
   HIPOK(hipGetLastError());
   gram_bf16_reduce_kernel<<<(unsigned)(tiles * 64), 256, 0, st>>>(
-      M, N, (int)TN, lower ? 1 : 0, (int)tiles, (int)nk, part, cexp, a0, b0, beta, C, ldc);
+      M, N, sq, (int)tiles, (int)nk, part, cexp, a0, b0, beta, C, ldc);
   HIPOK(hipGetLastError());
   return 0;
 }

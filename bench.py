@@ -263,6 +263,8 @@ def main():
                     help="one step only (for hardware-counter runs of rocprofv3 --pmc)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="device copies of 512 MiB (counter calibration) and exit")
+    ap.add_argument("--spmm-only", action="store_true",
+                    help="only the standalone SpMM measurement (for counter runs) and exit")
     ap.add_argument("--refine", type=int, default=-1,
                     help="correction solves of the outer refinement (default: 3 with fp32 "
                          "bases, 0 with fp64)")
@@ -287,6 +289,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"calibrate_copy_bytes": src.numel() * 8, "copies": 3}), flush=True)
+        return
+    if args.spmm_only:
+        print(json.dumps({"spmm_hbm": spmm_hbm(sylv, torch)}), flush=True)
         return
     if args.workload == "batch64":
         r = run_batch_compare(sylv, torch, np, args.steps, args.warmup, args.streams)

@@ -44,7 +44,18 @@ enum {
   SYLV_ERR_STATE = -5       /* call out of order (e.g. factors requested before a solve)     */
 };
 
-enum { SYLV_METHOD_CG = 0, SYLV_METHOD_BICGSTAB = 1 };
+/* Methods: factorized CG (Algorithm 4.1) and BiCGSTAB (Algorithm 4.2), and the further Krylov
+ * methods the factorization carries over to (Section 4's remark, Section 6): conjugate residual
+ * (CR, symmetric A and B, block Lanczos bases), conjugate gradient squared (CGS) and
+ * generalized product-type BiCG (GPBiCG), both with two operator applications per iteration
+ * on block Arnoldi bases. */
+enum {
+  SYLV_METHOD_CG = 0,
+  SYLV_METHOD_BICGSTAB = 1,
+  SYLV_METHOD_CR = 2,
+  SYLV_METHOD_CGS = 3,
+  SYLV_METHOD_GPBICG = 4
+};
 
 /* Storage precision of the Krylov bases. SYLV_FP64: everything in FP64. SYLV_MIXED_FP32: the
  * bases V, W (and the compact panels the sparse products read) are stored in FP32, halving the
@@ -177,6 +188,27 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res);
 /* Factorized BiCGSTAB, Algorithm 4.2 with R~0 = R0; on return X_{k+1} = V_{2k+2} Xc
  * W_{2k+2}^T. Same conventions as sylv_factored_cg. */
 int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res);
+
+/* Factorized conjugate residual (A and B symmetric; F need not be definite): the matrix-
+ * oriented CR recurrence (S = F(R), alpha = <R, S> / <Q, Q> with Q = F(P) kept by recurrence,
+ * beta = <R', S'> / <R, S>) with every iterate in the factored form of Corollary 3.3, sums on
+ * the cores (eq. (3.9)), inner products of cores (eq. (3.10)) and S by eq. (3.11). One block
+ * Lanczos step per side per iteration; X_{k+1} = V_{k+1} Xc W_{k+1}^T. Conventions and
+ * statuses as sylv_factored_cg; the context must have been created with method
+ * SYLV_METHOD_CR (it sizes one more basis block). SYLV_BREAKDOWN when <Q, Q> or <R, S> vanishes. */
+int sylv_factored_cr(void *ctx, double tol, int max_iter, sylv_result *res);
+
+/* Factorized conjugate gradient squared: V = F(P), alpha = rho / <R~0, V>, Q = U - alpha V,
+ * X += alpha (U + Q), R -= alpha F(U + Q), beta = rho' / rho, U = R + beta Q,
+ * P = U + beta (Q + beta P), with R~0 = R0, the cores as above and two block Arnoldi steps per
+ * side per iteration; X_{k+1} = V_{2k+2} Xc W_{2k+2}^T. Context created with SYLV_METHOD_CGS. */
+int sylv_factored_cgs(void *ctx, double tol, int max_iter, sylv_result *res);
+
+/* Factorized GPBiCG: the residual r_{k+1} = t_k - eta_k y_k - zeta_k F(t_k) with zeta_k, eta_k
+ * minimizing its norm over the pair (eta_0 = 0), the iterate updated through u_k, z_k, and
+ * two block Arnoldi steps per side per iteration; X_{k+1} = V_{2k+2} Xc W_{2k+2}^T. The history's
+ * omega entries hold zeta_k. Context created with SYLV_METHOD_GPBICG. */
+int sylv_factored_gpbicg(void *ctx, double tol, int max_iter, sylv_result *res);
 
 /* True residual of the current iterate in FP64: abs_res = ||A X + X B - C1 C2^T||_F and
  * rel_res = abs_res / ||C1 C2^T||_F (host pointers). Evaluated from the factors without

@@ -30,6 +30,7 @@ struct Layout {
   size_t off_U, off_Uw, off_coefV, off_coefW, off_btrp, off_btci, off_btval, off_tscr;
   size_t off_cscr, off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
   size_t off_Lx, off_M2, off_d1, off_d2, off_c2, off_cpart, cpart_cap = 0;
+  size_t off_Ex[5] = {0, 0, 0, 0, 0};  // further cores of CGS and GPBiCG
   size_t off_dots, off_flag, off_panV, off_panW, off_sellA, off_sellB;
   // outer refinement: correction contexts and the buffers of the sketch and of the residual of
   // the summed iterates (child: a correction context, whose operators belong to the parent)
@@ -59,6 +60,21 @@ size_t bump(size_t &cur, size_t bytes) {
 
 int64_t round_up(int64_t v, int64_t a) { return (v + a - 1) / a * a; }
 
+// Methods on block Lanczos bases (one operator per iteration: CG, CR) and on block Arnoldi
+// bases (two per iteration: BiCGSTAB, CGS, GPBiCG).
+bool lanczos_method(int m) { return m == SYLV_METHOD_CG || m == SYLV_METHOD_CR; }
+bool known_method(int m) { return m >= SYLV_METHOD_CG && m <= SYLV_METHOD_GPBICG; }
+// Blocks of each basis generated in max_iter iterations (with the step issued ahead).
+int64_t blocks_needed(int m, int max_iter) {
+  if (m == SYLV_METHOD_CG) return (int64_t)max_iter + 2;
+  if (m == SYLV_METHOD_CR) return (int64_t)max_iter + 3;
+  return 2 * (int64_t)max_iter + 2;
+}
+// Extra core buffers of the methods beyond X, R, P, Q, S, T.
+int extra_cores(int m) {
+  return m == SYLV_METHOD_CGS ? 2 : (m == SYLV_METHOD_GPBICG ? 5 : 0);
+}
+
 int check_csr_header(const sylv_csr &M, int64_t rows) {
   if (M.rows != rows || M.nnz < 0 || M.nnz >= ((int64_t)1 << 31)) return SYLV_ERR_INVALID;
   if (!M.row_ptr || (M.nnz > 0 && (!M.col_idx || !M.values))) return SYLV_ERR_INVALID;
@@ -71,14 +87,15 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   if (pb->n <= 0 || pb->m <= 0 || pb->s < 1 || pb->s > SYLV_MAX_S) return SYLV_ERR_INVALID;
   if (pb->s > std::min(pb->n, pb->m)) return SYLV_ERR_INVALID;
   if (pb->lyapunov && pb->n != pb->m) return SYLV_ERR_INVALID;
-  if (op->max_iter < 1 || (op->method != SYLV_METHOD_CG && op->method != SYLV_METHOD_BICGSTAB))
-    return SYLV_ERR_INVALID;
+  if (op->max_iter < 1 || !known_method(op->method)) return SYLV_ERR_INVALID;
+  // outer refinement drives CG and BiCGSTAB corrections only
+  if (op->refine_max > 0 && op->method > SYLV_METHOD_BICGSTAB) return SYLV_ERR_INVALID;
   if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32) return SYLV_ERR_INVALID;
   if (op->streams < 0 || op->streams > 2) return SYLV_ERR_INVALID;
   if (op->reorth < 0 || op->reorth > 2) return SYLV_ERR_INVALID;
   if (op->gram_precision < 0 || op->gram_precision > 2 || op->verify < 0 || op->verify > 1)
     return SYLV_ERR_INVALID;
-  if (op->method == SYLV_METHOD_BICGSTAB && op->reorth == 2 &&
+  if (!lanczos_method(op->method) && op->reorth == 2 &&
       !arnoldi_lagged_supported(pb->s, op->precision == SYLV_MIXED_FP32))
     return SYLV_ERR_INVALID;
   if (!pb->C1 || pb->ldc1 < pb->s) return SYLV_ERR_INVALID;
@@ -94,8 +111,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.max_iter = op->max_iter;
   L.fp32 = op->precision == SYLV_MIXED_FP32;
   L.esz = L.fp32 ? 4 : 8;
-  // blocks generated: CG k+2 after k+1 iterations; BiCGSTAB 2k+3
-  L.Jmax = (op->method == SYLV_METHOD_CG) ? (int64_t)op->max_iter + 2 : 2 * (int64_t)op->max_iter + 2;
+  // blocks generated: CG k+2 after k+1 iterations, CR k+3; two-operator methods 2k+3
+  L.Jmax = blocks_needed(op->method, op->max_iter);
   L.rmax = L.Jmax * L.s;
   if (L.rmax > (1 << 20)) return SYLV_ERR_INVALID;
   // multiple of 64 columns (whole 64-wide tiles of the residual Grams stay inside a row),
@@ -120,12 +137,13 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.off_R = bump(cur, c2);
   L.off_P = bump(cur, c2);
   L.off_Q = bump(cur, c2);
-  if (L.method == SYLV_METHOD_BICGSTAB) {
+  if (L.method != SYLV_METHOD_CG) {
     L.off_S = bump(cur, c2);
     L.off_T = bump(cur, c2);
   } else {
     L.off_S = L.off_T = 0;
   }
+  for (int i = 0; i < extra_cores(L.method); ++i) L.off_Ex[i] = bump(cur, c2);
   L.off_U = bump(cur, (size_t)L.n * L.s * 8);
   L.off_Uw = bump(cur, (size_t)L.m * L.s * 8);
   L.off_coefV = bump(cur, (size_t)L.ldb * 2 * L.s * 8);  // 2 s columns in the lagged step
@@ -153,7 +171,7 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.off_c2 = bump(cur, (size_t)L.m * L.s * 8);  // C2 (C1 for Lyapunov)
   // stream-K partial tiles of the core operator (BiCGSTAB): one 64 x 64 tile per output tile
   // and per chunk (at most 512 chunks), for cores of up to 1024 tiles
-  if (L.method == SYLV_METHOD_BICGSTAB) {
+  if (L.method != SYLV_METHOD_CG) {
     const int64_t T = L.ldc / 64 + 1;
     L.cpart_cap = (size_t)(512 + std::min<int64_t>(T * T, 1024)) * 4096;
     L.off_cpart = bump(cur, L.cpart_cap * 8);
@@ -297,6 +315,7 @@ struct Ctx {
   char *ws = nullptr;
   SideDesc sv{}, sw{};
   double *H, *G, *X, *R, *P, *Q, *S, *T, *Rt, *RL, *RR, *hist;
+  double *Ex[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
   double *cpart = nullptr;  // split-K scratch of the core operator
   DevState *ds;
   SideState *ssv, *ssw;
@@ -373,11 +392,14 @@ int read_state(Ctx *c) {
 
 int begin_solve(Ctx *c, double tol, int max_iter, int method) {
   const Layout &L = c->L;
-  const int64_t need_blocks = (method == SYLV_METHOD_CG) ? (int64_t)max_iter + 2 : 2 * (int64_t)max_iter + 2;
+  // the workspace holds the bases and cores of the method it was sized for
+  if (method != L.method && !(method == SYLV_METHOD_CG && L.method == SYLV_METHOD_BICGSTAB))
+    return SYLV_ERR_WORKSPACE;
+  const int64_t need_blocks = blocks_needed(method, max_iter);
   if (max_iter < 1 || need_blocks > L.Jmax || !(tol >= 0.0)) return SYLV_ERR_INVALID;
-  if (method == SYLV_METHOD_BICGSTAB && L.method != SYLV_METHOD_BICGSTAB) return SYLV_ERR_WORKSPACE;
   const size_t c2 = (size_t)L.ldc * L.ldc * 8;
-  double *zero[] = {c->H, c->G, c->X, c->R, c->P, c->Q, c->S, c->T};
+  double *zero[] = {c->H, c->G, c->X, c->R, c->P, c->Q, c->S, c->T,
+                    c->Ex[0], c->Ex[1], c->Ex[2], c->Ex[3], c->Ex[4]};
   for (double *z : zero)
     if (z) HIPOK(hipMemsetAsync(z, 0, c2, c->st));
   // the compact copy of block 1 (V_1, W_1) is the first SpMM input; earlier solves reused it.
@@ -416,8 +438,8 @@ int end_solve(Ctx *c, int max_iter, double seconds, sylv_result *res) {
   }
   c->relres = d.relres;
   if (c->prof) c->prof->flush(c->iters);
-  c->rank = (c->method == SYLV_METHOD_CG) ? (int64_t)c->iters * c->L.s
-                                          : 2 * (int64_t)c->iters * c->L.s;
+  c->rank = lanczos_method(c->method) ? (int64_t)c->iters * c->L.s
+                                       : 2 * (int64_t)c->iters * c->L.s;
   if (c->iters == 0) c->relres = 1.0;
   c->h_hist.assign((size_t)4 * max_iter, 0.0);
   HIPOK(hipMemcpy(c->h_hist.data(), c->hist, sizeof(double) * 4 * max_iter, hipMemcpyDeviceToHost));
@@ -486,7 +508,7 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->check_every = op->check_every > 0 ? op->check_every : 16;
   c->verify = op->verify;
   c->record_history = op->record_history;
-  c->lagged = L.method == SYLV_METHOD_BICGSTAB && op->reorth != 1 &&
+  c->lagged = !lanczos_method(L.method) && op->reorth != 1 &&
               arnoldi_lagged_supported((int)L.s, L.fp32);
   c->ws = reinterpret_cast<char *>((reinterpret_cast<uintptr_t>(workspace) + ALIGN - 1) / ALIGN * ALIGN);
   if (hipHostMalloc(reinterpret_cast<void **>(&c->h_ds), sizeof(DevState)) != hipSuccess) {
@@ -501,6 +523,7 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   c->Q = at<double>(c, L.off_Q);
   c->S = L.off_S ? at<double>(c, L.off_S) : nullptr;
   c->T = L.off_T ? at<double>(c, L.off_T) : nullptr;
+  for (int i = 0; i < extra_cores(L.method); ++i) c->Ex[i] = at<double>(c, L.off_Ex[i]);
   c->Rt = at<double>(c, L.off_rt);
   c->RL = at<double>(c, L.off_rl);
   c->RR = at<double>(c, L.off_rr);
@@ -848,7 +871,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
     const int64_t rows = w ? PL.m : PL.n;
     int ee;
     for (Ctx *cj : steps) {
-      if (cj->rank == 0 || cj->L.method == SYLV_METHOD_CG) continue;
+      if (cj->rank == 0 || lanczos_method(cj->L.method)) continue;
       const SideDesc &sd = w ? cj->sw : cj->sv;
       const int64_t q = cj->rank + cj->L.s;
       const int qk = (int)std::min<int64_t>(round_up(q, 32), cj->L.ldb);
@@ -866,7 +889,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
         const int p = (int)cj->rank, q = p + (int)CL.s;
         double *Ej = Es + eoff[j];
         prof_begin(P->sc, st);
-        if (CL.method == SYLV_METHOD_CG) {
+        if (lanczos_method(CL.method)) {
           if ((ee = launch_defect_band(r0, r1, sd.rp, sd.ci, sd.val, sd.basis, CL.fp32, CL.ldb, p, q,
                                        (int)CL.s, Hm, CL.ldc, at<double>(cj, CL.off_M2), CL.ldc,
                                        r0 == 0, Ej, PL.ldE, st)))
@@ -1415,6 +1438,167 @@ static int bicg_body(void *ctx, double tol, int max_iter, sylv_result *res) {
   return end_solve(c, max_iter, secs, res);
 }
 
+// ---- further factorized methods (CR on block Lanczos bases; CGS and GPBiCG on block Arnoldi
+// bases), on the context's stream: each iteration issues the basis steps its core products
+// need, then the core products (eq. (3.11)) and the elementwise core recurrences ----
+
+// Arnoldi steps up to `need` (inclusive), one at a time.
+static int arnoldi_upto(Ctx *c, int &next_step, int need) {
+  const SideDesc *sw = c->L.lyap ? nullptr : &c->sw;
+  for (; next_step <= need; ++next_step) {
+    int e = launch_arnoldi_pair((int)c->L.s, c->sv, sw, next_step, c->L.ldc, c->closure_tol, c->sc,
+                                c->ds, c->st, c->lagged);
+    if (e) return e;
+  }
+  return 0;
+}
+
+static int poll_done(Ctx *c, int k, int max_iter, bool &stop) {
+  stop = false;
+  if ((k + 1) % c->check_every == 0 && k + 1 < max_iter) {
+    int e = read_state(c);
+    if (e) return e;
+    stop = c->h_ds->done != 0;
+  }
+  return 0;
+}
+
+static int finish(Ctx *c, int max_iter, std::chrono::steady_clock::time_point t0,
+                  sylv_result *res) {
+  if (hipStreamSynchronize(c->st) != hipSuccess) return SYLV_ERR_HIP;
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return end_solve(c, max_iter, secs, res);
+}
+
+// Factorized conjugate residual: S = F(R) by eq. (3.11) each iteration (block Lanczos step k+1
+// first), Q = F(P) by recurrence; alpha = <R, S> / <Q, Q>, beta = <R+, S+> / <R, S>.
+static int cr_body(void *ctx, double tol, int max_iter, sylv_result *res) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return SYLV_ERR_INVALID;
+  const Layout &L = c->L;
+  const int s = (int)L.s;
+  auto t0 = std::chrono::steady_clock::now();
+  int e = begin_solve(c, tol, max_iter, SYLV_METHOD_CR);
+  if (e) return e;
+  const hipStream_t st = c->st;
+  const int *done = &c->ds->done;
+  const SideDesc *sw = L.lyap ? nullptr : &c->sw;
+  int steps = 0;
+  auto step = [&](int j) {
+    steps = j + 1;
+    return launch_lanczos_pair(s, c->sv, sw, j, L.ldc, c->closure_tol, c->sc, c->ds, st);
+  };
+  // S_0 = F(R_0), Q_0 = S_0, rho_0 = <R_0, S_0>, <Q_0, Q_0>
+  if ((e = step(0))) return e;
+  if ((e = launch_core_op(s, s, c->H, c->G, c->R, c->S, L.ldc, done, st, c->cpart, L.cpart_cap)))
+    return e;
+  if ((e = launch_cr_init(2 * s, c->R, c->S, c->Q, L.ldc, c->scc, c->ds, st))) return e;
+  for (int k = 0; k < max_iter; ++k) {
+    const int q = (k + 2) * s;  // R_{k+1}, Q_k: q x q; S_{k+1}: (q + s) x (q + s)
+    set_iter(c, k);
+    if ((e = launch_cr_xr(q, c->X, c->R, c->P, c->Q, L.ldc, c->scc, c->ds, c->hist, k, max_iter,
+                          st)))
+      return e;
+    if ((e = step(k + 1))) return e;
+    if ((e = launch_core_op(s, q, c->H, c->G, c->R, c->S, L.ldc, done, st, c->cpart,
+                            L.cpart_cap)))
+      return e;
+    if ((e = launch_cr_beta_pq(q + s, c->R, c->S, c->P, c->Q, L.ldc, c->scc, c->ds, c->hist, k,
+                               max_iter, st)))
+      return e;
+    bool stop;
+    if ((e = poll_done(c, k, max_iter, stop))) return e;
+    if (stop) break;
+  }
+  if ((steps + 1) % LZ_RING != 0 && (e = launch_lanczos_flush(s, c->sv, sw, steps + 1, st)))
+    return e;
+  return finish(c, max_iter, t0, res);
+}
+
+// Factorized CGS: V = F(P), alpha = rho / <R~0, V(1:s,1:s)>, Q = U - alpha V, W = U + Q,
+// X += alpha W, R -= alpha F(W), beta = rho+ / rho, U = R + beta Q, P = U + beta (Q + beta P).
+static int cgs_body(void *ctx, double tol, int max_iter, sylv_result *res) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return SYLV_ERR_INVALID;
+  const Layout &L = c->L;
+  const int s = (int)L.s;
+  auto t0 = std::chrono::steady_clock::now();
+  int e = begin_solve(c, tol, max_iter, SYLV_METHOD_CGS);
+  if (e) return e;
+  const hipStream_t st = c->st;
+  const int *done = &c->ds->done;
+  double *U = c->Ex[0], *V = c->S, *Qb = c->Q, *Wk = c->T, *AW = c->Ex[1];
+  if ((e = launch_copy_block(s, s, 1.0, c->R, L.ldc, false, U, L.ldc, st))) return e;  // U_0 = R_0
+  int next_step = 0;
+  for (int k = 0; k < max_iter; ++k) {
+    const int p = (2 * k + 1) * s, q = p + s;
+    const int need1 = 2 * k + (c->lagged ? 1 : 0);
+    set_iter(c, k);
+    if ((e = arnoldi_upto(c, next_step, need1))) return e;
+    if ((e = launch_core_op(s, p, c->H, c->G, c->P, V, L.ldc, done, st, c->cpart, L.cpart_cap)))
+      return e;
+    if ((e = launch_alpha_corner(s, c->Rt, V, L.ldc, c->ds, c->hist, k, max_iter, st))) return e;
+    if ((e = launch_cgs_qwx(q, U, V, Qb, Wk, c->X, L.ldc, c->ds, st))) return e;
+    if ((e = arnoldi_upto(c, next_step, need1 + 1))) return e;
+    if ((e = launch_core_op(s, q, c->H, c->G, Wk, AW, L.ldc, done, st, c->cpart, L.cpart_cap)))
+      return e;
+    if ((e = launch_axpy_rho_beta(s, q + s, AW, c->R, c->Rt, L.ldc, false, c->scc, c->ds, c->hist,
+                                  k, max_iter, st)))
+      return e;
+    if ((e = launch_cgs_up(q + s, c->R, Qb, U, c->P, L.ldc, c->ds, st))) return e;
+    bool stop;
+    if ((e = poll_done(c, k, max_iter, stop))) return e;
+    if (stop) break;
+  }
+  return finish(c, max_iter, t0, res);
+}
+
+// Factorized GPBiCG: p = r + beta (p - u), F(p), alpha, y and t, F(t), zeta and eta from the
+// two-term minimization (eta = 0 on the first iteration), u, z, x and r updates, beta, w.
+static int gpbicg_body(void *ctx, double tol, int max_iter, sylv_result *res) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return SYLV_ERR_INVALID;
+  const Layout &L = c->L;
+  const int s = (int)L.s;
+  auto t0 = std::chrono::steady_clock::now();
+  int e = begin_solve(c, tol, max_iter, SYLV_METHOD_GPBICG);
+  if (e) return e;
+  const hipStream_t st = c->st;
+  const int *done = &c->ds->done;
+  double *AP = c->Q, *T = c->S, *Tm = c->T, *AT = c->Ex[0], *Y = c->Ex[1], *U = c->Ex[2],
+         *Z = c->Ex[3], *Wv = c->Ex[4];
+  int next_step = 0;
+  for (int k = 0; k < max_iter; ++k) {
+    const int p = (2 * k + 1) * s, q = p + s;
+    const int need1 = 2 * k + (c->lagged ? 1 : 0);
+    set_iter(c, k);
+    if ((e = launch_gp_p(p, c->R, U, c->P, L.ldc, c->ds, st))) return e;
+    if ((e = arnoldi_upto(c, next_step, need1))) return e;
+    if ((e = launch_core_op(s, p, c->H, c->G, c->P, AP, L.ldc, done, st, c->cpart, L.cpart_cap)))
+      return e;
+    if ((e = launch_alpha_corner(s, c->Rt, AP, L.ldc, c->ds, c->hist, k, max_iter, st))) return e;
+    if ((e = launch_gp_yt(q, Tm, c->R, Wv, AP, Y, T, L.ldc, c->ds, st))) return e;
+    if ((e = arnoldi_upto(c, next_step, need1 + 1))) return e;
+    if ((e = launch_core_op(s, q, c->H, c->G, T, AT, L.ldc, done, st, c->cpart, L.cpart_cap)))
+      return e;
+    if ((e = launch_gp_zeta(q + s, AT, Y, T, L.ldc, k == 0, c->scc, c->ds, c->hist, k, max_iter,
+                            st)))
+      return e;
+    if ((e = launch_gp_update(q + s, AP, Tm, c->P, T, Y, AT, c->R, U, Z, c->X, L.ldc, c->scc,
+                              c->ds, st)))
+      return e;
+    if ((e = launch_axpy_rho_beta(s, q + s, nullptr, c->R, c->Rt, L.ldc, true, c->scc, c->ds,
+                                  c->hist, k, max_iter, st)))
+      return e;
+    if ((e = launch_gp_w(q + s, AT, AP, Wv, L.ldc, c->ds, st))) return e;
+    std::swap(T, Tm);  // t_k becomes t_{k-1} of the next iteration
+    bool stop;
+    if ((e = poll_done(c, k, max_iter, stop))) return e;
+    if (stop) break;
+  }
+  return finish(c, max_iter, t0, res);
+}
+
 // A solve followed, when the context verifies, by the true residual of the converged iterate:
 // if it misses tol (the recursive residual of the recurrence drifted from the true one), the
 // solve runs again with the recursive target lowered in proportion, at most twice.
@@ -1422,8 +1606,13 @@ static int solve_verified(void *ctx, int method, double tol, int max_iter, sylv_
   Ctx *c = reinterpret_cast<Ctx *>(ctx);
   if (!c) return SYLV_ERR_INVALID;
   auto run = [&](double t) {
-    return method == SYLV_METHOD_CG ? cg_body(ctx, t, max_iter, res)
-                                    : bicg_body(ctx, t, max_iter, res);
+    switch (method) {
+      case SYLV_METHOD_CG: return cg_body(ctx, t, max_iter, res);
+      case SYLV_METHOD_BICGSTAB: return bicg_body(ctx, t, max_iter, res);
+      case SYLV_METHOD_CR: return cr_body(ctx, t, max_iter, res);
+      case SYLV_METHOD_CGS: return cgs_body(ctx, t, max_iter, res);
+      default: return gpbicg_body(ctx, t, max_iter, res);
+    }
   };
   auto t0 = std::chrono::steady_clock::now();
   int st = run(tol);
@@ -1456,6 +1645,18 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
 
 int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res) {
   return solve_verified(ctx, SYLV_METHOD_BICGSTAB, tol, max_iter, res);
+}
+
+int sylv_factored_cr(void *ctx, double tol, int max_iter, sylv_result *res) {
+  return solve_verified(ctx, SYLV_METHOD_CR, tol, max_iter, res);
+}
+
+int sylv_factored_cgs(void *ctx, double tol, int max_iter, sylv_result *res) {
+  return solve_verified(ctx, SYLV_METHOD_CGS, tol, max_iter, res);
+}
+
+int sylv_factored_gpbicg(void *ctx, double tol, int max_iter, sylv_result *res) {
+  return solve_verified(ctx, SYLV_METHOD_GPBICG, tol, max_iter, res);
 }
 
 int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx, double *W,

@@ -26,8 +26,9 @@ size_t align_up(size_t b) { return (b + BALIGN - 1) / BALIGN * BALIGN; }
 // Relative cost of one instance: the Krylov bases' traffic and the core work both grow with the
 // rank, so (n + m) s iterations plus the core size is a fair ordering key.
 double cost_estimate(const sylv_problem &p, const sylv_options &o) {
-  const double r = (double)o.max_iter * p.s * (o.method == SYLV_METHOD_CG ? 1.0 : 2.0);
-  return (double)(p.n + p.m) * r + r * r * (o.method == SYLV_METHOD_CG ? 1.0 : r / 64.0);
+  const bool one = o.method == SYLV_METHOD_CG || o.method == SYLV_METHOD_CR;
+  const double r = (double)o.max_iter * p.s * (one ? 1.0 : 2.0);
+  return (double)(p.n + p.m) * r + r * r * (one ? 1.0 : r / 64.0);
 }
 
 void destroy_batch(Batch *b) {
@@ -144,9 +145,15 @@ int sylv_batch_solve(void *batch, double tol, sylv_result *res) {
         return;
       }
       for (int i : b->plan[k]) {
-        const int e = (b->method[i] == SYLV_METHOD_CG)
-                          ? sylv_factored_cg(b->ctx[i], tol, b->max_iter[i], &res[i])
-                          : sylv_factored_bicgstab(b->ctx[i], tol, b->max_iter[i], &res[i]);
+        int (*solve)(void *, double, int, sylv_result *) = sylv_factored_bicgstab;
+        switch (b->method[i]) {
+          case SYLV_METHOD_CG: solve = sylv_factored_cg; break;
+          case SYLV_METHOD_CR: solve = sylv_factored_cr; break;
+          case SYLV_METHOD_CGS: solve = sylv_factored_cgs; break;
+          case SYLV_METHOD_GPBICG: solve = sylv_factored_gpbicg; break;
+          default: break;
+        }
+        const int e = solve(b->ctx[i], tol, b->max_iter[i], &res[i]);
         if (e < 0) {
           err[k] = e;
           return;

@@ -26,6 +26,7 @@ struct DevState {
   int status;        // SYLV_OK / SYLV_BREAKDOWN once done
   int iters;         // completed iterations when done
   int rho_zero;      // BiCGSTAB: rho_{k+1} == 0 (breakdown after the update)
+  double eta;        // GPBiCG: second parameter of the two-term minimization (zeta in omega)
 };
 
 // State of one basis (V with H, or W with G) for the block orthonormalization of a new block.
@@ -647,6 +648,40 @@ int launch_bicg_update(int s, int p, double *X, double *R, double *P, const doub
                        const double *S, const double *T, const double *Rt, int64_t ldc,
                        const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
                        hipStream_t st);
+
+// Further factorized methods (core_more.hip): elementwise core recurrences and scalars of CR,
+// CGS and GPBiCG over q x q corners; the partials live in sc.partials.
+int launch_cr_init(int q, const double *R, const double *S, double *Q, int64_t ldc,
+                   const Scratch &sc, DevState *ds, hipStream_t st);
+int launch_cr_xr(int q, double *X, double *R, const double *P, const double *Q, int64_t ldc,
+                 const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
+                 hipStream_t st);
+int launch_cr_beta_pq(int q, const double *R, const double *S, double *P, double *Q,
+                      int64_t ldc, const Scratch &sc, DevState *ds, double *hist, int k,
+                      int max_iter, hipStream_t st);
+int launch_alpha_corner(int s, const double *Rt, const double *Z, int64_t ldc, DevState *ds,
+                        double *hist, int k, int max_iter, hipStream_t st);
+int launch_cgs_qwx(int q, const double *U, const double *V, double *Q, double *Wk, double *X,
+                   int64_t ldc, DevState *ds, hipStream_t st);
+// R -= alpha Z (unless gpbicg: R was updated by launch_gp_update) with ||R||^2, the stopping
+// test, rho_{k+1} and beta_k.
+int launch_axpy_rho_beta(int s, int q, const double *Z, double *R, const double *Rt, int64_t ldc,
+                         bool gpbicg, const Scratch &sc, DevState *ds, double *hist, int k,
+                         int max_iter, hipStream_t st);
+int launch_cgs_up(int q, const double *R, const double *Q, double *U, double *P, int64_t ldc,
+                  DevState *ds, hipStream_t st);
+int launch_gp_p(int q, const double *R, const double *U, double *P, int64_t ldc, DevState *ds,
+                hipStream_t st);
+int launch_gp_yt(int q, const double *Tm, const double *R, const double *Wv, const double *AP,
+                 double *Y, double *T, int64_t ldc, DevState *ds, hipStream_t st);
+int launch_gp_zeta(int q, const double *AT, const double *Y, const double *T, int64_t ldc,
+                   bool first, const Scratch &sc, DevState *ds, double *hist, int k, int max_iter,
+                   hipStream_t st);
+int launch_gp_update(int q, const double *AP, const double *Tm, const double *P, const double *T,
+                     const double *Y, const double *AT, double *R, double *U, double *Z,
+                     double *X, int64_t ldc, const Scratch &sc, DevState *ds, hipStream_t st);
+int launch_gp_w(int q, const double *AT, const double *AP, double *Wv, int64_t ldc, DevState *ds,
+                hipStream_t st);
 
 // Dense FP64 GEMM C (M x N) = alpha * op(A) op(B) + beta * C with element strides:
 // A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs], C(i,j) = C[i*ldc + j].

@@ -24,6 +24,7 @@ SYLV_OK, SYLV_NOT_CONVERGED, SYLV_BREAKDOWN = 0, 1, 2
 SYLV_ERR_INVALID, SYLV_ERR_HIP, SYLV_ERR_WORKSPACE = -1, -2, -3
 SYLV_ERR_RHS_RANK, SYLV_ERR_STATE = -4, -5
 SYLV_METHOD_CG, SYLV_METHOD_BICGSTAB = 0, 1
+SYLV_METHOD_CR, SYLV_METHOD_CGS, SYLV_METHOD_GPBICG = 2, 3, 4
 SYLV_FP64, SYLV_MIXED_FP32 = 0, 1
 
 
@@ -81,7 +82,8 @@ _lib.sylv_workspace_bytes.restype = c_size_t
 _lib.sylv_create.argtypes = [POINTER(c_void_p), POINTER(sylv_problem), POINTER(sylv_options),
                              c_void_p, c_size_t, c_void_p]
 _lib.sylv_create.restype = c_int
-for _f in ("sylv_factored_cg", "sylv_factored_bicgstab"):
+for _f in ("sylv_factored_cg", "sylv_factored_bicgstab", "sylv_factored_cr", "sylv_factored_cgs",
+           "sylv_factored_gpbicg"):
     getattr(_lib, _f).argtypes = [c_void_p, c_double, c_int, POINTER(sylv_result)]
     getattr(_lib, _f).restype = c_int
 _lib.sylv_residual_norm.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double)]
@@ -220,6 +222,25 @@ def sylv_factored_cg(ctx, tol: float, max_iter: int) -> sylv_result:
 
 def sylv_factored_bicgstab(ctx, tol: float, max_iter: int) -> sylv_result:
     return _solve(_lib.sylv_factored_bicgstab, ctx, tol, max_iter)
+
+
+def sylv_factored_cr(ctx, tol: float, max_iter: int) -> sylv_result:
+    return _solve(_lib.sylv_factored_cr, ctx, tol, max_iter)
+
+
+def sylv_factored_cgs(ctx, tol: float, max_iter: int) -> sylv_result:
+    return _solve(_lib.sylv_factored_cgs, ctx, tol, max_iter)
+
+
+def sylv_factored_gpbicg(ctx, tol: float, max_iter: int) -> sylv_result:
+    return _solve(_lib.sylv_factored_gpbicg, ctx, tol, max_iter)
+
+
+METHOD_CODES = {"cg": SYLV_METHOD_CG, "bicgstab": SYLV_METHOD_BICGSTAB, "cr": SYLV_METHOD_CR,
+                "cgs": SYLV_METHOD_CGS, "gpbicg": SYLV_METHOD_GPBICG}
+SOLVERS = {SYLV_METHOD_CG: "sylv_factored_cg", SYLV_METHOD_BICGSTAB: "sylv_factored_bicgstab",
+           SYLV_METHOD_CR: "sylv_factored_cr", SYLV_METHOD_CGS: "sylv_factored_cgs",
+           SYLV_METHOD_GPBICG: "sylv_factored_gpbicg"}
 
 
 def sylv_residual_norm(ctx):
@@ -374,6 +395,11 @@ class Solver:
     def factored_bicgstab(self, tol, max_iter=None):
         return sylv_factored_bicgstab(self.ctx, tol, max_iter or self.max_iter)
 
+    def solve(self, tol, max_iter=None):
+        """The method the context was created for."""
+        fn = globals()[SOLVERS[self.options.method]]
+        return fn(self.ctx, tol, max_iter or self.max_iter)
+
     def residual_norm(self):
         return sylv_residual_norm(self.ctx)
 
@@ -458,7 +484,7 @@ class Batch:
             m = n if p.lyapunov else p.B.shape[0]
             probs.append(sylv_problem(n, m, s, make_csr(n, *A), make_csr(m, *Bm),
                                       1 if p.lyapunov else 0, _ptr(C1), s, _ptr(C2), s))
-            method = SYLV_METHOD_CG if p.method == "cg" else SYLV_METHOD_BICGSTAB
+            method = METHOD_CODES[p.method]
             opts.append(default_options(method, p.max_iter, precision=precision))
         self.problems, self.options = probs, opts
         nbytes = sylv_batch_workspace_bytes(probs, opts)

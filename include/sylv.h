@@ -223,6 +223,24 @@ int sylv_residual_norm(void *ctx, double *abs_res, double *rel_res);
 int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx,
                      double *W, int64_t ldw, int64_t *rank_v, int64_t *rank_w);
 
+/* Low-rank compression of the current iterate (the step after the solve, Corollary 3.3's form):
+ * with V and W of orthonormal columns the singular values of X = V Xc W^T are those of the
+ * core, so a truncated SVD Xc ~= U_k diag(sigma) Y_k^T gives X ~= (V U_k) diag(sigma) (W Y_k)^T.
+ * sylv_compress finds the smallest rank k (at most max_rank when max_rank >= 0) with
+ * ||Xc - U_k diag(sigma) Y_k^T||_F <= rel_tol ||Xc||_F, evaluating that error directly; *rank
+ * and *rel_err (host, may be NULL) receive k and the achieved relative error. The SVD is formed
+ * in FP64 on the GPU from a randomized range of at most 256 columns (Gaussian test matrix, one
+ * power step) and one-sided Jacobi rotations on the projected core. Returns 0, or
+ * SYLV_NOT_CONVERGED when max_rank or the 256-column range cannot meet rel_tol (the best
+ * rank-k factors are kept). SYLV_ERR_STATE before a solve or after a refined solve;
+ * SYLV_ERR_INVALID with FP32 bases.
+ * sylv_get_compressed copies Z1 = V U_k (n x k, ldz1), sigma (k, descending) and Z2 = W Y_k
+ * (m x k, ldz2) into device buffers (any may be NULL; *rank receives k). A later solve discards
+ * the compression (SYLV_ERR_STATE until sylv_compress runs again). */
+int sylv_compress(void *ctx, double rel_tol, int64_t max_rank, int64_t *rank, double *rel_err);
+int sylv_get_compressed(void *ctx, double *Z1, int64_t ldz1, double *sigma, double *Z2,
+                        int64_t ldz2, int64_t *rank);
+
 /* Per-iteration history of the last solve, host arrays of capacity cap (any may be NULL):
  * relres[k] = ||R_{k+1}|| / ||R_0||, alpha[k], beta[k], omega[k] (omega only for BiCGSTAB;
  * beta[k] is undefined for the final iteration). *count receives the number of iterations. */

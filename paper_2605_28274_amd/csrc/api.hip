@@ -31,6 +31,10 @@ struct Layout {
   size_t off_cscr, off_partials, off_counters, off_ds, off_ssv, off_ssw, off_rt, off_rl, off_rr, off_hist;
   size_t off_Lx, off_M2, off_d1, off_d2, off_c2, off_cpart, cpart_cap = 0;
   size_t off_Ex[5] = {0, 0, 0, 0, 0};  // further cores of CGS and GPBiCG
+  // solution compression: l <= lc columns of the randomized range (rmax x lc panels)
+  int64_t lc = 0;
+  size_t off_cOm = 0, off_cY = 0, off_cZ = 0, off_cB = 0, off_cG = 0, off_cU = 0, off_cUk = 0,
+         off_cYk = 0, off_csig = 0, off_cidx = 0, off_cpt = 0, off_cinfo = 0;
   size_t off_dots, off_flag, off_panV, off_panW, off_sellA, off_sellB;
   // outer refinement: correction contexts and the buffers of the sketch and of the residual of
   // the summed iterates (child: a correction context, whose operators belong to the parent)
@@ -49,6 +53,7 @@ struct Layout {
 };
 
 constexpr int NLD = 64;         // row stride (doubles) of the narrow panels of the refinement
+constexpr int64_t COMPRESS_LMAX = 256;  // columns of the randomized range at most
 constexpr int REFINE_CAP = 4;   // correction solves at most
 constexpr size_t GPART_CAP = (size_t)1024 * 64 * 64;  // split-K partial tiles of the Grams
 
@@ -181,6 +186,22 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   L.off_sellA = child ? 0 : bump(cur, sell_bytes(L.n, pb->A.nnz));
   L.off_sellB = (L.lyap || child) ? L.off_sellA : bump(cur, sell_bytes(L.m, pb->B.nnz));
   L.off_dots = bump(cur, 16 * 8);
+  if (!child) {
+    L.lc = std::min<int64_t>(COMPRESS_LMAX, L.rmax);
+    const size_t panel = (size_t)L.rmax * L.lc * 8, wide = (size_t)L.lc * L.ldc * 8;
+    L.off_cOm = bump(cur, panel);
+    L.off_cY = bump(cur, wide);
+    L.off_cZ = bump(cur, wide);
+    L.off_cB = bump(cur, wide);
+    L.off_cG = bump(cur, (size_t)L.lc * L.lc * 8);
+    L.off_cU = bump(cur, panel);
+    L.off_cUk = bump(cur, panel);
+    L.off_cYk = bump(cur, panel);
+    L.off_csig = bump(cur, (size_t)L.lc * 8 * 2);
+    L.off_cidx = bump(cur, (size_t)L.lc * 4);
+    L.off_cpt = bump(cur, 1024 * 8);
+    L.off_cinfo = bump(cur, 64);
+  }
   L.off_flag = bump(cur, 16 * sizeof(int));
   if (!child && op->refine_max > 0) {
     if (op->refine_max > REFINE_CAP || op->refine_rank < 1 || op->refine_rank > SYLV_MAX_S ||
@@ -350,6 +371,8 @@ struct Ctx {
   int outer_steps = 0;
   int in_refine = 0;         // the refinement's own first solve is running
   int verify = 1;            // check the true residual after a converged solve
+  int64_t comp_k = -1;       // rank of the compressed solution (-1: none since the last solve)
+  double comp_err = 0.0;     // its relative Frobenius error
   int res_valid = 0;         // abs_res / rel_res hold the residual of the current iterate
   double res_abs = 0.0, res_rel = 0.0;
 };
@@ -420,6 +443,7 @@ int begin_solve(Ctx *c, double tol, int max_iter, int method) {
   if (err) return err;
   c->solved = 0;
   c->res_valid = 0;
+  c->comp_k = -1;
   c->method = method;
   c->max_iter_run = max_iter;
   return 0;
@@ -1438,6 +1462,95 @@ static int bicg_body(void *ctx, double tol, int max_iter, sylv_result *res) {
   return end_solve(c, max_iter, secs, res);
 }
 
+// ---- solution compression: truncated SVD of the core (randomized range with one power step,
+// one-sided Jacobi on the projected core, exact error of the truncated core) ----
+static int compress_core(Ctx *c, double rel_tol, int64_t max_rank) {
+  const Layout &L = c->L;
+  const hipStream_t st = c->st;
+  const int64_t r = c->rank, ldc = L.ldc, lm = L.lc;
+  double *X = c->X, *T = c->Q;  // a free core buffer after the solve holds the rank-k core
+  double *Om = at<double>(c, L.off_cOm), *Y = at<double>(c, L.off_cY), *Z = at<double>(c, L.off_cZ);
+  double *Bm = at<double>(c, L.off_cB), *G = at<double>(c, L.off_cG), *U = at<double>(c, L.off_cU);
+  double *Uk = at<double>(c, L.off_cUk), *Yk = at<double>(c, L.off_cYk);
+  double *sig = at<double>(c, L.off_csig), *sigk = sig + lm, *pt = at<double>(c, L.off_cpt);
+  int *idx = at<int>(c, L.off_cidx), *info = at<int>(c, L.off_cinfo);
+  c->comp_k = 0;
+  c->comp_err = 0.0;
+  if (r == 0) return 0;
+  double nx = 0.0;
+  int e = diff_norm(r, r, X, ldc, nullptr, 0, pt, nullptr, &nx, st);
+  if (e) return e;
+  if (nx == 0.0) return 0;
+  // rows of M (l x r) orthonormal: one-sided Jacobi, then normalized (rows of negligible norm
+  // dropped: Y's rank is below l)
+  std::vector<double> hs(lm);
+  std::vector<double> f(lm);
+  auto orth_rows = [&](double *M, int l) -> int {
+    int ee;
+    if ((ee = launch_jacobi_rows(l, r, M, ldc, G, lm, info, st))) return ee;
+    if ((ee = launch_row_norms(l, r, M, ldc, sig, st))) return ee;
+    HIPOK(hipMemcpyAsync(hs.data(), sig, sizeof(double) * l, hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    const double mx = *std::max_element(hs.begin(), hs.begin() + l);
+    for (int i = 0; i < l; ++i) f[i] = (hs[i] > 1e-14 * mx) ? 1.0 / hs[i] : 0.0;
+    HIPOK(hipMemcpyAsync(sig, f.data(), sizeof(double) * l, hipMemcpyHostToDevice, st));
+    return launch_scale_rows(l, r, M, ldc, sig, st);
+  };
+  int l = (int)std::min<int64_t>(r, std::min<int64_t>(lm, std::max<int64_t>(64, 2 * max_rank)));
+  for (;;) {
+    if ((e = launch_gauss_fill(r, l, 0xC0FFEEull + (uint64_t)l, Om, lm, st))) return e;
+    // Y^T = Omega^T Xc^T (l x r), orthonormal rows; one power step Y^T = (Q^T Xc) Xc^T
+    if ((e = launch_gemm(l, r, r, 1.0, Om, 1, lm, X, 1, ldc, 0.0, Y, ldc, st))) return e;
+    if ((e = orth_rows(Y, l))) return e;
+    // (each product is followed by an orthonormalization, so a direction keeps its singular
+    // value relative to the largest once, not its square: small ones stay above rounding)
+    if ((e = launch_gemm(l, r, r, 1.0, Y, ldc, 1, X, ldc, 1, 0.0, Z, ldc, st))) return e;
+    if ((e = orth_rows(Z, l))) return e;
+    if ((e = launch_gemm(l, r, r, 1.0, Z, ldc, 1, X, 1, ldc, 0.0, Y, ldc, st))) return e;
+    if ((e = orth_rows(Y, l))) return e;
+    // B = Q^T Xc (l x r); G B = D with orthogonal rows, sigma_i = ||D_i||
+    if ((e = launch_gemm(l, r, r, 1.0, Y, ldc, 1, X, ldc, 1, 0.0, Bm, ldc, st))) return e;
+    if ((e = launch_jacobi_rows(l, r, Bm, ldc, G, lm, info, st))) return e;
+    if ((e = launch_row_norms(l, r, Bm, ldc, sig, st))) return e;
+    HIPOK(hipMemcpyAsync(hs.data(), sig, sizeof(double) * l, hipMemcpyDeviceToHost, st));
+    HIPOK(hipStreamSynchronize(st));
+    std::vector<int> ord(l);
+    for (int i = 0; i < l; ++i) ord[i] = i;
+    std::stable_sort(ord.begin(), ord.end(), [&](int a, int b) { return hs[a] > hs[b]; });
+    // smallest k whose singular-value tail meets the tolerance
+    std::vector<double> tail(l + 1, 0.0);
+    for (int i = l - 1; i >= 0; --i) tail[i] = tail[i + 1] + hs[ord[i]] * hs[ord[i]];
+    int k = l;
+    for (int i = 0; i <= l; ++i)
+      if (std::sqrt(tail[i]) <= rel_tol * nx) {
+        k = i;
+        break;
+      }
+    if (max_rank >= 0) k = (int)std::min<int64_t>(k, max_rank);
+    // U = Q G^T (r x l); U_k, Y_k and sigma_k in descending order
+    if ((e = launch_gemm(r, l, l, 1.0, Y, 1, ldc, G, 1, lm, 0.0, U, lm, st))) return e;
+    HIPOK(hipMemcpyAsync(idx, ord.data(), sizeof(int) * l, hipMemcpyHostToDevice, st));
+    std::vector<double> hk(l);
+    for (int i = 0; i < l; ++i) hk[i] = hs[ord[i]];
+    HIPOK(hipMemcpyAsync(sigk, hk.data(), sizeof(double) * l, hipMemcpyHostToDevice, st));
+    double err = 0.0;
+    if (k > 0) {
+      if ((e = launch_gather_cols(r, k, idx, U, lm, sig, Uk, lm, st))) return e;  // U_k sigma_k
+      if ((e = launch_gather_rows_t(r, k, idx, Bm, ldc, sig, Yk, lm, st))) return e;
+      if ((e = launch_gemm(r, r, k, 1.0, Uk, lm, 1, Yk, 1, lm, 0.0, T, ldc, st))) return e;
+      if ((e = diff_norm(r, r, X, ldc, T, ldc, pt, &err, nullptr, st))) return e;
+      if ((e = launch_gather_cols(r, k, idx, U, lm, nullptr, Uk, lm, st))) return e;  // U_k
+    } else {
+      err = nx;
+    }
+    c->comp_k = k;
+    c->comp_err = err / nx;
+    if (err <= rel_tol * nx * (1.0 + 1e-12) || l >= r || l >= lm || (max_rank >= 0 && k >= max_rank))
+      return 0;
+    l = (int)std::min<int64_t>({2 * (int64_t)l, r, lm});
+  }
+}
+
 // ---- further factorized methods (CR on block Lanczos bases; CGS and GPBiCG on block Arnoldi
 // bases), on the context's stream: each iteration issues the basis steps its core products
 // need, then the core products (eq. (3.11)) and the elementwise core recurrences ----
@@ -1645,6 +1758,48 @@ int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
 
 int sylv_factored_bicgstab(void *ctx, double tol, int max_iter, sylv_result *res) {
   return solve_verified(ctx, SYLV_METHOD_BICGSTAB, tol, max_iter, res);
+}
+
+int sylv_compress(void *ctx, double rel_tol, int64_t max_rank, int64_t *rank, double *rel_err) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c || !(rel_tol >= 0.0)) return SYLV_ERR_INVALID;
+  if (!c->solved || c->parent || !c->kids.empty()) return SYLV_ERR_STATE;
+  if (c->L.fp32) return SYLV_ERR_INVALID;
+  int e = compress_core(c, rel_tol, max_rank);
+  if (e) {
+    c->comp_k = -1;
+    return e;
+  }
+  if (rank) *rank = c->comp_k;
+  if (rel_err) *rel_err = c->comp_err;
+  return c->comp_err <= rel_tol * (1.0 + 1e-12) ? 0 : SYLV_NOT_CONVERGED;
+}
+
+int sylv_get_compressed(void *ctx, double *Z1, int64_t ldz1, double *sigma, double *Z2,
+                        int64_t ldz2, int64_t *rank) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c) return SYLV_ERR_INVALID;
+  if (c->comp_k < 0) return SYLV_ERR_STATE;
+  const Layout &L = c->L;
+  const int64_t k = c->comp_k, r = c->rank, lm = L.lc;
+  if (rank) *rank = k;
+  if (k == 0) return 0;
+  if ((Z1 && ldz1 < k) || (Z2 && ldz2 < k)) return SYLV_ERR_INVALID;
+  hipStream_t st = c->st;
+  int e;
+  const double *V = static_cast<const double *>(c->sv.basis);
+  const double *W = static_cast<const double *>(c->sw.basis);
+  if (Z1 && (e = launch_gemm(L.n, k, r, 1.0, V, L.ldb, 1, at<double>(c, L.off_cUk), lm, 1, 0.0, Z1,
+                             ldz1, st)))
+    return e;
+  if (Z2 && (e = launch_gemm(L.m, k, r, 1.0, W, L.ldb, 1, at<double>(c, L.off_cYk), lm, 1, 0.0, Z2,
+                             ldz2, st)))
+    return e;
+  if (sigma)
+    HIPOK(hipMemcpyAsync(sigma, at<double>(c, L.off_csig) + lm, sizeof(double) * k,
+                         hipMemcpyDeviceToDevice, st));
+  HIPOK(hipStreamSynchronize(st));
+  return 0;
 }
 
 int sylv_factored_cr(void *ctx, double tol, int max_iter, sylv_result *res) {

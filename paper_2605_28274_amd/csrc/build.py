@@ -17,7 +17,7 @@ BUILD_DIR = os.path.join(ROOT, "_build")
 LIB = os.path.join(PKG, "libsylv.so")
 
 SOURCES = ["api.hip", "sparse.hip", "krylov.hip", "arnoldi.hip", "core.hip", "dense.hip",
-           "residual.hip", "refine.hip", "batch.hip", "gram_bf16.hip", "core_more.hip"] + [f"arnoldi_s{s}.hip" for s in range(1, 9)]
+           "residual.hip", "refine.hip", "batch.hip", "gram_bf16.hip", "core_more.hip", "compress.hip"] + [f"arnoldi_s{s}.hip" for s in range(1, 9)]
 ARCH = os.environ.get("SYLV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -683,6 +683,23 @@ int launch_gp_update(int q, const double *AP, const double *Tm, const double *P,
 int launch_gp_w(int q, const double *AT, const double *AP, double *Wv, int64_t ldc, DevState *ds,
                 hipStream_t st);
 
+// Solution compression (compress.hip).
+// Rows of M (nr x len, ldm) orthogonalized by one-sided Jacobi rotations: G M_in = M_out with G
+// (nr x nr, ldg) orthogonal; info[0] = sweeps.
+int launch_jacobi_rows(int nr, int64_t len, double *M, int64_t ldm, double *G, int64_t ldg,
+                       int *info, hipStream_t st);
+int launch_row_norms(int nr, int64_t len, const double *M, int64_t ldm, double *norms,
+                     hipStream_t st);
+int launch_scale_rows(int nr, int64_t len, double *M, int64_t ldm, const double *f,
+                      hipStream_t st);
+// ||A - B||_F (B may be null: ||A||_F) and ||A||_F to the host; partials: 1024 doubles.
+int diff_norm(int64_t r, int64_t c, const double *A, int64_t lda, const double *B, int64_t ldb,
+              double *partials, double *dnorm, double *anorm, hipStream_t st);
+int launch_gather_cols(int64_t rows, int k, const int *idx, const double *src, int64_t lds,
+                       const double *scale, double *dst, int64_t ldd, hipStream_t st);
+int launch_gather_rows_t(int64_t len, int k, const int *idx, const double *src, int64_t lds,
+                         const double *sig, double *dst, int64_t ldd, hipStream_t st);
+
 // Dense FP64 GEMM C (M x N) = alpha * op(A) op(B) + beta * C with element strides:
 // A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs], C(i,j) = C[i*ldc + j].
 int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t a_rs,

@@ -86,6 +86,11 @@ for _f in ("sylv_factored_cg", "sylv_factored_bicgstab", "sylv_factored_cr", "sy
            "sylv_factored_gpbicg"):
     getattr(_lib, _f).argtypes = [c_void_p, c_double, c_int, POINTER(sylv_result)]
     getattr(_lib, _f).restype = c_int
+_lib.sylv_compress.argtypes = [c_void_p, c_double, c_int64, POINTER(c_int64), POINTER(c_double)]
+_lib.sylv_compress.restype = c_int
+_lib.sylv_get_compressed.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_void_p, c_int64,
+                                     POINTER(c_int64)]
+_lib.sylv_get_compressed.restype = c_int
 _lib.sylv_residual_norm.argtypes = [c_void_p, POINTER(c_double), POINTER(c_double)]
 _lib.sylv_residual_norm.restype = c_int
 _lib.sylv_get_factors.argtypes = [c_void_p, c_void_p, c_int64, c_void_p, c_int64, c_void_p,
@@ -241,6 +246,25 @@ METHOD_CODES = {"cg": SYLV_METHOD_CG, "bicgstab": SYLV_METHOD_BICGSTAB, "cr": SY
 SOLVERS = {SYLV_METHOD_CG: "sylv_factored_cg", SYLV_METHOD_BICGSTAB: "sylv_factored_bicgstab",
            SYLV_METHOD_CR: "sylv_factored_cr", SYLV_METHOD_CGS: "sylv_factored_cgs",
            SYLV_METHOD_GPBICG: "sylv_factored_gpbicg"}
+
+
+def sylv_compress(ctx, rel_tol: float, max_rank: int = -1):
+    """Returns (status, rank, achieved relative error)."""
+    k, err = c_int64(), c_double()
+    rc = _lib.sylv_compress(ctx, c_double(rel_tol), c_int64(max_rank), byref(k), byref(err))
+    if rc < 0:
+        raise SylvError(rc, "sylv_compress")
+    return rc, k.value, err.value
+
+
+def sylv_get_compressed(ctx, Z1=None, sigma=None, Z2=None):
+    k = c_int64()
+    ld = lambda t: int(t.stride(0)) if t is not None and t.dim() == 2 else 0  # noqa: E731
+    rc = _lib.sylv_get_compressed(ctx, c_void_p(_ptr(Z1)), ld(Z1), c_void_p(_ptr(sigma)),
+                                  c_void_p(_ptr(Z2)), ld(Z2), byref(k))
+    if rc != 0:
+        raise SylvError(rc, "sylv_get_compressed")
+    return k.value
 
 
 def sylv_residual_norm(ctx):
@@ -413,6 +437,18 @@ class Solver:
         if rv:
             sylv_get_factors(self.ctx, V, X, W)
         return V[:, :rv], X[:rv, :rw], W[:, :rw]
+
+    def compress(self, rel_tol, max_rank=-1):
+        """Truncated SVD of the solution: (status, Z1, sigma, Z2, achieved relative error) with
+        X ~= Z1 diag(sigma) Z2^T, device tensors."""
+        import torch
+        st, k, err = sylv_compress(self.ctx, rel_tol, max_rank)
+        Z1 = torch.empty((self.n, max(k, 1)), dtype=torch.float64, device=self.device)
+        Z2 = torch.empty((self.m, max(k, 1)), dtype=torch.float64, device=self.device)
+        sig = torch.empty(max(k, 1), dtype=torch.float64, device=self.device)
+        if k:
+            sylv_get_compressed(self.ctx, Z1, sig, Z2)
+        return st, Z1[:, :k], sig[:k], Z2[:, :k], err
 
     def get_history(self, cap=None):
         return sylv_get_history(self.ctx, cap or self.max_iter)

@@ -1,5 +1,9 @@
 // Dispatch of the paired block Arnoldi / Lanczos steps to the per-block-size units, and the
 // partial-buffer size they need.
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "arnoldi_impl.h"
 
 #define ARN_DECL(SS)                                                                          \
@@ -24,6 +28,25 @@ size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t ma
 }
 
 bool arnoldi_lagged_supported(int s, bool fp32) { return !fp32 && s >= 1 && s <= 4; }
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int64_t, int64_t, int64_t>, int64_t> g_tune;
+std::tuple<int, int, int64_t, int64_t, int64_t> tkey(const TuneKey &k) {
+  return {k.s, k.esz, k.rows0, k.rows1, k.per_row};
+}
+}  // namespace
+
+int64_t tune_lookup(const TuneKey &k) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  auto it = g_tune.find(tkey(k));
+  return it == g_tune.end() ? 0 : it->second;
+}
+
+int64_t tune_store(const TuneKey &k, int64_t value) {
+  std::lock_guard<std::mutex> lock(g_tune_mu);
+  return g_tune.emplace(tkey(k), value).first->second;
+}
 
 int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                         double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st,

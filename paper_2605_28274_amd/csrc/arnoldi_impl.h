@@ -1252,8 +1252,13 @@ constexpr int64_t QR_MAXWG = 512;
 constexpr int64_t ROW_WG = 512;
 int64_t nb_rows(int64_t rows) { return std::min<int64_t>(cdiv(rows, TPB), ROW_WG); }
 int64_t nb_qr(int64_t rows) { return std::min<int64_t>(nb_rows(rows), QR_MAXWG); }
+// The block Lanczos SpMM may run on more workgroups (up to SPMM_WG_MAX, picked per shape by
+// the autotuner); its partial records are sized for that.
+constexpr int64_t SPMM_WG_MAX = 4096;
+int64_t nb_rows_max(int64_t rows) { return std::min<int64_t>(cdiv(rows, TPB), SPMM_WG_MAX); }
 size_t aux_len(int s, int64_t rows) {
-  return (size_t)(nb_rows(rows) + (cdiv(rows, UROWS) + nb_qr(rows) + nb_rows(rows)) * s * s + 16);
+  return (size_t)(nb_rows_max(rows) +
+                  (cdiv(rows, UROWS) + nb_qr(rows) + nb_rows_max(rows)) * s * s + 16);
 }
 
 
@@ -1561,6 +1566,57 @@ int lanczos_flush_t(const SideDesc &sv, const SideDesc *sw, int nblocks, hipStre
   return 0;
 }
 
+// Autotuner of the block Lanczos SpMM grid: per shape bucket (block size, element size, rows of
+// each basis rounded up to a power of two, stored entries per row), the first step of that
+// shape times the SpMM kernel with 512, 1024, 2048 and 4096 workgroups per basis (one warm-up
+// and three timed launches each, HIP events on the step's stream; the kernel only writes the
+// step's scratch, which the real launch then overwrites) and keeps the fastest in a
+// process-wide cache.
+template <int S, typename T>
+int64_t spmm_workgroups(const ArPair &P0, const SideDesc &sv, const SideDesc *sw, int jb,
+                        int64_t ldh, const DevState *ds, hipStream_t st) {
+  const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
+  auto pow2 = [](int64_t v) {
+    int64_t p = 1;
+    while (p < v) p <<= 1;
+    return p;
+  };
+  const int64_t nnz = sv.nnz + (sw ? sw->nnz : 0);
+  const int64_t per_row = (nnz + rows0 + rows1 - 1) / std::max<int64_t>(1, rows0 + rows1);
+  const TuneKey key{S, (int)sizeof(T), pow2(rows0), rows1 ? pow2(rows1) : 0, per_row};
+  int64_t best = tune_lookup(key);
+  if (best > 0) return best;
+  const int64_t cap = std::max(nb_rows_max(rows0), rows1 ? nb_rows_max(rows1) : 0);
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) {
+    if (a) (void)hipEventDestroy(a);
+    return ROW_WG;
+  }
+  float best_ms = 1e30f;
+  best = ROW_WG;
+  for (int64_t c = ROW_WG; c <= SPMM_WG_MAX; c *= 2) {
+    if (c > ROW_WG && c / 2 >= cap) break;  // no more workgroups than row tiles
+    ArPair P = P0;
+    for (int i = 0; i < P.nsides; ++i)
+      P.s[i].nb_spmm = (int)std::min<int64_t>(c, nb_rows_max(i ? rows1 : rows0));
+    set_ranges(P, P.s[0].nb_spmm, sw ? P.s[1].nb_spmm : 0);
+    lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+    (void)hipEventRecord(a, st);
+    for (int r = 0; r < 3; ++r) lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+    (void)hipEventRecord(b, st);
+    float ms = 0.f;
+    if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
+      break;
+    if (ms < best_ms) {
+      best_ms = ms;
+      best = c;
+    }
+  }
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  return tune_store(key, best);
+}
+
 template <int S, typename T>
 int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
                    double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {
@@ -1597,9 +1653,16 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     if ((jb + 2) % LZ_RING == 0) return lanczos_flush_t<S, T>(sv, sw, jb + 2, st);
     return 0;
   }
+  // SpMM workgroups per basis: the autotuner's choice for this shape (timed once per process
+  // and shape bucket, the first time a step of that shape runs)
+  const int64_t nsp = spmm_workgroups<S, T>(P, sv, sw, jb, ldh, ds, st);
+  ArPair Ps = P;
+  for (int i = 0; i < P.nsides; ++i) P.s[i].nb_spmm = Ps.s[i].nb_spmm = (int)std::min<int64_t>(
+      nsp, nb_rows_max(i ? rows1 : rows0));
+  set_ranges(Ps, Ps.s[0].nb_spmm, sw ? Ps.s[1].nb_spmm : 0);
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
   prof_begin(sc, st);
-  lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  lz_spmm_pair<S, T><<<total_blocks(Ps), TPB, 0, st>>>(Ps, jb, ldh, ds);
   HIPOK(hipGetLastError());
   lz_update_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
   HIPOK(hipGetLastError());

@@ -625,6 +625,15 @@ int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
 bool arnoldi_lagged_supported(int s, bool fp32);
 // Workspace doubles the paired Arnoldi step needs in Scratch::partials.
 size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols);
+// Process-wide cache of the autotuner (arnoldi.hip): a launch parameter per shape bucket.
+struct TuneKey {
+  int s, esz;
+  int64_t rows0, rows1, per_row;
+};
+int64_t tune_lookup(const TuneKey &k);  // 0 when the bucket has not been tuned
+// Keeps the first value stored for a bucket (solves tuning the same bucket at once on other
+// streams then all use it) and returns the value kept.
+int64_t tune_store(const TuneKey &k, int64_t value);
 
 // A solver context (api.hip); overlap = false keeps the Krylov steps on the caller's stream
 // (batches overlap their instances instead).

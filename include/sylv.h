@@ -256,22 +256,45 @@ const char *sylv_status_string(int status);
 const char *sylv_last_error(void);
 
 /* ---- batches of independent problems (one GPU) ----
- * Many problems of uneven sizes solved together: each instance gets its own context, carved
- * from one caller-owned workspace, and the instances are spread over nstreams HIP streams
- * (longest-first by estimated cost); one host thread per stream drives its instances, so the
- * small launches of different instances overlap on the device. Instance i uses
- * opts[i].method and opts[i].max_iter. Results are those of solving each instance alone
- * (same kernels, same order of arithmetic).
- * sylv_batch_workspace_bytes: sum of the instances' workspaces (0 if any is invalid).
- * sylv_batch_create: errors as sylv_create (the first failing instance's code).
+ * Many problems of uneven sizes solved together (not in the paper: the paper solves one
+ * problem of eq. (1.1) at a time). Each instance gets its own context, carved from one
+ * caller-owned workspace; instance i uses opts[i].method and opts[i].max_iter. Forms:
+ *   SYLV_BATCH_STREAMS  instances spread over nstreams HIP streams (longest-first by estimated
+ *                       cost), one host thread per stream solving its instances one after
+ *                       another; results are bit-identical to solving each instance alone.
+ *   SYLV_BATCH_GROUPED  instances with the same method (CG or BiCGSTAB), block size, form
+ *                       (Sylvester or Lyapunov), max_iter and closure_tol, FP64 and without
+ *                       refinement, form a group: the group's iterations advance in lock-step
+ *                       on one stream, every phase one kernel launch over the group's instance
+ *                       table; an instance that stopped (its device stop flag) drops out of the
+ *                       launches; the host polls one word per group (instances still running)
+ *                       every 16 iterations. Converged instances are verified on the true
+ *                       residual as single solves are. Results equal single solves up to
+ *                       rounding (other workgroup splits of the reductions). Instances that
+ *                       cannot join a group run as in SYLV_BATCH_STREAMS on nstreams streams.
+ *   SYLV_BATCH_GRAPH    SYLV_BATCH_GROUPED, with each 16-iteration segment of a group captured
+ *                       once as a HIP graph (the first solve that reaches it) and replayed by
+ *                       later solves with the same max_iter.
+ * sylv_batch_workspace_bytes: the instances' workspaces plus the group tables (0 if any
+ *   instance is invalid); the same size serves every form.
+ * sylv_batch_create_ex: errors as sylv_create (the first failing instance's code),
+ *   SYLV_ERR_INVALID for an unknown form. sylv_batch_create = the SYLV_BATCH_STREAMS form.
  * sylv_batch_solve: res[count] (host); returns the first error (< 0) or the largest status.
  * sylv_batch_context: context of instance i (for sylv_get_factors, sylv_residual_norm, ...);
- * owned by the batch. */
+ *   owned by the batch.
+ * sylv_batch_groups: number of groups (0 in the streams form). */
+#define SYLV_BATCH_STREAMS 0
+#define SYLV_BATCH_GROUPED 1
+#define SYLV_BATCH_GRAPH 2
 size_t sylv_batch_workspace_bytes(int count, const sylv_problem *probs, const sylv_options *opts);
 int sylv_batch_create(void **batch, int count, const sylv_problem *probs,
                       const sylv_options *opts, void *workspace, size_t ws_bytes, int nstreams);
+int sylv_batch_create_ex(void **batch, int count, const sylv_problem *probs,
+                         const sylv_options *opts, void *workspace, size_t ws_bytes, int nstreams,
+                         int form);
 int sylv_batch_solve(void *batch, double tol, sylv_result *res);
 void *sylv_batch_context(void *batch, int i);
+int sylv_batch_groups(void *batch);
 void sylv_batch_destroy(void *batch);
 
 /* ---- measurement hooks ---- */

@@ -1752,6 +1752,264 @@ static int solve_verified(void *ctx, int method, double tol, int max_iter, sylv_
   }
 }
 
+}  // extern "C"
+
+// ---- batch groups ----
+
+static void group_sides(Ctx *const *cs, int n, std::vector<GroupSide> &out) {
+  out.clear();
+  for (int i = 0; i < n; ++i) {
+    Ctx *c = cs[i];
+    const Layout &L = c->L;
+    const int64_t pair = L.n + (L.lyap ? 0 : L.m);
+    out.push_back(GroupSide{c->sv, c->sc, 0, pair, L.ldc, &c->ds->done});
+    if (!L.lyap) out.push_back(GroupSide{c->sw, c->sc, 1, pair, L.ldc, &c->ds->done});
+  }
+}
+
+static bool group_compatible(Ctx *const *cs, int n) {
+  if (n < 1) return false;
+  for (int i = 0; i < n; ++i) {
+    if (!group_eligible(cs[i])) return false;
+    const Layout &a = cs[0]->L, &b = cs[i]->L;
+    if (b.method != a.method || b.s != a.s || b.lyap != a.lyap ||
+        cs[i]->closure_tol != cs[0]->closure_tol || cs[i]->st != cs[0]->st)
+      return false;
+  }
+  return true;
+}
+
+bool group_eligible(void *ctx) {
+  Ctx *c = reinterpret_cast<Ctx *>(ctx);
+  if (!c || c->parent || c->L.fp32 || c->L.refine_max > 0 || c->kst != c->st) return false;
+  if (c->L.method == SYLV_METHOD_CG) return true;
+  return c->L.method == SYLV_METHOD_BICGSTAB && c->lagged;
+}
+
+static size_t group_split(Ctx *const *cs, int n, size_t &kbytes) {
+  std::vector<GroupSide> sides;
+  group_sides(cs, n, sides);
+  kbytes = krylov_group_bytes((int)cs[0]->L.s, cs[0]->L.method == SYLV_METHOD_CG, sides.data(),
+                              (int)sides.size());
+  if (kbytes == 0) return 0;
+  return kbytes + (sizeof(CoreInst) * n + 255) / 256 * 256 + 256 + (sizeof(int) * n + 255) / 256 * 256;
+}
+
+size_t group_bytes(void *const *ctxs, int n) {
+  Ctx *const *cs = reinterpret_cast<Ctx *const *>(ctxs);
+  if (!ctxs || !group_compatible(cs, n)) return 0;
+  size_t kb = 0;
+  return group_split(cs, n, kb);
+}
+
+void group_release(GroupRun &g) {
+  for (hipGraphExec_t e : g.exec)
+    if (e) (void)hipGraphExecDestroy(e);
+  g.exec.clear();
+  if (g.h_poll) (void)hipHostFree(g.h_poll);
+  g.h_poll = nullptr;
+}
+
+static int group_capture(GroupRun &g, int seg, int k0, int k1);
+
+int group_prepare(GroupRun &g, void *const *ctxs, int n, void *dev, size_t bytes, bool graphs,
+                  int max_iter) {
+  Ctx *const *cs = reinterpret_cast<Ctx *const *>(ctxs);
+  if (!ctxs || !group_compatible(cs, n)) return SYLV_ERR_INVALID;
+  size_t kb = 0;
+  const size_t need = group_split(cs, n, kb);
+  if (need == 0) return SYLV_ERR_WORKSPACE;
+  if (!dev || bytes < need || (reinterpret_cast<uintptr_t>(dev) & 255)) return SYLV_ERR_WORKSPACE;
+  const Layout &L0 = cs[0]->L;
+  g.ctx.assign(ctxs, ctxs + n);
+  g.method = L0.method;
+  g.s = (int)L0.s;
+  g.sym = L0.lyap;
+  g.st = cs[0]->st;
+  g.closure_tol = cs[0]->closure_tol;
+  g.graphs = graphs;
+  g.graph_max_iter = -1;
+  std::vector<GroupSide> sides;
+  group_sides(cs, n, sides);
+  char *p = static_cast<char *>(dev);
+  if (int e = krylov_group_create(&g.kg, &g.ka, g.s, g.method == SYLV_METHOD_CG, sides.data(),
+                                  (int)sides.size(), p, kb, g.st))
+    return e;
+  std::vector<CoreInst> tab(n);
+  g.min_ldc = INT64_MAX;
+  for (int i = 0; i < n; ++i) {
+    Ctx *c = cs[i];
+    tab[i] = CoreInst{c->H, c->G, c->X, c->R, c->P, c->Q, c->S, c->T, c->Rt, c->scc.partials,
+                      c->ds, c->hist, c->L.ldc, 0, 0};
+    g.min_ldc = std::min<int64_t>(g.min_ldc, c->L.ldc);
+  }
+  g.tab = reinterpret_cast<CoreInst *>(p + kb);
+  g.poll = reinterpret_cast<int *>(p + kb + (sizeof(CoreInst) * n + 255) / 256 * 256);
+  g.list = g.poll + 64;
+  HIPOK(hipMemcpyAsync(g.tab, tab.data(), sizeof(CoreInst) * n, hipMemcpyHostToDevice, g.st));
+  HIPOK(hipStreamSynchronize(g.st));
+  if (!g.h_poll &&
+      hipHostMalloc(reinterpret_cast<void **>(&g.h_poll), sizeof(int) * 8) != hipSuccess)
+    return SYLV_ERR_HIP;
+  if (graphs) {
+    // every segment up to max_iter is captured now, while no other work of the library runs:
+    // a capture in progress is invalidated by synchronous calls elsewhere in the process
+    g.graph_max_iter = max_iter;
+    for (int seg = 0; seg * GROUP_SEG < max_iter; ++seg)
+      if (int e = group_capture(g, seg, seg * GROUP_SEG, std::min(max_iter, (seg + 1) * GROUP_SEG)))
+        return e;
+  }
+  return 0;
+}
+
+// The launches of iteration k of every problem of the group (no host synchronization, so they
+// can be captured in a graph).
+static int group_iteration(GroupRun &g, int k) {
+  const int s = g.s;
+  const hipStream_t st = g.st;
+  // graphs run over every problem; otherwise the launches cover the problems still running
+  const KGroup &kv = g.graphs ? g.kg : g.ka;
+  const int *list = g.graphs ? nullptr : g.list;
+  const int n = g.graphs ? (int)g.ctx.size() : g.na;
+  int e;
+  if (g.method == SYLV_METHOD_CG) {
+    if ((e = launch_krylov_group(kv, k, g.closure_tol, st))) return e;
+    return launch_cg_group(s, g.sym != 0, (k + 1) * s, k, g.tab, list, n, st);
+  }
+  // lagged block Arnoldi: the core work of iteration k needs steps up to 2k + 2
+  for (int j = (k == 0 ? 0 : 2 * k + 1); j <= 2 * k + 2; ++j)
+    if ((e = launch_krylov_group(kv, j, g.closure_tol, st))) return e;
+  const int p = (2 * k + 1) * s;
+  const int64_t T = (p + 2 * s + 63) / 64 * 64;
+  if (T > g.min_ldc) return SYLV_ERR_WORKSPACE;
+  if ((e = launch_core_op_group(s, p, 0, g.tab, list, n, st))) return e;
+  if ((e = launch_bicg_group_s(s, p, k, g.tab, list, n, st))) return e;
+  if ((e = launch_core_op_group(s, p + s, 1, g.tab, list, n, st))) return e;
+  if ((e = launch_bicg_group_omega(s, p, g.tab, list, n, st))) return e;
+  return launch_bicg_group_update(s, p, k, g.tab, list, n, st);
+}
+
+// The poll after `steps` iterations: the problems still running (and, for the compacted
+// launches, the tables restricted to them), read back by the host. Block Lanczos first moves
+// the ring's partial group of blocks to the bases of the problems still in the launches, so
+// that a problem leaving them has all its basis columns in place.
+static int group_poll(GroupRun &g, int steps) {
+  const int n = (int)g.ctx.size();
+  int nread = 1;
+  if (!g.graphs) {
+    if (g.method == SYLV_METHOD_CG && steps > 0 && (steps + 1) % LZ_RING != 0)
+      if (int e = launch_krylov_group_flush(g.ka, steps + 1, g.st)) return e;
+    if (int e = launch_krylov_group_compact(g.kg, g.ka, g.poll + 1, g.st)) return e;
+    nread = 2 + GK_COUNT;
+  }
+  if (int e = launch_group_active(g.tab, n, g.poll, g.list, g.st)) return e;
+  HIPOK(hipMemcpyAsync(g.h_poll, g.poll, sizeof(int) * nread, hipMemcpyDeviceToHost, g.st));
+  HIPOK(hipStreamSynchronize(g.st));
+  g.na = g.h_poll[0];
+  if (!g.graphs) {
+    g.ka.nsides = g.h_poll[1];
+    for (int k = 0; k < GK_COUNT; ++k) g.ka.nblk[k] = g.h_poll[2 + k];
+  }
+  return 0;
+}
+
+// Iterations [k0, k1) of segment seg as one graph (captured, not run).
+static int group_capture(GroupRun &g, int seg, int k0, int k1) {
+  if ((int)g.exec.size() <= seg) g.exec.resize(seg + 1, nullptr);
+  if (g.exec[seg]) return 0;
+  HIPOK(hipStreamBeginCapture(g.st, hipStreamCaptureModeThreadLocal));
+  int e = 0;
+  for (int k = k0; k < k1 && !e; ++k) e = group_iteration(g, k);
+  hipGraph_t graph = nullptr;
+  const hipError_t ce = hipStreamEndCapture(g.st, &graph);
+  if (e) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return e;
+  }
+  HIPOK(ce);
+  const hipError_t ie = hipGraphInstantiate(&g.exec[seg], graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  HIPOK(ie);
+  return 0;
+}
+
+// Iterations [k0, k1): the segment's graph when it was captured for this max_iter, else the
+// launches themselves.
+static int group_segment(GroupRun &g, int seg, int k0, int k1, bool replay) {
+  if (replay && seg < (int)g.exec.size() && g.exec[seg]) {
+    HIPOK(hipGraphLaunch(g.exec[seg], g.st));
+    return 0;
+  }
+  for (int k = k0; k < k1; ++k)
+    if (int e = group_iteration(g, k)) return e;
+  return 0;
+}
+
+int group_solve(GroupRun &g, double tol, int max_iter, sylv_result *res) {
+  const int n = (int)g.ctx.size();
+  if (n < 1 || !res) return SYLV_ERR_INVALID;
+  auto t0 = std::chrono::steady_clock::now();
+  Ctx *const *cs = reinterpret_cast<Ctx *const *>(g.ctx.data());
+  for (int i = 0; i < n; ++i)
+    if (int e = begin_solve(cs[i], tol, max_iter, g.method)) return e;
+  const bool replay = g.graphs && g.graph_max_iter == max_iter;
+  if (!g.graphs)
+    if (int e = group_poll(g, 0)) return e;  // every problem starts in the launches
+  int steps = 0;  // iterations enqueued
+  for (int seg = 0; steps < max_iter; ++seg) {
+    const int k0 = seg * GROUP_SEG, k1 = std::min(max_iter, k0 + GROUP_SEG);
+    if (int e = group_segment(g, seg, k0, k1, replay)) return e;
+    steps = k1;
+    if (steps >= max_iter) break;
+    if (int e = group_poll(g, steps)) return e;
+    if (g.na == 0) break;
+  }
+  if (g.method == SYLV_METHOD_CG) {
+    // basis columns of the newest blocks still held only in the ring
+    if ((steps + 1) % LZ_RING != 0)
+      if (int e = launch_krylov_group_flush(g.kg, steps + 1, g.st)) return e;
+    if (g.sym)
+      for (int i = 0; i < n; ++i) {
+        const Layout &L = cs[i]->L;
+        if (int e = launch_mirror(std::min<int64_t>(L.ldc, (int64_t)(max_iter + 1) * L.s),
+                                  cs[i]->X, L.ldc, g.st))
+          return e;
+      }
+  }
+  HIPOK(hipStreamSynchronize(g.st));
+  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  int worst = 0;
+  for (int i = 0; i < n; ++i) {
+    Ctx *c = cs[i];
+    int st = end_solve(c, max_iter, secs, &res[i]);
+    if (st < 0) return st;
+    // verification as for a single solve: a converged iterate whose true residual misses tol
+    // is solved again alone with a lower recursive target
+    if (st == SYLV_OK && c->verify) {
+      double target = tol;
+      for (int round = 0;; ++round) {
+        double a = 0.0, r = 0.0;
+        if (int e = true_residual(c, &a, &r)) return e;
+        if (r <= tol || round == 2) {
+          if (r > tol) c->status = SYLV_NOT_CONVERGED;
+          res[i].status = c->status;
+          res[i].rel_res_true = r;
+          st = c->status;
+          break;
+        }
+        target *= std::min(0.5, 0.5 * tol / r);
+        st = g.method == SYLV_METHOD_CG ? cg_body(c, target, max_iter, &res[i])
+                                        : bicg_body(c, target, max_iter, &res[i]);
+        if (st != SYLV_OK) break;
+      }
+    }
+    worst = std::max(worst, st);
+  }
+  return worst;
+}
+
+extern "C" {
+
 int sylv_factored_cg(void *ctx, double tol, int max_iter, sylv_result *res) {
   return solve_verified(ctx, SYLV_METHOD_CG, tol, max_iter, res);
 }

@@ -61,6 +61,9 @@ struct ArSide {
   int nb_spmm, nb_upd, nb_qr;  // workgroups whose partials sit in aux
   int b0, nb;      // workgroup range of this basis in the current launch
   int64_t rpc;     // rows per chunk (gram) or rows per workgroup (update)
+  int64_t ldh;     // row stride of H
+  int nch;         // Gram chunks of this basis (partials the reduction sums)
+  const int *done; // the problem's stop flag (instance tables; null for a pair)
 };
 
 struct ArPair {
@@ -78,15 +81,64 @@ __device__ __forceinline__ ArSide side_of(const ArPair &P, int &lb, int &sd,
   return A;
 }
 
+// Compact block copies of one basis: the SpMM input and output of step jb are slots jb % ring
+// and (jb + 1) % ring (block Lanczos also reads slot (jb - 1) % ring and keeps the ring at 0).
+struct PanelSet {
+  void *p[LZ_RING];
+};
+
+// The bases of many independent problems in one launch (batches): entry i of `sides` (device
+// memory) is basis i with its workgroup range, chunking and record counts for this launch kind;
+// `owner` maps a workgroup to its basis, or, when every basis has unb workgroups, basis
+// bid / unb. The compact block slots follow from the step index jb.
+struct ArTab {
+  const ArSide *sides;
+  const unsigned short *owner;
+  const PanelSet *panels;
+  int nsides, unb, jb, ring;
+};
+
+__device__ __forceinline__ int owner_of(const ArTab &P, int bid) {
+  return P.unb > 0 ? bid / P.unb : (int)P.owner[bid];
+}
+
+__device__ __forceinline__ ArSide side_of(const ArTab &P, int &lb, int &sd,
+                                          int bid = (int)blockIdx.x) {
+  sd = owner_of(P, bid);
+  ArSide A = P.sides[sd];
+  if (P.unb > 0) {
+    A.b0 = sd * P.unb;
+    A.nb = P.unb;
+  }
+  const PanelSet &ps = P.panels[sd];
+  const int r = P.ring;
+  A.pin = ps.p[P.jb % r];
+  A.pout = ps.p[(P.jb + 1) % r];
+  A.pprev = ps.p[(P.jb + r - 1) % r];
+  A.ring = ps.p[0];
+  lb = bid - A.b0;
+  return A;
+}
+
+// A workgroup returns at once when its problem has stopped: the pair's solve flag, or the flag
+// of the instance whose basis the workgroup serves.
+__device__ __forceinline__ bool halted(const ArPair &, const DevState *ds, int = 0) {
+  return ds->done != 0;
+}
+__device__ __forceinline__ bool halted(const ArTab &P, const DevState *,
+                                       int bid = (int)blockIdx.x) {
+  return *P.sides[owner_of(P, bid)].done != 0;
+}
+
 // Rows a thread handles at once in the SpMM kernels (sliced ELLPACK): more loads in flight for
 // narrow blocks.
 template <int S>
 constexpr int spmm_nr() { return S == 1 ? 4 : S == 2 ? 2 : 1; }
 
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void spmm_pair(ArPair P, const DevState *ds) {
+template <int S, typename T, class PS>
+__global__ __launch_bounds__(TPB) void spmm_pair(PS P, const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
+  if (halted(P, ds)) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   double red[1] = {0.0};
@@ -164,11 +216,11 @@ struct Pack8<float> {
 // group 0 and rows past the chunk load its first row (both in bounds), neither is counted.
 // DUAL: the right-hand side is [pin, U] (S / 2 columns each: the provisional block and M times
 // it, for the lagged step), else U (S columns).
-template <int S, typename T, int NQ, bool DUAL = false>
-__global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int cw_log2,
+template <int S, typename T, int NQ, bool DUAL = false, class PS>
+__global__ __launch_bounds__(TPB) void gram_part_pair(PS P, int ncols, int cw_log2,
                                                       const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
+  if (halted(P, ds)) return;
   typedef Pack8<T> PK;
   typedef typename PK::type V8;
   constexpr int E = PK::N;
@@ -286,15 +338,15 @@ __global__ __launch_bounds__(TPB) void gram_part_pair(ArPair P, int ncols, int c
 // adds chunks [g nchunk / NG, (g+1) nchunk / NG) for its output (eight loads in flight, added
 // in chunk order), then group 0 adds the NG group sums in order and writes column block j of H
 // (store in sweep 1, add in sweep 2; pass 0: coefficients only) and the compact coefficients.
-__global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int ncols, int nchunk0,
-                                                        int nchunk1, int64_t ldh, int hcol,
+template <class PS>
+__global__ __launch_bounds__(TPB) void gram_reduce_pair(PS P, int S, int ncols, int hcol,
                                                         int pass, const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
+  if (halted(P, ds)) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   __shared__ double gs[NG][OPB];
-  const int nchunk = sd ? nchunk1 : nchunk0;
+  const int nchunk = A.nch;
   const int nout = ncols * S;
   const int ol = threadIdx.x % OPB, g = threadIdx.x / OPB;
   const int o = lb * OPB + ol;
@@ -320,7 +372,7 @@ __global__ __launch_bounds__(TPB) void gram_reduce_pair(ArPair P, int S, int nco
     for (int q = 0; q < NG; ++q) b += gs[q][ol];
     const int c = o / S, t = o % S;
     if (pass > 0) {
-      double *h = A.H + (int64_t)c * ldh + hcol + t;
+      double *h = A.H + (int64_t)c * A.ldh + hcol + t;
       *h = (pass == 1) ? b : *h + b;
     }
     A.coef[o] = b;
@@ -437,10 +489,10 @@ __device__ __forceinline__ void upart_record(const ArSide &A, int lb, const doub
 
 // U[r] -= V[r, 0:ncols] C for the workgroup's UROWS rows (16 per wave); with upart, also the
 // partials of U^T U of the updated rows for the first QR pass.
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int upart,
+template <int S, typename T, class PS>
+__global__ __launch_bounds__(TPB) void update_mfma_pair(PS P, int ncols, int upart,
                                                         const DevState *ds) {
-  if (ds->done) return;
+  if (halted(P, ds)) return;
   extern __shared__ double Cs[];
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
@@ -481,11 +533,11 @@ __global__ __launch_bounds__(TPB) void update_mfma_pair(ArPair P, int ncols, int
 
 // One workgroup per basis: Tw, Hw, e and the provisional subdiagonal block Rt of column block
 // j-1 (SideState); dcgs_hcol_body completes column block j-1 from them.
-template <int S>
-__global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t ldh,
-                                                     double closure_tol, const DevState *ds) {
+template <int S, class PS>
+__global__ __launch_bounds__(TPB) void dcgs_fix_pair(PS P, int jb, double closure_tol,
+                                                     const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
+  if (halted(P, ds)) return;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   constexpr int S2 = 2 * S, U4 = 4;
@@ -524,7 +576,7 @@ __global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t l
     for (int q = 0; q < S; ++q) {
       dd[p * S + q] = A.coef[(nf + p) * S2 + q];
       cc[p * S + q] = A.coef[(nf + p) * S2 + S + q];
-      Rt[p * S + q] = jb > 0 ? A.H[(int64_t)(nf + p) * ldh + nf - S + q] : 0.0;
+      Rt[p * S + q] = jb > 0 ? A.H[(int64_t)(nf + p) * A.ldh + nf - S + q] : 0.0;
     }
   double Gw[S * S], tr = 0.0;
   for (int i = 0; i < S * S; ++i) {
@@ -554,10 +606,10 @@ __global__ __launch_bounds__(TPB) void dcgs_fix_pair(ArPair P, int jb, int64_t l
 // The second pass of block j and the first pass of U in one pass over V_{0..j-1}: X = V [a b]
 // on matrix cores (2S coefficient columns), then per row V_j = (V~_j - X_a) Tw (written over the
 // provisional block) and U' = (U - X_b - V_j e) Tw; partials of U'^T U'.
-template <int S>
-__global__ __launch_bounds__(TPB) void dcgs_update_pair(ArPair P, int jb, const DevState *ds) {
+template <int S, class PS>
+__global__ __launch_bounds__(TPB) void dcgs_update_pair(PS P, int jb, const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
+  if (halted(P, ds)) return;
   constexpr int S2 = 2 * S;
   extern __shared__ double Cs[];
   int lb, sd;
@@ -617,8 +669,8 @@ __global__ __launch_bounds__(TPB) void dcgs_update_pair(ArPair P, int jb, const 
 // provisional U'_{j-1} = V~_j Rt = (V a + V_j Hw) Rt gives H[i, j-1] += a[i] Rt (rows i < j s)
 // and H[j, j-1] = Hw Rt; then C[i] = ([b; e][i] - H[i, 0:nf] a) Tw with the completed column
 // block j-1 (H[i, c] is zero for c < (i/S - 1) S).
-template <int S>
-__device__ __forceinline__ void dcgs_hcol_body(const ArPair &P, int bid, int jb, int64_t ldh) {
+template <int S, class PS>
+__device__ __forceinline__ void dcgs_hcol_body(const PS &P, int bid, int jb) {
   constexpr int S2 = 2 * S, U4 = 4;
   int lb, sd;
   const ArSide A = side_of(P, lb, sd, bid);
@@ -639,7 +691,7 @@ __device__ __forceinline__ void dcgs_hcol_body(const ArPair &P, int bid, int jb,
     for (int u = 0; u < U4; ++u) {
       const int c = c0 + u * WAVE;
       const bool ok = c < cend;
-      h[u] = ok ? A.H[(int64_t)i * ldh + c] : 0.0;
+      h[u] = ok ? A.H[(int64_t)i * A.ldh + c] : 0.0;
 #pragma unroll
       for (int t = 0; t < S; ++t) a[u][t] = ok ? A.coef[c * S2 + t] : 0.0;
     }
@@ -654,7 +706,7 @@ __device__ __forceinline__ void dcgs_hcol_body(const ArPair &P, int bid, int jb,
     for (int q = 0; q < S; ++q) {
       double v = 0.0;
       if (i < nf) {
-        v = A.H[(int64_t)i * ldh + ce + q];
+        v = A.H[(int64_t)i * A.ldh + ce + q];
         for (int t = 0; t < S; ++t) v = fma(A.coef[i * S2 + t], A.ss->Rt[t * S + q], v);
       } else {
         for (int t = 0; t < S; ++t) v = fma(A.ss->Hw[(i - nf) * S + t], A.ss->Rt[t * S + q], v);
@@ -662,7 +714,7 @@ __device__ __forceinline__ void dcgs_hcol_body(const ArPair &P, int bid, int jb,
       hf[q] = v;
     }
     for (int q = 0; q < S; ++q) {
-      A.H[(int64_t)i * ldh + ce + q] = hf[q];
+      A.H[(int64_t)i * A.ldh + ce + q] = hf[q];
       for (int t = 0; t < S; ++t) acc[t] = fma(hf[q], A.coef[(ce + q) * S2 + t], acc[t]);
     }
   }
@@ -676,7 +728,7 @@ __device__ __forceinline__ void dcgs_hcol_body(const ArPair &P, int bid, int jb,
     double v = 0.0;
 #pragma unroll
     for (int t = 0; t < S; ++t) v = fma(y[t], A.ss->Tw[t * S + lane], v);
-    A.H[(int64_t)i * ldh + nf + lane] = v;
+    A.H[(int64_t)i * A.ldh + nf + lane] = v;
   }
 }
 
@@ -739,9 +791,9 @@ struct UgShape {
 // LDS), the updated rows are written, and the basis values still in registers are multiplied
 // by them into the chunk partials part[lb][c][t]. The next block's loads are issued before the
 // current block is reduced. Basis columns past ncols are masked to zero (they may be stale).
-template <int S, typename T, int NQ>
-__global__ __launch_bounds__(TPB) void upd_gram_pair(ArPair P, int ncols, const DevState *ds) {
-  if (ds->done) return;
+template <int S, typename T, int NQ, class PS>
+__global__ __launch_bounds__(TPB) void upd_gram_pair(PS P, int ncols, const DevState *ds) {
+  if (halted(P, ds)) return;
   typedef Pack8<T> PK;
   typedef typename PK::type V8;
   constexpr int E = PK::N;
@@ -890,8 +942,8 @@ __device__ __forceinline__ void sum_records(const double *p, int n, double (&out
 // First Cholesky-QR pass and closure test from the partials of ||M V_j||^2 and U^T U (every
 // workgroup forms the same factors; workgroup 0 records them), then partials of
 // G2 = (U T1)^T (U T1).
-template <int S>
-__device__ __forceinline__ void qr2_body(const ArPair &P, int bid, double closure_tol) {
+template <int S, class PS>
+__device__ __forceinline__ void qr2_body(const PS &P, int bid, double closure_tol) {
   int lb, sd;
   const ArSide A = side_of(P, lb, sd, bid);
   __shared__ SideState st;
@@ -940,31 +992,30 @@ __device__ __forceinline__ void qr2_body(const ArPair &P, int bid, double closur
     for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + A.nb_upd * S * S + lb * S * S + i] = g[i];
 }
 
-template <int S>
-__global__ __launch_bounds__(TPB) void qr2_pair(ArPair P, double closure_tol, const DevState *ds) {
-  if (ds->done) return;
+template <int S, class PS>
+__global__ __launch_bounds__(TPB) void qr2_pair(PS P, double closure_tol, const DevState *ds) {
+  if (halted(P, ds)) return;
   qr2_body<S>(P, (int)blockIdx.x, closure_tol);
 }
 
 // The lagged step's last small kernels in one launch: workgroups [0, nq) run the first QR pass
 // of U' (Pq ranges), the rest the column blocks j-1 and j of H (Ph ranges).
-template <int S>
-__global__ __launch_bounds__(TPB) void dcgs_tail_pair(ArPair Pq, ArPair Ph, int nq, int jb,
-                                                      int64_t ldh, double closure_tol,
-                                                      const DevState *ds) {
+template <int S, class PS>
+__global__ __launch_bounds__(TPB) void dcgs_tail_pair(PS Pq, PS Ph, int nq, int jb,
+                                                      double closure_tol, const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
-  if ((int)blockIdx.x < nq) qr2_body<S>(Pq, (int)blockIdx.x, closure_tol);
-  else dcgs_hcol_body<S>(Ph, (int)blockIdx.x - nq, jb, ldh);
+  const int bid = (int)blockIdx.x;
+  if (bid < nq ? halted(Pq, ds, bid) : halted(Ph, ds, bid - nq)) return;
+  if (bid < nq) qr2_body<S>(Pq, bid, closure_tol);
+  else dcgs_hcol_body<S>(Ph, bid - nq, jb);
 }
 
 // Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
 // the new block U T to the compact copy and, with to_basis, to V[:, (j+1)s : (j+2)s] (block
 // Lanczos leaves the basis columns to lz_flush_pair); workgroup 0 records T and writes
 // H_{j+1,j}.
-template <int S, typename T>
-__device__ __forceinline__ void final_body(const ArPair &P, int bid, int jb, int64_t ldh,
-                                           int to_basis) {
+template <int S, typename T, class PS>
+__device__ __forceinline__ void final_body(const PS &P, int bid, int jb, int to_basis) {
   int lb, sd;
   const ArSide A = side_of(P, lb, sd, bid);
   __shared__ SideState st;
@@ -984,7 +1035,7 @@ __device__ __forceinline__ void final_body(const ArPair &P, int bid, int jb, int
       }
       for (int a = 0; a < S; ++a)
         for (int b = 0; b < S; ++b)
-          A.H[(int64_t)((jb + 1) * S + a) * ldh + jb * S + b] = st.Hs1[a * S + b];
+          A.H[(int64_t)((jb + 1) * S + a) * A.ldh + jb * S + b] = st.Hs1[a * S + b];
     }
   }
   __syncthreads();
@@ -1006,12 +1057,12 @@ __device__ __forceinline__ void final_body(const ArPair &P, int bid, int jb, int
   }
 }
 
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void final_pair(ArPair P, int jb, int64_t ldh, int to_basis,
+template <int S, typename T, class PS>
+__global__ __launch_bounds__(TPB) void final_pair(PS P, int jb, int to_basis,
                                                   const DevState *ds) {
   krylov_wave_priority();
-  if (ds->done) return;
-  final_body<S, T>(P, (int)blockIdx.x, jb, ldh, to_basis);
+  if (halted(P, ds)) return;
+  final_body<S, T>(P, (int)blockIdx.x, jb, to_basis);
 }
 
 // ---- block Lanczos step j for both bases (Algorithm 4.1, steps 4-5) ----
@@ -1023,8 +1074,8 @@ __device__ __forceinline__ double *aux_vju(const ArSide &A) {
 }
 
 // U = M V_j - V_{j-1} H_{j-1,j} (H_{j-1,j} = H_{j,j-1}^T); partials of ||M V_j||^2 and V_j^T U.
-template <int S, typename T>
-__device__ __forceinline__ void lz_spmm_body(const ArPair &P, int bid, int jb, int64_t ldh) {
+template <int S, typename T, class PS>
+__device__ __forceinline__ void lz_spmm_body(const PS &P, int bid, int jb) {
   int lb, sd;
   const ArSide A = side_of(P, lb, sd, bid);
   double hup[S * S];  // hup[u][t] = H_{j-1,j}[u][t] = H[j s + t][(j-1) s + u]
@@ -1032,7 +1083,7 @@ __device__ __forceinline__ void lz_spmm_body(const ArPair &P, int bid, int jb, i
   for (int u = 0; u < S; ++u)
 #pragma unroll
     for (int t = 0; t < S; ++t)
-      hup[u * S + t] = jb > 0 ? A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + u] : 0.0;
+      hup[u * S + t] = jb > 0 ? A.H[(int64_t)(jb * S + t) * A.ldh + (jb - 1) * S + u] : 0.0;
   double red[S * S + 1];
 #pragma unroll
   for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
@@ -1095,17 +1146,16 @@ __device__ __forceinline__ void lz_spmm_body(const ArPair &P, int bid, int jb, i
   }
 }
 
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void lz_spmm_pair(ArPair P, int jb, int64_t ldh,
-                                                    const DevState *ds) {
-  if (ds->done) return;
-  lz_spmm_body<S, T>(P, (int)blockIdx.x, jb, ldh);
+template <int S, typename T, class PS>
+__global__ __launch_bounds__(TPB) void lz_spmm_pair(PS P, int jb, const DevState *ds) {
+  if (halted(P, ds)) return;
+  lz_spmm_body<S, T>(P, (int)blockIdx.x, jb);
 }
 
 // H_jj = V_j^T U from the partials (every workgroup forms it; workgroup 0 writes column block j
 // of H: H_{j-1,j} and H_jj); U -= V_j H_jj; partials of U^T U.
-template <int S, typename T>
-__device__ __forceinline__ void lz_update_body(const ArPair &P, int bid, int jb, int64_t ldh) {
+template <int S, typename T, class PS>
+__device__ __forceinline__ void lz_update_body(const PS &P, int bid, int jb) {
   int lb, sd;
   const ArSide A = side_of(P, lb, sd, bid);
   double hjj[S * S];
@@ -1113,10 +1163,10 @@ __device__ __forceinline__ void lz_update_body(const ArPair &P, int bid, int jb,
   if (lb == 0 && threadIdx.x == 0) {
     for (int a = 0; a < S; ++a)
       for (int t = 0; t < S; ++t) {
-        A.H[(int64_t)(jb * S + a) * ldh + jb * S + t] = hjj[a * S + t];
+        A.H[(int64_t)(jb * S + a) * A.ldh + jb * S + t] = hjj[a * S + t];
         if (jb > 0)
-          A.H[(int64_t)((jb - 1) * S + a) * ldh + jb * S + t] =
-              A.H[(int64_t)(jb * S + t) * ldh + (jb - 1) * S + a];
+          A.H[(int64_t)((jb - 1) * S + a) * A.ldh + jb * S + t] =
+              A.H[(int64_t)(jb * S + t) * A.ldh + (jb - 1) * S + a];
       }
   }
   double g[S * S];
@@ -1147,11 +1197,10 @@ __device__ __forceinline__ void lz_update_body(const ArPair &P, int bid, int jb,
     for (int i = 0; i < S * S; ++i) A.aux[A.nb_spmm + lb * S * S + i] = g[i];
 }
 
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t ldh,
-                                                      const DevState *ds) {
-  if (ds->done) return;
-  lz_update_body<S, T>(P, (int)blockIdx.x, jb, ldh);
+template <int S, typename T, class PS>
+__global__ __launch_bounds__(TPB) void lz_update_pair(PS P, int jb, const DevState *ds) {
+  if (halted(P, ds)) return;
+  lz_update_body<S, T>(P, (int)blockIdx.x, jb);
 }
 
 // The whole block Lanczos step for small bases: one workgroup per basis runs the four phases
@@ -1159,23 +1208,23 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(ArPair P, int jb, int64_t 
 // block), with barriers where the separate kernels have launch boundaries; each phase's
 // reduction has a single record.
 template <int S, typename T>
-__global__ __launch_bounds__(TPB) void lz_fused_pair(ArPair P, int jb, int64_t ldh,
-                                                     double closure_tol, const DevState *ds) {
+__global__ __launch_bounds__(TPB) void lz_fused_pair(ArPair P, int jb, double closure_tol,
+                                                     const DevState *ds) {
   if (ds->done) return;
   const int bid = (int)blockIdx.x;
-  lz_spmm_body<S, T>(P, bid, jb, ldh);
+  lz_spmm_body<S, T>(P, bid, jb);
   __syncthreads();
-  lz_update_body<S, T>(P, bid, jb, ldh);
+  lz_update_body<S, T>(P, bid, jb);
   __syncthreads();
   qr2_body<S>(P, bid, closure_tol);
   __syncthreads();
-  final_body<S, T>(P, bid, jb, ldh, 0);
+  final_body<S, T>(P, bid, jb, 0);
 }
 
 // Basis columns of blocks [b0, b1) (b1 - b0 <= LZ_RING) from the block Lanczos ring: each
 // row receives (b1 - b0) s consecutive entries at once.
-template <int S, typename T>
-__global__ __launch_bounds__(TPB) void lz_flush_pair(ArPair P, int b0, int b1) {
+template <int S, typename T, class PS>
+__global__ __launch_bounds__(TPB) void lz_flush_pair(PS P, int b0, int b1) {
   int lb, sd;
   const ArSide A = side_of(P, lb, sd);
   const T *ring = static_cast<const T *>(A.ring);
@@ -1212,8 +1261,10 @@ int64_t gram_rpc(int s, int64_t rows, int64_t total_rows) {
   return std::max<int64_t>(rpc, 1);
 }
 
-ArSide make_side(const SideDesc &d, const Scratch &sc, int idx, size_t half, size_t aux_len) {
+ArSide make_side(const SideDesc &d, const Scratch &sc, int idx, size_t half, size_t aux_len,
+                 int64_t ldh) {
   ArSide a{};
+  a.ldh = ldh;
   a.rows = d.rows;
   a.nnz = d.nnz;
   a.rp = d.rp;
@@ -1347,8 +1398,8 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   P.nsides = sw ? 2 : 1;
   const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
   const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
-  P.s[0] = make_side(sv, sc, 0, half, aux0);
-  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  P.s[0] = make_side(sv, sc, 0, half, aux0, ldh);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1, ldh);
   for (int i = 0; i < P.nsides; ++i) {
     const int64_t rows = i ? rows1 : rows0;
     P.s[i].nb_spmm = (int)nb_rows(rows);
@@ -1380,6 +1431,8 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
   if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
     return SYLV_ERR_WORKSPACE;
+  P.s[0].nch = nch0;
+  P.s[1].nch = nch1;
   // coefficient chunk of the MFMA update in LDS (at most 64 KiB)
   const size_t lds =
       (size_t)std::min((ncols + 127) / 128 * 128, UPD_KCH<S>()) * S * sizeof(double);
@@ -1394,7 +1447,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   };
   auto reduce = [&](int pass) {
     set_ranges(P, rtiles, sw ? rtiles : 0);
-    gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S, ncols, nch0, nch1, ldh, jb * S, pass,
+    gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S, ncols, jb * S, pass,
                                                       ds);
     return hipGetLastError();
   };
@@ -1440,7 +1493,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, 1, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, 1, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
@@ -1456,8 +1509,8 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   P.nsides = sw ? 2 : 1;
   const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
   const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
-  P.s[0] = make_side(sv, sc, 0, half, aux0);
-  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  P.s[0] = make_side(sv, sc, 0, half, aux0, ldh);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1, ldh);
   for (int i = 0; i < P.nsides; ++i) {
     const SideDesc &d = i ? *sw : sv;
     const int64_t rows = i ? rows1 : rows0;
@@ -1487,6 +1540,8 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   const int nch0 = (int)cdiv(rows0, rpc0), nch1 = sw ? (int)cdiv(rows1, rpc1) : 0;
   if ((size_t)nch0 * nout + aux0 > half || (size_t)nch1 * nout + aux1 > half)
     return SYLV_ERR_WORKSPACE;
+  P.s[0].nch = nch0;
+  P.s[1].nch = nch1;
   P.s[0].rpc = rpc0;
   P.s[1].rpc = rpc1;
   set_ranges(P, nch0, nch1);
@@ -1509,14 +1564,14 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   }
   const int64_t rtiles = cdiv(nout, OPB);
   set_ranges(P, rtiles, sw ? rtiles : 0);
-  gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S2, ncols, nch0, nch1, ldh, jb * S, 0, ds);
+  gram_reduce_pair<<<total_blocks(P), TPB, 0, st>>>(P, S2, ncols, jb * S, 0, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_GRAM, bytes_g, 2.0 * total * ncols * S2, st);
 
   // second pass of block j: Tw, e, final column block j-1
   prof_begin(sc, st);
   set_ranges(P, 1, sw ? 1 : 0);
-  dcgs_fix_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, closure_tol, ds);
+  dcgs_fix_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, jb, closure_tol, ds);
   HIPOK(hipGetLastError());
   // final V_j and U' in one pass over V_{0..j-1}, with the U'^T U' partials
   const size_t lds = (size_t)std::max(
@@ -1536,10 +1591,10 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
   prof_begin(sc, st);
   const int nq = (int)total_blocks(P);
-  dcgs_tail_pair<S><<<(unsigned)nq + total_blocks(Ph), TPB, 0, st>>>(P, Ph, nq, jb, ldh,
+  dcgs_tail_pair<S><<<(unsigned)nq + total_blocks(Ph), TPB, 0, st>>>(P, Ph, nq, jb,
                                                                       closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, 1, ds);
+  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, 1, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
@@ -1600,9 +1655,9 @@ int64_t spmm_workgroups(const ArPair &P0, const SideDesc &sv, const SideDesc *sw
     for (int i = 0; i < P.nsides; ++i)
       P.s[i].nb_spmm = (int)std::min<int64_t>(c, nb_rows_max(i ? rows1 : rows0));
     set_ranges(P, P.s[0].nb_spmm, sw ? P.s[1].nb_spmm : 0);
-    lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+    lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ds);
     (void)hipEventRecord(a, st);
-    for (int r = 0; r < 3; ++r) lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+    for (int r = 0; r < 3; ++r) lz_spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ds);
     (void)hipEventRecord(b, st);
     float ms = 0.f;
     if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&ms, a, b) != hipSuccess)
@@ -1626,8 +1681,8 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   const int64_t rows0 = sv.rows, rows1 = sw ? sw->rows : 0;
   const size_t aux0 = aux_len(S, rows0), aux1 = sw ? aux_len(S, rows1) : 0;
   if (aux0 > half || aux1 > half) return SYLV_ERR_WORKSPACE;
-  P.s[0] = make_side(sv, sc, 0, half, aux0);
-  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1);
+  P.s[0] = make_side(sv, sc, 0, half, aux0, ldh);
+  if (sw) P.s[1] = make_side(*sw, sc, 1, half, aux1, ldh);
   // small bases: the whole step in one launch, one workgroup per basis
   const bool fused = rows0 + rows1 <= LZ_FUSED_ROWS;
   for (int i = 0; i < P.nsides; ++i) {
@@ -1645,7 +1700,7 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   if (fused) {
     set_ranges(P, 1, sw ? 1 : 0);
     prof_begin(sc, st);
-    lz_fused_pair<S, T><<<P.nsides, TPB, 0, st>>>(P, jb, ldh, closure_tol, ds);
+    lz_fused_pair<S, T><<<P.nsides, TPB, 0, st>>>(P, jb, closure_tol, ds);
     HIPOK(hipGetLastError());
     prof_end(sc, FAM_SPMM,
              12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 8.0 * total * S * 9,
@@ -1662,9 +1717,9 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   set_ranges(Ps, Ps.s[0].nb_spmm, sw ? Ps.s[1].nb_spmm : 0);
   set_ranges(P, nb_rows(rows0), sw ? nb_rows(rows1) : 0);
   prof_begin(sc, st);
-  lz_spmm_pair<S, T><<<total_blocks(Ps), TPB, 0, st>>>(Ps, jb, ldh, ds);
+  lz_spmm_pair<S, T><<<total_blocks(Ps), TPB, 0, st>>>(Ps, jb, ds);
   HIPOK(hipGetLastError());
-  lz_update_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, ds);
+  lz_update_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ds);
   HIPOK(hipGetLastError());
   // matrix + gather V_j + read V_{j-1}, V_j + U write/read (local three-term step)
   prof_end(sc, FAM_SPMM,
@@ -1674,7 +1729,7 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, ldh, 0, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, 0, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   // block jb + 1 completes a group of ring slots: the group goes to the basis
@@ -1682,6 +1737,106 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   return 0;
 }
 
+
+// ---- batch groups: the step of every basis of many problems in one launch per phase ----
+// The tables (one ArSide per basis and launch kind, the workgroup owners, the compact block
+// slots) are built once (krylov_group_create); a step only passes the step index. Bases of
+// problems that stopped return at once (their problem's flag).
+
+inline ArTab group_tab(const KGroup &g, int kind, int jb, int ring, int unb = 0) {
+  ArTab t;
+  t.sides = static_cast<const ArSide *>(g.tab[kind]);
+  t.owner = unb > 0 ? nullptr : g.own[kind];
+  t.panels = static_cast<const PanelSet *>(g.panels);
+  t.nsides = g.nsides;
+  t.unb = unb;
+  t.jb = jb;
+  t.ring = ring;
+  return t;
+}
+
+// Block Lanczos step jb of every basis (the multi-kernel step of lanczos_pair_t).
+template <int S>
+int lanczos_group_t(const KGroup &g, int jb, double closure_tol, hipStream_t st) {
+  const ArTab R = group_tab(g, GK_ROWS, jb, LZ_RING), Q = group_tab(g, GK_QR, jb, LZ_RING);
+  lz_spmm_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(R, jb, nullptr);
+  HIPOK(hipGetLastError());
+  lz_update_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(R, jb, nullptr);
+  HIPOK(hipGetLastError());
+  qr2_pair<S><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, closure_tol, nullptr);
+  HIPOK(hipGetLastError());
+  final_pair<S, double><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, jb, 0, nullptr);
+  HIPOK(hipGetLastError());
+  if ((jb + 2) % LZ_RING == 0) {
+    lz_flush_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(R, jb + 2 - LZ_RING,
+                                                                        jb + 2);
+    HIPOK(hipGetLastError());
+  }
+  return 0;
+}
+
+// Basis columns of the last, partial group of ring slots before block nblocks.
+template <int S>
+int lanczos_group_flush_t(const KGroup &g, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return 0;
+  const ArTab R = group_tab(g, GK_ROWS, 0, LZ_RING);
+  lz_flush_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(
+      R, (nblocks - 1) / LZ_RING * LZ_RING, nblocks);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+// Lagged block Arnoldi step jb of every basis (FP64, the launches of arnoldi_lagged_t).
+template <int S>
+int arnoldi_group_t(const KGroup &g, int jb, double closure_tol, hipStream_t st) {
+  if constexpr (S > 4) {
+    return SYLV_ERR_INVALID;
+  } else {
+    constexpr int S2 = 2 * S;
+    const int ncols = (jb + 1) * S, nf = jb * S, nout = ncols * S2;
+    if (nout > g.max_nout) return SYLV_ERR_WORKSPACE;
+    const ArTab R = group_tab(g, GK_ROWS, jb, 2);
+    spmm_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(R, nullptr);
+    HIPOK(hipGetLastError());
+    const ArTab C = group_tab(g, GK_CHUNK, jb, 2);
+    {
+      constexpr int QM = gram_nq_max<S2, double>();
+      int cw_log2 = 8, nq = 1;
+      if (ncols <= TPB) cw_log2 = log2_exact(pow2_ceil(ncols));
+      else nq = std::min(QM, pow2_ceil((ncols + TPB - 1) / TPB));
+      const size_t glds = cw_log2 < 8 ? (size_t)TPB * S2 * sizeof(double) : 0;
+      const unsigned nb = (unsigned)g.nblk[GK_CHUNK];
+      switch (nq) {
+        case 1: gram_part_pair<S2, double, 1, true><<<nb, TPB, glds, st>>>(C, ncols, cw_log2, nullptr); break;
+        case 2: gram_part_pair<S2, double, std::min(2, QM), true><<<nb, TPB, glds, st>>>(C, ncols, cw_log2, nullptr); break;
+        case 4: gram_part_pair<S2, double, std::min(4, QM), true><<<nb, TPB, glds, st>>>(C, ncols, cw_log2, nullptr); break;
+        default: gram_part_pair<S2, double, QM, true><<<nb, TPB, glds, st>>>(C, ncols, cw_log2, nullptr); break;
+      }
+      HIPOK(hipGetLastError());
+    }
+    const int rtiles = (int)cdiv(nout, OPB);
+    gram_reduce_pair<<<(unsigned)(g.nsides * rtiles), TPB, 0, st>>>(
+        group_tab(g, GK_ROWS, jb, 2, rtiles), S2, ncols, jb * S, 0, nullptr);
+    HIPOK(hipGetLastError());
+    dcgs_fix_pair<S><<<(unsigned)g.nsides, TPB, 0, st>>>(group_tab(g, GK_ROWS, jb, 2, 1), jb,
+                                                         closure_tol, nullptr);
+    HIPOK(hipGetLastError());
+    const size_t lds = (size_t)std::max(
+        std::min((nf + 127) / 128 * 128, UPD_KCH<S2>()) * S2 * (int)sizeof(double), 8);
+    dcgs_update_pair<S><<<(unsigned)g.nblk[GK_UPD], TPB, lds, st>>>(
+        group_tab(g, GK_UPD, jb, 2), jb, nullptr);
+    HIPOK(hipGetLastError());
+    const int hw = (int)cdiv(ncols, TPB / WAVE);
+    const ArTab Q = group_tab(g, GK_QR, jb, 2);
+    const int nq = g.nblk[GK_QR];
+    dcgs_tail_pair<S><<<(unsigned)(nq + g.nsides * hw), TPB, 0, st>>>(
+        Q, group_tab(g, GK_ROWS, jb, 2, hw), nq, jb, closure_tol, nullptr);
+    HIPOK(hipGetLastError());
+    final_pair<S, double><<<(unsigned)nq, TPB, 0, st>>>(Q, jb, 1, nullptr);
+    HIPOK(hipGetLastError());
+    return 0;
+  }
+}
 
 }  // namespace
 
@@ -1700,6 +1855,13 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   int lanczos_flush_##SS(const SideDesc &sv, const SideDesc *sw, int nblocks, hipStream_t st) { \
     return sv.fp32 ? lanczos_flush_t<SS, float>(sv, sw, nblocks, st)                            \
                    : lanczos_flush_t<SS, double>(sv, sw, nblocks, st);                          \
+  }                                                                                             \
+  int krylov_group_step_##SS(const KGroup &g, int jb, double closure_tol, hipStream_t st) {     \
+    return g.lanczos ? lanczos_group_t<SS>(g, jb, closure_tol, st)                              \
+                     : arnoldi_group_t<SS>(g, jb, closure_tol, st);                             \
+  }                                                                                             \
+  int krylov_group_flush_##SS(const KGroup &g, int nblocks, hipStream_t st) {                   \
+    return lanczos_group_flush_t<SS>(g, nblocks, st);                                           \
   }                                                                                             \
   int arnoldi_lagged_##SS(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,          \
                           double closure_tol, const Scratch &sc, DevState *ds, hipStream_t st) {\

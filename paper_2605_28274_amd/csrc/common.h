@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <vector>
 
 #include "sylv.h"
 
@@ -625,6 +626,118 @@ int launch_arnoldi_pair(int s, const SideDesc &sv, const SideDesc *sw, int jb, i
 bool arnoldi_lagged_supported(int s, bool fp32);
 // Workspace doubles the paired Arnoldi step needs in Scratch::partials.
 size_t arnoldi_partials_needed(int s, int64_t rows_v, int64_t rows_w, int64_t max_cols);
+// ---- batch groups: the block Krylov step of many problems of one block size per launch ----
+// One basis of a group (host description of where its data and scratch live).
+struct GroupSide {
+  SideDesc d;
+  Scratch sc;         // the problem's Krylov scratch (partials split between its two bases)
+  int idx;            // 0: V basis, 1: W basis (second half of the partials)
+  int64_t pair_rows;  // rows of both bases of the problem (chunking of the Gram sweeps)
+  int64_t ldh;        // row stride of the basis' H (or G)
+  const int *done;    // the problem's DevState::done (device)
+};
+
+// Launch kinds of a group: row tiles (SpMM, local update, ring flush), QR workgroups, Gram
+// chunks, update row blocks.
+enum { GK_ROWS = 0, GK_QR, GK_CHUNK, GK_UPD, GK_COUNT };
+
+// Device tables of a group (arnoldi.hip). tab[kind] holds one basis record per basis with that
+// kind's workgroup range; own[kind] maps each workgroup of the kind to its basis.
+struct KGroup {
+  int s = 0, lanczos = 0, nsides = 0;
+  const void *tab[GK_COUNT] = {};
+  const unsigned short *own[GK_COUNT] = {};
+  int nblk[GK_COUNT] = {};
+  const void *panels = nullptr;
+  int max_nout = 0;  // Gram outputs per chunk the partial buffers of every basis hold
+  int *idx = nullptr;  // device scratch of the compaction
+};
+// Device bytes of a group's tables; 0 if a basis does not fit its scratch.
+size_t krylov_group_bytes(int s, bool lanczos, const GroupSide *sides, int n);
+// Builds the tables into dev (krylov_group_bytes bytes, 256-aligned), synchronously on st: g
+// covers every basis; act has room for the same tables restricted to the bases whose problem
+// still runs, which launch_krylov_group_compact fills (then act.nsides = counts[0] and
+// act.nblk[k] = counts[1 + k], read back by the host, make it usable).
+int krylov_group_create(KGroup *g, KGroup *act, int s, bool lanczos, const GroupSide *sides, int n,
+                        void *dev, size_t bytes, hipStream_t st);
+int launch_krylov_group_compact(const KGroup &g, const KGroup &act, int *counts, hipStream_t st);
+// Bounds for sizing before the contexts exist: bytes per basis of `rows` rows, and per group.
+size_t krylov_side_bytes_bound(int64_t rows);
+size_t krylov_group_bytes_fixed();
+// Step jb of every basis (block Lanczos, or lagged block Arnoldi with FP64 bases, s <= 4).
+int launch_krylov_group(const KGroup &g, int jb, double closure_tol, hipStream_t st);
+// Block Lanczos: basis columns of the last partial group of ring slots before block nblocks.
+int launch_krylov_group_flush(const KGroup &g, int nblocks, hipStream_t st);
+
+// One problem of a batch group as the core kernels see it (device table, one entry per
+// problem; the kernels take the problem from blockIdx.y). Cores as in a single solve.
+struct CoreInst {
+  const double *H, *G;
+  double *X, *R, *P, *Q, *S, *T;
+  const double *Rt;
+  double *part;  // the problem's core-stream reduction partials
+  DevState *ds;
+  double *hist;
+  int64_t ldc;
+  int max_iter, pad_;
+};
+// The group launches take the problem of blockIdx.y from list (the problems still running,
+// n of them), or all problems of tab in order when list is null.
+// CG iteration k (p = (k+1) s) of every problem: P_k, <P_k, Q_k>, alpha, X, R, the stopping
+// test, rho and beta (core.hip).
+int launch_cg_group(int s, bool sym, int p, int k, const CoreInst *tab, const int *list, int n,
+                    hipStream_t st);
+// BiCGSTAB iteration k (p = (2k+1) s): which = 0: Q = op(P) on p, 1: T = op(S) on p + s
+// (dense.hip); alpha and S; <T, S>, <T, T>; omega, X, R, P, the stopping test (core.hip).
+int launch_core_op_group(int s, int p, int which, const CoreInst *tab, const int *list, int n,
+                         hipStream_t st);
+int launch_bicg_group_s(int s, int p, int k, const CoreInst *tab, const int *list, int n,
+                        hipStream_t st);
+int launch_bicg_group_omega(int s, int p, const CoreInst *tab, const int *list, int n,
+                            hipStream_t st);
+int launch_bicg_group_update(int s, int p, int k, const CoreInst *tab, const int *list, int n,
+                             hipStream_t st);
+// The problems of the group still running: *count (device) and their indices in list.
+int launch_group_active(const CoreInst *tab, int n, int *count, int *list, hipStream_t st);
+
+// A batch group (api.hip): problems with the same method, block size, form (Sylvester or
+// Lyapunov) and iteration limit whose iterations advance in lock-step on one stream, every
+// phase one launch for all of them. The host polls one small record every GROUP_SEG iterations;
+// problems that stopped in between return at once through their flags, and the poll removes
+// them from the launches (the tables of the running problems are compacted on the device). With
+// graphs, each segment of GROUP_SEG iterations is captured once, when the group is set up, as a
+// HIP graph over the full tables that every solve replays.
+constexpr int GROUP_SEG = 16;
+struct GroupRun {
+  std::vector<void *> ctx;
+  int method = 0, s = 0, sym = 0;
+  hipStream_t st = nullptr;
+  KGroup kg;                 // tables of every basis
+  KGroup ka;                 // tables of the bases of the problems still running
+  CoreInst *tab = nullptr;   // device, one entry per problem
+  int *list = nullptr;       // device: the problems still running
+  int *poll = nullptr;       // device: [problems running, bases running, workgroups per kind]
+  int *h_poll = nullptr;     // pinned copy of poll
+  int na = 0;                // problems in the launches (compacted form)
+  int64_t min_ldc = 0;
+  double closure_tol = 0.0;
+  bool graphs = false;       // replayed graphs over the full tables; else compacted launches
+  int graph_max_iter = -1;
+  std::vector<hipGraphExec_t> exec;  // per segment
+};
+// Whether a context can join a group: FP64 bases, no outer refinement, factored CG or the
+// lagged factored BiCGSTAB, Krylov steps on the context's own stream.
+bool group_eligible(void *ctx);
+// Device bytes of the group's tables (0: the problems cannot form one group).
+size_t group_bytes(void *const *ctxs, int n);
+// With graphs, every segment of iterations up to max_iter is captured here (solves with another
+// iteration limit launch the kernels instead).
+int group_prepare(GroupRun &g, void *const *ctxs, int n, void *dev, size_t bytes, bool graphs,
+                  int max_iter);
+// One solve of every problem of the group (verified like a single solve); res[n].
+int group_solve(GroupRun &g, double tol, int max_iter, sylv_result *res);
+void group_release(GroupRun &g);
+
 // Process-wide cache of the autotuner (arnoldi.hip): a launch parameter per shape bucket.
 struct TuneKey {
   int s, esz;

@@ -232,7 +232,7 @@ __device__ __forceinline__ void cg_tile_q(const CgTile<S> &T, const CgGeom &g, i
 }
 
 template <int S, bool SYM>
-__global__ __launch_bounds__(TPB) void cg_pq_kernel(int p, const double *__restrict__ H,
+__device__ __forceinline__ void cg_pq_body(int p, const double *__restrict__ H,
                                                     const double *__restrict__ G,
                                                     const double *__restrict__ R,
                                                     const double *__restrict__ Pprev,
@@ -265,7 +265,7 @@ __global__ __launch_bounds__(TPB) void cg_pq_kernel(int p, const double *__restr
 }
 
 template <int S, bool SYM>
-__global__ __launch_bounds__(TPB) void cg_xr_kernel(int p, const double *__restrict__ H,
+__device__ __forceinline__ void cg_xr_body(int p, const double *__restrict__ H,
                                                     const double *__restrict__ G,
                                                     const double *__restrict__ Pk,
                                                     double *__restrict__ X,
@@ -328,7 +328,7 @@ __global__ __launch_bounds__(TPB) void cg_xr_kernel(int p, const double *__restr
 
 // One workgroup: ||R_{k+1}|| / ||R_0|| from the partials, the stopping test, rho_{k+1} and
 // beta_k (CG).
-__global__ __launch_bounds__(TPB) void cg_converge_kernel(const double *rr_part, int nb,
+__device__ __forceinline__ void cg_converge_body(const double *rr_part, int nb,
                                                           DevState *ds, double *hist, int k,
                                                           int max_iter) {
   if (ds->done) return;
@@ -351,7 +351,7 @@ __global__ __launch_bounds__(TPB) void cg_converge_kernel(const double *rr_part,
 
 // alpha = rho / <R~0, Q(1:s,1:s)> (every workgroup forms it from the s x s corner), then
 // S = [R 0; 0 0] - alpha Q over (p+s)^2.
-__global__ __launch_bounds__(TPB) void bicg_s_kernel(int s, int q, const double *__restrict__ Q,
+__device__ __forceinline__ void bicg_s_body(int s, int q, const double *__restrict__ Q,
                                                      const double *__restrict__ R,
                                                      double *__restrict__ S,
                                                      const double *__restrict__ Rt, int64_t ldc,
@@ -379,7 +379,7 @@ __global__ __launch_bounds__(TPB) void bicg_s_kernel(int s, int q, const double 
 
 // Partials of <T, S> and <T, T> over (p+2s)^2 (S is zero beyond p+s, so <T, S> is the
 // inner product with T(1:(2k+2)s, 1:(2k+2)s) of Alg. 4.2 step 13).
-__global__ __launch_bounds__(TPB) void bicg_omega_kernel(int q, const double *__restrict__ T,
+__device__ __forceinline__ void bicg_omega_body(int q, const double *__restrict__ T,
                                                          const double *__restrict__ S,
                                                          int64_t ldc, double *partials,
                                                          const DevState *ds) {
@@ -399,7 +399,7 @@ __global__ __launch_bounds__(TPB) void bicg_omega_kernel(int q, const double *__
 // beta = (alpha / omega)(rho_{k+1} / rho_k), formed in every workgroup from the partials; then
 // X += alpha P + omega S; R = S - omega T; P = R + beta (P - omega Q) over (p+2s)^2 (old X is
 // zero beyond 2ks, P beyond p, Q and S beyond p+s); partials of ||R||^2.
-__global__ __launch_bounds__(TPB) void bicg_update_kernel(int s, int q, double *__restrict__ X,
+__device__ __forceinline__ void bicg_update_body(int s, int q, double *__restrict__ X,
                                                           double *__restrict__ R,
                                                           double *__restrict__ P,
                                                           const double *__restrict__ Q,
@@ -455,7 +455,7 @@ __global__ __launch_bounds__(TPB) void bicg_update_kernel(int s, int q, double *
 }
 
 // One workgroup: relative residual, stopping test, breakdown on rho_{k+1} = 0, rho update.
-__global__ __launch_bounds__(TPB) void bicg_converge_kernel(const double *rr_part, int nb,
+__device__ __forceinline__ void bicg_converge_body(const double *rr_part, int nb,
                                                             DevState *ds, double *hist, int k,
                                                             int max_iter) {
   if (ds->done) return;
@@ -475,6 +475,116 @@ __global__ __launch_bounds__(TPB) void bicg_converge_kernel(const double *rr_par
   }
   ds->rho = ds->rho_next;
   hist[2 * max_iter + k] = ds->beta;
+}
+
+// ---- kernels: one problem per launch, or one problem per blockIdx.y over a group table ----
+
+template <int S, bool SYM>
+__global__ __launch_bounds__(TPB) void cg_pq_kernel(int p, const double *H, const double *G,
+                                                    const double *R, const double *Pprev,
+                                                    double *Pk, int64_t ldc, double *partials,
+                                                    const DevState *ds) {
+  cg_pq_body<S, SYM>(p, H, G, R, Pprev, Pk, ldc, partials, ds);
+}
+
+// CG iteration k of every problem of the group: P_k is the Q buffer for even k and the P
+// buffer for odd k (the other holds P_{k-1}).
+template <int S, bool SYM>
+__global__ __launch_bounds__(TPB) void cg_pq_group(const CoreInst *tab, const int *list, int p, int k) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  cg_pq_body<S, SYM>(p, c.H, c.G, c.R, (k & 1) ? c.Q : c.P, (k & 1) ? c.P : c.Q, c.ldc, c.part,
+                     c.ds);
+}
+
+template <int S, bool SYM>
+__global__ __launch_bounds__(TPB) void cg_xr_kernel(int p, const double *H, const double *G,
+                                                    const double *Pk, double *X, double *R,
+                                                    int64_t ldc, const double *pq_part,
+                                                    int pq_nb, double *partials, DevState *ds,
+                                                    double *hist, int k, int max_iter) {
+  cg_xr_body<S, SYM>(p, H, G, Pk, X, R, ldc, pq_part, pq_nb, partials, ds, hist, k, max_iter);
+}
+
+template <int S, bool SYM>
+__global__ __launch_bounds__(TPB) void cg_xr_group(const CoreInst *tab, const int *list, int p, int k, int nb,
+                                                   int rr_off) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  cg_xr_body<S, SYM>(p, c.H, c.G, (k & 1) ? c.P : c.Q, c.X, c.R, c.ldc, c.part, nb,
+                     c.part + rr_off, c.ds, c.hist, k, c.max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void cg_converge_kernel(const double *rr_part, int nb,
+                                                          DevState *ds, double *hist, int k,
+                                                          int max_iter) {
+  cg_converge_body(rr_part, nb, ds, hist, k, max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void cg_converge_group(const CoreInst *tab, const int *list, int nb, int rr_off,
+                                                         int k) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  cg_converge_body(c.part + rr_off, nb, c.ds, c.hist, k, c.max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_s_kernel(int s, int q, const double *Q,
+                                                     const double *R, double *S,
+                                                     const double *Rt, int64_t ldc, DevState *ds,
+                                                     double *hist, int k, int max_iter) {
+  bicg_s_body(s, q, Q, R, S, Rt, ldc, ds, hist, k, max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_s_group(const CoreInst *tab, const int *list, int s, int q, int k) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  bicg_s_body(s, q, c.Q, c.R, c.S, c.Rt, c.ldc, c.ds, c.hist, k, c.max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_omega_kernel(int q, const double *T, const double *S,
+                                                         int64_t ldc, double *partials,
+                                                         const DevState *ds) {
+  bicg_omega_body(q, T, S, ldc, partials, ds);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_omega_group(const CoreInst *tab, const int *list, int q) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  bicg_omega_body(q, c.T, c.S, c.ldc, c.part, c.ds);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_update_kernel(int s, int q, double *X, double *R,
+                                                          double *P, const double *Q,
+                                                          const double *S, const double *T,
+                                                          const double *Rt, int64_t ldc,
+                                                          const double *om_part, int om_nb,
+                                                          double *partials, DevState *ds,
+                                                          double *hist, int k, int max_iter) {
+  bicg_update_body(s, q, X, R, P, Q, S, T, Rt, ldc, om_part, om_nb, partials, ds, hist, k,
+                   max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_update_group(const CoreInst *tab, const int *list, int s, int q,
+                                                         int k, int nb, int rr_off) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  bicg_update_body(s, q, c.X, c.R, c.P, c.Q, c.S, c.T, c.Rt, c.ldc, c.part, nb, c.part + rr_off,
+                   c.ds, c.hist, k, c.max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_converge_kernel(const double *rr_part, int nb,
+                                                            DevState *ds, double *hist, int k,
+                                                            int max_iter) {
+  bicg_converge_body(rr_part, nb, ds, hist, k, max_iter);
+}
+
+__global__ __launch_bounds__(TPB) void bicg_converge_group(const CoreInst *tab, const int *list, int nb,
+                                                           int rr_off, int k) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  bicg_converge_body(c.part + rr_off, nb, c.ds, c.hist, k, c.max_iter);
+}
+
+// The problems of the group still running: *count and their indices in list (in order).
+__global__ void group_active_kernel(const CoreInst *tab, int n, int *count, int *list) {
+  if (threadIdx.x != 0) return;
+  int c = 0;
+  for (int i = 0; i < n; ++i)
+    if (!tab[i].ds->done) list[c++] = i;
+  *count = c;
 }
 
 unsigned grid_q(int q) { return (unsigned)(q < NBLK ? (q < 1 ? 1 : q) : NBLK); }
@@ -568,6 +678,66 @@ int launch_bicg_update(int s, int p, double *X, double *R, double *P, const doub
                                         ds, hist, k, max_iter);
   HIPOK(hipGetLastError());
   bicg_converge_kernel<<<1, TPB, 0, st>>>(rr, (int)g, ds, hist, k, max_iter);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+// ---- batch groups: one launch per phase for every problem of the group ----
+
+int launch_cg_group(int s, bool sym, int p, int k, const CoreInst *tab, const int *list, int n,
+                    hipStream_t st) {
+  const unsigned g = cg_grid(p + s);
+  const dim3 grid(g, (unsigned)n);
+  switch (s) {
+#define CASE(SS)                                                                        \
+  case SS:                                                                              \
+    if (sym) {                                                                          \
+      cg_pq_group<SS, true><<<grid, TPB, 0, st>>>(tab, list, p, k);                           \
+      cg_xr_group<SS, true><<<grid, TPB, 0, st>>>(tab, list, p, k, (int)g, CG_MAXWG);         \
+    } else {                                                                            \
+      cg_pq_group<SS, false><<<grid, TPB, 0, st>>>(tab, list, p, k);                          \
+      cg_xr_group<SS, false><<<grid, TPB, 0, st>>>(tab, list, p, k, (int)g, CG_MAXWG);        \
+    }                                                                                   \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: return SYLV_ERR_INVALID;
+  }
+  HIPOK(hipGetLastError());
+  cg_converge_group<<<dim3(1, (unsigned)n), TPB, 0, st>>>(tab, list, (int)g, CG_MAXWG, k);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_bicg_group_s(int s, int p, int k, const CoreInst *tab, const int *list, int n,
+                        hipStream_t st) {
+  const int q = p + s;
+  bicg_s_group<<<dim3(grid_q(q), (unsigned)n), TPB, 0, st>>>(tab, list, s, q, k);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_bicg_group_omega(int s, int p, const CoreInst *tab, const int *list, int n,
+                            hipStream_t st) {
+  const int q = p + 2 * s;
+  bicg_omega_group<<<dim3(grid_q(q), (unsigned)n), TPB, 0, st>>>(tab, list, q);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_bicg_group_update(int s, int p, int k, const CoreInst *tab, const int *list, int n,
+                             hipStream_t st) {
+  const int q = p + 2 * s;
+  const unsigned g = grid_q(q);
+  bicg_update_group<<<dim3(g, (unsigned)n), TPB, 0, st>>>(tab, list, s, q, k, (int)g, 2 * NBLK);
+  HIPOK(hipGetLastError());
+  bicg_converge_group<<<dim3(1, (unsigned)n), TPB, 0, st>>>(tab, list, (int)g, 2 * NBLK, k);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_group_active(const CoreInst *tab, int n, int *count, int *list, hipStream_t st) {
+  group_active_kernel<<<1, 64, 0, st>>>(tab, n, count, list);
   HIPOK(hipGetLastError());
   return 0;
 }

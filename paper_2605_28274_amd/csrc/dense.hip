@@ -244,12 +244,11 @@ __device__ __forceinline__ void core_tile_part(Smem &sm, WaveAcc &acc, const dou
 
 // One workgroup per complementary pair of tiles b and T*T - 1 - b, i.e. (I, J) and
 // (T-1-I, T-1-J): their sequences add up to the same length for every b.
-__global__ __launch_bounds__(256, 2) void core_op_kernel(int s, int p, int T,
-                                                         const double *__restrict__ H,
-                                                         const double *__restrict__ G,
-                                                         const double *__restrict__ P,
-                                                         double *__restrict__ Q, int64_t ldc,
-                                                         const int *done) {
+__device__ __forceinline__ void core_op_body(int s, int p, int T, const double *__restrict__ H,
+                                             const double *__restrict__ G,
+                                             const double *__restrict__ P,
+                                             double *__restrict__ Q, int64_t ldc,
+                                             const int *done) {
   if (done && *done) return;
   __shared__ Smem sm;
   const int w = threadIdx.x >> 6, wm = w >> 1, wn = w & 1;
@@ -268,6 +267,21 @@ __global__ __launch_bounds__(256, 2) void core_op_kernel(int s, int p, int T,
     });
     if (t == t2) break;
   }
+}
+
+__global__ __launch_bounds__(256, 2) void core_op_kernel(int s, int p, int T, const double *H,
+                                                         const double *G, const double *P,
+                                                         double *Q, int64_t ldc,
+                                                         const int *done) {
+  core_op_body(s, p, T, H, G, P, Q, ldc, done);
+}
+
+// The core operator of every problem of a batch group (blockIdx.y): Q = op(P) (which = 0) or
+// T = op(S) (which = 1).
+__global__ __launch_bounds__(256, 2) void core_op_group(const CoreInst *tab, const int *list,
+                                                        int s, int p, int T, int which) {
+  const CoreInst &c = tab[list ? list[blockIdx.y] : blockIdx.y];
+  core_op_body(s, p, T, c.H, c.G, which ? c.S : c.P, which ? c.T : c.Q, c.ldc, &c.ds->done);
 }
 
 // Stream-K form: the concatenated sequence of all tiles (row-major) is cut into chunks of c
@@ -709,6 +723,15 @@ int launch_core_op(int s, int p, const double *H, const double *G, const double 
     }
   }
   core_op_kernel<<<(unsigned)((tiles + 1) / 2), 256, 0, st>>>(s, p, T, H, G, P, Q, ldc, done);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_core_op_group(int s, int p, int which, const CoreInst *tab, const int *list, int n,
+                         hipStream_t st) {
+  const int T = (p + s + BM - 1) / BM;
+  core_op_group<<<dim3((unsigned)((T * T + 1) / 2), (unsigned)n), 256, 0, st>>>(tab, list, s, p,
+                                                                                 T, which);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -26,6 +26,7 @@ SYLV_ERR_RHS_RANK, SYLV_ERR_STATE = -4, -5
 SYLV_METHOD_CG, SYLV_METHOD_BICGSTAB = 0, 1
 SYLV_METHOD_CR, SYLV_METHOD_CGS, SYLV_METHOD_GPBICG = 2, 3, 4
 SYLV_FP64, SYLV_MIXED_FP32 = 0, 1
+SYLV_BATCH_STREAMS, SYLV_BATCH_GROUPED, SYLV_BATCH_GRAPH = 0, 1, 2
 
 
 class SylvError(RuntimeError):
@@ -143,6 +144,11 @@ _lib.sylv_batch_workspace_bytes.restype = c_size_t
 _lib.sylv_batch_create.argtypes = [POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p,
                                    c_size_t, c_int]
 _lib.sylv_batch_create.restype = c_int
+_lib.sylv_batch_create_ex.argtypes = [POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p,
+                                      c_size_t, c_int, c_int]
+_lib.sylv_batch_create_ex.restype = c_int
+_lib.sylv_batch_groups.argtypes = [c_void_p]
+_lib.sylv_batch_groups.restype = c_int
 _lib.sylv_batch_solve.argtypes = [c_void_p, c_double, c_void_p]
 _lib.sylv_batch_solve.restype = c_int
 _lib.sylv_batch_context.argtypes = [c_void_p, c_int]
@@ -485,6 +491,22 @@ def sylv_batch_create(problems, options, workspace, nstreams: int):
     return h
 
 
+def sylv_batch_create_ex(problems, options, workspace, nstreams: int, form: int):
+    P = (sylv_problem * len(problems))(*problems)
+    O = (sylv_options * len(options))(*options)
+    h = c_void_p()
+    rc = _lib.sylv_batch_create_ex(byref(h), len(problems), P, O, c_void_p(_ptr(workspace)),
+                                   c_size_t(workspace.numel() * workspace.element_size()),
+                                   int(nstreams), int(form))
+    if rc != 0:
+        raise SylvError(rc, "sylv_batch_create_ex")
+    return h
+
+
+def sylv_batch_groups(batch) -> int:
+    return int(_lib.sylv_batch_groups(batch))
+
+
 def sylv_batch_solve(batch, tol: float, count: int):
     R = (sylv_result * count)()
     rc = _lib.sylv_batch_solve(batch, c_double(tol), R)
@@ -505,7 +527,7 @@ class Batch:
     """Device copies and contexts of a batch of problems (workloads.Problem-like objects with
     A, B, C1, C2, lyapunov, method, max_iter), solved together by sylv_batch_solve."""
 
-    def __init__(self, problems, nstreams=8, precision=0, device="cuda"):
+    def __init__(self, problems, nstreams=8, precision=0, device="cuda", form=None, verify=1):
         import torch
         self._keep = []
         probs, opts = [], []
@@ -521,13 +543,14 @@ class Batch:
             probs.append(sylv_problem(n, m, s, make_csr(n, *A), make_csr(m, *Bm),
                                       1 if p.lyapunov else 0, _ptr(C1), s, _ptr(C2), s))
             method = METHOD_CODES[p.method]
-            opts.append(default_options(method, p.max_iter, precision=precision))
+            opts.append(default_options(method, p.max_iter, precision=precision, verify=verify))
         self.problems, self.options = probs, opts
         nbytes = sylv_batch_workspace_bytes(probs, opts)
         if nbytes == 0:
             raise SylvError(SYLV_ERR_INVALID, "sylv_batch_workspace_bytes")
         self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
-        self.handle = sylv_batch_create(probs, opts, self.workspace, nstreams)
+        self.form = SYLV_BATCH_STREAMS if form is None else form
+        self.handle = sylv_batch_create_ex(probs, opts, self.workspace, nstreams, self.form)
         self.count = len(probs)
 
     def solve(self, tol):
@@ -535,6 +558,9 @@ class Batch:
 
     def context(self, i):
         return sylv_batch_context(self.handle, i)
+
+    def groups(self):
+        return sylv_batch_groups(self.handle)
 
     def close(self):
         if getattr(self, "handle", None) is not None:

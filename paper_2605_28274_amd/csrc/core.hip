@@ -60,17 +60,27 @@ __device__ __forceinline__ void put_partials(double (&v)[NV], double *partials) 
     for (int i = 0; i < NV; ++i) partials[(size_t)blockIdx.x * NV + i] = v[i];
 }
 
-// Sums nb partial records of NV values in a fixed order; the result is returned to every
-// thread (all threads must call).
-template <int NV>
+// Sums nb <= MAXB partial records of NV values in a fixed order (thread t adds records t,
+// t + TPB, ... in turn, then the block sum); the result is returned to every thread (all TPB
+// threads must call). The records are loaded all at once, so their latencies overlap.
+template <int NV, int MAXB>
 __device__ __forceinline__ void sum_partials(const double *partials, int nb, double (&out)[NV]) {
   __shared__ double lds[16 * NV];
   __shared__ double res[NV];
+  constexpr int PER = (MAXB + TPB - 1) / TPB;
+  double v[PER][NV];
 #pragma unroll
-  for (int i = 0; i < NV; ++i) out[i] = 0.0;
-  for (int b = threadIdx.x; b < nb; b += blockDim.x)
+  for (int u = 0; u < PER; ++u) {
+    const int b = (int)threadIdx.x + u * TPB;
 #pragma unroll
-    for (int i = 0; i < NV; ++i) out[i] += partials[(size_t)b * NV + i];
+    for (int i = 0; i < NV; ++i) v[u][i] = b < nb ? partials[(size_t)b * NV + i] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < NV; ++i) {
+    out[i] = 0.0;
+#pragma unroll
+    for (int u = 0; u < PER; ++u) out[i] += v[u][i];
+  }
   block_sum<NV>(out, lds);
   if (threadIdx.x == 0)
 #pragma unroll
@@ -81,211 +91,210 @@ __device__ __forceinline__ void sum_partials(const double *partials, int nb, dou
 }
 
 // ---- CG (block-tridiagonal H and G from block Lanczos) ----
-// Two passes over the cores per iteration, on 32 x 64 tiles:
+// Two passes over the cores per iteration:
 //   cg_pq_kernel: P_k = R_k + beta_{k-1} P_{k-1} (Alg. 4.1 step 14 of the previous iteration,
 //     written to the other P buffer) and partials of <P_k, Q_k>, with
 //     Q_k = [H P_k, 0] + [P_k G^T; 0] (eq. (3.11), step 6) formed in registers, not stored;
 //   cg_xr_kernel: alpha_k = rho_k / <P_k, Q_k> (step 7), Q_k formed again from the stored P_k
 //     (same arithmetic on the same values, so the same Q_k), X += alpha P_k, R -= alpha Q_k
 //     (steps 8-9) and partials of ||R_{k+1}||^2.
-// H and G are block tridiagonal (|blk(i) - blk(l)| <= 1), so a tile's Q needs P_k on the rows of
-// H's band times the tile's columns and on the tile's rows times the columns of G's band; both
-// strips are staged in LDS. With SYM (Lyapunov: G = H and R_0 = R_L R_L^T) every core is
-// symmetric: only entries i >= j are formed and stored, an entry above the diagonal is read
-// from its mirror, and the inner products count off-diagonal entries twice.
-constexpr int CT_I = 32, CT_J = 64, CG_GRID = 2048;
+// H and G are block tridiagonal (|blk(i) - blk(l)| <= 1): Q(i, j) needs P on the rows of H's
+// band around i in column j and on row i at the columns of G's band around j. With SYM
+// (Lyapunov: G = H and R_0 = R_L R_L^T) every core is symmetric: only entries i >= j are formed
+// and stored, an entry above the diagonal is read from its mirror, and the inner products count
+// off-diagonal entries twice.
+//
+// Column-panel form: a wave owns 64 consecutive columns j of the cores (one per lane) and a
+// chunk of rows, which it walks one block row b at a time with P on block rows b-1, b, b+1 of
+// its columns in registers: the band of H on a row of block b spans exactly those rows, so H P
+// needs no exchange between lanes (the H entries of a row are the same for the whole wave; the
+// chunk's band of H is staged in LDS once). P G^T needs P on the row at the columns of G's band
+// around j: the row, with 2S columns on each side, goes through a small LDS buffer of the wave.
+// Every P entry is read once per chunk (plus one block row above and below it and the side
+// columns); the next block row, and X and R of the next outputs, are loaded while the current
+// one is formed. Work items (panel, chunk) are spread over the waves of the grid; the reductions
+// keep one record per workgroup.
+constexpr int CG_GRID = 2048;
 
 template <int S>
-struct CgTile {
-  double pc[CT_I + 4 * S][CT_J];  // P rows [ra, rb) x the tile's columns
-  double hl[CT_I][2 * S];         // the tile's rows x P columns [ca, j0) (left of the tile)
-  double hr[CT_I][2 * S];         // the tile's rows x P columns [j0 + 64, cb) (right of it)
-  double hb[CT_I][3 * S];         // the band of H on the tile's rows
-};
-
-__host__ __device__ inline int cg_tiles_j(int q) { return (q + CT_J - 1) / CT_J; }
-__host__ __device__ inline int cg_tiles(int q) { return ((q + CT_I - 1) / CT_I) * cg_tiles_j(q); }
-
-// Next tile at or after t (stride gridDim.x) that holds an entry to form: all tiles, or with SYM
-// those reaching the lower triangle.
-template <bool SYM>
-__device__ __forceinline__ int cg_next_tile(int t, int q) {
-  const int tj = cg_tiles_j(q), nt = cg_tiles(q);
-  for (; t < nt; t += gridDim.x) {
-    const int i0 = (t / tj) * CT_I, j0 = (t % tj) * CT_J;
-    if (!SYM || (i0 + CT_I - 1 < q - 1 ? i0 + CT_I - 1 : q - 1) >= j0) break;
-  }
-  return t;
-}
-
-// P_k(l, j) for l, j < p (zero outside): FORM reads R and the previous P and forms
-// R + beta P_prev; otherwise it reads the stored P_k. SYM maps l < j to (j, l).
-template <bool SYM, bool FORM>
-__device__ __forceinline__ double cg_pval(int l, int j, int p, const double *__restrict__ R,
-                                          const double *__restrict__ Pp, double beta,
-                                          int64_t ldc) {
-  if (l >= p || j >= p) return 0.0;
-  const int64_t o = (SYM && l < j) ? (int64_t)j * ldc + l : (int64_t)l * ldc + j;
-  return FORM ? fma(beta, Pp[o], R[o]) : Pp[o];
-}
-
-// Tile geometry: P rows [ra, rb) meet H's band on the tile's rows, P columns [ca, cb) meet G's
-// band on its columns (both clipped to p).
-struct CgGeom {
-  int i0, j0, ra, rb, ca, cb;
-};
-
+__host__ __device__ constexpr int cg_chunk_max() { return S <= 4 ? 128 : 64; }
 template <int S>
-__device__ __forceinline__ CgGeom cg_geom(int t, int p) {
-  const int q = p + S, tj = cg_tiles_j(q);
-  CgGeom g;
-  g.i0 = (t / tj) * CT_I;
-  g.j0 = (t % tj) * CT_J;
-  const int imax = (g.i0 + CT_I - 1 < q - 1) ? g.i0 + CT_I - 1 : q - 1;
-  const int jmax = (g.j0 + CT_J - 1 < q - 1) ? g.j0 + CT_J - 1 : q - 1;
-  g.ra = (g.i0 / S - 1) * S > 0 ? (g.i0 / S - 1) * S : 0;
-  g.rb = (imax / S + 2) * S < p ? (imax / S + 2) * S : p;
-  g.ca = (g.j0 / S - 1) * S > 0 ? (g.j0 / S - 1) * S : 0;
-  g.cb = (jmax / S + 2) * S < p ? (jmax / S + 2) * S : p;
-  return g;
+__host__ __device__ inline int cg_chunk_rows(int q) {
+  const int nc = (q + 63) / 64;
+  int cr = (int)(((int64_t)q * nc + 4095) / 4096);
+  cr = cr < 4 * S ? 4 * S : (cr > cg_chunk_max<S>() ? cg_chunk_max<S>() : cr);
+  return cr / S * S;
 }
-
-// Fills the two P strips and the H band of a tile into LDS and this thread's G band (column
-// j0 + (t & 63)) into gb. No barrier: the caller brackets it.
-template <int S, bool SYM, bool FORM>
-__device__ __forceinline__ void cg_stage(CgTile<S> &T, const CgGeom &g, int p,
-                                         const double *__restrict__ H,
-                                         const double *__restrict__ G,
-                                         const double *__restrict__ R,
-                                         const double *__restrict__ Pp, double beta, int64_t ldc,
-                                         double (&gb)[3 * S]) {
-  const int q = p + S;
-  const int j = g.j0 + (threadIdx.x & (CT_J - 1));
-  const int jc = j < q ? j : q - 1;
-  const int bj = jc / S;
-  const int l0 = bj > 0 ? (bj - 1) * S : 0;
-  const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
-#pragma unroll
-  for (int t = 0; t < 3 * S; ++t) gb[t] = (l0 + t < l1) ? G[(int64_t)jc * ldc + l0 + t] : 0.0;
-  // the tile's own rows of P sit inside the column strip; only the columns of G's band left and
-  // right of the tile are staged apart
-  const int nr = g.rb > g.ra ? g.rb - g.ra : 0;
-  const int nl = g.j0 - g.ca, nrt = g.cb > g.j0 + CT_J ? g.cb - g.j0 - CT_J : 0;
-  for (int e = threadIdx.x; e < nr * CT_J; e += TPB)
-    T.pc[e / CT_J][e % CT_J] =
-        cg_pval<SYM, FORM>(g.ra + e / CT_J, g.j0 + e % CT_J, p, R, Pp, beta, ldc);
-  for (int e = threadIdx.x; e < CT_I * nl; e += TPB)
-    T.hl[e / nl][e % nl] = cg_pval<SYM, FORM>(g.i0 + e / nl, g.ca + e % nl, p, R, Pp, beta, ldc);
-  for (int e = threadIdx.x; e < CT_I * nrt; e += TPB)
-    T.hr[e / nrt][e % nrt] =
-        cg_pval<SYM, FORM>(g.i0 + e / nrt, g.j0 + CT_J + e % nrt, p, R, Pp, beta, ldc);
-  for (int e = threadIdx.x; e < CT_I * 3 * S; e += TPB) {
-    const int ii = e / (3 * S), t = e % (3 * S);
-    const int ic = g.i0 + ii < q ? g.i0 + ii : q - 1;
-    const int l = (ic / S > 0 ? (ic / S - 1) * S : 0) + t;
-    T.hb[ii][t] = l < p ? H[(int64_t)ic * ldc + l] : 0.0;
-  }
-}
-
-// Q_k on this thread's 8 entries of the tile (rows i0 + (t >> 6) + 4u, column j0 + (t & 63))
-// into qv, and P_k there into pk, from the staged strips.
 template <int S>
-__device__ __forceinline__ void cg_tile_q(const CgTile<S> &T, const CgGeom &g, int p,
-                                          const double (&gb)[3 * S], double (&qv)[8],
-                                          double (&pk)[8]) {
-  const int q = p + S;
-  const int jj = threadIdx.x & (CT_J - 1), iw = threadIdx.x >> 6;
-  const int j = g.j0 + jj;
-  const int jc = j < q ? j : q - 1;
-  const int bj = jc / S;
-  const int l0 = bj > 0 ? (bj - 1) * S : 0;
-  const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
+__host__ __device__ inline int cg_items(int q) {
+  const int cr = cg_chunk_rows<S>(q);
+  return ((q + 63) / 64) * ((q + cr - 1) / cr);
+}
+
+// PQ: P_k = R + beta P_prev is formed and stored, v += <P_k, Q_k>. Otherwise (XR): P_k is read,
+// X += alpha P_k, R -= alpha Q_k, v += ||R||^2. sc = beta (PQ) or alpha (XR).
+template <int S, bool SYM, bool PQ>
+__device__ __forceinline__ void cg_panels(int p, const double *__restrict__ H,
+                                          const double *__restrict__ G,
+                                          const double *__restrict__ Rin,
+                                          const double *__restrict__ Pin, double *__restrict__ Pout,
+                                          double *__restrict__ X, double *__restrict__ Rio,
+                                          int64_t ldc, double sc, double &v) {
+  constexpr int W = 64 + 4 * S, HB = cg_chunk_max<S>() * 3 * S;
+  __shared__ double buf[TPB / 64][W];
+  __shared__ double hbuf[TPB / 64][HB];  // the band of H on the chunk's rows
+  // the wave index is uniform: everything derived from it (items, rows, H addresses) stays in
+  // scalar registers and H is read with scalar loads
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *bw = buf[wv], *hb = hbuf[wv];
+  const int q = p + S, nc = (q + 63) / 64, cr = cg_chunk_rows<S>(q);
+  const int items = nc * ((q + cr - 1) / cr);
+  const double beta = PQ ? sc : 0.0;
+  // P(l, j) is split in a raw load (into a and, for PQ, b: R and P_prev, or the stored P_k)
+  // and the combination P = a + beta b, taken where the value is used, so that a load in
+  // flight is not waited for early
+  auto ld = [&](int l, int j, double &a, double &b) {
+    const bool in = l >= 0 && j >= 0 && l < p && j < p;
+    const int64_t o = (SYM && l < j) ? (int64_t)j * ldc + l : (int64_t)l * ldc + j;
+    a = in ? (PQ ? Rin[o] : Pin[o]) : 0.0;
+    b = (PQ && in) ? Pin[o] : 0.0;
+  };
+  auto pv = [&](double a, double b) { return PQ ? fma(beta, b, a) : a; };
+  for (int it = (int)blockIdx.x * (TPB / 64) + wv; it < items; it += (int)gridDim.x * (TPB / 64)) {
+    const int c = it % nc, r = it / nc;
+    const int j0 = 64 * c, j = j0 + lane;
+    int r0 = r * cr;
+    const int r1 = (r0 + cr < q) ? r0 + cr : q;
+    if (SYM && r1 <= j0) continue;  // above the diagonal: nothing to form
+    if (SYM && r0 < j0) r0 = j0 / S * S;
+    // G's band on column j: G(j, l) for l in [l0, l1)
+    const int jc = j < q ? j : q - 1, bj = jc / S;
+    const int l0 = bj > 0 ? (bj - 1) * S : 0;
+    const int l1 = (bj + 2) * S < p ? (bj + 2) * S : p;
+    double gb[3 * S];
 #pragma unroll
-  for (int u = 0; u < 8; ++u) {
-    const int ii = iw + 4 * u, i = g.i0 + ii;
-    const int ic = i < q ? i : q - 1;
-    const int bi = ic / S;
-    const int li0 = bi > 0 ? (bi - 1) * S : 0;
-    double a = 0.0;
-    // H P: row i of H meets rows li0 .. li0 + 3S of P (zero at and past p)
-    if (j < p) {
+    for (int t = 0; t < 3 * S; ++t)
+      gb[t] = (j < q && l0 + t < l1) ? G[(int64_t)jc * ldc + l0 + t] : 0.0;
+    const int gpos = l0 - j0 + 2 * S;  // buffer position of column l0
+    // side column of this lane (lanes < 4S): 2S columns left and right of the panel
+    const int hc = lane < 2 * S ? j0 - 2 * S + lane : j0 + 64 + (lane - 2 * S);
+    const bool hl = lane < 4 * S;
+    const int hpos = lane < 2 * S ? lane : 64 + lane;
+    // the band of H on rows [r0, r1): row i, entry t = H(i, (i/S - 1) S + t)
+    __builtin_amdgcn_wave_barrier();
+    for (int e = lane; e < (r1 - r0) * 3 * S; e += 64) {
+      const int i = r0 + e / (3 * S), l = (i / S - 1) * S + e % (3 * S);
+      hb[e] = (l >= 0 && l < p) ? H[(int64_t)i * ldc + l] : 0.0;
+    }
+    __builtin_amdgcn_wave_barrier();
+    // window: block rows b-1, b, b+1 at column j; the side columns on block row b
+    const int b0 = r0 / S, b1 = (r1 + S - 1) / S;
+    double w[3][S], hw[S];
 #pragma unroll
-      for (int t = 0; t < 3 * S; ++t) {
-        const int l = li0 + t;
-        a = fma(T.hb[ii][t], l < g.rb ? T.pc[l - g.ra][jj] : 0.0, a);
+    for (int a = 0; a < S; ++a) {
+      double x0, y0, x1, y1, x2, y2, x3 = 0.0, y3 = 0.0;
+      ld((b0 - 1) * S + a, j, x0, y0);
+      ld(b0 * S + a, j, x1, y1);
+      ld((b0 + 1) * S + a, j, x2, y2);
+      if (hl) ld(b0 * S + a, hc, x3, y3);
+      w[0][a] = pv(x0, y0);
+      w[1][a] = pv(x1, y1);
+      w[2][a] = pv(x2, y2);
+      hw[a] = pv(x3, y3);
+    }
+    // X and R of a block row's outputs (XR); issued one block row ahead, before the P
+    // prefetch, so that waiting for them leaves the later loads in flight (the counter of
+    // outstanding memory operations drains in issue order)
+    auto ld_xr = [&](int b, double (&xo)[S], double (&ro)[S]) {
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        const int i = b * S + a;
+        const int64_t o = (int64_t)i * ldc + j;
+        const bool in = i < r1 && j < q && (!SYM || i >= j);
+        xo[a] = (in && i < p && j < p) ? X[o] : 0.0;
+        ro[a] = in ? Rio[o] : 0.0;
+      }
+    };
+    double xo[S], ro[S];
+    if (!PQ) ld_xr(b0, xo, ro);
+    for (int b = b0; b < b1; ++b) {
+      double xn[S], rn[S], nx[S], ny[S], nh[S], nk[S];
+      if (!PQ) ld_xr(b + 1, xn, rn);
+      // the next block rows of P, in flight while this one is formed
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        ld((b + 2) * S + a, j, nx[a], ny[a]);
+        nh[a] = nk[a] = 0.0;
+        if (hl) ld((b + 1) * S + a, hc, nh[a], nk[a]);
+      }
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        const int i = b * S + a;
+        // H P: row i of H on block rows b-1 .. b+1
+        double qv = 0.0;
+        const double *hr = hb + (i - r0) * 3 * S;
+#pragma unroll
+        for (int t = 0; t < 3 * S; ++t) qv = fma(hr[t], w[t / S][t % S], qv);
+        // P G^T: row i at the columns of G's band, through the wave's buffer
+        bw[2 * S + lane] = w[1][a];
+        if (hl) bw[hpos] = hw[a];
+        __builtin_amdgcn_wave_barrier();
+#pragma unroll
+        for (int t = 0; t < 3 * S; ++t) qv = fma(bw[gpos + t], gb[t], qv);
+        __builtin_amdgcn_wave_barrier();
+        const double pk = w[1][a];
+        const int64_t o = (int64_t)i * ldc + j;
+        if (PQ) {
+          if (i < p && j < p && (!SYM || i >= j)) {
+            Pout[o] = pk;
+            v = fma((SYM && i > j) ? 2.0 * pk : pk, qv, v);
+          }
+        } else if (i < q && j < q && (!SYM || i >= j)) {
+          if (i < p && j < p) X[o] = fma(sc, pk, xo[a]);
+          const double rv = fma(-sc, qv, ro[a]);
+          Rio[o] = rv;
+          v = fma((SYM && i > j) ? 2.0 * rv : rv, rv, v);
+        }
+      }
+#pragma unroll
+      for (int a = 0; a < S; ++a) {
+        w[0][a] = w[1][a];
+        w[1][a] = w[2][a];
+        w[2][a] = pv(nx[a], ny[a]);
+        hw[a] = pv(nh[a], nk[a]);
+        if (!PQ) {
+          xo[a] = xn[a];
+          ro[a] = rn[a];
+        }
       }
     }
-    // P G^T: row i of P meets the band of row j of G
-    if (ic < p) {
-#pragma unroll
-      for (int t = 0; t < 3 * S; ++t) {
-        const int l = l0 + t;
-        const double v = l < g.j0            ? T.hl[ii][l - g.ca]
-                         : l < g.j0 + CT_J ? T.pc[i - g.ra][l - g.j0]
-                                           : T.hr[ii][l - g.j0 - CT_J];
-        a = fma(l < l1 ? v : 0.0, gb[t], a);
-      }
-    }
-    qv[u] = a;
-    pk[u] = (i < g.rb && i >= g.ra) ? T.pc[i - g.ra][jj] : 0.0;
   }
 }
 
 template <int S, bool SYM>
 __device__ __forceinline__ void cg_pq_body(int p, const double *__restrict__ H,
-                                                    const double *__restrict__ G,
-                                                    const double *__restrict__ R,
-                                                    const double *__restrict__ Pprev,
-                                                    double *__restrict__ Pk, int64_t ldc,
-                                                    double *partials, const DevState *ds) {
+                                           const double *__restrict__ G,
+                                           const double *__restrict__ R,
+                                           const double *__restrict__ Pprev,
+                                           double *__restrict__ Pk, int64_t ldc,
+                                           double *partials, const DevState *ds) {
   if (ds->done) return;
-  __shared__ CgTile<S> T;
-  const int q = p + S, nt = cg_tiles(q);
-  const double beta = ds->beta;
   double v[1] = {0.0};
-  for (int t = cg_next_tile<SYM>(blockIdx.x, q); t < nt;
-       t = cg_next_tile<SYM>(t + gridDim.x, q)) {
-    const CgGeom g = cg_geom<S>(t, p);
-    double gb[3 * S], qv[8], pk[8];
-    __syncthreads();  // the previous tile's readers are done
-    cg_stage<S, SYM, true>(T, g, p, H, G, R, Pprev, beta, ldc, gb);
-    __syncthreads();
-    cg_tile_q<S>(T, g, p, gb, qv, pk);
-    const int j = g.j0 + (threadIdx.x & (CT_J - 1));
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = g.i0 + (threadIdx.x >> 6) + 4 * u;
-      if (i < p && j < p && (!SYM || i >= j)) {
-        Pk[(int64_t)i * ldc + j] = pk[u];
-        v[0] = fma((SYM && i > j) ? 2.0 * pk[u] : pk[u], qv[u], v[0]);
-      }
-    }
-  }
+  cg_panels<S, SYM, true>(p, H, G, R, Pprev, Pk, nullptr, nullptr, ldc, ds->beta, v[0]);
   put_partials<1>(v, partials);
 }
 
 template <int S, bool SYM>
 __device__ __forceinline__ void cg_xr_body(int p, const double *__restrict__ H,
-                                                    const double *__restrict__ G,
-                                                    const double *__restrict__ Pk,
-                                                    double *__restrict__ X,
-                                                    double *__restrict__ R, int64_t ldc,
-                                                    const double *pq_part, int pq_nb,
-                                                    double *partials, DevState *ds,
-                                                    double *hist, int k, int max_iter) {
+                                           const double *__restrict__ G,
+                                           const double *__restrict__ Pk,
+                                           double *__restrict__ X, double *__restrict__ R,
+                                           int64_t ldc, const double *pq_part, int pq_nb,
+                                           double *partials, DevState *ds, double *hist, int k,
+                                           int max_iter) {
   if (ds->done) return;
-  __shared__ CgTile<S> T;
-  const int q = p + S, nt = cg_tiles(q);
-  // the first tile's strips load while the <P, Q> partials are summed
-  int t = cg_next_tile<SYM>(blockIdx.x, q);
-  CgGeom g{};
-  double gb[3 * S];
-  if (t < nt) {
-    g = cg_geom<S>(t, p);
-    cg_stage<S, SYM, false>(T, g, p, H, G, nullptr, Pk, 0.0, ldc, gb);
-  }
   double pq[1];
-  sum_partials<1>(pq_part, pq_nb, pq);
+  sum_partials<1, CG_GRID>(pq_part, pq_nb, pq);
   if (!(pq[0] > 0.0) || !isfinite(pq[0])) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
       ds->pq = pq[0];
@@ -300,29 +309,7 @@ __device__ __forceinline__ void cg_xr_body(int p, const double *__restrict__ H,
     hist[max_iter + k] = alpha;
   }
   double v[1] = {0.0};
-  while (t < nt) {
-    __syncthreads();  // the strips are in place
-    double qv[8], pk[8];
-    cg_tile_q<S>(T, g, p, gb, qv, pk);
-    const int j = g.j0 + (threadIdx.x & (CT_J - 1));
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int i = g.i0 + (threadIdx.x >> 6) + 4 * u;
-      if (i < q && j < q && (!SYM || i >= j)) {
-        const int64_t o = (int64_t)i * ldc + j;
-        if (i < p && j < p) X[o] = fma(alpha, pk[u], X[o]);
-        const double r = fma(-alpha, qv[u], R[o]);
-        R[o] = r;
-        v[0] = fma((SYM && i > j) ? 2.0 * r : r, r, v[0]);
-      }
-    }
-    t = cg_next_tile<SYM>(t + gridDim.x, q);
-    if (t < nt) {
-      g = cg_geom<S>(t, p);
-      __syncthreads();  // the previous tile's readers are done
-      cg_stage<S, SYM, false>(T, g, p, H, G, nullptr, Pk, 0.0, ldc, gb);
-    }
-  }
+  cg_panels<S, SYM, false>(p, H, G, nullptr, Pk, nullptr, X, R, ldc, alpha, v[0]);
   put_partials<1>(v, partials);
 }
 
@@ -333,7 +320,7 @@ __device__ __forceinline__ void cg_converge_body(const double *rr_part, int nb,
                                                           int max_iter) {
   if (ds->done) return;
   double rr[1];
-  sum_partials<1>(rr_part, nb, rr);
+  sum_partials<1, CG_GRID>(rr_part, nb, rr);
   if (threadIdx.x != 0) return;
   const double rel = sqrt(rr[0]) / ds->normR0;
   ds->relres = rel;
@@ -412,7 +399,7 @@ __device__ __forceinline__ void bicg_update_body(int s, int q, double *__restric
                                                           int max_iter) {
   if (ds->done) return;
   double ts_tt[2];
-  sum_partials<2>(om_part, om_nb, ts_tt);
+  sum_partials<2, NBLK>(om_part, om_nb, ts_tt);
   const double ts = ts_tt[0], tt = ts_tt[1];
   const double omega = ts / tt;
   if (!(tt > 0.0) || !isfinite(tt) || omega == 0.0 || !isfinite(omega)) {
@@ -460,7 +447,7 @@ __device__ __forceinline__ void bicg_converge_body(const double *rr_part, int nb
                                                             int max_iter) {
   if (ds->done) return;
   double rr[1];
-  sum_partials<1>(rr_part, nb, rr);
+  sum_partials<1, NBLK>(rr_part, nb, rr);
   if (threadIdx.x != 0) return;
   const double rel = sqrt(rr[0]) / ds->normR0;
   ds->relres = rel;
@@ -604,12 +591,22 @@ int launch_setup_scalars(int s, const double *RL, const double *RR, double *R, d
 constexpr int CG_MAXWG = 4096;
 static_assert(CG_GRID <= CG_MAXWG, "CG partials fit their ranges");
 
-unsigned cg_grid(int q) { return (unsigned)std::min(cg_tiles(q), CG_GRID); }
+unsigned cg_grid(int s, int q) {
+  int items = 0;
+  switch (s) {
+#define CASE(SS) \
+  case SS: items = cg_items<SS>(q); break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+    default: break;
+  }
+  return (unsigned)std::max(1, std::min((items + TPB / 64 - 1) / (TPB / 64), CG_GRID));
+}
 
 int launch_cg_pq(int s, int p, bool sym, const double *H, const double *G, const double *R,
                  const double *Pprev, double *Pk, int64_t ldc, const Scratch &sc, DevState *ds,
                  hipStream_t st) {
-  const unsigned g = cg_grid(p + s);
+  const unsigned g = cg_grid(s, p + s);
   switch (s) {
 #define CASE(SS)                                                                              \
   case SS:                                                                                    \
@@ -629,7 +626,7 @@ int launch_cg_pq(int s, int p, bool sym, const double *H, const double *G, const
 int launch_cg_xr(int s, int p, bool sym, const double *H, const double *G, const double *Pk,
                  double *X, double *R, int64_t ldc, const Scratch &sc, DevState *ds, double *hist,
                  int k, int max_iter, hipStream_t st) {
-  const unsigned g = cg_grid(p + s);
+  const unsigned g = cg_grid(s, p + s);
   double *rr = sc.partials + CG_MAXWG;
   switch (s) {
 #define CASE(SS)                                                                            \
@@ -686,7 +683,7 @@ int launch_bicg_update(int s, int p, double *X, double *R, double *P, const doub
 
 int launch_cg_group(int s, bool sym, int p, int k, const CoreInst *tab, const int *list, int n,
                     hipStream_t st) {
-  const unsigned g = cg_grid(p + s);
+  const unsigned g = cg_grid(s, p + s);
   const dim3 grid(g, (unsigned)n);
   switch (s) {
 #define CASE(SS)                                                                        \

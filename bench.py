@@ -10,7 +10,10 @@ largest single-GPU configuration. Other workloads (same JSON line):
   c5bi  Lyapunov factored BiCGSTAB, FP64, 2D CD 1024^2 (Pe = 1), s = 1, 200-iteration window
   batch64  64 independent instances (2D A with n in [1024, 32768]; 1D or 2D B with m in [512,
         16384]; s in {1, 2, 4}; CG on Laplacians and BiCGSTAB on Pe = 10 alternately), solved as
-        one batch over --streams streams, beside the same instances one after another
+        one batch in the grouped form (instances of one method and block size advance in
+        lock-step, one launch per phase over the group's instance table), beside the streams
+        form, the grouped form replaying captured HIP graphs, and the same instances one after
+        another
 
 One step = one pass of the whole path over resident inputs: sylv_create (CSR validation, B^T,
 sliced-ELLPACK copies, QR of C1 and C2), the factored solve with the verified stopping rule (the
@@ -418,15 +421,17 @@ def spmm_hbm(sylv, torch):
 
 def run_batch_compare(sylv, torch, np, steps, warmup, nstreams=8):
     """The 64-instance batch: wall time of sylv_batch_solve over all instances (every instance
-    verified against its true residual), then the same instances solved one after another on one
-    stream (FP64 plain, one context at a time)."""
+    verified against its true residual) in the grouped form, in the streams form (instances spread
+    over `nstreams` streams, one host thread each), in the grouped form with HIP-graph segments,
+    and the same instances solved one after another on one stream (FP64 plain, one context at a
+    time)."""
     from workloads import configs
     probs = configs.batch64()
     for p in probs:  # workspace sized for the instances' needs (CG up to ~1000 iterations)
         p.max_iter = 1500 if p.method == "cg" else 600
 
-    def timed(ns, nsteps):
-        b = sylv.Batch(probs, nstreams=ns)
+    def timed(ns, nsteps, form=None):
+        b = sylv.Batch(probs, nstreams=ns, form=sylv.SYLV_BATCH_STREAMS if form is None else form)
         for _ in range(warmup):
             b.solve(1e-8)
         torch.cuda.synchronize()
@@ -441,19 +446,25 @@ def run_batch_compare(sylv, torch, np, steps, warmup, nstreams=8):
         torch.cuda.empty_cache()
         return dt, res, rels
 
-    dt, res, rels = timed(nstreams, steps)
+    def row(dt, res, rels):
+        iters = sum(r.iters for r in res)
+        return {"time_to_1e-8_ms": round(1000 * dt, 3), "iters": iters,
+                "iters_per_s": round(iters / dt, 2), "max_true_rel_res": float(max(rels)),
+                "statuses": sorted(set(int(r.status) for r in res))}
+
+    dt, res, rels = timed(nstreams, steps, sylv.SYLV_BATCH_GROUPED)
+    dtg, res_g, rels_g = timed(nstreams, steps, sylv.SYLV_BATCH_GRAPH)
+    dtm, res_m, rels_m = timed(nstreams, steps, sylv.SYLV_BATCH_STREAMS)
     dts, res_s, rels_s = timed(1, 1)
-    iters = sum(r.iters for r in res)
     return {"workload": "batch of 64 seeded instances (2D A, n 1024-32768; 1D/2D B, m 512-16384; "
                         "s in {1,2,4}; CG/BiCGSTAB alternating), tol 1e-8",
             "instances": len(probs), "streams": nstreams,
-            "batched": {"time_to_1e-8_ms": round(1000 * dt, 3), "iters": iters,
-                        "iters_per_s": round(iters / dt, 2), "max_true_rel_res": float(max(rels)),
-                        "statuses": sorted(set(int(r.status) for r in res))},
-            "sequential_fp64_plain": {"time_to_1e-8_ms": round(1000 * dts, 3),
-                                      "iters": sum(r.iters for r in res_s),
-                                      "max_true_rel_res": float(max(rels_s))},
-            "speedup_vs_sequential": round(dts / dt, 3)}
+            "batched": {"form": "grouped", **row(dt, res, rels)},
+            "batched_graph": {"form": "grouped, HIP-graph segments", **row(dtg, res_g, rels_g)},
+            "batched_streams": {"form": "streams", **row(dtm, res_m, rels_m)},
+            "sequential_fp64_plain": row(dts, res_s, rels_s),
+            "speedup_vs_sequential": round(dts / dt, 3),
+            "speedup_vs_streams": round(dtm / dt, 3)}
 
 
 if __name__ == "__main__":

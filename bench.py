@@ -246,6 +246,10 @@ def main():
     ap.add_argument("--workload", default="c5cg",
                     choices=["c1", "c2", "c3", "c5cg", "c5bi", "batch64"])
     ap.add_argument("--streams", type=int, default=8, help="streams of the batched run")
+    ap.add_argument("--batch-group", default=None,
+                    help="METHOD:S, e.g. cg:4: time only that group of the 64-instance batch in "
+                         "the grouped form, without verification (one group runs on the calling "
+                         "thread; for kernel traces)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the mixed / batched comparisons")
@@ -295,6 +299,10 @@ def main():
         return
     if args.spmm_only:
         print(json.dumps({"spmm_hbm": spmm_hbm(sylv, torch)}), flush=True)
+        return
+    if args.batch_group:
+        print(json.dumps(run_batch_group(sylv, torch, args.batch_group, args.steps, args.warmup)),
+              flush=True)
         return
     if args.workload == "batch64":
         r = run_batch_compare(sylv, torch, np, args.steps, args.warmup, args.streams)
@@ -417,6 +425,28 @@ def spmm_hbm(sylv, torch):
                          "frac": round(nbytes / t / 1e9 / PEAK_HBM_GBS, 3)}
         out[name] = {"bytes": nbytes, **res}
     return out
+
+
+def run_batch_group(sylv, torch, spec, steps, warmup):
+    """One group of the 64-instance batch (method and block size), grouped form, recursive
+    stopping test only: wall time per solve (a breakdown of the batch's time)."""
+    from workloads import configs
+    method, s = spec.split(":")
+    probs = [p for p in configs.batch64() if p.method == method and p.s == int(s)]
+    for p in probs:
+        p.max_iter = 1500 if p.method == "cg" else 600
+    b = sylv.Batch(probs, nstreams=1, form=sylv.SYLV_BATCH_GROUPED, verify=0)
+    for _ in range(warmup):
+        b.solve(1e-8)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = b.solve(1e-8)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    b.close()
+    return {"batch_group": spec, "instances": len(probs), "groups": 1,
+            "ms_per_solve": round(1000 * dt, 3), "iters": [r.iters for r in res]}
 
 
 def run_batch_compare(sylv, torch, np, steps, warmup, nstreams=8):

@@ -384,8 +384,9 @@ def measured_traffic(workload, family, precision):
 
 
 def spmm_hbm(sylv, torch):
-    """SpMM (sliced ELLPACK, FP64) on two large operators: algorithmic bytes 12 nnz +
-    4 (rows + 1) + 16 rows s per call over its HIP-event time. Warm: 20 launches back to back
+    """SpMM (sliced ELLPACK, FP64) on three large operators (the last, 336 MB, larger than the
+    256 MB last-level cache): algorithmic bytes 12 nnz + 4 (rows + 1) + 16 rows s per call over
+    its HIP-event time. Warm: 20 launches back to back
     between two events (the library's SpMM call only enqueues), per launch. Cold: one launch
     right after a 512 MiB read that evicts the caches (a read, so that no dirty lines are left
     to write back); the read keeps the stream busy while the launch is enqueued, so the events
@@ -396,7 +397,8 @@ def spmm_hbm(sylv, torch):
     flush = torch.ones(64 * 2 ** 20, dtype=torch.float64, device="cuda")
     batch = 20
     for name, M, s in (("2D 1024^2 (n = 1048576), s = 1", stencils.cd2d(1024, 1024, 0.0), 1),
-                       ("3D 64^3 (n = 262144), s = 4", stencils.cd3d(64, 64, 64, 10.0), 4)):
+                       ("3D 64^3 (n = 262144), s = 4", stencils.cd3d(64, 64, 64, 10.0), 4),
+                       ("2D 2048^2 (n = 4194304), s = 1", stencils.cd2d(2048, 2048, 0.0), 1)):
         rp, ci, va = sylv.csr_tensors(M)
         csr = sylv.make_csr(M.shape[0], rp, ci, va)
         buf = torch.empty(sylv.sylv_sell_bytes(csr), dtype=torch.uint8, device="cuda")

@@ -5,6 +5,11 @@
 // the host polls the device's stop flag every `check_every` iterations (iterations enqueued
 // after the stop return at kernel entry).
 #include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
+#include <string>
+#include <thread>
 #include <chrono>
 #include <cmath>
 #include <cstdio>
@@ -1806,6 +1811,8 @@ void group_release(GroupRun &g) {
   for (hipGraphExec_t e : g.exec)
     if (e) (void)hipGraphExecDestroy(e);
   g.exec.clear();
+  if (g.vst) (void)hipStreamDestroy(g.vst);
+  g.vst = nullptr;
   if (g.h_poll) (void)hipHostFree(g.h_poll);
   g.h_poll = nullptr;
 }
@@ -1850,6 +1857,8 @@ int group_prepare(GroupRun &g, void *const *ctxs, int n, void *dev, size_t bytes
   HIPOK(hipStreamSynchronize(g.st));
   if (!g.h_poll &&
       hipHostMalloc(reinterpret_cast<void **>(&g.h_poll), sizeof(int) * 8) != hipSuccess)
+    return SYLV_ERR_HIP;
+  if (!graphs && !g.vst && hipStreamCreateWithFlags(&g.vst, hipStreamNonBlocking) != hipSuccess)
     return SYLV_ERR_HIP;
   if (graphs) {
     // every segment up to max_iter is captured now, while no other work of the library runs:
@@ -1945,64 +1954,166 @@ static int group_segment(GroupRun &g, int seg, int k0, int k1, bool replay) {
   return 0;
 }
 
+// The end of one problem's solve: the symmetric core completed (Lyapunov CG), the state and
+// history read back, and, for a converged problem that verifies, its FP64 true residual. A true
+// residual that misses tol is left for a solve of its own (*again), which must not run while
+// the group still launches (the problem's stop flag would be cleared).
+static int group_finish(GroupRun &g, Ctx *c, double tol, int max_iter, double secs,
+                        sylv_result *r, bool *again) {
+  *again = false;
+  if (g.method == SYLV_METHOD_CG && g.sym) {
+    const Layout &L = c->L;
+    if (int e = launch_mirror(std::min<int64_t>(L.ldc, (int64_t)(max_iter + 1) * L.s), c->X,
+                              L.ldc, c->st))
+      return e;
+  }
+  const int st = end_solve(c, max_iter, secs, r);
+  if (st < 0) return st;
+  if (st == SYLV_OK && c->verify) {
+    double a = 0.0, rel = 0.0;
+    if (int e = true_residual(c, &a, &rel)) return e;
+    r->rel_res_true = rel;
+    *again = rel > tol;
+  }
+  return 0;
+}
+
 int group_solve(GroupRun &g, double tol, int max_iter, sylv_result *res) {
   const int n = (int)g.ctx.size();
   if (n < 1 || !res) return SYLV_ERR_INVALID;
   auto t0 = std::chrono::steady_clock::now();
+  auto secs = [&] {
+    return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  };
   Ctx *const *cs = reinterpret_cast<Ctx *const *>(g.ctx.data());
   for (int i = 0; i < n; ++i)
     if (int e = begin_solve(cs[i], tol, max_iter, g.method)) return e;
   const bool replay = g.graphs && g.graph_max_iter == max_iter;
-  if (!g.graphs)
-    if (int e = group_poll(g, 0)) return e;  // every problem starts in the launches
-  int steps = 0;  // iterations enqueued
-  for (int seg = 0; steps < max_iter; ++seg) {
-    const int k0 = seg * GROUP_SEG, k1 = std::min(max_iter, k0 + GROUP_SEG);
-    if (int e = group_segment(g, seg, k0, k1, replay)) return e;
-    steps = k1;
-    if (steps >= max_iter) break;
-    if (int e = group_poll(g, steps)) return e;
-    if (g.na == 0) break;
-  }
-  if (g.method == SYLV_METHOD_CG) {
-    // basis columns of the newest blocks still held only in the ring
-    if ((steps + 1) % LZ_RING != 0)
-      if (int e = launch_krylov_group_flush(g.kg, steps + 1, g.st)) return e;
-    if (g.sym)
-      for (int i = 0; i < n; ++i) {
-        const Layout &L = cs[i]->L;
-        if (int e = launch_mirror(std::min<int64_t>(L.ldc, (int64_t)(max_iter + 1) * L.s),
-                                  cs[i]->X, L.ldc, g.st))
-          return e;
+  // compacted launches: a problem that has left the launches is finished (state, history, true
+  // residual) by a second host thread on the side stream while this one keeps launching
+  std::vector<char> queued(n, 0), again(n, 0), running(n, 1);
+  std::vector<int> list(n);
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<int> todo;
+  bool closed = false;
+  int ferr = 0;
+  std::string fmsg;
+  int dev = 0;
+  HIPOK(hipGetDevice(&dev));
+  const bool side = !g.graphs && g.vst;
+  std::thread finisher;
+  if (side)
+    finisher = std::thread([&] {
+      if (hipSetDevice(dev) != hipSuccess) {
+        std::lock_guard<std::mutex> lk(mu);
+        ferr = SYLV_ERR_HIP;
       }
+      for (;;) {
+        int i;
+        {
+          std::unique_lock<std::mutex> lk(mu);
+          cv.wait(lk, [&] { return closed || !todo.empty(); });
+          if (todo.empty()) return;
+          i = todo.front();
+          todo.pop_front();
+          if (ferr) continue;
+        }
+        Ctx *c = cs[i];
+        c->st = c->kst = g.vst;
+        bool ag = false;
+        const int e = group_finish(g, c, tol, max_iter, secs(), &res[i], &ag);
+        c->st = c->kst = g.st;
+        again[i] = ag;
+        if (e) {
+          std::lock_guard<std::mutex> lk(mu);
+          ferr = e;
+          fmsg = sylv_last_error();
+        }
+      }
+    });
+  auto stop_finisher = [&] {
+    if (!side) return 0;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      closed = true;
+    }
+    cv.notify_all();
+    finisher.join();
+    if (ferr) note_error(fmsg.c_str());
+    return ferr;
+  };
+  auto run = [&]() -> int {
+    if (!g.graphs)
+      if (int e = group_poll(g, 0)) return e;  // every problem starts in the launches
+    int steps = 0;  // iterations enqueued
+    if (int e = group_segment(g, 0, 0, std::min(max_iter, GROUP_SEG), replay)) return e;
+    for (int seg = 0;; ++seg) {
+      steps = std::min(max_iter, (seg + 1) * GROUP_SEG);
+      if (steps >= max_iter) break;
+      if (int e = group_poll(g, steps)) return e;
+      if (g.na == 0) break;
+      if (side) {
+        HIPOK(hipMemcpyAsync(list.data(), g.list, sizeof(int) * g.na, hipMemcpyDeviceToHost,
+                             g.st));
+        HIPOK(hipStreamSynchronize(g.st));
+        std::fill(running.begin(), running.end(), 0);
+        for (int j = 0; j < g.na; ++j) running[list[j]] = 1;
+        {
+          std::lock_guard<std::mutex> lk(mu);
+          for (int i = 0; i < n; ++i)
+            if (!running[i] && !queued[i]) {
+              queued[i] = 1;
+              todo.push_back(i);
+            }
+        }
+        cv.notify_one();
+      }
+      if (int e = group_segment(g, seg + 1, steps, std::min(max_iter, steps + GROUP_SEG), replay))
+        return e;
+    }
+    // basis columns of the newest blocks still held only in the ring (the problems that were in
+    // the last launches; the others were written at the poll that removed them)
+    const KGroup &last = g.graphs ? g.kg : g.ka;
+    if (g.method == SYLV_METHOD_CG && (steps + 1) % LZ_RING != 0 && last.nsides > 0)
+      if (int e = launch_krylov_group_flush(last, steps + 1, g.st)) return e;
+    HIPOK(hipStreamSynchronize(g.st));
+    return 0;
+  };
+  const int e1 = run();
+  const int e2 = stop_finisher();
+  if (e1) return e1;
+  if (e2) return e2;
+  for (int i = 0; i < n; ++i) {
+    if (queued[i]) continue;
+    bool ag = false;
+    if (int e = group_finish(g, cs[i], tol, max_iter, secs(), &res[i], &ag)) return e;
+    again[i] = ag;
   }
-  HIPOK(hipStreamSynchronize(g.st));
-  const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  // verification as for a single solve: a converged iterate whose true residual misses tol is
+  // solved again alone with a lower recursive target
   int worst = 0;
   for (int i = 0; i < n; ++i) {
     Ctx *c = cs[i];
-    int st = end_solve(c, max_iter, secs, &res[i]);
-    if (st < 0) return st;
-    // verification as for a single solve: a converged iterate whose true residual misses tol
-    // is solved again alone with a lower recursive target
-    if (st == SYLV_OK && c->verify) {
-      double target = tol;
-      for (int round = 0;; ++round) {
-        double a = 0.0, r = 0.0;
-        if (int e = true_residual(c, &a, &r)) return e;
-        if (r <= tol || round == 2) {
-          if (r > tol) c->status = SYLV_NOT_CONVERGED;
-          res[i].status = c->status;
-          res[i].rel_res_true = r;
-          st = c->status;
-          break;
-        }
+    int st = res[i].status;
+    if (again[i]) {
+      double target = tol, r = res[i].rel_res_true;
+      for (int round = 1;; ++round) {
         target *= std::min(0.5, 0.5 * tol / r);
         st = g.method == SYLV_METHOD_CG ? cg_body(c, target, max_iter, &res[i])
                                         : bicg_body(c, target, max_iter, &res[i]);
         if (st != SYLV_OK) break;
+        double a = 0.0;
+        if (int e = true_residual(c, &a, &r)) return e;
+        res[i].rel_res_true = r;
+        if (r <= tol || round == 2) {
+          if (r > tol) c->status = SYLV_NOT_CONVERGED;
+          st = c->status;
+          break;
+        }
       }
     }
+    res[i].status = st;
     worst = std::max(worst, st);
   }
   return worst;

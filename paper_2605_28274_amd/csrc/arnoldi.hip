@@ -261,6 +261,7 @@ int launch_krylov_group_compact(const KGroup &g, const KGroup &act, int *counts,
 }
 
 int launch_krylov_group(const KGroup &g, int jb, double closure_tol, hipStream_t st) {
+  if (g.nsides < 1) return 0;  // no basis in the launches
   switch (g.s) {
 #define CASE(SS) \
   case SS: return krylov_group_step_##SS(g, jb, closure_tol, st);
@@ -271,7 +272,7 @@ int launch_krylov_group(const KGroup &g, int jb, double closure_tol, hipStream_t
 }
 
 int launch_krylov_group_flush(const KGroup &g, int nblocks, hipStream_t st) {
-  if (!g.lanczos) return 0;
+  if (!g.lanczos || g.nsides < 1) return 0;
   switch (g.s) {
 #define CASE(SS) \
   case SS: return krylov_group_flush_##SS(g, nblocks, st);

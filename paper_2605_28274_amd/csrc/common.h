@@ -721,6 +721,7 @@ struct GroupRun {
   int na = 0;                // problems in the launches (compacted form)
   int64_t min_ldc = 0;
   double closure_tol = 0.0;
+  hipStream_t vst = nullptr; // compacted form: problems that left are finished on this stream
   bool graphs = false;       // replayed graphs over the full tables; else compacted launches
   int graph_max_iter = -1;
   std::vector<hipGraphExec_t> exec;  // per segment

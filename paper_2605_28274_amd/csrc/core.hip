@@ -683,6 +683,7 @@ int launch_bicg_update(int s, int p, double *X, double *R, double *P, const doub
 
 int launch_cg_group(int s, bool sym, int p, int k, const CoreInst *tab, const int *list, int n,
                     hipStream_t st) {
+  if (n < 1) return 0;  // no problem in the launches
   const unsigned g = cg_grid(s, p + s);
   const dim3 grid(g, (unsigned)n);
   switch (s) {
@@ -708,6 +709,7 @@ int launch_cg_group(int s, bool sym, int p, int k, const CoreInst *tab, const in
 
 int launch_bicg_group_s(int s, int p, int k, const CoreInst *tab, const int *list, int n,
                         hipStream_t st) {
+  if (n < 1) return 0;  // no problem in the launches
   const int q = p + s;
   bicg_s_group<<<dim3(grid_q(q), (unsigned)n), TPB, 0, st>>>(tab, list, s, q, k);
   HIPOK(hipGetLastError());
@@ -716,6 +718,7 @@ int launch_bicg_group_s(int s, int p, int k, const CoreInst *tab, const int *lis
 
 int launch_bicg_group_omega(int s, int p, const CoreInst *tab, const int *list, int n,
                             hipStream_t st) {
+  if (n < 1) return 0;  // no problem in the launches
   const int q = p + 2 * s;
   bicg_omega_group<<<dim3(grid_q(q), (unsigned)n), TPB, 0, st>>>(tab, list, q);
   HIPOK(hipGetLastError());
@@ -724,6 +727,7 @@ int launch_bicg_group_omega(int s, int p, const CoreInst *tab, const int *list, 
 
 int launch_bicg_group_update(int s, int p, int k, const CoreInst *tab, const int *list, int n,
                              hipStream_t st) {
+  if (n < 1) return 0;  // no problem in the launches
   const int q = p + 2 * s;
   const unsigned g = grid_q(q);
   bicg_update_group<<<dim3(g, (unsigned)n), TPB, 0, st>>>(tab, list, s, q, k, (int)g, 2 * NBLK);

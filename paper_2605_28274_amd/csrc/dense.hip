@@ -729,6 +729,7 @@ int launch_core_op(int s, int p, const double *H, const double *G, const double 
 
 int launch_core_op_group(int s, int p, int which, const CoreInst *tab, const int *list, int n,
                          hipStream_t st) {
+  if (n < 1) return 0;  // no problem in the launches
   const int T = (p + s + BM - 1) / BM;
   core_op_group<<<dim3((unsigned)((T * T + 1) / 2), (unsigned)n), 256, 0, st>>>(tab, list, s, p,
                                                                                  T, which);

@@ -2206,9 +2206,8 @@ int sylv_get_factors(void *ctx, double *V, int64_t ldv, double *Xc, int64_t ldx,
       if (L.fp32)
         return launch_widen(sd.rows, rj, static_cast<const float *>(sd.basis), L.ldb, dst, ldd,
                             c->st);
-      HIPOK(hipMemcpy2DAsync(dst, ldd * 8, sd.basis, L.ldb * 8, rj * 8, sd.rows,
-                             hipMemcpyDeviceToDevice, c->st));
-      return 0;
+      return launch_copy_rows(sd.rows, rj, static_cast<const double *>(sd.basis), L.ldb, dst,
+                              ldd, c->st);
     };
     int e;
     if (V && (e = copy_basis(V + off, ldv, cj->sv))) return e;

@@ -950,6 +950,9 @@ int launch_orth_small(int q, const double *G, int64_t ldg, double *T, int64_t ld
                       double *dinfo, hipStream_t st);
 int launch_copy_block(int rows, int cols, double alpha, const double *src, int64_t lds, bool trans,
                       double *dst, int64_t ldd, hipStream_t st);
+// dst (rows x cols, row stride ldd) = src (row stride lds), FP64 (refine.hip).
+int launch_copy_rows(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
+                     int64_t ldd, hipStream_t st);
 int launch_diag_fill(int k, double v, double *dst, int64_t ldd, hipStream_t st);
 int launch_axpy_narrow(int64_t rows, int q, double alpha, const double *F, int64_t ldf, double *Y,
                        int64_t ldy, hipStream_t st);

@@ -157,6 +157,31 @@ __global__ __launch_bounds__(TPB) void copy_block_kernel(int rows, int cols, dou
           alpha * (trans ? src[(int64_t)j * lds + i] : src[(int64_t)i * lds + j]);
 }
 
+// dst (rows x cols, ldd) = src (lds): rows strided over the workgroups, each thread four
+// elements of a row at a time (their loads issued together).
+__global__ __launch_bounds__(TPB) void copy_rows_kernel(int64_t rows, int64_t cols,
+                                                        const double *__restrict__ src,
+                                                        int64_t lds, double *__restrict__ dst,
+                                                        int64_t ldd) {
+  for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
+    const double *a = src + i * lds;
+    double *b = dst + i * ldd;
+    for (int64_t j0 = threadIdx.x; j0 < cols; j0 += 4 * TPB) {
+      double v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + u * TPB;
+        v[u] = j < cols ? a[j] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t j = j0 + u * TPB;
+        if (j < cols) b[j] = v[u];
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(TPB) void diag_fill_kernel(int k, double v, double *dst, int64_t ldd) {
   const int i = threadIdx.x;
   if (i < k) dst[(int64_t)i * ldd + i] = v;
@@ -275,6 +300,15 @@ int launch_copy_block(int rows, int cols, double alpha, const double *src, int64
   if (rows <= 0 || cols <= 0) return 0;
   copy_block_kernel<<<(unsigned)std::min(rows, 2048), TPB, 0, st>>>(rows, cols, alpha, src, lds,
                                                                     trans ? 1 : 0, dst, ldd);
+  HIPOK(hipGetLastError());
+  return 0;
+}
+
+int launch_copy_rows(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
+                     int64_t ldd, hipStream_t st) {
+  if (rows <= 0 || cols <= 0) return 0;
+  copy_rows_kernel<<<(unsigned)std::min<int64_t>(rows, 8192), TPB, 0, st>>>(rows, cols, src, lds,
+                                                                            dst, ldd);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -133,7 +133,7 @@ __device__ __forceinline__ bool halted(const ArTab &P, const DevState *,
 // Rows a thread handles at once in the SpMM kernels (sliced ELLPACK): more loads in flight for
 // narrow blocks.
 template <int S>
-constexpr int spmm_nr() { return S == 1 ? 4 : S == 2 ? 2 : 1; }
+constexpr int spmm_nr() { return S == 2 ? 2 : 1; }
 
 template <int S, typename T, class PS>
 __global__ __launch_bounds__(TPB) void spmm_pair(PS P, const DevState *ds) {
@@ -1087,26 +1087,28 @@ __device__ __forceinline__ void lz_spmm_body(const PS &P, int bid, int jb) {
   double red[S * S + 1];
 #pragma unroll
   for (int i = 0; i < S * S + 1; ++i) red[i] = 0.0;
-  // one row's local three-term update and its partials
-  auto finish = [&](int64_t r, double (&acc)[S]) {
+  // one row's local three-term update and its partials, from the row's entries of blocks j-1
+  // and j (loaded before the row's SpMM, so that their latency overlaps it)
+  auto load_v = [&](int64_t r, double (&vp)[S], double (&vj)[S]) {
+    const T *p = static_cast<const T *>(A.pprev) + r * S;  // block j-1
+    const T *q = static_cast<const T *>(A.pin) + r * S;    // block j
+#pragma unroll
+    for (int u = 0; u < S; ++u) {
+      vp[u] = jb > 0 ? (double)p[u] : 0.0;
+      vj[u] = (double)q[u];
+    }
+  };
+  auto finish = [&](int64_t r, double (&acc)[S], const double (&vp)[S], const double (&vj)[S]) {
 #pragma unroll
     for (int t = 0; t < S; ++t) red[S * S] = fma(acc[t], acc[t], red[S * S]);
-    if (jb > 0) {
-      const T *vp = static_cast<const T *>(A.pprev) + r * S;  // block j-1
 #pragma unroll
-      for (int u = 0; u < S; ++u) {
-        const double vu = (double)vp[u];
+    for (int u = 0; u < S; ++u)
 #pragma unroll
-        for (int t = 0; t < S; ++t) acc[t] = fma(-vu, hup[u * S + t], acc[t]);
-      }
-    }
-    const T *vj = static_cast<const T *>(A.pin) + r * S;
+      for (int t = 0; t < S; ++t) acc[t] = fma(-vp[u], hup[u * S + t], acc[t]);
 #pragma unroll
-    for (int a = 0; a < S; ++a) {
-      const double va = (double)vj[a];
+    for (int a = 0; a < S; ++a)
 #pragma unroll
-      for (int t = 0; t < S; ++t) red[a * S + t] = fma(va, acc[t], red[a * S + t]);
-    }
+      for (int t = 0; t < S; ++t) red[a * S + t] = fma(vj[a], acc[t], red[a * S + t]);
 #pragma unroll
     for (int t = 0; t < S; ++t) A.U[r * S + t] = acc[t];
   };
@@ -1116,24 +1118,28 @@ __device__ __forceinline__ void lz_spmm_body(const PS &P, int bid, int jb) {
     for (int64_t r0 = (int64_t)lb * TPB + threadIdx.x; r0 < A.rows; r0 += NR * step) {
       int64_t r[NR];
       bool ok[NR];
+      double vp[NR][S], vj[NR][S];
 #pragma unroll
       for (int i = 0; i < NR; ++i) {
         r[i] = r0 + i * step;
         ok[i] = r[i] < A.rows;
+        load_v(ok[i] ? r[i] : 0, vp[i], vj[i]);
       }
       double acc[NR][S];
       sell_rows<NR, S>(A.sell, r, ok, static_cast<const T *>(A.pin), S, acc);
 #pragma unroll
       for (int i = 0; i < NR; ++i)
-        if (ok[i]) finish(r[i], acc[i]);
+        if (ok[i]) finish(r[i], acc[i], vp[i], vj[i]);
     }
   } else {
     for (int64_t r0 = (int64_t)lb * TPB; r0 < A.rows; r0 += (int64_t)A.nb * TPB) {
       const int64_t r1 = (r0 + TPB < A.rows) ? r0 + TPB : A.rows;
       const int64_t r = r0 + threadIdx.x;
+      double vp[S], vj[S];
+      load_v(r < r1 ? r : r0, vp, vj);
       double acc[S];
       spmm_rows<S>(r0, r1, A.rp, A.ci, A.val, static_cast<const T *>(A.pin), S, acc);
-      if (r < r1) finish(r, acc);
+      if (r < r1) finish(r, acc, vp, vj);
     }
   }
   __shared__ double lds[16 * (S * S + 1)];

@@ -67,7 +67,7 @@ enum { SYLV_FP64 = 0, SYLV_MIXED_FP32 = 1 };
 
 /* Compressed sparse row matrix: rows x rows, int32 row_ptr (rows + 1 entries, row_ptr[0] = 0)
  * and col_idx (nnz entries, sorted and unique within each row, 0 <= col < rows), float64
- * values (nnz). Device pointers, borrowed until sylv_destroy. */
+ * values (nnz); rows < 2^31 and nnz < 2^31. Device pointers, borrowed until sylv_destroy. */
 typedef struct {
   int64_t rows;
   int64_t nnz;
@@ -344,7 +344,8 @@ int sylv_sell_spmm(const sylv_csr *A, const void *sell, int64_t s, const double 
 /* Transpose of a square CSR matrix (rows x rows, nnz entries) into caller buffers:
  * out_row_ptr (rows + 1), out_col_idx (nnz), out_values (nnz). The result is canonical
  * (sorted column indices), so it is bit-identical to any other exact transpose. scratch:
- * device buffer of at least sylv_csr_transpose_scratch_bytes(rows) bytes. */
+ * device buffer of at least sylv_csr_transpose_scratch_bytes(rows) bytes (0 for rows < 0 or
+ * rows >= 2^31). */
 size_t sylv_csr_transpose_scratch_bytes(int64_t rows);
 int sylv_csr_transpose(const sylv_csr *A, int32_t *out_row_ptr, int32_t *out_col_idx,
                        double *out_values, void *scratch, void *stream);
@@ -368,10 +369,26 @@ int sylv_csr_transpose_noalloc(const sylv_csr *A, int32_t *out_row_ptr, int32_t 
 /* C (M x N, ldc) = alpha * op(A) op(B) + beta * C in FP64 on FP64 MFMA, with element strides:
  * A(i,k) = A[i*a_rs + k*a_cs], B(k,j) = B[k*b_rs + j*b_cs] (a transpose is a swap of the two
  * strides). The dense contraction behind the Gram products of the residual evaluation and the
- * core operator eq. (3.11). beta == 0 ignores C's old contents. */
+ * core operator eq. (3.11). beta == 0 ignores C's old contents. M, N, K < 2^31. */
 int sylv_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t a_rs,
                int64_t a_cs, const double *B, int64_t b_rs, int64_t b_cs, double beta, double *C,
                int64_t ldc, void *stream);
+
+/* C (M x N, ldc) = A^T B, or C += A^T B with accumulate != 0, for row-major operands A (K x M,
+ * lda) and B (K x N, ldb) read down their K rows: the tall-skinny Gram products of the stacked
+ * factors that the true-residual evaluation forms (inner products of Section 2 between tall
+ * factors, eq. (3.10)), on FP64 matrix cores. K >= 1; lda and ldb are multiples of 8 with
+ * lda >= M and ldb >= N rounded up to a multiple of 64 (the columns up to there are read; their
+ * values only reach entries of C that are not written). symmetric != 0 (M == N, B == A): only
+ * the tiles on and below the diagonal are computed and the upper triangle of C is then copied
+ * from the lower one. work: device scratch of work_bytes bytes (8-byte aligned; NULL allowed)
+ * for partial tiles; with sylv_gram_work_bytes(M, N, K) bytes every product runs in its
+ * fastest form (large Grams on 128 x 128 tiles, split over K where the output has few tiles),
+ * with less some run with fewer workgroups. Waits for the product. */
+size_t sylv_gram_work_bytes(int64_t M, int64_t N, int64_t K);
+int sylv_gram(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+              int64_t ldb, int symmetric, int accumulate, double *C, int64_t ldc, void *work,
+              size_t work_bytes, void *stream);
 
 #ifdef __cplusplus
 }

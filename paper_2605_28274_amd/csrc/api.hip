@@ -50,6 +50,7 @@ struct Layout {
   size_t off_Om, off_Zb, off_Yb, off_Eb, off_Fb, off_Pp, off_Qp, off_sa, off_sb, off_sc2, off_sd,
       off_sk, off_sT, off_tn, off_atrp, off_atci, off_atval, off_atscr, off_GL, off_GN, off_Mc,
       off_T1, off_Es, off_rinfo, off_gpart;
+  size_t gpart_cap = 0;  // doubles of split-K / stream-K partial tiles of the residual Grams
   // split-BF16 residual Grams: packed chunk, column maxima / exponents, FP32 partials
   int gram_prec = 0;
   int64_t cpad = 0;
@@ -60,7 +61,6 @@ struct Layout {
 constexpr int NLD = 64;         // row stride (doubles) of the narrow panels of the refinement
 constexpr int64_t COMPRESS_LMAX = 256;  // columns of the randomized range at most
 constexpr int REFINE_CAP = 4;   // correction solves at most
-constexpr size_t GPART_CAP = (size_t)1024 * 64 * 64;  // split-K partial tiles of the Grams
 
 size_t bump(size_t &cur, size_t bytes) {
   const size_t o = (cur + ALIGN - 1) / ALIGN * ALIGN;
@@ -86,7 +86,9 @@ int extra_cores(int m) {
 }
 
 int check_csr_header(const sylv_csr &M, int64_t rows) {
-  if (M.rows != rows || M.nnz < 0 || M.nnz >= ((int64_t)1 << 31)) return SYLV_ERR_INVALID;
+  if (M.rows != rows || M.rows < 0 || M.rows > INT32_MAX || M.nnz < 0 ||
+      M.nnz >= ((int64_t)1 << 31))
+    return SYLV_ERR_INVALID;
   if (!M.row_ptr || (M.nnz > 0 && (!M.col_idx || !M.values))) return SYLV_ERR_INVALID;
   return 0;
 }
@@ -95,6 +97,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   if (!pb || !op) return SYLV_ERR_INVALID;
   L.child = child ? 1 : 0;
   if (pb->n <= 0 || pb->m <= 0 || pb->s < 1 || pb->s > SYLV_MAX_S) return SYLV_ERR_INVALID;
+  // column indices are int32: at most 2^31 - 1 rows (this also keeps every size below in int64)
+  if (pb->n > INT32_MAX || pb->m > INT32_MAX) return SYLV_ERR_INVALID;
   if (pb->s > std::min(pb->n, pb->m)) return SYLV_ERR_INVALID;
   if (pb->lyapunov && pb->n != pb->m) return SYLV_ERR_INVALID;
   if (op->max_iter < 1 || !known_method(op->method)) return SYLV_ERR_INVALID;
@@ -270,7 +274,8 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
     L.ldE = round_up(L.rmax + 2 * L.s, 64) +
             L.refine_max * round_up(L.child_rmax + 2 * L.refine_q, 64) + 64;
     L.off_Es = bump(cur, (size_t)L.rc_rows * L.ldE * 8);
-    L.off_gpart = bump(cur, (size_t)GPART_CAP * 8);
+    L.gpart_cap = gram_part_doubles(L.cmax, L.rc_rows);
+    L.off_gpart = bump(cur, L.gpart_cap * 8);
     L.gram_prec = op->gram_precision;
     if (L.gram_prec > 0) {
       L.cpad = bf16_pack_width(L.cmax);
@@ -987,7 +992,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
           const char *pb = B.ptr + (B.rowed ? r0 * B.ld * B.esz : 0);
           prof_begin(P->sc, st);
           if ((ee = launch_gram(A.cols, B.cols, nr, pa, A.f32, A.ld, pb, B.f32, B.ld, beta,
-                                G + offs[a] * ldG + offs[b], ldG, a == b, st, gpart, GPART_CAP)))
+                                G + offs[a] * ldG + offs[b], ldG, a == b, st, gpart, PL.gpart_cap)))
             return ee;
           prof_end(P->sc, FAM_RES_GRAM,
                    (double)nr * (a == b ? A.cols * A.esz : A.cols * A.esz + B.cols * B.esz), fl,
@@ -1029,7 +1034,7 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
   }
   // ||R||^2 = <G_L M, M G_N>: G_L M as A^T B on the symmetric Gram; M G_N into G_L's storage
   if ((e = launch_gram(cL, cN, cL, GL, false, ldG, Mc, false, ldG, 0.0, T1, ldG, false, st, gpart,
-                       GPART_CAP)))
+                       PL.gpart_cap)))
     return e;
   if ((e = launch_gemm_nn(cL, cN, cN, Mc, ldG, GN, ldG, GL, ldG, st))) return e;
   if ((e = launch_dot(cL, cN, T1, ldG, GL, ldG, P->dots, P->sc, st))) return e;
@@ -2256,11 +2261,36 @@ int sylv_spmm(const sylv_csr *A, int64_t s, const double *X, int64_t ldx, double
   return launch_spmm((int)s, A->rows, A->row_ptr, A->col_idx, A->values, X, ldx, Y, ldy, st);
 }
 
+size_t sylv_gram_work_bytes(int64_t M, int64_t N, int64_t K) {
+  if (M < 1 || N < 1 || K < 1 || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return 0;
+  return gram_part_doubles(std::max(M, N), K) * 8;
+}
+
+int sylv_gram(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda, const double *B,
+              int64_t ldb, int symmetric, int accumulate, double *C, int64_t ldc, void *work,
+              size_t work_bytes, void *stream) {
+  if (M < 0 || N < 0 || K < 1 || M > INT32_MAX || N > INT32_MAX || K > INT32_MAX)
+    return SYLV_ERR_INVALID;
+  if (M == 0 || N == 0) return 0;
+  if (!A || !B || !C || ldc < N || (symmetric && M != N)) return SYLV_ERR_INVALID;
+  if (lda < round_up(M, 64) || ldb < round_up(N, 64) || lda % 8 || ldb % 8)
+    return SYLV_ERR_INVALID;
+  if (work && reinterpret_cast<uintptr_t>(work) % 8) return SYLV_ERR_INVALID;
+  hipStream_t st = reinterpret_cast<hipStream_t>(stream);
+  int e = launch_gram(M, N, K, A, false, lda, B, false, ldb, accumulate ? 1.0 : 0.0, C, ldc,
+                      symmetric != 0, st, static_cast<double *>(work), work ? work_bytes / 8 : 0);
+  if (e) return e;
+  if (symmetric && (e = launch_mirror(M, C, ldc, st))) return e;
+  HIPOK(hipStreamSynchronize(st));
+  return 0;
+}
+
 int sylv_dgemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, int64_t a_rs,
                int64_t a_cs, const double *B, int64_t b_rs, int64_t b_cs, double beta, double *C,
                int64_t ldc, void *stream) {
   if (M < 0 || N < 0 || K < 0 || ldc < N || (M > 0 && N > 0 && (!C || (K > 0 && (!A || !B)))))
     return SYLV_ERR_INVALID;
+  if (M > INT32_MAX || N > INT32_MAX || K > INT32_MAX) return SYLV_ERR_INVALID;
   hipStream_t st = reinterpret_cast<hipStream_t>(stream);
   int e = launch_gemm(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc, st);
   if (e) return e;

@@ -836,7 +836,10 @@ int launch_gemm(int64_t M, int64_t N, int64_t K, double alpha, const double *A, 
 // `lower` computes the tiles on and below the diagonal only (M == N; launch_mirror completes).
 // A and B are float (a_fp32 / b_fp32) or double; row strides multiples of 8 elements.
 // part (part_cap doubles, may be null): scratch that lets launches with few output tiles split
-// K over several workgroups (deterministic: slices summed in order).
+// K over several workgroups (deterministic: slices summed in order). FP64 Grams of at least 256
+// tiles of 128 x 128 run on 128 x 128 tiles when part holds their stream-K slots
+// (gram_part_doubles gives a size that does for every Gram of up to that many columns).
+size_t gram_part_doubles(int64_t max_cols, int64_t rows);
 int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
                 const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
                 bool lower, hipStream_t st, double *part = nullptr, size_t part_cap = 0);

@@ -20,6 +20,7 @@ constexpr int LD = BM + 1;  // +1 pad: fewer bank conflicts on the transposed fi
 static_assert(BM == BN, "one LDS slab shape serves both operands");
 
 typedef double v4d __attribute__((ext_vector_type(4)));
+typedef double v2d __attribute__((ext_vector_type(2)));
 
 struct WaveAcc {
   v4d c[2][2];
@@ -524,15 +525,18 @@ __global__ __launch_bounds__(256, 2) void gram_stream_kernel(
 }
 
 // The remaining tiles cut by chunk boundaries: boundary wb (between chunks wb and wb + 1)
-// handles the tile it falls in unless an earlier boundary falls in the same tile; 16 workgroups
-// per boundary, one element per thread. Tile indices count from dp.
+// handles the tile it falls in unless an earlier boundary falls in the same tile; TW * TW / 256
+// workgroups per boundary (TW the tile width), one element per thread. Tile indices count from
+// dp.
+template <int TW>
 __global__ __launch_bounds__(256) void gram_stream_fix_kernel(const GramSeq sq, int64_t M,
                                                               int64_t N, int64_t nsl, int64_t dp,
                                                               int64_t c,
                                                               const double *__restrict__ part,
                                                               double beta, double *__restrict__ C,
                                                               int64_t ldc) {
-  const int wb = (int)(blockIdx.x / 16), sub = (int)(blockIdx.x % 16);
+  constexpr int SUBS = TW * TW / 256;
+  const int wb = (int)(blockIdx.x / SUBS), sub = (int)(blockIdx.x % SUBS);
   const int64_t pb = (int64_t)(wb + 1) * c, total = (sq.count() - dp) * nsl;
   if (pb >= total || pb % nsl == 0) return;
   const int64_t tr = pb / nsl, ts = tr * nsl;
@@ -542,14 +546,186 @@ __global__ __launch_bounds__(256) void gram_stream_fix_kernel(const GramSeq sq, 
   double v = 0.0;
   for (int w = w0; w <= w1; ++w) {
     const int slot = 2 * w + ((int64_t)w * c / nsl == tr ? 0 : 1);
-    v += part[(size_t)slot * (BM * BN) + e];
+    v += part[(size_t)slot * (TW * TW) + e];
   }
   int I, J;
   sq.tile(dp + tr, I, J);
-  const int64_t gi = (int64_t)I * BM + e / BN, gj = (int64_t)J * BN + e % BN;
+  const int64_t gi = (int64_t)I * TW + e / TW, gj = (int64_t)J * TW + e % TW;
   if (gi < M && gj < N) {
     double *cp = C + gi * ldc + gj;
     *cp = (beta == 0.0) ? v : *cp + v;
+  }
+}
+
+// ---- 128 x 128 tiles: the large FP64 Grams ----
+// Each 256-thread workgroup owns a 128 x 128 output tile, each wave a 64 x 64 quarter (4 x 4
+// MFMA tiles, sixteen accumulators), two workgroups per CU. K runs in slabs of 16 rows through
+// two LDS buffers: at slab t, after one barrier, the waves store slab t + 1 (loaded into
+// registers during slab t - 1) into the free buffer, issue the global loads of slab t + 2, and
+// run the slab's 64 MFMAs per wave on the current buffer. Per flop this reads half the LDS and
+// L2 bytes of the 64 x 64 tiles and meets a barrier half as often. FP64 operands only.
+constexpr int TW2 = 128, BK2 = 16;
+constexpr int LW2 = TW2 + 16;  // slab row of 128 doubles, padded by 32 banks: the two rows
+                               // that one LDS pass of an MFMA operand read meets do not collide
+constexpr int GRAM_WIDE_WG = 512;  // two workgroups per CU (72 KB of LDS each)
+
+struct Smem2 {
+  double A[2][BK2][LW2];
+  double B[2][BK2][LW2];
+};
+
+struct Acc2 {
+  v4d c[4][4];
+};
+
+// MFMA operand layout as in mma_slab; each step of 4 rows reads its operands, then runs its 16
+// MFMAs (the other workgroup on the CU covers the LDS latency).
+__device__ __forceinline__ void mma2(const double (&As)[BK2][LW2], const double (&Bs)[BK2][LW2],
+                                     Acc2 &acc, int wm, int wn) {
+  const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+  const double *pa = &As[lk][wm * 64 + li], *pb = &Bs[lk][wn * 64 + li];
+#pragma unroll
+  for (int q = 0; q < BK2 / 4; ++q) {
+    double a[4], b[4];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      a[t] = pa[q * 4 * LW2 + t * 16];
+      b[t] = pb[q * 4 * LW2 + t * 16];
+    }
+#pragma unroll
+    for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+      for (int tj = 0; tj < 4; ++tj)
+        acc.c[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc.c[ti][tj], 0, 0, 0);
+  }
+}
+
+__device__ __forceinline__ void zero_acc2(Acc2 &acc) {
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc.c[ti][tj] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+template <typename F>
+__device__ __forceinline__ void for_each_acc2(const Acc2 &acc, int wm, int wn, F f) {
+  const int lane = threadIdx.x & 63;
+  const int col = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        f(wm * 64 + ti * 16 + v * 4 + rq, wn * 64 + tj * 16 + col, acc.c[ti][tj][v]);
+}
+
+// acc += A(:, i0 ..)^T B(:, j0 ..) over K slabs [a, b) of tile (i0, j0); the slab past the last
+// full one holds the last K % BK2 rows, zero-filled past K.
+__device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, int64_t j0,
+                                            int64_t K, const double *__restrict__ A, int64_t lda,
+                                            const double *__restrict__ B, int64_t ldb, int64_t a,
+                                            int64_t b, int wm, int wn) {
+  const int64_t nfull = K / BK2;
+  const int64_t bf = b < nfull ? b : nfull;
+  if (bf > a) {
+    // one thread's share of a slab: rows threadIdx.x / 64 + 4 u, the column pair
+    // 2 (threadIdx.x % 64) (a wave reads whole 1 KB slab rows). A column pair at or past the
+    // leading dimension reads column 0 instead: in bounds, and it only feeds outputs that are
+    // not stored.
+    const int kr = threadIdx.x >> 6, c = 2 * (threadIdx.x & 63);
+    const double *pa = A + (i0 + c < lda ? i0 + c : 0) + kr * lda;
+    const double *pb = B + (j0 + c < ldb ? j0 + c : 0) + kr * ldb;
+    v2d ra[BK2 / 4], rb[BK2 / 4];
+    auto load = [&](int64_t l) {
+#pragma unroll
+      for (int u = 0; u < BK2 / 4; ++u) {
+        ra[u] = *reinterpret_cast<const v2d *>(pa + (l + 4 * u) * lda);
+        rb[u] = *reinterpret_cast<const v2d *>(pb + (l + 4 * u) * ldb);
+      }
+    };
+    auto store = [&](int buf) {
+#pragma unroll
+      for (int u = 0; u < BK2 / 4; ++u) {
+        *reinterpret_cast<v2d *>(&sm.A[buf][kr + 4 * u][c]) = ra[u];
+        *reinterpret_cast<v2d *>(&sm.B[buf][kr + 4 * u][c]) = rb[u];
+      }
+    };
+    const int64_t nsl = bf - a;
+    load(a * BK2);
+    __syncthreads();  // earlier users of both buffers are done
+    store(0);
+    load((a + (nsl > 1 ? 1 : 0)) * BK2);
+    for (int64_t t = 0; t < nsl; ++t) {
+      __syncthreads();  // slab t is in buffer t % 2 for every wave; the other buffer is free
+      const int cur = (int)(t & 1);
+      if (t + 1 < nsl) {
+        store(cur ^ 1);
+        load((a + (t + 2 < nsl ? t + 2 : nsl - 1)) * BK2);
+      }
+      mma2(sm.A[cur], sm.B[cur], acc, wm, wn);
+    }
+  }
+  if (b > nfull) {
+    const int64_t kb = nfull * BK2;
+    __syncthreads();
+    for (int e = threadIdx.x; e < BK2 * TW2; e += 256) {
+      const int kk = e / TW2, ii = e % TW2;
+      const bool in = kb + kk < K;
+      sm.A[0][kk][ii] = (in && i0 + ii < lda) ? A[(kb + kk) * lda + i0 + ii] : 0.0;
+      sm.B[0][kk][ii] = (in && j0 + ii < ldb) ? B[(kb + kk) * ldb + j0 + ii] : 0.0;
+    }
+    __syncthreads();
+    mma2(sm.A[0], sm.B[0], acc, wm, wn);
+  }
+}
+
+// Stream-K schedule as gram_stream_kernel's, over 128 x 128 tiles (partial slots of 128 x 128).
+__global__ __launch_bounds__(256, 2) void gram_wide_kernel(
+    const GramSeq sq, int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
+    const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
+    int64_t nsl, int64_t dp, int64_t c, int nchunks, double *__restrict__ part) {
+  const int G = (int)gridDim.x, per = G >> 3;
+  const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
+  __shared__ Smem2 sm;
+  const int wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
+  auto store_c = [&](const Acc2 &acc, int64_t i0, int64_t j0) {
+    for_each_acc2(acc, wm, wn, [&](int ii, int jj, double v) {
+      const int64_t gi = i0 + ii, gj = j0 + jj;
+      if (gi < M && gj < N) {
+        double *cp = C + gi * ldc + gj;
+        *cp = (beta == 0.0) ? v : *cp + v;
+      }
+    });
+  };
+  for (int64_t t = w; t < dp; t += G) {
+    int I, J;
+    sq.tile(t, I, J);
+    const int64_t i0 = (int64_t)I * TW2, j0 = (int64_t)J * TW2;
+    Acc2 acc;
+    zero_acc2(acc);
+    gram_piece2(sm, acc, i0, j0, K, A, lda, B, ldb, 0, nsl, wm, wn);
+    store_c(acc, i0, j0);
+  }
+  if (w >= nchunks) return;
+  const int64_t total = (sq.count() - dp) * nsl;
+  const int64_t c0 = (int64_t)w * c, c1 = (c0 + c < total) ? c0 + c : total;
+  for (int64_t pos = c0; pos < c1;) {
+    const int64_t tr = pos / nsl, ts = tr * nsl;
+    const int64_t a = pos - ts, b = ((c1 < ts + nsl) ? c1 : ts + nsl) - ts;
+    int I, J;
+    sq.tile(dp + tr, I, J);
+    const int64_t i0 = (int64_t)I * TW2, j0 = (int64_t)J * TW2;
+    Acc2 acc;
+    zero_acc2(acc);
+    gram_piece2(sm, acc, i0, j0, K, A, lda, B, ldb, a, b, wm, wn);
+    if (a == 0 && b == nsl) {
+      store_c(acc, i0, j0);
+    } else {
+      double *pt = part + (size_t)(2 * w + (pos == c0 ? 0 : 1)) * (TW2 * TW2);
+      for_each_acc2(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * TW2 + jj] = v; });
+    }
+    pos = ts + b;
   }
 }
 
@@ -758,6 +934,39 @@ int launch_gemm_nn(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda
   return 0;
 }
 
+// Stream-K launch of gram_wide_kernel when its partial slots fit (two per stream-K chunk, one
+// chunk per workgroup); returns 1 when it did not launch.
+static int launch_gram_wide(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
+                            const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
+                            bool lower, hipStream_t st, double *part, size_t part_cap) {
+  const int64_t TM = (M + TW2 - 1) / TW2, TN = (N + TW2 - 1) / TW2;
+  const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
+  const int64_t G = GRAM_WIDE_WG, nsl = (K + BK2 - 1) / BK2, dp = tiles / G * G;
+  const int64_t total = (tiles - dp) * nsl;
+  const int64_t c = std::max<int64_t>((total + G - 1) / G, 4);
+  const int64_t nchunks = (total + c - 1) / c;
+  if ((size_t)(2 * nchunks) * (TW2 * TW2) > part_cap) return 1;
+  const GramSeq sq{(int)TM, (int)TN, lower ? 1 : 0};
+  gram_wide_kernel<<<(unsigned)G, 256, 0, st>>>(sq, M, N, K, A, lda, B, ldb, beta, C, ldc, nsl,
+                                                dp, c, (int)nchunks, part);
+  HIPOK(hipGetLastError());
+  if (nchunks > 1) {
+    gram_stream_fix_kernel<TW2><<<(unsigned)(nchunks - 1) * (TW2 * TW2 / 256), 256, 0, st>>>(
+        sq, M, N, nsl, dp, c, part, beta, C, ldc);
+    HIPOK(hipGetLastError());
+  }
+  return 0;
+}
+
+// FP64 Grams of at least this many 128 x 128 tiles take gram_wide_kernel
+constexpr int64_t GRAM_WIDE_MIN_TILES = 256;
+
+size_t gram_part_doubles(int64_t max_cols, int64_t rows) {
+  // the wide form's slots for a full round of workgroups where its Grams can occur
+  return (max_cols >= 2048 && rows >= 4096) ? (size_t)2 * GRAM_WIDE_WG * TW2 * TW2
+                                            : (size_t)1024 * BM * BN;
+}
+
 int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int64_t lda,
                 const void *B, bool b_fp32, int64_t ldb, double beta, double *C, int64_t ldc,
                 bool lower, hipStream_t st, double *part, size_t part_cap) {
@@ -767,6 +976,15 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
   if (lda < TM * BM || ldb < TN * BN || lda % 8 || ldb % 8) return SYLV_ERR_INVALID;
   if (K <= 0) return 0;
   const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
+  if (!a_fp32 && !b_fp32 && part) {
+    const int64_t TM2 = (M + TW2 - 1) / TW2, TN2 = (N + TW2 - 1) / TW2;
+    if ((lower ? TM2 * (TM2 + 1) / 2 : TM2 * TN2) >= GRAM_WIDE_MIN_TILES) {
+      const int e = launch_gram_wide(M, N, K, static_cast<const double *>(A), lda,
+                                     static_cast<const double *>(B), ldb, beta, C, ldc, lower, st,
+                                     part, part_cap);
+      if (e <= 0) return e;  // launched, or an error; 1: the slots do not fit
+    }
+  }
   // many tiles: whole tiles in rounds of 512 workgroups (two per CU), the rest in stream-K
   // form, when the partial slots fit
   if (part && tiles >= 64) {
@@ -787,7 +1005,7 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
 #undef GRAM_SK
       HIPOK(hipGetLastError());
       if (nchunks > 1) {
-        gram_stream_fix_kernel<<<(unsigned)(nchunks - 1) * 16, 256, 0, st>>>(
+        gram_stream_fix_kernel<BM><<<(unsigned)(nchunks - 1) * (BM * BN / 256), 256, 0, st>>>(
             sq, M, N, nsl, dp, c, part, beta, C, ldc);
         HIPOK(hipGetLastError());
       }

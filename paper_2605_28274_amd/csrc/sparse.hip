@@ -160,7 +160,10 @@ int launch_spmm_rows(int s, int64_t r0, int64_t r1, const int32_t *rp, const int
   return 0;
 }
 
-size_t csr_transpose_scratch(int64_t rows) { return (size_t)(rows + 2) * 2 * sizeof(int) + 256; }
+size_t csr_transpose_scratch(int64_t rows) {
+  if (rows < 0 || rows > INT32_MAX) return 0;  // int32 row pointers
+  return (size_t)(rows + 2) * 2 * sizeof(int) + 256;
+}
 
 namespace {
 __global__ void fill_int_kernel(int64_t len, int *__restrict__ dst, int v) {

@@ -139,6 +139,11 @@ _lib.sylv_sell_spmm.restype = c_int
 _lib.sylv_dgemm.argtypes = [c_int64, c_int64, c_int64, c_double, c_void_p, c_int64, c_int64,
                             c_void_p, c_int64, c_int64, c_double, c_void_p, c_int64, c_void_p]
 _lib.sylv_dgemm.restype = c_int
+_lib.sylv_gram_work_bytes.argtypes = [c_int64, c_int64, c_int64]
+_lib.sylv_gram_work_bytes.restype = c_size_t
+_lib.sylv_gram.argtypes = [c_int64, c_int64, c_int64, c_void_p, c_int64, c_void_p, c_int64, c_int,
+                           c_int, c_void_p, c_int64, c_void_p, c_size_t, c_void_p]
+_lib.sylv_gram.restype = c_int
 _lib.sylv_batch_workspace_bytes.argtypes = [c_int, c_void_p, c_void_p]
 _lib.sylv_batch_workspace_bytes.restype = c_size_t
 _lib.sylv_batch_create.argtypes = [POINTER(c_void_p), c_int, c_void_p, c_void_p, c_void_p,
@@ -375,6 +380,20 @@ def sylv_dgemm(M, N, K, alpha, A, a_rs, a_cs, B, b_rs, b_cs, beta, C, ldc, strea
                          b_cs, beta, c_void_p(_ptr(C)), ldc, _stream(stream))
     if rc != 0:
         raise SylvError(rc, "sylv_dgemm")
+
+
+def sylv_gram_work_bytes(M: int, N: int, K: int) -> int:
+    return int(_lib.sylv_gram_work_bytes(M, N, K))
+
+
+def sylv_gram(M, N, K, A, lda, B, ldb, C, ldc, symmetric=False, accumulate=False, work=None,
+              work_bytes=0, stream=None) -> None:
+    """C = A^T B (C += with accumulate) for row-major K x M and K x N device operands."""
+    rc = _lib.sylv_gram(M, N, K, c_void_p(_ptr(A)), lda, c_void_p(_ptr(B)), ldb,
+                        1 if symmetric else 0, 1 if accumulate else 0, c_void_p(_ptr(C)), ldc,
+                        c_void_p(_ptr(work)), work_bytes, _stream(stream))
+    if rc != 0:
+        raise SylvError(rc, "sylv_gram")
 
 
 def sylv_csr_transpose_scratch_bytes(rows: int) -> int:

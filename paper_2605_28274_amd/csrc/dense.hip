@@ -145,9 +145,26 @@ __device__ __forceinline__ void load_slab(const TA *A, int64_t lda, const TB *B,
   else load_cols(B + l * ldb, ldb, rb);
 }
 
+// Zeroes the elements of a "rows" slab at slab column lim and beyond (a select, so whatever was
+// read there is dropped).
+__device__ __forceinline__ void mask_rows(RegSlab &r, int lim) {
+  const int k = (threadIdx.x & 3) * 8;
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    if (k + 2 * u >= lim) r.v[u].x = 0.0;
+    if (k + 2 * u + 1 >= lim) r.v[u].y = 0.0;
+  }
+}
+
+// lim: the K columns of the row-form operands from the slab start that are used (>= BK: all);
+// the rest are stored as zeros.
 template <bool A_T, bool B_ROWS>
-__device__ __forceinline__ void store_slab(Smem &sm, int buf, const RegSlab &ra,
-                                           const RegSlab &rb) {
+__device__ __forceinline__ void store_slab(Smem &sm, int buf, RegSlab &ra, RegSlab &rb,
+                                           int64_t lim) {
+  if (lim < BK) {
+    if (!A_T) mask_rows(ra, (int)lim);
+    if (B_ROWS) mask_rows(rb, (int)lim);
+  }
   if (A_T) store_cols(sm.As[buf], ra);
   else store_rows(sm.As[buf], ra);
   if (B_ROWS) store_rows(sm.Bs[buf], rb);
@@ -157,33 +174,36 @@ __device__ __forceinline__ void store_slab(Smem &sm, int buf, const RegSlab &ra,
 // One pipelined product over K slabs [l_begin, l_end) (multiples of BK): acc += A(i0.., l) B(l, j0..)
 // with the operand forms above (A, B point at row/column i0 and j0). Global loads run two slabs
 // ahead of the MFMAs (two register sets, the loop unrolled by two so they stay static); LDS is
-// double-buffered with one barrier per slab.
+// double-buffered with one barrier per slab. Row-form operands enter with their K columns at
+// kmax and beyond as zeros (applied when a slab is stored to LDS, after its loads have landed).
 template <bool A_T, bool B_ROWS, typename TA = double, typename TB = double>
 __device__ __forceinline__ void pipelined(Smem &sm, WaveAcc &acc, int wm, int wn, const TA *A,
                                           int64_t lda, const TB *B, int64_t ldb,
-                                          int64_t l_begin, int64_t l_end) {
+                                          int64_t l_begin, int64_t l_end,
+                                          int64_t kmax = INT64_MAX) {
   if (l_begin >= l_end) return;
   const int64_t nsl = (l_end - l_begin) / BK;
   // Prefetches are unconditional (a slab index past the end re-reads the last slab, always in
   // bounds), so the number of loads in flight is the same on every path and the wait before an
   // LDS fill only covers the older register set.
   auto lslab = [&](int64_t t) { return l_begin + (t < nsl ? t : nsl - 1) * BK; };
+  auto lim = [&](int64_t t) { return kmax - lslab(t); };
   RegSlab ra0, rb0, ra1, rb1;
   load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(0), ra0, rb0);
   load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(1), ra1, rb1);
   __syncthreads();  // previous users of the LDS buffers are done
-  store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0);
+  store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0, lim(0));
   __syncthreads();
   // invariant at slab t: LDS[t % 2] holds slab t; register set (t+1) % 2 holds slab t+1
   int64_t t = 0;
   for (; t + 1 < nsl; t += 2) {
     load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(t + 2), ra0, rb0);
     mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);
-    store_slab<A_T, B_ROWS>(sm, 1, ra1, rb1);
+    store_slab<A_T, B_ROWS>(sm, 1, ra1, rb1, lim(t + 1));
     __syncthreads();
     load_slab<A_T, B_ROWS, TA, TB>(A, lda, B, ldb, lslab(t + 3), ra1, rb1);
     mma_slab(sm.As[1], sm.Bs[1], acc, wm, wn);
-    store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0);
+    store_slab<A_T, B_ROWS>(sm, 0, ra0, rb0, lim(t + 2));
     __syncthreads();
   }
   if (t < nsl) mma_slab(sm.As[0], sm.Bs[0], acc, wm, wn);  // odd slab count: the last slab
@@ -204,7 +224,7 @@ __host__ __device__ inline int core_start(int s, int idx) {  // first K of tile 
 // (J < Tp) and ns[J] P G^T slabs (I < Tp).
 constexpr int CT_MAX = 32;  // tiles per side of the stream-K form
 struct CoreTab {
-  int T, Tp, pk;
+  int T, Tp, pk, p;
   int ns[CT_MAX], colpre[CT_MAX + 1], rowpre[CT_MAX + 1];
   __host__ __device__ int nh(int I, int J) const { return J < Tp ? ns[I] : 0; }
   __host__ __device__ int len(int I, int J) const { return nh(I, J) + (I < Tp ? ns[J] : 0); }
@@ -219,6 +239,7 @@ CoreTab make_core_tab(int s, int p, int T) {
   t.T = T;
   t.Tp = (p + BM - 1) / BM;
   t.pk = (p + BK - 1) / BK * BK;
+  t.p = p;
   for (int i = 0; i < T; ++i) t.ns[i] = (t.pk - core_start(s, i)) / BK;
   for (int i = 0; i < T; ++i) t.colpre[i + 1] = t.colpre[i] + t.ns[i];
   for (int i = 0; i < T; ++i)
@@ -227,20 +248,22 @@ CoreTab make_core_tab(int s, int p, int T) {
 }
 
 // Slabs [a, b) of tile (I, J)'s sequence (nH H P slabs from K = lsH, then P G^T slabs from lsG)
-// into acc.
+// into acc. Columns of H and G at or past p are stored to LDS as zeros: they belong to Krylov
+// steps that may be writing them on the other stream (they meet the exact-zero rows of P, but a
+// provisional non-finite value would still reach the sum through a product with zero).
 __device__ __forceinline__ void core_tile_part(Smem &sm, WaveAcc &acc, const double *H,
                                                const double *G, const double *P, int64_t ldc,
-                                               int I, int J, int nH, int lsH, int lsG, int a,
-                                               int b, int wm, int wn) {
+                                               int p, int I, int J, int nH, int lsH, int lsG,
+                                               int a, int b, int wm, int wn) {
   const int i0 = I * BM, j0 = J * BN;
   const int ha = a < nH ? a : nH, hb = b < nH ? b : nH;
   if (hb > ha)
     pipelined<false, false>(sm, acc, wm, wn, H + (int64_t)i0 * ldc, ldc, P + j0, ldc,
-                            lsH + ha * BK, lsH + hb * BK);
+                            lsH + ha * BK, lsH + hb * BK, p);
   const int ga = (a > nH ? a : nH) - nH, gb = (b > nH ? b : nH) - nH;
   if (gb > ga)
     pipelined<false, true>(sm, acc, wm, wn, P + (int64_t)i0 * ldc, ldc, G + (int64_t)j0 * ldc,
-                           ldc, lsG + ga * BK, lsG + gb * BK);
+                           ldc, lsG + ga * BK, lsG + gb * BK, p);
 }
 
 // One workgroup per complementary pair of tiles b and T*T - 1 - b, i.e. (I, J) and
@@ -262,7 +285,7 @@ __device__ __forceinline__ void core_op_body(int s, int p, int T, const double *
     const int nG = I * BM < p ? (pk - lsG) / BK : 0;
     WaveAcc acc;
     zero_acc(acc);
-    core_tile_part(sm, acc, H, G, P, ldc, I, J, nH, lsH, lsG, 0, nH + nG, wm, wn);
+    core_tile_part(sm, acc, H, G, P, ldc, p, I, J, nH, lsH, lsG, 0, nH + nG, wm, wn);
     for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) {
       Q[(int64_t)(I * BM + ii) * ldc + J * BN + jj] = v;
     });
@@ -321,7 +344,7 @@ __global__ __launch_bounds__(256, 2) void core_op_stream_kernel(const CoreTab ta
       const int b = (c1 < off + l ? c1 : off + l) - off;
       WaveAcc acc;
       zero_acc(acc);
-      core_tile_part(sm, acc, H, G, P, ldc, I, J, tab.nh(I, J), tab.pk - tab.ns[I] * BK,
+      core_tile_part(sm, acc, H, G, P, ldc, tab.p, I, J, tab.nh(I, J), tab.pk - tab.ns[I] * BK,
                      tab.pk - tab.ns[J] * BK, a, b, wm, wn);
       double *pt = part + (size_t)(I * T + J + w) * (BM * BN);
       for_each_acc(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * BN + jj] = v; });

@@ -47,11 +47,39 @@ __global__ __launch_bounds__(TPB) void band_pack_kernel(int p, int q, int s,
 }
 
 // E(r - r0, c) = (M V)(r, c) - sum_t V(r, base(c) + t) Hb(t, c) for c < p (one wave per row,
-// lanes across columns; only rows 0 <= base + t < q of the band enter).
-template <typename T>
+// lanes across columns, four columns per lane; only rows 0 <= base + t < q of the band enter).
+// Every load is unconditional and in bounds (columns past p read column p - 1, band rows outside
+// [0, q) read a clamped row with weight zero; only the store is guarded), so a lane's loads of
+// a column chunk issue together. A row of at most DEFECT_NZ entries keeps its column indices and
+// values in registers, padded with zero weights on the row itself; longer rows take the entry
+// loop. SS = s (the band spans 3 SS rows).
+constexpr int DEFECT_NZ = 8;
+
+template <typename T, int SS>
+__device__ __forceinline__ void defect_band_store(const T *__restrict__ vr, int j0, int lane,
+                                                  int p, int q, const double *__restrict__ Hb,
+                                                  int64_t ldhb, const double (&acc)[4],
+                                                  double *__restrict__ er) {
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int j = j0 + u * WAVE + lane, jc = j < p ? j : p - 1;
+    const int base = (jc / SS - 1) * SS;
+    double v = acc[u];
+#pragma unroll
+    for (int t = 0; t < 3 * SS; ++t) {
+      const int row = base + t;
+      const bool in = row >= 0 && row < q;
+      const double h = Hb[(int64_t)t * ldhb + jc];
+      v = fma(-(double)vr[in ? row : 0], in ? h : 0.0, v);
+    }
+    if (j < p) er[j] = v;
+  }
+}
+
+template <typename T, int SS>
 __global__ __launch_bounds__(TPB) void defect_band_kernel(
     int64_t r0, int64_t r1, const int32_t *__restrict__ rp, const int32_t *__restrict__ ci,
-    const double *__restrict__ val, const T *__restrict__ V, int64_t ldv, int p, int q, int s,
+    const double *__restrict__ val, const T *__restrict__ V, int64_t ldv, int p, int q,
     const double *__restrict__ Hb, int64_t ldhb, double *__restrict__ E, int64_t lde) {
   const int64_t r = r0 + (int64_t)blockIdx.x * (TPB / WAVE) + threadIdx.x / WAVE;
   const int lane = threadIdx.x & (WAVE - 1);
@@ -59,30 +87,45 @@ __global__ __launch_bounds__(TPB) void defect_band_kernel(
   const int b = rp[r], e = rp[r + 1];
   const T *vr = V + r * ldv;
   double *er = E + (r - r0) * lde;
+  auto cols = [&](int j0, int (&jc)[4]) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int j = j0 + u * WAVE + lane;
+      jc[u] = j < p ? j : p - 1;
+    }
+  };
+  if (e - b <= DEFECT_NZ) {
+    const T *xs[DEFECT_NZ];
+    double as[DEFECT_NZ];
+#pragma unroll
+    for (int k = 0; k < DEFECT_NZ; ++k) {
+      const bool in = b + k < e;
+      as[k] = in ? val[b + k] : 0.0;
+      xs[k] = V + (in ? (int64_t)ci[b + k] : r) * ldv;
+    }
+    for (int j0 = 0; j0 < p; j0 += 4 * WAVE) {
+      int jc[4];
+      cols(j0, jc);
+      double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int k = 0; k < DEFECT_NZ; ++k)
+#pragma unroll
+        for (int u = 0; u < 4; ++u) acc[u] = fma(as[k], (double)xs[k][jc[u]], acc[u]);
+      defect_band_store<T, SS>(vr, j0, lane, p, q, Hb, ldhb, acc, er);
+    }
+    return;
+  }
   for (int j0 = 0; j0 < p; j0 += 4 * WAVE) {
+    int jc[4];
+    cols(j0, jc);
     double acc[4] = {0.0, 0.0, 0.0, 0.0};
     for (int z = b; z < e; ++z) {
       const double a = val[z];
       const T *x = V + (int64_t)ci[z] * ldv;
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const int j = j0 + u * WAVE + lane;
-        if (j < p) acc[u] = fma(a, (double)x[j], acc[u]);
-      }
+      for (int u = 0; u < 4; ++u) acc[u] = fma(a, (double)x[jc[u]], acc[u]);
     }
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-      const int j = j0 + u * WAVE + lane;
-      if (j < p) {
-        const int base = (j / s - 1) * s;
-        double v = acc[u];
-        for (int t = 0; t < 3 * s; ++t) {
-          const int row = base + t;
-          if (row >= 0 && row < q) v = fma(-(double)vr[row], Hb[(int64_t)t * ldhb + j], v);
-        }
-        er[j] = v;
-      }
-    }
+    defect_band_store<T, SS>(vr, j0, lane, p, q, Hb, ldhb, acc, er);
   }
 }
 
@@ -142,15 +185,24 @@ int launch_defect_band(int64_t r0, int64_t r1, const int32_t *rp, const int32_t 
     band_pack_kernel<<<(unsigned)((p + TPB - 1) / TPB), TPB, 0, st>>>(p, q, s, H, ldh, Hb, ldhb);
     HIPOK(hipGetLastError());
   }
+  if (s < 1 || s > SYLV_MAX_S) return SYLV_ERR_INVALID;
   const int64_t nr = r1 - r0;
   const unsigned g = (unsigned)((nr + 3) / 4);
-  if (v_fp32)
-    defect_band_kernel<float><<<g, TPB, 0, st>>>(r0, r1, rp, ci, val, static_cast<const float *>(V),
-                                                 ldv, p, q, s, Hb, ldhb, E, lde);
-  else
-    defect_band_kernel<double><<<g, TPB, 0, st>>>(r0, r1, rp, ci, val,
-                                                  static_cast<const double *>(V), ldv, p, q, s, Hb,
-                                                  ldhb, E, lde);
+  switch (s) {
+#define CASE(SS)                                                                                 \
+  case SS:                                                                                       \
+    if (v_fp32)                                                                                  \
+      defect_band_kernel<float, SS><<<g, TPB, 0, st>>>(r0, r1, rp, ci, val,                      \
+                                                       static_cast<const float *>(V), ldv, p, q, \
+                                                       Hb, ldhb, E, lde);                        \
+    else                                                                                         \
+      defect_band_kernel<double, SS><<<g, TPB, 0, st>>>(r0, r1, rp, ci, val,                     \
+                                                        static_cast<const double *>(V), ldv, p,  \
+                                                        q, Hb, ldhb, E, lde);                    \
+    break;
+    CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
+#undef CASE
+  }
   HIPOK(hipGetLastError());
   return 0;
 }

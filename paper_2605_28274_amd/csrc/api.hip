@@ -971,9 +971,40 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
         for (const Seg &A : segs) pb += (double)nr * A.cols * A.esz;
         prof_end(P->sc, FAM_RES_PACK, pb + 4.0 * (double)nr * offs.back(), 0.0, st);
       }
+      // the FP64 blocks of the chunk as one launch on 128 x 128 tiles (whole-tile rounds across
+      // all of them) when they are large enough and the partial slots fit
+      std::vector<char> batched(segs.size() * segs.size(), 0);
+      {
+        GramJob jobs[GRAM_JOBS_MAX];
+        int nj = 0;
+        double jbytes = 0.0, jfl = 0.0;
+        for (size_t a = 0; a < segs.size() && nj < GRAM_JOBS_MAX; ++a)
+          for (size_t b = 0; b <= a && nj < GRAM_JOBS_MAX; ++b) {
+            const Seg &A = segs[a], &B = segs[b];
+            if (bf16_block(a, b) || A.f32 || B.f32) continue;
+            const char *pa = A.ptr + (A.rowed ? r0 * A.ld * A.esz : 0);
+            const char *pb = B.ptr + (B.rowed ? r0 * B.ld * B.esz : 0);
+            jobs[nj++] = GramJob{GramSeq{0, 0, a == b ? 1 : 0}, A.cols, B.cols,
+                                 reinterpret_cast<const double *>(pa), A.ld,
+                                 reinterpret_cast<const double *>(pb), B.ld,
+                                 G + offs[a] * ldG + offs[b], ldG, 0};
+            batched[a * segs.size() + b] = 1;
+            jbytes += (double)nr * (a == b ? A.cols * A.esz : A.cols * A.esz + B.cols * B.esz);
+            jfl += (a == b ? (double)A.cols * (A.cols + 1) : 2.0 * A.cols * B.cols) * nr;
+          }
+        int je = 1;
+        if (nj > 1) {
+          prof_begin(P->sc, st);
+          je = launch_gram_jobs(jobs, nj, nr, beta, st, gpart, PL.gpart_cap);
+          if (je < 0) return je;
+          if (je == 0) prof_end(P->sc, FAM_RES_GRAM, jbytes, jfl, st);
+        }
+        if (je != 0) std::fill(batched.begin(), batched.end(), 0);
+      }
       for (size_t a = 0; a < segs.size(); ++a)
         for (size_t b = 0; b <= a; ++b) {
           const Seg &A = segs[a], &B = segs[b];
+          if (batched[a * segs.size() + b]) continue;
           // useful flops of the block (lower triangle only when a == b)
           const double fl = (a == b ? (double)A.cols * (A.cols + 1) : 2.0 * A.cols * B.cols) * nr;
           if (bf16_block(a, b)) {

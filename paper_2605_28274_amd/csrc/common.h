@@ -896,6 +896,32 @@ struct GramSeq {
   }
 };
 
+// One FP64 Gram C (+)= A^T B of a job table (all jobs over the same K rows): sq.lower selects
+// the lower-triangle form (M == N); sq's tile counts and t0 are filled in by the launcher.
+struct GramJob {
+  GramSeq sq;
+  int64_t M, N;
+  const double *A;
+  int64_t lda;
+  const double *B;
+  int64_t ldb;
+  double *C;
+  int64_t ldc;
+  int64_t t0;
+};
+constexpr int GRAM_JOBS_MAX = 8;
+struct GramJobs {
+  GramJob j[GRAM_JOBS_MAX];
+  int n;
+  int64_t total;
+};
+// 128 x 128 tiles of a Gram (the lower triangle with `lower`)
+int64_t gram_wide_tiles(int64_t M, int64_t N, bool lower);
+// The jobs (n <= GRAM_JOBS_MAX) as one launch on 128 x 128 tiles; returns 1 (nothing launched)
+// when part cannot hold the stream-K slots, so the caller runs the jobs one by one.
+int launch_gram_jobs(const GramJob *jobs, int n, int64_t K, double beta, hipStream_t st,
+                     double *part, size_t part_cap);
+
 
 // Split-BF16 Grams (gram_bf16.hip). The stacked columns of one row chunk come from up to
 // BF_MAX_SEGS segments: segment i supplies columns [col0, col0 + cols) from a row-major source

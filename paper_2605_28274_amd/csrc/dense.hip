@@ -703,52 +703,95 @@ __device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, in
   }
 }
 
-// Stream-K schedule as gram_stream_kernel's, over 128 x 128 tiles (partial slots of 128 x 128).
-__global__ __launch_bounds__(256, 2) void gram_wide_kernel(
-    const GramSeq sq, int64_t M, int64_t N, int64_t K, const double *__restrict__ A, int64_t lda,
-    const double *__restrict__ B, int64_t ldb, double beta, double *__restrict__ C, int64_t ldc,
-    int64_t nsl, int64_t dp, int64_t c, int nchunks, double *__restrict__ part) {
+// Stream-K schedule as gram_stream_kernel's, over 128 x 128 tiles (partial slots of 128 x 128),
+// for a table of Gram products that share K: the tiles of all jobs form one sequence (job q's
+// tiles from jobs.j[q].t0 on, each job in its own visiting order), so several products of one
+// row chunk run as one launch with whole-tile rounds across all of them.
+__device__ __forceinline__ const GramJob &job_of(const GramJobs &jobs, int64_t t, int64_t &lt) {
+  int q = 0;
+  while (q + 1 < jobs.n && jobs.j[q + 1].t0 <= t) ++q;
+  lt = t - jobs.j[q].t0;
+  return jobs.j[q];
+}
+
+__global__ __launch_bounds__(256, 2) void gram_wide_kernel(const GramJobs jobs, int64_t K,
+                                                           double beta, int64_t nsl, int64_t dp,
+                                                           int64_t c, int nchunks,
+                                                           double *__restrict__ part) {
   const int G = (int)gridDim.x, per = G >> 3;
   const int w = (int)(blockIdx.x & 7) * per + (int)(blockIdx.x >> 3);
   __shared__ Smem2 sm;
   const int wv = threadIdx.x >> 6, wm = wv >> 1, wn = wv & 1;
-  auto store_c = [&](const Acc2 &acc, int64_t i0, int64_t j0) {
+  auto store_c = [&](const Acc2 &acc, const GramJob &jb, int64_t i0, int64_t j0) {
     for_each_acc2(acc, wm, wn, [&](int ii, int jj, double v) {
       const int64_t gi = i0 + ii, gj = j0 + jj;
-      if (gi < M && gj < N) {
-        double *cp = C + gi * ldc + gj;
+      if (gi < jb.M && gj < jb.N) {
+        double *cp = jb.C + gi * jb.ldc + gj;
         *cp = (beta == 0.0) ? v : *cp + v;
       }
     });
   };
   for (int64_t t = w; t < dp; t += G) {
+    int64_t lt;
+    const GramJob &jb = job_of(jobs, t, lt);
     int I, J;
-    sq.tile(t, I, J);
+    jb.sq.tile(lt, I, J);
     const int64_t i0 = (int64_t)I * TW2, j0 = (int64_t)J * TW2;
     Acc2 acc;
     zero_acc2(acc);
-    gram_piece2(sm, acc, i0, j0, K, A, lda, B, ldb, 0, nsl, wm, wn);
-    store_c(acc, i0, j0);
+    gram_piece2(sm, acc, i0, j0, K, jb.A, jb.lda, jb.B, jb.ldb, 0, nsl, wm, wn);
+    store_c(acc, jb, i0, j0);
   }
   if (w >= nchunks) return;
-  const int64_t total = (sq.count() - dp) * nsl;
+  const int64_t total = (jobs.total - dp) * nsl;
   const int64_t c0 = (int64_t)w * c, c1 = (c0 + c < total) ? c0 + c : total;
   for (int64_t pos = c0; pos < c1;) {
     const int64_t tr = pos / nsl, ts = tr * nsl;
     const int64_t a = pos - ts, b = ((c1 < ts + nsl) ? c1 : ts + nsl) - ts;
+    int64_t lt;
+    const GramJob &jb = job_of(jobs, dp + tr, lt);
     int I, J;
-    sq.tile(dp + tr, I, J);
+    jb.sq.tile(lt, I, J);
     const int64_t i0 = (int64_t)I * TW2, j0 = (int64_t)J * TW2;
     Acc2 acc;
     zero_acc2(acc);
-    gram_piece2(sm, acc, i0, j0, K, A, lda, B, ldb, a, b, wm, wn);
+    gram_piece2(sm, acc, i0, j0, K, jb.A, jb.lda, jb.B, jb.ldb, a, b, wm, wn);
     if (a == 0 && b == nsl) {
-      store_c(acc, i0, j0);
+      store_c(acc, jb, i0, j0);
     } else {
       double *pt = part + (size_t)(2 * w + (pos == c0 ? 0 : 1)) * (TW2 * TW2);
       for_each_acc2(acc, wm, wn, [&](int ii, int jj, double v) { pt[ii * TW2 + jj] = v; });
     }
     pos = ts + b;
+  }
+}
+
+// The tiles of a job table cut by stream-K chunk boundaries (as gram_stream_fix_kernel<128>).
+__global__ __launch_bounds__(256) void gram_wide_fix_kernel(const GramJobs jobs, int64_t nsl,
+                                                            int64_t dp, int64_t c,
+                                                            const double *__restrict__ part,
+                                                            double beta) {
+  constexpr int SUBS = TW2 * TW2 / 256;
+  const int wb = (int)(blockIdx.x / SUBS), sub = (int)(blockIdx.x % SUBS);
+  const int64_t pb = (int64_t)(wb + 1) * c, total = (jobs.total - dp) * nsl;
+  if (pb >= total || pb % nsl == 0) return;
+  const int64_t tr = pb / nsl, ts = tr * nsl;
+  if ((int64_t)wb * c > ts) return;
+  const int w0 = (int)(ts / c), w1 = (int)((ts + nsl - 1) / c);
+  const int e = sub * 256 + threadIdx.x;
+  double v = 0.0;
+  for (int w = w0; w <= w1; ++w) {
+    const int slot = 2 * w + ((int64_t)w * c / nsl == tr ? 0 : 1);
+    v += part[(size_t)slot * (TW2 * TW2) + e];
+  }
+  int64_t lt;
+  const GramJob &jb = job_of(jobs, dp + tr, lt);
+  int I, J;
+  jb.sq.tile(lt, I, J);
+  const int64_t gi = (int64_t)I * TW2 + e / TW2, gj = (int64_t)J * TW2 + e % TW2;
+  if (gi < jb.M && gj < jb.N) {
+    double *cp = jb.C + gi * jb.ldc + gj;
+    *cp = (beta == 0.0) ? v : *cp + v;
   }
 }
 
@@ -957,32 +1000,61 @@ int launch_gemm_nn(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda
   return 0;
 }
 
-// Stream-K launch of gram_wide_kernel when its partial slots fit (two per stream-K chunk, one
-// chunk per workgroup); returns 1 when it did not launch.
-static int launch_gram_wide(int64_t M, int64_t N, int64_t K, const double *A, int64_t lda,
-                            const double *B, int64_t ldb, double beta, double *C, int64_t ldc,
-                            bool lower, hipStream_t st, double *part, size_t part_cap) {
-  const int64_t TM = (M + TW2 - 1) / TW2, TN = (N + TW2 - 1) / TW2;
-  const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
-  const int64_t G = GRAM_WIDE_WG, nsl = (K + BK2 - 1) / BK2, dp = tiles / G * G;
-  const int64_t total = (tiles - dp) * nsl;
+// FP64 Grams of at least this many 128 x 128 tiles take gram_wide_kernel
+constexpr int64_t GRAM_WIDE_MIN_TILES = 256;
+
+// Stream-K launch of gram_wide_kernel over a job table when its partial slots fit (two per
+// stream-K chunk, one chunk per workgroup); returns 1 when it did not launch.
+static int launch_gram_wide(GramJobs &jobs, int64_t K, double beta, hipStream_t st, double *part,
+                            size_t part_cap) {
+  jobs.total = 0;
+  for (int q = 0; q < jobs.n; ++q) {
+    GramJob &jb = jobs.j[q];
+    const int TM = (int)((jb.M + TW2 - 1) / TW2), TN = (int)((jb.N + TW2 - 1) / TW2);
+    jb.sq = GramSeq{TM, TN, jb.sq.lower};
+    jb.t0 = jobs.total;
+    jobs.total += jb.sq.count();
+  }
+  const int64_t G = GRAM_WIDE_WG, nsl = (K + BK2 - 1) / BK2, dp = jobs.total / G * G;
+  const int64_t total = (jobs.total - dp) * nsl;
   const int64_t c = std::max<int64_t>((total + G - 1) / G, 4);
   const int64_t nchunks = (total + c - 1) / c;
   if ((size_t)(2 * nchunks) * (TW2 * TW2) > part_cap) return 1;
-  const GramSeq sq{(int)TM, (int)TN, lower ? 1 : 0};
-  gram_wide_kernel<<<(unsigned)G, 256, 0, st>>>(sq, M, N, K, A, lda, B, ldb, beta, C, ldc, nsl,
-                                                dp, c, (int)nchunks, part);
+  gram_wide_kernel<<<(unsigned)G, 256, 0, st>>>(jobs, K, beta, nsl, dp, c, (int)nchunks, part);
   HIPOK(hipGetLastError());
   if (nchunks > 1) {
-    gram_stream_fix_kernel<TW2><<<(unsigned)(nchunks - 1) * (TW2 * TW2 / 256), 256, 0, st>>>(
-        sq, M, N, nsl, dp, c, part, beta, C, ldc);
+    gram_wide_fix_kernel<<<(unsigned)(nchunks - 1) * (TW2 * TW2 / 256), 256, 0, st>>>(
+        jobs, nsl, dp, c, part, beta);
     HIPOK(hipGetLastError());
   }
   return 0;
 }
 
-// FP64 Grams of at least this many 128 x 128 tiles take gram_wide_kernel
-constexpr int64_t GRAM_WIDE_MIN_TILES = 256;
+int64_t gram_wide_tiles(int64_t M, int64_t N, bool lower) {
+  const int64_t TM = (M + TW2 - 1) / TW2, TN = (N + TW2 - 1) / TW2;
+  return lower ? TM * (TM + 1) / 2 : TM * TN;
+}
+
+int launch_gram_jobs(const GramJob *jobs, int n, int64_t K, double beta, hipStream_t st,
+                     double *part, size_t part_cap) {
+  if (n < 1 || n > GRAM_JOBS_MAX || K <= 0 || !part) return 1;
+  GramJobs t{};
+  t.n = 0;
+  for (int q = 0; q < n; ++q) {
+    const GramJob &jb = jobs[q];
+    if (jb.M <= 0 || jb.N <= 0) continue;
+    if ((jb.sq.lower && jb.M != jb.N) || jb.lda % 8 || jb.ldb % 8 || jb.lda < jb.M ||
+        jb.ldb < jb.N)
+      return SYLV_ERR_INVALID;
+    t.j[t.n++] = jb;
+  }
+  if (t.n == 0) return 0;
+  int64_t tiles = 0;
+  for (int q = 0; q < t.n; ++q) tiles += gram_wide_tiles(t.j[q].M, t.j[q].N, t.j[q].sq.lower);
+  if (tiles < GRAM_WIDE_MIN_TILES) return 1;
+  return launch_gram_wide(t, K, beta, st, part, part_cap);
+}
+
 
 size_t gram_part_doubles(int64_t max_cols, int64_t rows) {
   // the wide form's slots for a full round of workgroups where its Grams can occur
@@ -999,14 +1071,13 @@ int launch_gram(int64_t M, int64_t N, int64_t K, const void *A, bool a_fp32, int
   if (lda < TM * BM || ldb < TN * BN || lda % 8 || ldb % 8) return SYLV_ERR_INVALID;
   if (K <= 0) return 0;
   const int64_t tiles = lower ? TM * (TM + 1) / 2 : TM * TN;
-  if (!a_fp32 && !b_fp32 && part) {
-    const int64_t TM2 = (M + TW2 - 1) / TW2, TN2 = (N + TW2 - 1) / TW2;
-    if ((lower ? TM2 * (TM2 + 1) / 2 : TM2 * TN2) >= GRAM_WIDE_MIN_TILES) {
-      const int e = launch_gram_wide(M, N, K, static_cast<const double *>(A), lda,
-                                     static_cast<const double *>(B), ldb, beta, C, ldc, lower, st,
-                                     part, part_cap);
-      if (e <= 0) return e;  // launched, or an error; 1: the slots do not fit
-    }
+  if (!a_fp32 && !b_fp32 && part && gram_wide_tiles(M, N, lower) >= GRAM_WIDE_MIN_TILES) {
+    GramJobs t{};
+    t.n = 1;
+    t.j[0] = GramJob{GramSeq{0, 0, lower ? 1 : 0}, M, N, static_cast<const double *>(A), lda,
+                     static_cast<const double *>(B), ldb, C, ldc, 0};
+    const int e = launch_gram_wide(t, K, beta, st, part, part_cap);
+    if (e <= 0) return e;  // launched, or an error; 1: the slots do not fit
   }
   // many tiles: whole tiles in rounds of 512 workgroups (two per CU), the rest in stream-K
   // form, when the partial slots fit

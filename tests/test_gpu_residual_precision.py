@@ -37,12 +37,18 @@ def _problem(case):
         return stencils.make_problem("sb", stencils.cd2d(36, 30, 10.0),
                                      stencils.cd1d(1500, 10.0), 2, 73,
                                      method="bicgstab"), "bicgstab", 1e-9, 200
+    if case == "large":
+        # 1500 iterations of Lyapunov CG on 30000 rows (two row chunks): the FP64 blocks of the
+        # stacked Gram (1501 and 1502 columns: 300 tiles of 128 x 128) run as one launch per
+        # chunk over a table of the three products
+        return stencils.make_problem("lg", stencils.cd1d(30000), None, 1, 76, lyapunov=True,
+                                     method="cg"), "cg", 1e-300, 1500
     # unconverged: residual far above rounding, hundreds of stacked columns
     return stencils.make_problem("un", stencils.cd1d(2500), None, 2, 74, lyapunov=True,
                                  method="cg"), "cg", 1e-14, 250
 
 
-@pytest.mark.parametrize("case", ["lyap_cg", "sylv_cg", "sylv_bicgstab", "unconverged"])
+@pytest.mark.parametrize("case", ["lyap_cg", "sylv_cg", "sylv_bicgstab", "unconverged", "large"])
 def test_split_bf16_residual_grams(sylv, case):
     p, method, tol, cap = _problem(case)
     code = sylv.SYLV_METHOD_CG if method == "cg" else sylv.SYLV_METHOD_BICGSTAB
@@ -53,13 +59,16 @@ def test_split_bf16_residual_grams(sylv, case):
         res = slv.factored_cg(tol) if method == "cg" else slv.factored_bicgstab(tol)
         rels[gp] = slv.residual_norm()[1]
         if gp == 0:
-            V, X, W = (t.cpu().numpy() for t in slv.get_factors())
-            dense = dense_rel_residual(p, V @ X @ W.T)
+            dense = None
+            if p.n <= 5000:  # the dense residual of the large case would take 7 GB
+                V, X, W = (t.cpu().numpy() for t in slv.get_factors())
+                dense = dense_rel_residual(p, V @ X @ W.T)
             iters = res.iters
         else:
             assert res.iters == iters  # the solve itself is the same
         slv.close()
-    assert abs(rels[0] - dense) <= 1e-6 * dense + 1e-14, (rels[0], dense)
+    if dense is not None:
+        assert abs(rels[0] - dense) <= 1e-6 * dense + 1e-14, (rels[0], dense)
     # defect blocks in split BF16: their share of ||R||^2 is tiny, so the norm stays FP64-close
     assert abs(rels[1] - rels[0]) <= 1e-6 * rels[0], (rels[1], rels[0])
     # every block in split BF16: about 1e-5 relative per Gram entry

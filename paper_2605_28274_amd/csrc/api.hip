@@ -640,19 +640,30 @@ int ctx_create(void **out, const sylv_problem *pb, const sylv_options *op, void 
   // SELL copies of A and B^T for the Krylov SpMM (CSR stays in use if the padding is large)
   if (!parent) c->sv.sell = SellMat{};
   if (!parent) {
+    int nar = 0;
     e = build_sell(L.n, pb->A.nnz, pb->A.row_ptr, pb->A.col_idx, pb->A.values,
-                   at<void>(c, L.off_sellA), st);
-    if (e == 0) c->sv.sell = sell_view(L.n, pb->A.nnz, at<void>(c, L.off_sellA));
-    else if (e != SYLV_ERR_WORKSPACE) return fail(e);
+                   at<void>(c, L.off_sellA), st, true, &nar);
+    if (e == 0) {
+      c->sv.sell = sell_view(L.n, pb->A.nnz, at<void>(c, L.off_sellA));
+      c->sv.sell.narrow = nar;
+    } else if (e != SYLV_ERR_WORKSPACE) {
+      return fail(e);
+    }
   }
   if (parent) {
   } else if (L.lyap) {
     c->sw.sell = c->sv.sell;
   } else {
     c->sw.sell = SellMat{};
-    e = build_sell(L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<void>(c, L.off_sellB), st);
-    if (e == 0) c->sw.sell = sell_view(L.m, pb->B.nnz, at<void>(c, L.off_sellB));
-    else if (e != SYLV_ERR_WORKSPACE) return fail(e);
+    int nar = 0;
+    e = build_sell(L.m, pb->B.nnz, c->btrp, c->btci, c->btval, at<void>(c, L.off_sellB), st,
+                   true, &nar);
+    if (e == 0) {
+      c->sw.sell = sell_view(L.m, pb->B.nnz, at<void>(c, L.off_sellB));
+      c->sw.sell.narrow = nar;
+    } else if (e != SYLV_ERR_WORKSPACE) {
+      return fail(e);
+    }
   }
   // QR factorizations C1 = V_1 R_L, C2 = W_1 R_R (Alg. 4.1 step 1, Alg. 4.2 step 2)
   const int s = (int)L.s;

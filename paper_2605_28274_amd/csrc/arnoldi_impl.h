@@ -40,6 +40,12 @@ constexpr int GRAM_UCH = 128;  // right-hand rows staged in LDS at a time by gra
 // their waves take the higher issue priority on a SIMD they share (1% on the C2 solve).
 __device__ __forceinline__ void krylov_wave_priority() { __builtin_amdgcn_s_setprio(3); }
 
+// Algorithmic bytes of one pass over a side's operator: value and column index per entry (12
+// bytes as CSR or wide SELL, 6 in the narrow SELL form).
+inline double mat_bytes(const SideDesc &d) {
+  return (d.sell.ci && d.sell.narrow ? 6.0 : 12.0) * (double)d.nnz;
+}
+
 struct ArSide {
   int64_t rows, nnz;
   const int32_t *rp, *ci;
@@ -1429,7 +1435,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   spmm_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_SPMM,
-           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,
+           mat_bytes(sv) + (sw ? mat_bytes(*sw) : 0.0) + 4.0 * (total + 2) + 16.0 * total * S,
            2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S, st);
 
   // chunking of the Gram sweeps
@@ -1538,7 +1544,7 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   spmm_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_SPMM,
-           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 16.0 * total * S,
+           mat_bytes(sv) + (sw ? mat_bytes(*sw) : 0.0) + 4.0 * (total + 2) + 16.0 * total * S,
            2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S, st);
 
   // [V_{0..j-1}; V~_j]^T [V~_j, U]
@@ -1709,7 +1715,7 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
     lz_fused_pair<S, T><<<P.nsides, TPB, 0, st>>>(P, jb, closure_tol, ds);
     HIPOK(hipGetLastError());
     prof_end(sc, FAM_SPMM,
-             12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 8.0 * total * S * 9,
+             mat_bytes(sv) + (sw ? mat_bytes(*sw) : 0.0) + 4.0 * (total + 2) + 8.0 * total * S * 9,
              2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S + 14.0 * total * S * S, st);
     if ((jb + 2) % LZ_RING == 0) return lanczos_flush_t<S, T>(sv, sw, jb + 2, st);
     return 0;
@@ -1729,7 +1735,7 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   HIPOK(hipGetLastError());
   // matrix + gather V_j + read V_{j-1}, V_j + U write/read (local three-term step)
   prof_end(sc, FAM_SPMM,
-           12.0 * (sv.nnz + (sw ? sw->nnz : 0)) + 4.0 * (total + 2) + 8.0 * total * S * 6,
+           mat_bytes(sv) + (sw ? mat_bytes(*sw) : 0.0) + 4.0 * (total + 2) + 8.0 * total * S * 6,
            2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S + 8.0 * total * S * S, st);
   set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
   prof_begin(sc, st);

@@ -227,14 +227,20 @@ __device__ __forceinline__ void spmm_rows(int64_t r0, int64_t r1, const int32_t 
 // per row, column-major inside the slice: entry q of row r sits at off[k] + 64 q + (r % 64).
 // Short rows are padded with value 0 and their own row index as column. Every load of the
 // SpMM below is then one contiguous 64-lane access, and no row pointer lies on the dependent
-// path of the gathers.
+// path of the gathers. Narrow form (the solver's own copies of a matrix whose every value is
+// exactly a float and whose every column lies within 32767 of its row): the entries are stored
+// as float values and int16 column offsets from the row (6 instead of 12 bytes per entry, the
+// same products bit for bit), in the regions of the wide arrays.
 struct SellMat {
   int64_t rows;
   int64_t nslices;
   const int32_t *width;  // [nslices]
   const int64_t *off;    // [nslices]
-  const int32_t *ci;     // [capacity]
+  const int32_t *ci;     // [capacity] (not null whenever the copy exists)
   const double *val;     // [capacity]
+  int narrow;            // entries in cd / valf instead of ci / val
+  const int16_t *cd;     // [capacity] column - row (narrow)
+  const float *valf;     // [capacity] (narrow)
 };
 
 // Capacity (entries) reserved for the SELL copy of a CSR matrix with nnz entries: up to 25%
@@ -260,9 +266,24 @@ inline SellMat sell_view(int64_t rows, int64_t nnz, void *buf) {
   m.off = reinterpret_cast<const int64_t *>(p);
   p += al(ns * 8);
   m.ci = reinterpret_cast<const int32_t *>(p);
+  m.cd = reinterpret_cast<const int16_t *>(p);
   p += al(cap * 4);
   m.val = reinterpret_cast<const double *>(p);
+  m.valf = reinterpret_cast<const float *>(p);
+  m.narrow = 0;
   return m;
+}
+
+// Entry q of a slice at position `at` of row r: its column and value (either form).
+__device__ __forceinline__ void sell_entry(const SellMat &M, int64_t at, int64_t r, bool in,
+                                           int &c, double &a) {
+  if (M.narrow) {
+    c = in ? (int)(r + M.cd[at]) : 0;
+    a = in ? (double)M.valf[at] : 0.0;
+  } else {
+    c = in ? M.ci[at] : 0;
+    a = in ? M.val[at] : 0.0;
+  }
 }
 
 // acc = A[r, :] X[:, 0:S] for one row r < rows (thread r % 64 of a wave-aligned slice). Rows
@@ -311,11 +332,7 @@ __device__ __forceinline__ void sell_row(const SellMat &M, int64_t r,
     int c[8];
     double a[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const bool in = q0 + u < w;
-      c[u] = in ? M.ci[base + 64 * (q0 + u)] : 0;
-      a[u] = in ? M.val[base + 64 * (q0 + u)] : 0.0;
-    }
+    for (int u = 0; u < 8; ++u) sell_entry(M, base + 64 * (q0 + u), r, q0 + u < w, c[u], a[u]);
     double x[8][S];
 #pragma unroll
     for (int u = 0; u < 8; ++u) gather_row<S>(X, c[u], ldx, vec, q0 + u < w, x[u]);
@@ -351,11 +368,9 @@ __device__ __forceinline__ void sell_rows(const SellMat &M, const int64_t (&r)[N
 #pragma unroll
     for (int i = 0; i < NR; ++i)
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const bool in = q0 + u < w[i];
-        c[i][u] = in ? M.ci[base[i] + 64 * (q0 + u)] : 0;
-        a[i][u] = in ? M.val[base[i] + 64 * (q0 + u)] : 0.0;
-      }
+      for (int u = 0; u < 8; ++u)
+        sell_entry(M, base[i] + 64 * (q0 + u), ok[i] ? r[i] : 0, q0 + u < w[i], c[i][u],
+                   a[i][u]);
     double x[NR][8][S];
 #pragma unroll
     for (int i = 0; i < NR; ++i)
@@ -377,9 +392,10 @@ __device__ __forceinline__ void sell_rows(const SellMat &M, const int64_t (&r)[N
 
 // Builds the SELL copy of a CSR matrix into buf (sell_bytes(rows, nnz) bytes). Returns
 // SYLV_ERR_WORKSPACE when the padded size exceeds the reserved capacity (the caller then keeps
-// using CSR). Synchronizes the stream.
+// using CSR). Synchronizes the stream. With allow_narrow, the narrow form is built when every
+// entry allows it, and *narrow (required then) tells which form was built.
 int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *val,
-               void *buf, hipStream_t st);
+               void *buf, hipStream_t st, bool allow_narrow = false, int *narrow = nullptr);
 int launch_sell_spmm(int s, const SellMat &M, const double *X, int64_t ldx, double *Y, int64_t ldy,
                      hipStream_t st);
 

@@ -265,6 +265,41 @@ __global__ void sell_fill_kernel(int64_t rows, const int32_t *__restrict__ rp,
   }
 }
 
+// flag |= 1 when an entry of row r does not fit the narrow form (its value is not exactly a
+// float, or its column is more than 32767 away from the row)
+__global__ void sell_narrow_check_kernel(int64_t rows, const int32_t *__restrict__ rp,
+                                         const int32_t *__restrict__ ci,
+                                         const double *__restrict__ val, int *flag) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  bool ok = true;
+  for (int64_t q = rp[r]; q < rp[r + 1]; ++q) {
+    const double v = val[q];
+    const int64_t d = (int64_t)ci[q] - r;
+    ok = ok && (double)(float)v == v && d >= -32767 && d <= 32767;
+  }
+  if (!ok) atomicOr(flag, 1);
+}
+
+__global__ void sell_fill_narrow_kernel(int64_t rows, const int32_t *__restrict__ rp,
+                                        const int32_t *__restrict__ ci,
+                                        const double *__restrict__ val,
+                                        const int32_t *__restrict__ width,
+                                        const int64_t *__restrict__ off, int16_t *__restrict__ cd,
+                                        float *__restrict__ valf) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= rows) return;
+  const int64_t k = r >> 6;
+  const int w = width[k];
+  const int64_t base = off[k] + (r & 63);
+  const int b = rp[r], len = rp[r + 1] - b;
+  for (int q = 0; q < w; ++q) {
+    const bool in = q < len;
+    cd[base + 64 * q] = in ? (int16_t)(ci[b + q] - r) : (int16_t)0;
+    valf[base + 64 * q] = in ? (float)val[b + q] : 0.0f;
+  }
+}
+
 template <int S>
 __global__ __launch_bounds__(256) void sell_spmm_kernel(SellMat M, const double *__restrict__ X,
                                                         int64_t ldx, double *__restrict__ Y,
@@ -281,16 +316,27 @@ __global__ __launch_bounds__(256) void sell_spmm_kernel(SellMat M, const double 
 }  // namespace
 
 int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, const double *val,
-               void *buf, hipStream_t st) {
+               void *buf, hipStream_t st, bool allow_narrow, int *narrow) {
   SellMat m = sell_view(rows, nnz, buf);
   const int64_t ns = m.nslices;
   int32_t *width = const_cast<int32_t *>(m.width);
   int64_t *off = const_cast<int64_t *>(m.off);
+  const unsigned gr = (unsigned)((rows + 255) / 256);
   sell_width_kernel<<<(unsigned)((ns + 255) / 256), 256, 0, st>>>(rows, ns, rp, width);
   HIPOK(hipGetLastError());
+  // the narrow-form flag lives in the offsets' first word until the offsets are written
+  int *flag = reinterpret_cast<int *>(off);
+  if (allow_narrow) {
+    fill_int_kernel<<<1, 64, 0, st>>>(1, flag, 0);
+    HIPOK(hipGetLastError());
+    sell_narrow_check_kernel<<<gr, 256, 0, st>>>(rows, rp, ci, val, flag);
+    HIPOK(hipGetLastError());
+  }
   std::vector<int32_t> hw(ns);
   std::vector<int64_t> ho(ns);
+  int hflag = 1;
   HIPOK(hipMemcpyAsync(hw.data(), width, ns * 4, hipMemcpyDeviceToHost, st));
+  if (allow_narrow) HIPOK(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPOK(hipStreamSynchronize(st));
   int64_t tot = 0;
   for (int64_t k = 0; k < ns; ++k) {
@@ -298,11 +344,18 @@ int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, 
     tot += 64 * (int64_t)hw[k];
   }
   if (tot > sell_capacity(rows, nnz)) return SYLV_ERR_WORKSPACE;
+  const bool nar = allow_narrow && hflag == 0;
   HIPOK(hipMemcpyAsync(off, ho.data(), ns * 8, hipMemcpyHostToDevice, st));
-  sell_fill_kernel<<<(unsigned)((rows + 255) / 256), 256, 0, st>>>(
-      rows, rp, ci, val, width, off, const_cast<int32_t *>(m.ci), const_cast<double *>(m.val));
+  if (nar)
+    sell_fill_narrow_kernel<<<gr, 256, 0, st>>>(rows, rp, ci, val, width, off,
+                                                const_cast<int16_t *>(m.cd),
+                                                const_cast<float *>(m.valf));
+  else
+    sell_fill_kernel<<<gr, 256, 0, st>>>(rows, rp, ci, val, width, off,
+                                         const_cast<int32_t *>(m.ci), const_cast<double *>(m.val));
   HIPOK(hipGetLastError());
   HIPOK(hipStreamSynchronize(st));
+  if (narrow) *narrow = nar ? 1 : 0;
   return 0;
 }
 

@@ -167,3 +167,25 @@ def test_c3_bicgstab_window_vs_oracle(sylv):
     with open(os.path.join(GOLDEN, "c3_bicgstab_window.json")) as f:
         gold = json.load(f)
     _window(sylv, configs.c3_bicgstab(), "bicgstab", gold, ("alpha", "omega", "beta", "relres"))
+
+
+@pytest.mark.parametrize("nx", [32767, 32768])
+def test_narrow_sell_limit_vs_oracle(sylv, nx):
+    """The solver's SELL copy of an operator whose values are all exact floats and whose columns
+    lie within 32767 of their rows is stored narrow (float values, 16-bit column offsets); one
+    column further it is stored wide. A Laplacian on an nx x 2 grid (column offsets +-1 and
+    +-nx) sits on both sides of that limit; the first iterations of factored CG (Alg. 4.1)
+    against the oracle to 1e-10, and the two forms give the same products bit for bit where
+    both apply (the values are exact)."""
+    A = stencils.cd2d(nx, 2)
+    B = stencils.cd1d(300)
+    p = stencils.make_problem("nl", A, B, 1, 81, method="cg")
+    iters = 12
+    res, slv = gpu_solve(sylv, p, "cg", 1e-300, iters)
+    assert res.status == sylv.SYLV_NOT_CONVERGED and res.iters == iters
+    _, _, _, info = factored.solve(p, tol=1e-300, max_iter=iters)
+    h = slv.get_history()
+    for key in ("alpha", "relres"):
+        assert relmax(h[key][:iters], info[key][:iters]) < 1e-10, key
+    assert relmax(h["beta"][:iters - 1], info["beta"][:iters - 1]) < 1e-10
+    slv.close()

@@ -57,13 +57,17 @@ enum {
   SYLV_METHOD_GPBICG = 4
 };
 
-/* Storage precision of the Krylov bases. SYLV_FP64: everything in FP64. SYLV_MIXED_FP32: the
- * bases V, W (and the compact panels the sparse products read) are stored in FP32, halving the
- * dominant memory traffic of the block Arnoldi/Lanczos steps; products are accumulated in FP64
- * and the H, G blocks, the cores, the scalars and the residual evaluation stay FP64. The
- * recurrence then reaches a true-residual floor of roughly the FP32 unit roundoff times the
- * conditioning of the operator; sylv_refine_* recovers full accuracy (outer refinement). */
-enum { SYLV_FP64 = 0, SYLV_MIXED_FP32 = 1 };
+/* Precision. SYLV_FP64: everything in FP64. SYLV_MIXED_FP32: the bases V, W (and the compact
+ * panels the sparse products read) are stored in FP32, halving the dominant memory traffic of
+ * the block Arnoldi/Lanczos steps; products are accumulated in FP64 and the H, G blocks, the
+ * cores, the scalars and the residual evaluation stay FP64. The recurrence then reaches a
+ * true-residual floor of roughly the FP32 unit roundoff times the conditioning of the operator;
+ * the outer refinement options (refine_max and the other refine_* fields of sylv_options)
+ * recover full accuracy. SYLV_MIXED_BF16SPLIT: FP64 bases and recurrence, with the Gram
+ * contractions of the true-residual evaluation in split BF16 on the BF16 matrix cores (the same
+ * as SYLV_FP64 with gram_precision 1, or gram_precision 2 when that is asked for; see
+ * gram_precision below). */
+enum { SYLV_FP64 = 0, SYLV_MIXED_FP32 = 1, SYLV_MIXED_BF16SPLIT = 2 };
 
 /* Compressed sparse row matrix: rows x rows, int32 row_ptr (rows + 1 entries, row_ptr[0] = 0)
  * and col_idx (nnz entries, sorted and unique within each row, 0 <= col < rows), float64
@@ -98,7 +102,8 @@ typedef struct {
  * work); <= 0 selects the default, 16. closure_tol: a new basis block whose norm after orthogonalization is at most
  * closure_tol times ||M V_j||_F is replaced by a zero block (Krylov space exhausted); <= 0
  * selects the default of the precision (1e-12 for FP64, 1e-6 for FP32 bases).
- * precision: SYLV_FP64 or SYLV_MIXED_FP32 (storage of the bases, see above).
+ * precision: SYLV_FP64, SYLV_MIXED_FP32 (storage of the bases) or SYLV_MIXED_BF16SPLIT, see
+ * above.
  * Outer refinement (0 < refine_max <= 4; used with SYLV_MIXED_FP32): after the solve, the
  * residual R = C1 C2^T - A X - X B of the iterate is sketched, Y = R Omega with a Gaussian
  * m x refine_rank matrix, compressed to the rank-k right-hand side P (R^T P)^T with P an

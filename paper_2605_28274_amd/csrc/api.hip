@@ -104,7 +104,9 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
   if (op->max_iter < 1 || !known_method(op->method)) return SYLV_ERR_INVALID;
   // outer refinement drives CG and BiCGSTAB corrections only
   if (op->refine_max > 0 && op->method > SYLV_METHOD_BICGSTAB) return SYLV_ERR_INVALID;
-  if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32) return SYLV_ERR_INVALID;
+  if (op->precision != SYLV_FP64 && op->precision != SYLV_MIXED_FP32 &&
+      op->precision != SYLV_MIXED_BF16SPLIT)
+    return SYLV_ERR_INVALID;
   if (op->streams < 0 || op->streams > 2) return SYLV_ERR_INVALID;
   if (op->reorth < 0 || op->reorth > 2) return SYLV_ERR_INVALID;
   if (op->gram_precision < 0 || op->gram_precision > 2 || op->verify < 0 || op->verify > 1)
@@ -276,7 +278,9 @@ int make_layout(const sylv_problem *pb, const sylv_options *op, Layout &L, bool 
     L.off_Es = bump(cur, (size_t)L.rc_rows * L.ldE * 8);
     L.gpart_cap = gram_part_doubles(L.cmax, L.rc_rows);
     L.off_gpart = bump(cur, L.gpart_cap * 8);
-    L.gram_prec = op->gram_precision;
+    // SYLV_MIXED_BF16SPLIT: FP64 bases with the split-BF16 residual Grams (at least form 1)
+    L.gram_prec = op->precision == SYLV_MIXED_BF16SPLIT ? std::max(op->gram_precision, 1)
+                                                        : op->gram_precision;
     if (L.gram_prec > 0) {
       L.cpad = bf16_pack_width(L.cmax);
       L.off_pack = bump(cur, bf16_pack_bytes(L.rc_rows, L.cpad));

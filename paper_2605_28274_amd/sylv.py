@@ -25,7 +25,7 @@ SYLV_ERR_INVALID, SYLV_ERR_HIP, SYLV_ERR_WORKSPACE = -1, -2, -3
 SYLV_ERR_RHS_RANK, SYLV_ERR_STATE = -4, -5
 SYLV_METHOD_CG, SYLV_METHOD_BICGSTAB = 0, 1
 SYLV_METHOD_CR, SYLV_METHOD_CGS, SYLV_METHOD_GPBICG = 2, 3, 4
-SYLV_FP64, SYLV_MIXED_FP32 = 0, 1
+SYLV_FP64, SYLV_MIXED_FP32, SYLV_MIXED_BF16SPLIT = 0, 1, 2
 SYLV_BATCH_STREAMS, SYLV_BATCH_GROUPED, SYLV_BATCH_GRAPH = 0, 1, 2
 
 

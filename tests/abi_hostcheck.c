@@ -167,7 +167,7 @@ static void check_workspace_sizing(void) {
       case 2: b.max_iter = 0; break;
       case 3: b.max_iter = -3; break;
       case 4: b.max_iter = INT32_MAX; break;
-      case 5: b.precision = 2; break;
+      case 5: b.precision = 3; break;
       case 6: b.streams = 3; break;
       case 7: b.streams = -1; break;
       case 8: b.reorth = 3; break;

@@ -92,7 +92,7 @@ def test_precision_and_refine_options_validated():
     assert sylv.sylv_workspace_bytes(p, ref) > sylv.sylv_workspace_bytes(p, base)
     for bad in (dict(refine_max=5), dict(refine_max=1, refine_rank=0),
                 dict(refine_max=1, refine_rank=9), dict(refine_max=1, refine_max_iter=0),
-                dict(precision=2), dict(streams=3), dict(streams=-1), dict(reorth=3),
+                dict(precision=3), dict(streams=3), dict(streams=-1), dict(reorth=3),
                 dict(reorth=2)):  # the lagged pass needs FP64 bases (base is FP32)
         kw = dict(precision=sylv.SYLV_MIXED_FP32) if bad == dict(reorth=2) else {}
         kw.update(bad)
@@ -105,3 +105,12 @@ def test_precision_and_refine_options_validated():
     assert sylv.sylv_workspace_bytes(p5, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50,
                                                               reorth=2)) == 0
     assert sylv.sylv_workspace_bytes(p5, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50)) > 0
+
+
+def test_bf16split_precision_is_fp64_bases_with_split_grams():
+    p = _problem(n=4096, m=2048, s=2, nnzA=20000, nnzB=6000)
+    size = lambda **kw: sylv.sylv_workspace_bytes(
+        p, sylv.default_options(sylv.SYLV_METHOD_BICGSTAB, 50, **kw))
+    # the same workspace as FP64 bases with split-BF16 residual Grams (form 1, or 2 when asked)
+    assert size(precision=sylv.SYLV_MIXED_BF16SPLIT) == size(gram_precision=1) > size()
+    assert size(precision=sylv.SYLV_MIXED_BF16SPLIT, gram_precision=2) == size(gram_precision=2)

@@ -111,3 +111,17 @@ def test_verified_solve_rejects_a_true_residual_above_tol(sylv):
     assert res0.status == sylv.SYLV_OK and res0.rel_res_true < 0
     assert slv.residual_norm()[1] > tol
     slv.close()
+
+
+def test_bf16split_precision_equals_split_grams(sylv):
+    """precision = SYLV_MIXED_BF16SPLIT is FP64 bases with the split-BF16 residual Grams of
+    gram_precision 1: the same solve and the same residual norm, bit for bit."""
+    p, method, tol, cap = _problem("sylv_cg")
+    out = []
+    for kw in (dict(precision=sylv.SYLV_MIXED_BF16SPLIT), dict(gram_precision=1)):
+        slv = sylv.Solver(p.A, p.B, p.C1, p.C2, lyapunov=p.lyapunov, method=sylv.SYLV_METHOD_CG,
+                          max_iter=cap, verify=0, **kw)
+        res = slv.factored_cg(tol)
+        out.append((res.status, res.iters, slv.residual_norm()[1]))
+        slv.close()
+    assert out[0] == out[1]

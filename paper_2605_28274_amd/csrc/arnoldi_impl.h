@@ -1019,30 +1019,49 @@ __global__ __launch_bounds__(TPB) void dcgs_tail_pair(PS Pq, PS Ph, int nq, int 
 // Second Cholesky-QR pass from the G2 partials (every workgroup forms the same factor), then
 // the new block U T to the compact copy and, with to_basis, to V[:, (j+1)s : (j+2)s] (block
 // Lanczos leaves the basis columns to lz_flush_pair); workgroup 0 records T and writes
-// H_{j+1,j}.
-template <int S, typename T, class PS>
-__device__ __forceinline__ void final_body(const PS &P, int bid, int jb, int to_basis) {
+// H_{j+1,j}. ONEPASS (a single column, s = 1): the QR of one column is its normalization, the
+// first pass alone (closure test, T = 1 / ||U||, H_{j+1,j} = ||U||), formed here from the
+// partials of ||M V_j||^2 and U^T U, so qr2_pair does not run.
+template <int S, typename T, bool ONEPASS, class PS>
+__device__ __forceinline__ void final_body(const PS &P, int bid, int jb, int to_basis,
+                                           double closure_tol) {
   int lb, sd;
   const ArSide A = side_of(P, lb, sd, bid);
   __shared__ SideState st;
-  double G2[S * S];
-  sum_records<S * S>(A.aux + A.nb_spmm + A.nb_upd * S * S, A.nb_qr, G2);
-  if (threadIdx.x == 0) {
-    st.mode = A.ss->mode;
-    for (int i = 0; i < S * S; ++i) {
-      st.T1[i] = A.ss->T1[i];
-      st.Hs1[i] = A.ss->Hs1[i];
-    }
-    finish_pass2(&st, S, G2);
-    if (lb == 0) {
-      for (int i = 0; i < S * S; ++i) {
-        A.ss->T[i] = st.T[i];
-        A.ss->Hs1[i] = st.Hs1[i];
+  if (ONEPASS) {
+    double ref[1], G1[S * S];
+    sum_records<1>(A.aux, A.nb_spmm, ref);
+    sum_records<S * S>(A.aux + A.nb_spmm, A.nb_upd, G1);
+    if (threadIdx.x == 0) {
+      st.ref2 = ref[0];
+      finish_pass1(&st, S, closure_tol, G1);
+      for (int i = 0; i < S * S; ++i) st.T[i] = st.T1[i];
+      if (lb == 0) {
+        A.ss->ref2 = st.ref2;
+        A.ss->mode = st.mode;
+        for (int i = 0; i < S * S; ++i) A.ss->T1[i] = st.T1[i];
       }
-      for (int a = 0; a < S; ++a)
-        for (int b = 0; b < S; ++b)
-          A.H[(int64_t)((jb + 1) * S + a) * A.ldh + jb * S + b] = st.Hs1[a * S + b];
     }
+  } else {
+    double G2[S * S];
+    sum_records<S * S>(A.aux + A.nb_spmm + A.nb_upd * S * S, A.nb_qr, G2);
+    if (threadIdx.x == 0) {
+      st.mode = A.ss->mode;
+      for (int i = 0; i < S * S; ++i) {
+        st.T1[i] = A.ss->T1[i];
+        st.Hs1[i] = A.ss->Hs1[i];
+      }
+      finish_pass2(&st, S, G2);
+    }
+  }
+  if (threadIdx.x == 0 && lb == 0) {
+    for (int i = 0; i < S * S; ++i) {
+      A.ss->T[i] = st.T[i];
+      A.ss->Hs1[i] = st.Hs1[i];
+    }
+    for (int a = 0; a < S; ++a)
+      for (int b = 0; b < S; ++b)
+        A.H[(int64_t)((jb + 1) * S + a) * A.ldh + jb * S + b] = st.Hs1[a * S + b];
   }
   __syncthreads();
   double Tq[S * S];
@@ -1063,12 +1082,12 @@ __device__ __forceinline__ void final_body(const PS &P, int bid, int jb, int to_
   }
 }
 
-template <int S, typename T, class PS>
-__global__ __launch_bounds__(TPB) void final_pair(PS P, int jb, int to_basis,
+template <int S, typename T, bool ONEPASS = false, class PS>
+__global__ __launch_bounds__(TPB) void final_pair(PS P, int jb, int to_basis, double closure_tol,
                                                   const DevState *ds) {
   krylov_wave_priority();
   if (halted(P, ds)) return;
-  final_body<S, T>(P, (int)blockIdx.x, jb, to_basis);
+  final_body<S, T, ONEPASS>(P, (int)blockIdx.x, jb, to_basis, closure_tol);
 }
 
 // ---- block Lanczos step j for both bases (Algorithm 4.1, steps 4-5) ----
@@ -1217,8 +1236,8 @@ __global__ __launch_bounds__(TPB) void lz_update_pair(PS P, int jb, const DevSta
 
 // The whole block Lanczos step for small bases: one workgroup per basis runs the four phases
 // (SpMM and local three-term update, H_jj and U update, first and second QR pass with the new
-// block), with barriers where the separate kernels have launch boundaries; each phase's
-// reduction has a single record.
+// block; one QR pass for a single column), with barriers where the separate kernels have launch
+// boundaries; each phase's reduction has a single record.
 template <int S, typename T>
 __global__ __launch_bounds__(TPB) void lz_fused_pair(ArPair P, int jb, double closure_tol,
                                                      const DevState *ds) {
@@ -1228,9 +1247,13 @@ __global__ __launch_bounds__(TPB) void lz_fused_pair(ArPair P, int jb, double cl
   __syncthreads();
   lz_update_body<S, T>(P, bid, jb);
   __syncthreads();
+  if (S == 1) {  // one column: normalization, one pass
+    final_body<S, T, true>(P, bid, jb, 0, closure_tol);
+    return;
+  }
   qr2_body<S>(P, bid, closure_tol);
   __syncthreads();
-  final_body<S, T>(P, bid, jb, 0);
+  final_body<S, T, false>(P, bid, jb, 0, closure_tol);
 }
 
 // Basis columns of blocks [b0, b1) (b1 - b0 <= LZ_RING) from the block Lanczos ring: each
@@ -1505,7 +1528,7 @@ int arnoldi_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
   prof_begin(sc, st);
   qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, 1, ds);
+  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, 1, closure_tol, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
@@ -1606,7 +1629,7 @@ int arnoldi_lagged_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh
   dcgs_tail_pair<S><<<(unsigned)nq + total_blocks(Ph), TPB, 0, st>>>(P, Ph, nq, jb,
                                                                       closure_tol, ds);
   HIPOK(hipGetLastError());
-  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, 1, ds);
+  final_pair<S, double><<<total_blocks(P), TPB, 0, st>>>(P, jb, 1, 0.0, ds);
   HIPOK(hipGetLastError());
   prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
   return 0;
@@ -1739,11 +1762,17 @@ int lanczos_pair_t(const SideDesc &sv, const SideDesc *sw, int jb, int64_t ldh,
            2.0 * (sv.nnz + (sw ? sw->nnz : 0)) * S + 8.0 * total * S * S, st);
   set_ranges(P, nb_qr(rows0), sw ? nb_qr(rows1) : 0);
   prof_begin(sc, st);
-  qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
-  HIPOK(hipGetLastError());
-  final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, 0, ds);
-  HIPOK(hipGetLastError());
-  prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  if (S == 1) {  // one column: normalization, one pass (final_body)
+    final_pair<S, T, true><<<total_blocks(P), TPB, 0, st>>>(P, jb, 0, closure_tol, ds);
+    HIPOK(hipGetLastError());
+    prof_end(sc, FAM_QR, 8.0 * total * S * 2, 2.0 * total * S * S, st);
+  } else {
+    qr2_pair<S><<<total_blocks(P), TPB, 0, st>>>(P, closure_tol, ds);
+    HIPOK(hipGetLastError());
+    final_pair<S, T><<<total_blocks(P), TPB, 0, st>>>(P, jb, 0, closure_tol, ds);
+    HIPOK(hipGetLastError());
+    prof_end(sc, FAM_QR, 8.0 * total * S * 3, 6.0 * total * S * S, st);
+  }
   // block jb + 1 completes a group of ring slots: the group goes to the basis
   if ((jb + 2) % LZ_RING == 0) return lanczos_flush_t<S, T>(sv, sw, jb + 2, st);
   return 0;
@@ -1775,10 +1804,17 @@ int lanczos_group_t(const KGroup &g, int jb, double closure_tol, hipStream_t st)
   HIPOK(hipGetLastError());
   lz_update_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(R, jb, nullptr);
   HIPOK(hipGetLastError());
-  qr2_pair<S><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, closure_tol, nullptr);
-  HIPOK(hipGetLastError());
-  final_pair<S, double><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, jb, 0, nullptr);
-  HIPOK(hipGetLastError());
+  if (S == 1) {  // one column: normalization, one pass (final_body)
+    final_pair<S, double, true><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, jb, 0, closure_tol,
+                                                                          nullptr);
+    HIPOK(hipGetLastError());
+  } else {
+    qr2_pair<S><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, closure_tol, nullptr);
+    HIPOK(hipGetLastError());
+    final_pair<S, double><<<(unsigned)g.nblk[GK_QR], TPB, 0, st>>>(Q, jb, 0, closure_tol,
+                                                                   nullptr);
+    HIPOK(hipGetLastError());
+  }
   if ((jb + 2) % LZ_RING == 0) {
     lz_flush_pair<S, double><<<(unsigned)g.nblk[GK_ROWS], TPB, 0, st>>>(R, jb + 2 - LZ_RING,
                                                                         jb + 2);
@@ -1844,7 +1880,7 @@ int arnoldi_group_t(const KGroup &g, int jb, double closure_tol, hipStream_t st)
     dcgs_tail_pair<S><<<(unsigned)(nq + g.nsides * hw), TPB, 0, st>>>(
         Q, group_tab(g, GK_ROWS, jb, 2, hw), nq, jb, closure_tol, nullptr);
     HIPOK(hipGetLastError());
-    final_pair<S, double><<<(unsigned)nq, TPB, 0, st>>>(Q, jb, 1, nullptr);
+    final_pair<S, double><<<(unsigned)nq, TPB, 0, st>>>(Q, jb, 1, 0.0, nullptr);
     HIPOK(hipGetLastError());
     return 0;
   }

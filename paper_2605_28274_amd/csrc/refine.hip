@@ -157,8 +157,9 @@ __global__ __launch_bounds__(TPB) void copy_block_kernel(int rows, int cols, dou
           alpha * (trans ? src[(int64_t)j * lds + i] : src[(int64_t)i * lds + j]);
 }
 
-// dst (rows x cols, ldd) = src (lds): rows strided over the workgroups, each thread four
+// dst (rows x cols, ldd) = src (lds): rows strided over the workgroups, each thread CR
 // elements of a row at a time (their loads issued together).
+constexpr int CR = 8;
 __global__ __launch_bounds__(TPB) void copy_rows_kernel(int64_t rows, int64_t cols,
                                                         const double *__restrict__ src,
                                                         int64_t lds, double *__restrict__ dst,
@@ -166,15 +167,15 @@ __global__ __launch_bounds__(TPB) void copy_rows_kernel(int64_t rows, int64_t co
   for (int64_t i = blockIdx.x; i < rows; i += gridDim.x) {
     const double *a = src + i * lds;
     double *b = dst + i * ldd;
-    for (int64_t j0 = threadIdx.x; j0 < cols; j0 += 4 * TPB) {
-      double v[4];
+    for (int64_t j0 = threadIdx.x; j0 < cols; j0 += CR * TPB) {
+      double v[CR];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < CR; ++u) {
         const int64_t j = j0 + u * TPB;
-        v[u] = j < cols ? a[j] : 0.0;
+        v[u] = a[j < cols ? j : 0];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
+      for (int u = 0; u < CR; ++u) {
         const int64_t j = j0 + u * TPB;
         if (j < cols) b[j] = v[u];
       }
@@ -307,8 +308,8 @@ int launch_copy_block(int rows, int cols, double alpha, const double *src, int64
 int launch_copy_rows(int64_t rows, int64_t cols, const double *src, int64_t lds, double *dst,
                      int64_t ldd, hipStream_t st) {
   if (rows <= 0 || cols <= 0) return 0;
-  copy_rows_kernel<<<(unsigned)std::min<int64_t>(rows, 8192), TPB, 0, st>>>(rows, cols, src, lds,
-                                                                            dst, ldd);
+  copy_rows_kernel<<<(unsigned)std::min<int64_t>(rows, 16384), TPB, 0, st>>>(rows, cols, src, lds,
+                                                                             dst, ldd);
   HIPOK(hipGetLastError());
   return 0;
 }

@@ -644,13 +644,11 @@ __device__ __forceinline__ void for_each_acc2(const Acc2 &acc, int wm, int wn, F
 }
 
 // acc += A(:, i0 ..)^T B(:, j0 ..) over K slabs [a, b) of tile (i0, j0); the slab past the last
-// full one holds the last K % BK2 rows, zero-filled past K. With `idle` the wave takes part in
-// the loads and barriers but forms nothing (its acc stays zero): the strictly upper quarter of a
-// diagonal tile of a lower-triangle Gram, which the mirror overwrites.
+// full one holds the last K % BK2 rows, zero-filled past K.
 __device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, int64_t j0,
                                             int64_t K, const double *__restrict__ A, int64_t lda,
                                             const double *__restrict__ B, int64_t ldb, int64_t a,
-                                            int64_t b, int wm, int wn, bool idle) {
+                                            int64_t b, int wm, int wn) {
   const int64_t nfull = K / BK2;
   const int64_t bf = b < nfull ? b : nfull;
   if (bf > a) {
@@ -688,7 +686,7 @@ __device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, in
         store(cur ^ 1);
         load((a + (t + 2 < nsl ? t + 2 : nsl - 1)) * BK2);
       }
-      if (!idle) mma2(sm.A[cur], sm.B[cur], acc, wm, wn);
+      mma2(sm.A[cur], sm.B[cur], acc, wm, wn);
     }
   }
   if (b > nfull) {
@@ -701,7 +699,7 @@ __device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, in
       sm.B[0][kk][ii] = (in && j0 + ii < ldb) ? B[(kb + kk) * ldb + j0 + ii] : 0.0;
     }
     __syncthreads();
-    if (!idle) mma2(sm.A[0], sm.B[0], acc, wm, wn);
+    mma2(sm.A[0], sm.B[0], acc, wm, wn);
   }
 }
 
@@ -741,8 +739,7 @@ __global__ __launch_bounds__(256, 2) void gram_wide_kernel(const GramJobs jobs, 
     const int64_t i0 = (int64_t)I * TW2, j0 = (int64_t)J * TW2;
     Acc2 acc;
     zero_acc2(acc);
-    gram_piece2(sm, acc, i0, j0, K, jb.A, jb.lda, jb.B, jb.ldb, 0, nsl, wm, wn,
-                jb.sq.lower && I == J && wm < wn);
+    gram_piece2(sm, acc, i0, j0, K, jb.A, jb.lda, jb.B, jb.ldb, 0, nsl, wm, wn);
     store_c(acc, jb, i0, j0);
   }
   if (w >= nchunks) return;
@@ -758,8 +755,7 @@ __global__ __launch_bounds__(256, 2) void gram_wide_kernel(const GramJobs jobs, 
     const int64_t i0 = (int64_t)I * TW2, j0 = (int64_t)J * TW2;
     Acc2 acc;
     zero_acc2(acc);
-    gram_piece2(sm, acc, i0, j0, K, jb.A, jb.lda, jb.B, jb.ldb, a, b, wm, wn,
-                jb.sq.lower && I == J && wm < wn);
+    gram_piece2(sm, acc, i0, j0, K, jb.A, jb.lda, jb.B, jb.ldb, a, b, wm, wn);
     if (a == 0 && b == nsl) {
       store_c(acc, jb, i0, j0);
     } else {

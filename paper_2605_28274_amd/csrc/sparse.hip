@@ -80,7 +80,7 @@ __global__ __launch_bounds__(1024) void scan_kernel(int64_t len, const int *__re
     buf[threadIdx.x] = v;
     __syncthreads();
     for (int off = 1; off < 1024; off <<= 1) {  // Hillis-Steele inclusive scan
-      int t = (threadIdx.x >= off) ? buf[threadIdx.x - off] : 0;
+      int t = ((int)threadIdx.x >= off) ? buf[threadIdx.x - off] : 0;
       __syncthreads();
       buf[threadIdx.x] += t;
       __syncthreads();

@@ -952,8 +952,14 @@ int stacked_residual(Ctx *P, const std::vector<Ctx *> &steps, double *abs_res, d
                                        PL.ldE, st)))
             return ee;
         }
-        // algorithmic: the basis rows read once, the defect rows written once, the operator
-        prof_end(P->sc, FAM_RES_DEFECT, (double)nr * (CL.esz * q + 8.0 * p), 2.0 * nr * q * p, st);
+        // algorithmic: the basis rows read once, the defect rows written once; flops of the
+        // operator rows (their average length) and the band (3 s entries per column), or of the
+        // dense Hessenberg product
+        const double row_nnz = sd.rows > 0 ? (double)sd.nnz / (double)sd.rows : 0.0;
+        const double dflops = lanczos_method(CL.method)
+                                  ? 2.0 * nr * p * (row_nnz + 3.0 * CL.s)
+                                  : 2.0 * nr * p * (row_nnz + (double)q);
+        prof_end(P->sc, FAM_RES_DEFECT, (double)nr * (CL.esz * q + 8.0 * p), dflops, st);
       }
       // compact sources (QR defects, C2) next to the defects
       for (const Fill &f : (w ? fillN : fillL))

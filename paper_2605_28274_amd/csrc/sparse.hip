@@ -300,17 +300,38 @@ __global__ void sell_fill_narrow_kernel(int64_t rows, const int32_t *__restrict_
   }
 }
 
-template <int S>
+// NR rows per thread, from NR consecutive blocks of 256 rows (each block read by whole slices);
+// NR > 1 lets a launch over a large operator fit the GPU in one round of workgroups, with NR
+// rows of loads in flight per thread.
+template <int S, int NR>
 __global__ __launch_bounds__(256) void sell_spmm_kernel(SellMat M, const double *__restrict__ X,
                                                         int64_t ldx, double *__restrict__ Y,
                                                         int64_t ldy) {
-  const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (r >= M.rows) return;
-  double acc[S];
-  sell_row<S>(M, r, X, ldx, acc);
-  double *y = Y + r * ldy;
+  if (NR == 1) {
+    const int64_t r = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (r >= M.rows) return;
+    double acc[S];
+    sell_row<S>(M, r, X, ldx, acc);
+    double *y = Y + r * ldy;
 #pragma unroll
-  for (int t = 0; t < S; ++t) y[t] = acc[t];
+    for (int t = 0; t < S; ++t) y[t] = acc[t];
+    return;
+  }
+  int64_t r[NR];
+  bool ok[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    r[i] = ((int64_t)blockIdx.x * NR + i) * 256 + threadIdx.x;
+    ok[i] = r[i] < M.rows;
+  }
+  if (!ok[0]) return;
+  double acc[NR][S];
+  sell_rows<NR, S>(M, r, ok, X, ldx, acc);
+#pragma unroll
+  for (int i = 0; i < NR; ++i)
+    if (ok[i])
+#pragma unroll
+      for (int t = 0; t < S; ++t) Y[r[i] * ldy + t] = acc[i][t];
 }
 
 }  // namespace
@@ -362,10 +383,18 @@ int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, 
 int launch_sell_spmm(int s, const SellMat &M, const double *X, int64_t ldx, double *Y, int64_t ldy,
                      hipStream_t st) {
   if (M.rows <= 0) return 0;
-  const unsigned g = (unsigned)((M.rows + 255) / 256);
+  // two rows per thread (one column) where one row per thread would take more than one round
+  // of 2048 workgroups (eight per CU)
+  const bool two = s == 1 && M.rows > (int64_t)2048 * 256;
+  const unsigned g = (unsigned)((M.rows + (two ? 511 : 255)) / (two ? 512 : 256));
+  if (two) {
+    sell_spmm_kernel<1, 2><<<g, 256, 0, st>>>(M, X, ldx, Y, ldy);
+    HIPOK(hipGetLastError());
+    return 0;
+  }
   switch (s) {
 #define CASE(SS) \
-  case SS: sell_spmm_kernel<SS><<<g, 256, 0, st>>>(M, X, ldx, Y, ldy); break;
+  case SS: sell_spmm_kernel<SS, 1><<<g, 256, 0, st>>>(M, X, ldx, Y, ldy); break;
     CASE(1) CASE(2) CASE(3) CASE(4) CASE(5) CASE(6) CASE(7) CASE(8)
 #undef CASE
     default: return SYLV_ERR_INVALID;

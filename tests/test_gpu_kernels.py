@@ -116,11 +116,15 @@ def test_sell_spmm_stencils(sylv, s):
     _sell_case(sylv, stencils.cd3d(16, 8, 9, 10.0), s)
 
 
-@pytest.mark.parametrize("grid,s", [("2d1024", 1), ("3d64", 4)])
+@pytest.mark.parametrize("grid,s", [("2d1024", 1), ("2d1023", 1), ("3d64", 4)])
 def test_sell_spmm_chained_full_size(sylv, grid, s):
     # the operators the bandwidth figure is measured on, at full size; three products issued
-    # back to back on one stream without waiting in between (the call only enqueues)
-    M = stencils.cd2d(1024, 1024, 0.0) if grid == "2d1024" else stencils.cd3d(64, 64, 64, 10.0)
+    # back to back on one stream without waiting in between (the call only enqueues). Over
+    # 2048 x 256 rows with one column each thread takes two rows; 1023^2 rows leave a ragged
+    # last workgroup (its second block of 256 rows partly past the end)
+    M = {"2d1024": lambda: stencils.cd2d(1024, 1024, 0.0),
+         "2d1023": lambda: stencils.cd2d(1023, 1023, 3.0),
+         "3d64": lambda: stencils.cd3d(64, 64, 64, 10.0)}[grid]()
     rp, ci, va = sylv.csr_tensors(M)
     csr = sylv.make_csr(M.shape[0], rp, ci, va)
     buf = torch.empty(sylv.sylv_sell_bytes(csr), dtype=torch.uint8, device="cuda")

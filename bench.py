@@ -279,8 +279,9 @@ def main():
     if args.refine < 0:
         args.refine = 3 if args.precision == "fp32" else 0
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU: the path would shard by rows "
-                                   "(see the design notes); --gpus must be 1"}))
+        print(json.dumps({"error": "the solver runs on one GPU (a multi-GPU form would split "
+                                   "the basis rows over the GPUs and sum the Gram partials "
+                                   "across them); --gpus must be 1"}))
         sys.exit(2)
 
     import numpy as np

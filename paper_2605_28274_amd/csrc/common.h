@@ -934,7 +934,9 @@ struct GramJobs {
 // 128 x 128 tiles of a Gram (the lower triangle with `lower`)
 int64_t gram_wide_tiles(int64_t M, int64_t N, bool lower);
 // The jobs (n <= GRAM_JOBS_MAX) as one launch on 128 x 128 tiles; returns 1 (nothing launched)
-// when part cannot hold the stream-K slots, so the caller runs the jobs one by one.
+// when part cannot hold the stream-K slots or the jobs have fewer than 256 tiles, so the caller
+// runs the jobs one by one; SYLV_ERR_INVALID for a leading dimension below the width or not a
+// multiple of 8 (as launch_gram).
 int launch_gram_jobs(const GramJob *jobs, int n, int64_t K, double beta, hipStream_t st,
                      double *part, size_t part_cap);
 

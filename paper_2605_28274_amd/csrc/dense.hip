@@ -686,7 +686,11 @@ __device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, in
         store(cur ^ 1);
         load((a + (t + 2 < nsl ? t + 2 : nsl - 1)) * BK2);
       }
+      // the slab's MFMAs first: the co-resident workgroup's stores and loads take the issue
+      // slots they leave
+      __builtin_amdgcn_s_setprio(1);
       mma2(sm.A[cur], sm.B[cur], acc, wm, wn);
+      __builtin_amdgcn_s_setprio(0);
     }
   }
   if (b > nfull) {

@@ -602,13 +602,14 @@ struct Acc2 {
 };
 
 // MFMA operand layout as in mma_slab; each step of 4 rows reads its operands, then runs its 16
-// MFMAs (the other workgroup on the CU covers the LDS latency).
+// MFMAs (the other workgroup on the CU covers the LDS latency). Steps [Q0, Q1) of the slab.
+template <int Q0 = 0, int Q1 = BK2 / 4>
 __device__ __forceinline__ void mma2(const double (&As)[BK2][LW2], const double (&Bs)[BK2][LW2],
                                      Acc2 &acc, int wm, int wn) {
   const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
   const double *pa = &As[lk][wm * 64 + li], *pb = &Bs[lk][wn * 64 + li];
 #pragma unroll
-  for (int q = 0; q < BK2 / 4; ++q) {
+  for (int q = Q0; q < Q1; ++q) {
     double a[4], b[4];
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
@@ -682,14 +683,18 @@ __device__ __forceinline__ void gram_piece2(Smem2 &sm, Acc2 &acc, int64_t i0, in
     for (int64_t t = 0; t < nsl; ++t) {
       __syncthreads();  // slab t is in buffer t % 2 for every wave; the other buffer is free
       const int cur = (int)(t & 1);
+      // the slab's MFMAs at a raised priority: the co-resident workgroup's stores and loads take
+      // the issue slots they leave. The first step's MFMAs go before this wave's own store of
+      // slab t + 1, whose wait for the loads issued a slab ago comes that much later.
+      __builtin_amdgcn_s_setprio(1);
+      mma2<0, 1>(sm.A[cur], sm.B[cur], acc, wm, wn);
+      __builtin_amdgcn_s_setprio(0);
       if (t + 1 < nsl) {
         store(cur ^ 1);
         load((a + (t + 2 < nsl ? t + 2 : nsl - 1)) * BK2);
       }
-      // the slab's MFMAs first: the co-resident workgroup's stores and loads take the issue
-      // slots they leave
       __builtin_amdgcn_s_setprio(1);
-      mma2(sm.A[cur], sm.B[cur], acc, wm, wn);
+      mma2<1, BK2 / 4>(sm.A[cur], sm.B[cur], acc, wm, wn);
       __builtin_amdgcn_s_setprio(0);
     }
   }

@@ -174,11 +174,17 @@ __global__ __launch_bounds__(256, 2) void gram_bf16_kernel(const char *__restric
   Frag f0, f1;
   load_frag(slab(t0), ca, cb, g, f0);
   int t = t0;
+  // matrix-core work at a raised wave priority: the co-resident waves' load issue takes the
+  // slots it leaves
   for (; t + 1 < t1; t += 2) {
     load_frag(slab(t + 1), ca, cb, g, f1);
+    __builtin_amdgcn_s_setprio(1);
     mma_frag(f0, acc);
+    __builtin_amdgcn_s_setprio(0);
     load_frag(slab(t + 2), ca, cb, g, f0);
+    __builtin_amdgcn_s_setprio(1);
     mma_frag(f1, acc);
+    __builtin_amdgcn_s_setprio(0);
   }
   if (t < t1) mma_frag(f0, acc);
   float *pt = part + ((size_t)kz * ntiles + tile) * (PT * PT);

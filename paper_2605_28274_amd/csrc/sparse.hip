@@ -301,8 +301,8 @@ __global__ void sell_fill_narrow_kernel(int64_t rows, const int32_t *__restrict_
 }
 
 // NR rows per thread, from NR consecutive blocks of 256 rows (each block read by whole slices);
-// NR > 1 lets a launch over a large operator fit the GPU in one round of workgroups, with NR
-// rows of loads in flight per thread.
+// NR > 1 keeps NR rows of loads in flight per thread and divides the workgroups of a launch over
+// a large operator by NR.
 template <int S, int NR>
 __global__ __launch_bounds__(256) void sell_spmm_kernel(SellMat M, const double *__restrict__ X,
                                                         int64_t ldx, double *__restrict__ Y,
@@ -383,8 +383,8 @@ int build_sell(int64_t rows, int64_t nnz, const int32_t *rp, const int32_t *ci, 
 int launch_sell_spmm(int s, const SellMat &M, const double *X, int64_t ldx, double *Y, int64_t ldy,
                      hipStream_t st) {
   if (M.rows <= 0) return 0;
-  // two rows per thread (one column) where one row per thread would take more than one round
-  // of 2048 workgroups (eight per CU)
+  // two rows per thread (one column) where one row per thread would take more than the 2048
+  // workgroups the GPU holds at once (eight per CU)
   const bool two = s == 1 && M.rows > (int64_t)2048 * 256;
   const unsigned g = (unsigned)((M.rows + (two ? 511 : 255)) / (two ? 512 : 256));
   if (two) {

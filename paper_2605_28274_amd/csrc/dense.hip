@@ -583,10 +583,11 @@ __global__ __launch_bounds__(256) void gram_stream_fix_kernel(const GramSeq sq, 
 // ---- 128 x 128 tiles: the large FP64 Grams ----
 // Each 256-thread workgroup owns a 128 x 128 output tile, each wave a 64 x 64 quarter (4 x 4
 // MFMA tiles, sixteen accumulators), two workgroups per CU. K runs in slabs of 16 rows through
-// two LDS buffers: at slab t, after one barrier, the waves store slab t + 1 (loaded into
-// registers during slab t - 1) into the free buffer, issue the global loads of slab t + 2, and
-// run the slab's 64 MFMAs per wave on the current buffer. Per flop this reads half the LDS and
-// L2 bytes of the 64 x 64 tiles and meets a barrier half as often. FP64 operands only.
+// two LDS buffers: at slab t, after one barrier, the waves run the first 16 of the slab's 64
+// MFMAs per wave on the current buffer, store slab t + 1 (loaded into registers during slab
+// t - 1) into the free buffer, issue the global loads of slab t + 2, and run the other 48. Per
+// flop this reads half the LDS and L2 bytes of the 64 x 64 tiles and meets a barrier half as
+// often. FP64 operands only.
 constexpr int TW2 = 128, BK2 = 16;
 constexpr int LW2 = TW2 + 16;  // slab row of 128 doubles, padded by 32 banks: the two rows
                                // that one LDS pass of an MFMA operand read meets do not collide

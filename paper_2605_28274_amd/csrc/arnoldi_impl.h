@@ -24,6 +24,7 @@
 // instantiate them for groups of block sizes (parallel compilation), arnoldi.hip dispatches.
 #pragma once
 #include <algorithm>
+#include <type_traits>
 
 #include "common.h"
 
@@ -1274,6 +1275,16 @@ __global__ __launch_bounds__(TPB) void lz_flush_pair(PS P, int b0, int b1) {
         for (int t = 0; t < S; ++t) v[k * S + t] = src[t];
       }
     T *dst = basis + r * A.ldb + (int64_t)b0 * S;
+    if constexpr (std::is_same<T, double>::value) {
+      if (b1 - b0 == LZ_RING) {
+        // a full ring: LZ_RING s consecutive doubles of the row, 16-byte aligned (the basis
+        // leading dimension is a multiple of 64, b0 of LZ_RING), written 16 bytes at a time
+#pragma unroll
+        for (int k = 0; k < LZ_RING * S; k += 2)
+          *reinterpret_cast<double2 *>(dst + k) = make_double2(v[k], v[k + 1]);
+        continue;
+      }
+    }
 #pragma unroll
     for (int k = 0; k < LZ_RING; ++k)
       if (b0 + k < b1)
